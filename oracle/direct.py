@@ -1,0 +1,62 @@
+"""Exact discrete solutions by direct routes (oracle).
+
+* R2, slab by slab: the space-time system is block lower triangular in time
+  (eq. waveform_patch_solve), so it can be solved one slab after another, each
+  by Newton with a sparse direct solve of the slab block bordered by the
+  zero-mean pressure constraints (the timestepping view of Sec. 3, where the
+  same discretisation is coupled over one time element at a time).
+* R3, all at once: Newton on the whole space-time system with a dense LU of
+  the bordered space-time Jacobian (the monolithic direct comparison of
+  Sec. 4.1), for tiny meshes only.
+Both return free vectors whose pressure has zero mean per temporal node.
+"""
+import numpy as np
+import scipy.linalg as la
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+
+
+def solve_slab_by_slab(level, tol=1e-13, maxit=30):
+    nf, N, nq = level.n_free, level.N, level.nq
+    st = N * nq
+    po = level.mesh.p_offset
+    x = np.zeros((nf, N, nq))
+    C = sp.lil_matrix((nf * nq, nq))
+    for a in range(nq):
+        for i in range(po, nf):
+            C[i * nq + a, a] = 1.0
+    C = C.tocsr()
+    for n in range(N):
+        idx = (np.arange(nf)[:, None] * st + n * nq + np.arange(nq)[None, :]).ravel()
+        for it in range(maxit):
+            F = level.residual(x, slabs=[n]).ravel()[idx]
+            if np.linalg.norm(F) <= tol * max(1.0, np.linalg.norm(x[:, n, :])):
+                break
+            J = level.jacobian(x, slabs=[n])
+            Jn = J[idx][:, idx]
+            B = sp.bmat([[Jn, C], [C.T, None]], format="csc")
+            d = spla.spsolve(B, np.concatenate([-F, np.zeros(nq)]))[: nf * nq]
+            x[:, n, :] += d.reshape(nf, nq)
+    return x
+
+
+def solve_all_at_once(level, tol=1e-13, maxit=30):
+    nf, N, nq = level.n_free, level.N, level.nq
+    po = level.mesh.p_offset
+    n = level.n_st
+    C = np.zeros((n, N * nq))
+    st = N * nq
+    for k in range(N * nq):
+        C[np.arange(po, nf) * st + k, k] = 1.0
+    x = np.zeros(n)
+    for it in range(maxit):
+        F = level.residual(x.reshape(nf, N, nq)).ravel()
+        if np.linalg.norm(F) <= tol * max(1.0, np.linalg.norm(x)):
+            break
+        J = level.jacobian(x.reshape(nf, N, nq)).toarray()
+        B = np.block([[J, C], [C.T, np.zeros((N * nq, N * nq))]])
+        d = la.solve(B, np.concatenate([-F, np.zeros(N * nq)]))[:n]
+        x += d
+    return x.reshape(nf, N, nq)

@@ -1,0 +1,132 @@
+"""Seeded synthetic workloads for the space-time Navier-Stokes solver.
+
+This module only draws random numbers and names problem sizes.  It holds none
+of the method's arithmetic: the manufactured-solution modes it draws are passed
+explicitly, as plain arrays, to both the CPU oracle and the HIP library, so the
+two consume identical numbers without sharing any code that computes with them.
+
+Manufactured solution family (stated here so the arrays can be read):
+
+* stream function  psi(t,x,y) = sum_m c_m sin(a_m pi x) sin(b_m pi y) cos(w_m t + th_m)
+  with velocity u = (d psi/dy, -d psi/dx); every mode gives u.n = 0 on the
+  boundary of the unit square, so the Dirichlet data has zero net flux;
+* pressure  p(t,x,y) = sum_m d_m cos(al_m pi x) cos(be_m pi y) cos(w'_m t + th'_m)
+  with (al_m, be_m) != (0, 0), so every mode has zero mean over the square.
+
+Arrays: ``psi_ab`` int32 (n_psi, 2) = (a, b); ``psi_coef`` float64 (n_psi, 3)
+= (c, w, th); ``p_ab`` int32 (n_p, 2) = (al, be); ``p_coef`` float64 (n_p, 3)
+= (d, w', th').
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = ["Problem", "draw_modes", "config_problem", "batch_problems",
+           "arrival_times", "CONFIG_NAMES"]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One space-time Navier-Stokes problem on the unit square."""
+    mesh_n: int            # finest mesh: mesh_n x mesh_n squares, each cut into 2 triangles
+    n_levels: int          # spatial multigrid levels (finest .. mesh_n / 2**(n_levels-1))
+    q: int                 # DG degree in time
+    n_slabs: int           # N time slabs on [0, t_final]
+    t_final: float
+    reynolds: float
+    psi_ab: np.ndarray
+    psi_coef: np.ndarray
+    p_ab: np.ndarray
+    p_coef: np.ndarray
+    seed: int = 0
+
+    @property
+    def n_free_spatial(self) -> int:
+        m = self.mesh_n
+        return 2 * (2 * m - 1) ** 2 + (m + 1) ** 2
+
+    @property
+    def n_st(self) -> int:
+        return self.n_free_spatial * self.n_slabs * (self.q + 1)
+
+
+def draw_modes(seed: int, n_psi: int = 4, n_p: int = 3, max_wave: int = 4,
+               omega: float = math.pi):
+    """Draw manufactured-solution modes with numpy's default_rng(seed).
+
+    a, b ~ U{1..max_wave}; c ~ N(0,1); th ~ U[0, 2 pi); (al, be) ~ U{0..4}^2
+    without (0,0); d ~ N(0,1); every temporal frequency is ``omega``.
+    """
+    rng = np.random.default_rng(seed)
+    psi_ab = rng.integers(1, max_wave + 1, size=(n_psi, 2)).astype(np.int32)
+    c = rng.standard_normal(n_psi)
+    th = rng.uniform(0.0, 2.0 * math.pi, n_psi)
+    psi_coef = np.stack([c, np.full(n_psi, omega), th], axis=1)
+    p_ab = np.zeros((n_p, 2), dtype=np.int32)
+    for m in range(n_p):
+        while True:
+            ab = rng.integers(0, 5, size=2)
+            if ab[0] != 0 or ab[1] != 0:
+                break
+        p_ab[m] = ab
+    d = rng.standard_normal(n_p)
+    thp = rng.uniform(0.0, 2.0 * math.pi, n_p)
+    p_coef = np.stack([d, np.full(n_p, omega), thp], axis=1)
+    return (np.ascontiguousarray(psi_ab), np.ascontiguousarray(psi_coef),
+            np.ascontiguousarray(p_ab), np.ascontiguousarray(p_coef))
+
+
+CONFIG_NAMES = {
+    0: "ns_p2p1_dg0_m4_n4_re1",
+    1: "ns_p2p1_dg1_m32_n32_re100",
+    4: "ns_p2p1_dg1_m128_n64_re1000",
+}
+
+
+def config_problem(config: int, index: int = 0) -> Problem:
+    """The fixed single-solve workloads (configs 0, 1 and 4); seed = 1000*config + index."""
+    seed = 1000 * config + index
+    if config == 0:
+        modes = draw_modes(seed, 4, 3, 4)
+        return Problem(4, 2, 0, 4, 1.0, 1.0, *modes, seed=seed)
+    if config == 1:
+        modes = draw_modes(seed, 4, 3, 4)
+        return Problem(32, 4, 1, 32, 1.0, 100.0, *modes, seed=seed)
+    if config == 4:
+        modes = draw_modes(seed, 16, 3, 8)
+        return Problem(128, 6, 1, 64, 1.0, 1000.0, *modes, seed=seed)
+    raise ValueError(f"no fixed workload for config {config}")
+
+
+def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,
+                  reynolds: float, seed: int, t_final: float = 1.0,
+                  n_psi: int = 4, n_p: int = 3) -> Problem:
+    """A seeded problem of arbitrary (small) size for tests."""
+    modes = draw_modes(seed, n_psi, n_p, 4)
+    return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, *modes, seed=seed)
+
+
+def batch_problems(n: int = 64, seed0: int = 2000, meshes=(8, 16, 32, 64),
+                   slab_range=(8, 128)) -> list:
+    """The uneven batch: mesh ~ U{meshes}, N ~ U[slab_range], q ~ U{0,1},
+    R = 10**U[0,3]; problem j uses seed seed0 + j; levels go down to 4x4."""
+    out = []
+    for j in range(n):
+        rng = np.random.default_rng(seed0 + j)
+        m = int(rng.choice(meshes))
+        nsl = int(rng.integers(slab_range[0], slab_range[1] + 1))
+        q = int(rng.integers(0, 2))
+        re = float(10.0 ** rng.uniform(0.0, 3.0))
+        levels = int(round(math.log2(m / 4))) + 1
+        modes = draw_modes(seed0 + j, 4, 3, 4)
+        out.append(Problem(m, levels, q, nsl, 1.0, re, *modes, seed=seed0 + j))
+    return out
+
+
+def arrival_times(rate: float, n: int, seed: int = 3000) -> np.ndarray:
+    """Poisson arrivals: cumulative sums of exponential gaps with mean 1/rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
