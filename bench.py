@@ -1,0 +1,226 @@
+"""Benchmark: space-time DoFs relaxed per second by one waveform-relaxation
+Vanka sweep on the finest level of the largest single solve (128x128
+triangle-split mesh, Taylor-Hood P2-P1, DG(1) in time, 64 slabs, Re = 1000,
+16 stream-function modes), FP32 patch factors with FP64 residual and update.
+
+One timed step = one Chebyshev-weighted relaxation sweep on the finest level:
+space-time residual r = b - A x (FP64), waveform-relaxation patch sweep over
+all 16,641 vertex patches x 64 slabs (forward block substitution in time),
+deterministic gather of the patch corrections fused with the Chebyshev update.
+The operator is assembled at the Newton start (the first Jacobian a solve
+needs), factors and the eigen-estimate come from the library's setup; none of
+that setup is inside the timed region.
+
+Prints ONE JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, AMD-published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds_budget: float = 20.0) -> dict:
+    """Time the oracle's sweep (residual + patch solves + Chebyshev update) on a
+    bounded sample with the same per-patch work as the benchmark workload:
+    16x16 mesh (289 patches, interior blocks of 78x78 per slab), q = 1,
+    64 slabs, Re = 1000; single-threaded BLAS/LAPACK."""
+    code = r"""
+import os, sys, time, json
+sys.path.insert(0, %r)
+import numpy as np
+import stwr_workloads as w
+from oracle.multigrid import Hierarchy, Options
+from oracle.smoother import chebyshev
+prob = w.Problem(16, 2, 1, 64, 1.0, 1000.0, *w.draw_modes(4000, 16, 3, 8), seed=4000)
+H = Hierarchy(prob, Options())
+L0 = H.levels[0]
+H.assemble(L0.initial_guess().ravel(), with_smoothers=False)
+from oracle.smoother import PatchSmoother
+sm = PatchSmoother(L0, H.A[0])
+b = np.random.default_rng(1).standard_normal(L0.n_st)
+x0 = np.random.default_rng(2).standard_normal(L0.n_st)
+t0 = time.perf_counter(); n = 0
+while True:
+    x = chebyshev(H.A[0], sm.apply, b, x0, 1, 5.0, 22.0)
+    n += 1
+    if time.perf_counter() - t0 > %f: break
+dt = (time.perf_counter() - t0) / n
+print(json.dumps({"n_st": L0.n_st, "sweep_s": dt, "sweeps": n}))
+""" % (ROOT, seconds_budget)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    t0 = time.perf_counter()
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if res.returncode != 0:
+        log(res.stderr[-2000:])
+        return {"value": None, "unit": "st-DoF/s", "cores": 1, "kind": "oracle",
+                "sample": "failed"}
+    out = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": out["n_st"] / out["sweep_s"], "unit": "st-DoF/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"oracle WR sweep (residual + 289 vertex-patch solves x 64 slabs + "
+                       f"Chebyshev update) on a 16x16 mesh, q=1, N=64, Re=1000 "
+                       f"({out['n_st']} st-DoFs, same per-patch work as the 128x128 workload), "
+                       f"{out['sweeps']} sweeps, wall {time.perf_counter() - t0:.1f}s incl. setup"),
+            "sweep_s": out["sweep_s"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mesh", type=int, default=128)
+    ap.add_argument("--slabs", type=int, default=64)
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--vcycles", type=int, default=3)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    prob = w.config_problem(4)
+    if (args.mesh, args.slabs, args.levels) != (128, 64, 6):
+        prob = w.Problem(args.mesh, args.levels, 1, args.slabs, 1.0, 1000.0,
+                         prob.psi_ab, prob.psi_coef, prob.p_ab, prob.p_coef, seed=prob.seed)
+    prec = binding.FP32 if args.prec == "fp32" else binding.FP64
+    ctx = binding.Context(0)
+    opts = binding.default_opts()
+    opts.smoother_prec = prec
+    t = time.perf_counter()
+    P = binding.Problem(ctx, prob, opts)
+    n_st, nf, n_patch = P.sizes(0)
+    log(f"[bench] problem created: n_st={n_st} patches={n_patch} "
+        f"bytes={ctx.bytes_in_use() / 1e9:.1f} GB ({time.perf_counter() - t:.1f}s)")
+    U = P.vec()
+    torch.cuda.synchronize()
+    t = time.perf_counter(); P.assemble(U); torch.cuda.synchronize(); t_asm = time.perf_counter() - t
+    log(f"[bench] assembled all levels in {t_asm:.2f}s")
+    t = time.perf_counter(); P.patch_factor(0, prec); torch.cuda.synchronize(); t_fac = time.perf_counter() - t
+    log(f"[bench] factored finest level in {t_fac:.2f}s")
+    t = time.perf_counter(); lam = P.eig_estimate(0); t_eig = time.perf_counter() - t
+    log(f"[bench] lambda={lam:.6f} ({t_eig:.2f}s)")
+    a, bnd = opts.cheb_lo * lam, opts.cheb_hi * lam
+
+    g = torch.Generator(device="cpu").manual_seed(4000)
+    b = torch.randn(n_st, generator=g, dtype=torch.float64).to("cuda")
+    x = torch.zeros(n_st, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        P.relax(0, b, x, 1, a, bnd)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.kernel_times()   # reset
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        P.relax(0, b, x, 1, a, bnd)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    ms_step = ms_total / args.steps
+    if not math.isfinite(float(x.norm())):
+        raise RuntimeError("relaxation produced non-finite values")
+    log(f"[bench] {args.steps} sweeps: {ms_step:.3f} ms/sweep (wall {wall:.3f}s) kernels={kt}")
+
+    # algorithmic bytes of one patch-sweep launch: every (patch, slab) inverse
+    # block once, the residual of every patch DoF once per slab, the patch
+    # outputs once; see DESIGN for the derivation
+    s_f = 4 if prec == binding.FP32 else 8
+    H = None
+    sweep_ms, sweep_n = kt["sweep"]
+    info_bytes = patch_sweep_bytes(prob, s_f)
+    sweep_avg_ms = sweep_ms / max(sweep_n, 1)
+    achieved = info_bytes / (sweep_avg_ms * 1e-3) / 1e9
+
+    # one full V(2,2) cycle on all levels (outside the timed region)
+    P.setup_smoothers()
+    vx = P.vec()
+    torch.cuda.synchronize()
+    tv = time.perf_counter()
+    for _ in range(args.vcycles):
+        P.vcycle(b, vx)
+    torch.cuda.synchronize()
+    vc_ms = (time.perf_counter() - tv) / args.vcycles * 1e3
+
+    out = {
+        "metric": "space-time DoFs relaxed/s per WR sweep",
+        "value": n_st / (ms_step * 1e-3),
+        "unit": "st-DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 patch factors/solves, f64 residual/update",
+        "data": "synthetic manufactured solution (seeded Fourier modes)",
+        "config": {"workload": f"{w.CONFIG_NAMES.get(4)} finest-level WR sweep" if args.mesh == 128
+                   else f"ns_p2p1_dg1_m{args.mesh}_n{args.slabs} finest-level WR sweep",
+                   "mesh": args.mesh, "q": 1, "slabs": args.slabs, "reynolds": 1000.0,
+                   "levels": args.levels, "st_dofs": n_st, "patches": n_patch,
+                   "smoother_prec": args.prec, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_patch_sweep", "avg_ms": sweep_avg_ms,
+                     "algorithmic_bytes": info_bytes},
+        "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "setup_s": {"assemble_all_levels": t_asm, "factor_finest": t_fac, "eig_estimate": t_eig},
+        "vcycle_ms": vc_ms,
+        "lambda_finest": lam,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    P.close()
+    ctx.close()
+
+
+def patch_sweep_bytes(prob, s_f: int) -> int:
+    """Algorithmic bytes of one patch-sweep launch on the finest level:
+    sum over patches of N (m^2 s_f + 8 m + 8 m), m = (q+1) nb the slab block size:
+    the inverse block, the residual gather and the patch output per slab."""
+    from paper_2407_13997_amd import binding
+    info = binding.mesh_info(prob.mesh_n)
+    hist = info[12:52]
+    nq = prob.q + 1
+    tot = 0
+    for nb, cnt in enumerate(hist):
+        m = nb * nq
+        tot += int(cnt) * prob.n_slabs * (m * m * s_f + 16 * m)
+    return tot
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * stwr.h - C ABI of the space-time waveform-relaxation multigrid library for
+ * incompressible Navier-Stokes on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Taylor-Hood P2-P1 in space times upwind DG(q) in time (q in {0,1}),
+ * solved all at once in space-time by Newton's method, FGMRES preconditioned
+ * by geometric multigrid V-cycles whose smoother is the waveform-relaxation
+ * Vanka+star patch relaxation with Chebyshev weights.  Paper sections:
+ *   weak form ............. Sec. 2, eq. nsfem (with eq. dgintime)
+ *   V-cycle ............... Sec. 3, Alg. 1
+ *   FGMRES, Chebyshev ..... Sec. 3 (interval [0.25 lam, 1.05 lam], 10-step estimate)
+ *   transfers ............. Sec. 3, P = I (x) blockdiag(P_u, P_phi), R = P^T
+ *   patch relaxation ...... Sec. 3 Vanka+star patches, eq. waveform_patch_solve
+ *   Newton ................ Sec. 4.2
+ *
+ * Conventions shared by every call
+ * ---------------------------------
+ * Mesh: unit square, mesh_n x mesh_n squares, each cut from bottom-right to
+ *   top-left.  Level 0 is the finest; level l has mesh_n >> l squares a side.
+ * Free spatial DoFs of a level with M squares a side (Dirichlet velocity DoFs
+ *   on the boundary are eliminated): interior P2 node k = (gi-1) + (2M-1)(gj-1)
+ *   (gi, gj in 1..2M-1 on the (2M+1)^2 node grid of spacing 1/(2M)) owns
+ *   velocity DoFs 2k (x) and 2k+1 (y); the pressure at vertex v = i + (M+1) j
+ *   is DoF 2(2M-1)^2 + v.
+ * Space-time vectors: float64, length n_st = n_free * n_slabs * (q+1), index
+ *   (dof * n_slabs + n) * (q+1) + a, i.e. [free DoF][slab][temporal node];
+ *   temporal nodes are the right Gauss-Radau points of each slab.
+ * Memory: every vector argument is a DEVICE pointer on the context's device,
+ *   owned by the caller, non-overlapping unless stated.  Work is enqueued on
+ *   the context's stream; calls that return host scalars synchronise it.
+ * Errors: every call returns an stwr_status; no C++ exception crosses the
+ *   ABI.  stwr_last_error() gives the message of the last failure on the
+ *   context.  On STWR_ERR_ARG and STWR_ERR_BUDGET outputs are untouched.
+ */
+#ifndef STWR_H
+#define STWR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STWR_OK = 0,
+  STWR_ERR_ARG = -1,           /* bad argument (null pointer, level out of range, ...) */
+  STWR_ERR_OOM = -2,           /* device allocation failed */
+  STWR_ERR_BUDGET = -3,        /* problem does not fit the context's HBM budget */
+  STWR_ERR_DEVICE = -4,        /* HIP runtime error */
+  STWR_ERR_SINGULAR = -5,      /* a patch or coarse block had a zero/non-finite pivot */
+  STWR_ERR_NONFINITE = -6,     /* NaN/Inf met in a residual norm */
+  STWR_ERR_NOT_CONVERGED = -7, /* iteration limit reached (stats still filled) */
+  STWR_ERR_STATE = -8          /* call made before the data it needs exists */
+} stwr_status;
+
+enum { STWR_FP64 = 0, STWR_FP32 = 1 };
+
+typedef struct stwr_ctx stwr_ctx;
+typedef struct stwr_problem stwr_problem;
+
+/* One space-time Navier-Stokes problem (manufactured solution, Sec. 2 forms
+ * with forcing).  The modes are read during stwr_problem_create and copied:
+ *   psi(t,x,y) = sum_m c_m sin(a_m pi x) sin(b_m pi y) cos(w_m t + th_m),
+ *   u = (d psi/dy, -d psi/dx),
+ *   p(t,x,y)   = sum_m d_m cos(al_m pi x) cos(be_m pi y) cos(w'_m t + th'_m).
+ * psi_ab: host int32[n_psi_modes][2] = (a, b); psi_coef: host f64[n][3] =
+ * (c, w, th); p_ab: host int32[n_p_modes][2]; p_coef: host f64[n][3].
+ * mesh_n must be divisible by 2^(n_levels-1) with mesh_n >> (n_levels-1) >= 2;
+ * q in {0, 1}; n_slabs >= 1. */
+typedef struct {
+  int32_t mesh_n, n_levels, q, n_slabs;
+  double t_final, reynolds;
+  int32_t n_psi_modes, n_p_modes;
+  const int32_t* psi_ab;
+  const double* psi_coef;
+  const int32_t* p_ab;
+  const double* p_coef;
+} stwr_problem_desc;
+
+/* Solver options (Sec. 3 and 4.2).  stwr_default_opts fills V(2,2),
+ * Chebyshev [0.25, 1.05] * lam, 10 estimation steps, FP64 smoother,
+ * FGMRES(30) with rtol 1e-10 and 200 iterations, Newton rtol 1e-10, 20 steps. */
+typedef struct {
+  int32_t nu_pre, nu_post;
+  double cheb_lo, cheb_hi;
+  int32_t eig_steps;
+  int32_t smoother_prec;       /* STWR_FP64 or STWR_FP32 patch factors and relaxation */
+  int32_t gmres_restart, gmres_maxit;
+  double gmres_rtol;
+  int32_t newton_maxit;
+  double newton_rtol;
+} stwr_solver_opts;
+
+#define STWR_MAX_NEWTON 64
+#define STWR_MAX_LEVELS 16
+
+/* Iteration record of stwr_fgmres / stwr_newton_solve (host memory). */
+typedef struct {
+  int32_t newton_its;
+  int32_t linear_its_total;
+  int32_t linear_its[STWR_MAX_NEWTON];
+  double fnorm[STWR_MAX_NEWTON + 1];      /* ||F|| before each step and at the end */
+  double lambda[STWR_MAX_LEVELS];         /* last eigen-estimate per smoothed level */
+  double final_rel_residual;              /* FGMRES: last relative residual */
+  double setup_seconds, solve_seconds;    /* host wall clock of setup and Krylov phases */
+} stwr_stats;
+
+/* ---- context ---------------------------------------------------------- */
+int32_t stwr_default_opts(stwr_solver_opts* opts);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  hbm_budget bounds the
+ * device bytes all problems of this context may hold (0 = no bound). */
+int32_t stwr_ctx_create(int32_t device, void* hip_stream, uint64_t hbm_budget, stwr_ctx** out);
+int32_t stwr_ctx_destroy(stwr_ctx* ctx);
+int32_t stwr_ctx_set_stream(stwr_ctx* ctx, void* hip_stream);
+const char* stwr_last_error(const stwr_ctx* ctx);
+/* Bytes currently held by the context's problems. */
+int32_t stwr_ctx_bytes_in_use(const stwr_ctx* ctx, uint64_t* bytes);
+
+/* Kernel timing: when enabled, the library brackets every launch of the
+ * patch-sweep kernel (and of the space-time operator kernel) with HIP events
+ * on the context's stream.  stwr_ctx_kernel_times synchronises the stream and
+ * returns, per kernel class k (0 = patch sweep, 1 = operator apply/residual,
+ * 2 = patch gather/update), the summed milliseconds and launch count since
+ * the last reset; it then resets the counters.  ms and launches hold 3 entries. */
+int32_t stwr_ctx_set_timing(stwr_ctx* ctx, int32_t enable);
+int32_t stwr_ctx_kernel_times(stwr_ctx* ctx, double* ms, int64_t* launches);
+
+/* ---- host-only queries (no device needed) ------------------------------ */
+/* Device bytes stwr_problem_create would allocate (factors at the chosen
+ * precision, operators, maps, Krylov and smoother workspaces). */
+int32_t stwr_problem_bytes(const stwr_problem_desc* desc, const stwr_solver_opts* opts,
+                           uint64_t* bytes);
+/* Host-built structure of one mesh with M squares a side, for checking the
+ * setup against closed-form counts.  out[0..11] = n_free, n_nodes_p2,
+ * n_vertices, n_cells, csr_nnz, n_patches, sum_patch_dofs, max_patch_dofs,
+ * interior-patch nonzeros (velocity-velocity), interior-patch nonzeros
+ * (velocity-pressure), interior-patch nonzeros (pressure-velocity),
+ * number of distinct patch sizes; out[12..] = histogram of patch sizes
+ * 0..39 (40 entries).  out must hold 52 int64. */
+int32_t stwr_mesh_info(int32_t mesh_n, int64_t* out);
+
+/* ---- problem ------------------------------------------------------------ */
+int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc,
+                            const stwr_solver_opts* opts, stwr_problem** out);
+int32_t stwr_problem_destroy(stwr_problem* p);
+int32_t stwr_problem_sizes(const stwr_problem* p, int32_t level, int64_t* n_st,
+                           int64_t* n_spatial_free, int32_t* n_patches);
+int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts);
+
+/* Nonlinear space-time residual F(U) of eq. nsfem (level 0), U and F of
+ * length n_st(0).  Boundary values are the exact velocity at the temporal
+ * nodes; the initial value is the P2 interpolant of the velocity at t = 0. */
+int32_t stwr_nonlinear_residual(stwr_problem* p, const double* U, double* F);
+
+/* Jacobian dF/dU at U (level 0 vector) on every level: the iterate is
+ * injected to the coarse nodes and each level rediscretised; also factors
+ * the coarsest level (bordered by one zero-mean pressure constraint per
+ * temporal node).  Invalidates patch factors and eigen-estimates. */
+int32_t stwr_assemble(stwr_problem* p, const double* U);
+
+/* Copy of the assembled operator of a level (host memory): row_ptr
+ * (n_free+1 int32), col (nnz int32), values (nnz * n_slabs * (q+1)^2 f64,
+ * [nz][slab][a][b]), mass (nnz f64: the velocity mass matrix whose
+ * -e0 e1^T (x) M couples slab n to slab n-1).  Pass NULL to query nnz only. */
+int32_t stwr_get_operator(stwr_problem* p, int32_t level, int64_t* nnz, int32_t* row_ptr,
+                          int32_t* col, double* values, double* mass);
+
+/* y = A_l x  and  r = b - A_l x  (space-time operator of level l). */
+int32_t stwr_apply(stwr_problem* p, int32_t level, const double* x, double* y);
+int32_t stwr_residual(stwr_problem* p, int32_t level, const double* b, const double* x,
+                      double* r);
+
+/* Extract every patch block A_{v,n} = R_v J_{l,n} R_v^T of level l and
+ * invert it (partial pivoting) in precision prec (STWR_FP64/STWR_FP32). */
+int32_t stwr_patch_factor(stwr_problem* p, int32_t level, int32_t prec);
+
+/* One additive waveform-relaxation Vanka application z = sum_v R_v^T A_v^{-1} R_v r:
+ * per patch, forward block substitution over the slabs (eq. waveform_patch_solve). */
+int32_t stwr_patch_apply(stwr_problem* p, int32_t level, const double* r, double* z);
+
+/* lam = max real Ritz value of M^{-1} A_l after opts.eig_steps Arnoldi steps
+ * from v0[i] = frac(0.6180339887498949 i) - 0.5 (normalised). */
+int32_t stwr_eig_estimate(stwr_problem* p, int32_t level, double* lambda);
+
+/* n_steps Chebyshev-accelerated relaxation sweeps on A_l x = b over [a, bnd];
+ * x is updated in place. */
+int32_t stwr_relax(stwr_problem* p, int32_t level, const double* b, double* x,
+                   int32_t n_steps, double a, double bnd);
+
+/* rc = R rf (fine_level -> fine_level+1);  xf += P ec. */
+int32_t stwr_restrict(stwr_problem* p, int32_t fine_level, const double* rf, double* rc);
+int32_t stwr_prolong_add(stwr_problem* p, int32_t fine_level, const double* ec, double* xf);
+
+/* Exact solve on the coarsest level; x has zero-mean pressure per temporal node. */
+int32_t stwr_coarse_solve(stwr_problem* p, const double* b, double* x);
+
+/* Factor every smoothed level at opts.smoother_prec and estimate lam on each. */
+int32_t stwr_setup_smoothers(stwr_problem* p);
+
+/* One V-cycle of Alg. 1 on level 0 with zero initial guess: x = V(b). */
+int32_t stwr_vcycle(stwr_problem* p, const double* b, double* x);
+
+/* FGMRES(restart) on A_0 x = b, x starting at 0, right-preconditioned by one
+ * V-cycle, constant pressure projected out of each preconditioned vector. */
+int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* stats);
+
+/* Newton's method from the U given (zero = the standard start), in place:
+ * assemble, factor, estimate, FGMRES, U += dU, until ||F|| <= rtol ||F_0||. */
+int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats);
+
+/* Subtract the mean pressure per (slab, temporal node) from x (level l). */
+int32_t stwr_project_pressure(stwr_problem* p, int32_t level, double* x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STWR_H */

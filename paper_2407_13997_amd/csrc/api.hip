@@ -1,0 +1,1205 @@
+// C ABI of the space-time WR multigrid library: problem object, allocation
+// plan and HBM budget, and the host control of Alg. 1 (V-cycle), Chebyshev
+// relaxation, the eigen-estimate, FGMRES and Newton (Secs. 3 and 4.2).  Every
+// arithmetic step on space-time data runs in the gfx950 kernels; the host only
+// keeps scalars (Krylov Hessenberg columns, Givens rotations, the 10x10 Ritz
+// problem) and launches.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "stwr.h"
+
+using namespace stwr;
+
+namespace {
+
+struct StwrError : std::runtime_error {
+  int32_t code;
+  StwrError(int32_t c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw StwrError(e_ == hipErrorOutOfMemory ? STWR_ERR_OOM : STWR_ERR_DEVICE,          \
+                      std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct stwr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;
+  uint64_t in_use = 0;
+  std::string last_error;
+  std::mutex mu;
+  // kernel timing: event pairs recorded around launches of each class
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[3];
+
+  hipEvent_t take_event() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  ~stwr_ctx() {
+    for (auto& v : marks)
+      for (auto& pr : v) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+// RAII bracket of one kernel launch with a pair of events (timing mode only).
+struct KernelMark {
+  stwr_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr;
+  KernelMark(stwr_ctx* ctx, int k) : c(ctx), cls(k) {
+    if (c->timing && (a = c->take_event())) (void)hipEventRecord(a, c->stream);
+  }
+  ~KernelMark() {
+    if (!a) return;
+    hipEvent_t b = c->take_event();
+    if (!b) { c->pool.push_back(a); return; }
+    (void)hipEventRecord(b, c->stream);
+    c->marks[cls].push_back({a, b});
+  }
+};
+}  // namespace
+
+namespace {
+
+// Device allocation owned by a problem.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Level {
+  HostLevel H;
+  HostTransfer Tr;        // to the next coarser level (valid if not coarsest)
+  int N = 0, NQ = 0;
+  double dt = 0.0;
+  int64_t n_st = 0;
+  LevelView view{};
+  PatchView pview{};
+  int fac_prec = -1;      // precision of the current factors, -1 = none
+  size_t fac_budgeted = 0;  // factor bytes already charged to the context
+  double lambda = 0.0;
+  bool has_lambda = false;
+  std::vector<int64_t> fac_off, y_off, mp_off;
+  // device arrays
+  int *row_ptr = nullptr, *col = nullptr, *cells = nullptr, *cell_p2 = nullptr,
+      *cell_dofs = nullptr, *cell_nz = nullptr, *node_free = nullptr;
+  int *patch_ptr = nullptr, *patch_dofs = nullptr, *patch_nbu = nullptr, *patch_nz = nullptr,
+      *dof_ptr = nullptr, *dof_slot = nullptr, *slot_patch = nullptr;
+  int64_t *patch_nz_off = nullptr, *d_fac_off = nullptr, *d_y_off = nullptr, *d_mp_off = nullptr;
+  double *Jv = nullptr, *Mv = nullptr, *Mp = nullptr, *Y = nullptr;
+  void* fac = nullptr;
+  size_t fac_bytes = 0;
+  int *P_ptr = nullptr, *P_col = nullptr, *R_ptr = nullptr, *R_col = nullptr, *inject = nullptr;
+  double *P_val = nullptr, *R_val = nullptr;
+  double *r = nullptr, *d = nullptr, *x = nullptr, *b = nullptr;
+  double* Binv = nullptr;   // coarsest only
+  int coarse_mm = 0;
+};
+
+}  // namespace
+
+struct stwr_problem {
+  stwr_ctx* ctx = nullptr;
+  stwr_problem_desc desc{};
+  stwr_solver_opts opts{};
+  std::vector<int> psi_ab, p_ab;
+  std::vector<double> psi_coef, p_coef;
+  std::vector<Level> lv;
+  RefTables tab{};
+  RefTables* d_tab = nullptr;
+  MmsDev mms{};
+  std::vector<DBuf> bufs;
+  uint64_t bytes = 0;
+  bool assembled = false;
+  // Krylov workspace
+  int restart = 0;
+  double *V = nullptr, *Z = nullptr;
+  double *dscal = nullptr, *partial = nullptr;
+  int* dstatus = nullptr;
+  int* hstatus_pinned = nullptr;
+
+  hipStream_t s() const { return ctx->stream; }
+
+  template <typename T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) throw StwrError(STWR_ERR_OOM, "hipMalloc failed for " + std::to_string(count * sizeof(T)) + " bytes");
+    bufs.push_back({ptr, count * sizeof(T)});
+    return (T*)ptr;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* d = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+  }
+  void release(void* ptr) {
+    for (auto it = bufs.begin(); it != bufs.end(); ++it)
+      if (it->p == ptr) {
+        (void)hipFree(it->p);
+        bufs.erase(it);
+        return;
+      }
+  }
+};
+
+namespace {
+
+thread_local std::string g_tls_error;
+
+int32_t fail(stwr_ctx* ctx, int32_t code, const std::string& msg) {
+  if (ctx) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->last_error = msg;
+  }
+  g_tls_error = msg;
+  return code;
+}
+
+template <typename F>
+int32_t guarded(stwr_ctx* ctx, F&& f) {
+  try {
+    return f();
+  } catch (const StwrError& e) {
+    return fail(ctx, e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, STWR_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(ctx, STWR_ERR_ARG, e.what());
+  }
+}
+
+void check_desc(const stwr_problem_desc* d) {
+  if (!d) throw StwrError(STWR_ERR_ARG, "null problem descriptor");
+  if (d->q < 0 || d->q > 1) throw StwrError(STWR_ERR_ARG, "q must be 0 or 1");
+  if (d->n_levels < 1 || d->n_levels > STWR_MAX_LEVELS) throw StwrError(STWR_ERR_ARG, "bad n_levels");
+  if (d->mesh_n < 2 || d->n_slabs < 1) throw StwrError(STWR_ERR_ARG, "bad mesh_n or n_slabs");
+  if (d->mesh_n % (1 << (d->n_levels - 1)) != 0 || (d->mesh_n >> (d->n_levels - 1)) < 2)
+    throw StwrError(STWR_ERR_ARG, "mesh_n must be divisible by 2^(n_levels-1) with a coarsest mesh of >= 2");
+  if (!(d->t_final > 0.0)) throw StwrError(STWR_ERR_ARG, "t_final must be positive");
+  if (d->n_psi_modes < 0 || d->n_p_modes < 0) throw StwrError(STWR_ERR_ARG, "bad mode counts");
+  if ((d->n_psi_modes > 0 && (!d->psi_ab || !d->psi_coef)) || (d->n_p_modes > 0 && (!d->p_ab || !d->p_coef)))
+    throw StwrError(STWR_ERR_ARG, "null mode arrays");
+  const int mc = d->mesh_n >> (d->n_levels - 1);
+  const int nfc = 2 * (2 * mc - 1) * (2 * mc - 1) + (mc + 1) * (mc + 1);
+  if (nfc * (d->q + 1) + d->q + 1 > 2048)
+    throw StwrError(STWR_ERR_ARG, "coarsest level too large for the dense coarse solve (use more levels)");
+}
+
+void check_opts(const stwr_solver_opts* o) {
+  if (!o) throw StwrError(STWR_ERR_ARG, "null options");
+  if (o->nu_pre < 0 || o->nu_post < 0 || o->eig_steps < 1 || o->eig_steps > 64 || o->gmres_restart < 1 ||
+      o->gmres_restart > 200 || o->gmres_maxit < 1 || o->newton_maxit < 0 || o->newton_maxit > STWR_MAX_NEWTON ||
+      (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
+      !(o->cheb_lo > 0.0))
+    throw StwrError(STWR_ERR_ARG, "invalid solver options");
+}
+
+int vw_of(int prec) { return prec == STWR_FP32 ? 4 : 2; }
+int round_up(int m, int w) { return (m + w - 1) / w * w; }
+
+// Element count of the factor storage of one level at a precision.
+int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
+  int64_t tot = 0;
+  for (int v = 0; v < H.nv; ++v) {
+    const int m = (H.patch_ptr[v + 1] - H.patch_ptr[v]) * NQ;
+    tot += (int64_t)N * m * round_up(m, vw_of(prec));
+  }
+  return tot;
+}
+
+struct Plan {
+  uint64_t bytes = 0;
+};
+
+uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, int prec, bool coarsest) {
+  const int64_t nnz = H.row_ptr[H.nf];
+  const int64_t n_st = (int64_t)H.nf * N * NQ;
+  uint64_t b = 0;
+  b += (uint64_t)nnz * N * NQ * NQ * 8 + nnz * 8;                       // Jv, Mv
+  b += (uint64_t)(H.nf + 1 + nnz) * 4;                                  // CSR
+  b += (uint64_t)H.nc * (3 + 6 + 15 + 225) * 4 + (uint64_t)H.nn * 4;    // cell maps
+  b += (uint64_t)(H.nv + 1) * 4 * 2 + (uint64_t)H.patch_dofs.size() * 4 * 2 + H.patch_nz.size() * 4;
+  b += (uint64_t)(H.nv + 1) * 8 * 4 + (uint64_t)(H.nf + 1 + H.patch_dofs.size()) * 4;
+  b += (uint64_t)4 * n_st * 8;                                          // r, d, x, b
+  if (!coarsest) {
+    b += (uint64_t)fac_elems(H, N, NQ, prec) * (prec == STWR_FP32 ? 4 : 8);
+    int64_t mp = 0;
+    for (int v = 0; v < H.nv; ++v) mp += (int64_t)H.patch_nbu[v] * H.patch_nbu[v];
+    b += (uint64_t)mp * 8;
+    b += (uint64_t)H.patch_dofs.size() * N * NQ * 8;                    // Y
+  } else {
+    const int64_t mm = (int64_t)H.nf * NQ + NQ;
+    b += (uint64_t)N * mm * mm * 8;
+  }
+  if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
+  return b;
+}
+
+void build_levels(const stwr_problem_desc* d, std::vector<Level>& lv) {
+  lv.resize(d->n_levels);
+  for (int l = 0; l < d->n_levels; ++l) {
+    build_level(d->mesh_n >> l, lv[l].H);
+    lv[l].N = d->n_slabs;
+    lv[l].NQ = d->q + 1;
+    lv[l].dt = d->t_final / d->n_slabs;
+    lv[l].n_st = (int64_t)lv[l].H.nf * d->n_slabs * (d->q + 1);
+  }
+  for (int l = 0; l + 1 < d->n_levels; ++l) build_transfer(lv[l].H, lv[l + 1].H, lv[l].Tr);
+}
+
+uint64_t plan_bytes(const stwr_problem_desc* d, const stwr_solver_opts* o, const std::vector<Level>& lv) {
+  uint64_t b = 0;
+  const int L = (int)lv.size();
+  for (int l = 0; l < L; ++l)
+    b += level_bytes(lv[l].H, l + 1 < L ? &lv[l].Tr : nullptr, d->n_slabs, d->q + 1, o->smoother_prec, l == L - 1);
+  const int64_t n0 = lv[0].n_st;
+  b += (uint64_t)(2 * o->gmres_restart + 1) * n0 * 8;
+  b += (uint64_t)(256 + 4) * 256 * 8 + sizeof(RefTables) + 4096;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Level upload
+void upload_level(stwr_problem* P, Level& L, bool coarsest) {
+  HostLevel& H = L.H;
+  L.row_ptr = P->upload(H.row_ptr);
+  L.col = P->upload(H.col);
+  L.cells = P->upload(H.cells);
+  L.cell_p2 = P->upload(H.cell_p2);
+  L.cell_dofs = P->upload(H.cell_dofs);
+  L.cell_nz = P->upload(H.cell_nz);
+  L.node_free = P->upload(H.node_free);
+  const int64_t nnz = H.row_ptr[H.nf];
+  L.Jv = P->alloc<double>((size_t)nnz * L.N * L.NQ * L.NQ);
+  L.Mv = P->alloc<double>((size_t)nnz);
+  L.r = P->alloc<double>(L.n_st);
+  L.d = P->alloc<double>(L.n_st);
+  L.x = P->alloc<double>(L.n_st);
+  L.b = P->alloc<double>(L.n_st);
+  LevelView& v = L.view;
+  v.M = H.M; v.nf = H.nf; v.po = H.po; v.nv = H.nv; v.nc = H.nc; v.N = L.N; v.NQ = L.NQ;
+  v.dt = L.dt; v.h = 1.0 / H.M; v.nnz = nnz;
+  v.row_ptr = L.row_ptr; v.col = L.col; v.cells = L.cells; v.cell_p2 = L.cell_p2;
+  v.cell_dofs = L.cell_dofs; v.cell_nz = L.cell_nz; v.node_free = L.node_free;
+  v.n2 = H.n2; v.n1 = H.n1;
+  // patches (the coarsest level is solved directly and needs none)
+  PatchView& pv = L.pview;
+  pv.n_patch = H.nv;
+  if (!coarsest) {
+    L.patch_ptr = P->upload(H.patch_ptr);
+    L.patch_dofs = P->upload(H.patch_dofs);
+    L.patch_nbu = P->upload(H.patch_nbu);
+    L.patch_nz_off = P->upload(H.patch_nz_off);
+    L.patch_nz = P->upload(H.patch_nz);
+    L.dof_ptr = P->upload(H.dof_ptr);
+    L.dof_slot = P->upload(H.dof_slot);
+    L.slot_patch = P->upload(H.slot_patch);
+    L.y_off.assign(H.nv + 1, 0);
+    L.mp_off.assign(H.nv + 1, 0);
+    for (int p = 0; p < H.nv; ++p) {
+      const int nb = H.patch_ptr[p + 1] - H.patch_ptr[p];
+      L.y_off[p + 1] = L.y_off[p] + (int64_t)nb * L.N * L.NQ;
+      L.mp_off[p + 1] = L.mp_off[p] + (int64_t)H.patch_nbu[p] * H.patch_nbu[p];
+    }
+    L.d_y_off = P->upload(L.y_off);
+    L.d_mp_off = P->upload(L.mp_off);
+    L.Mp = P->alloc<double>(L.mp_off[H.nv]);
+    L.Y = P->alloc<double>(L.y_off[H.nv]);
+    L.d_fac_off = P->alloc<int64_t>(H.nv + 1);
+    pv.patch_ptr = L.patch_ptr; pv.patch_dofs = L.patch_dofs; pv.patch_nbu = L.patch_nbu;
+    pv.patch_nz_off = L.patch_nz_off; pv.patch_nz = L.patch_nz; pv.fac_off = L.d_fac_off;
+    pv.y_off = L.d_y_off; pv.mp_off = L.d_mp_off; pv.dof_ptr = L.dof_ptr; pv.dof_slot = L.dof_slot;
+    pv.slot_patch = L.slot_patch;
+    L.P_ptr = P->upload(L.Tr.p_ptr);
+    L.P_col = P->upload(L.Tr.p_col);
+    L.P_val = P->upload(L.Tr.p_val);
+    L.R_ptr = P->upload(L.Tr.r_ptr);
+    L.R_col = P->upload(L.Tr.r_col);
+    L.R_val = P->upload(L.Tr.r_val);
+  } else {
+    L.coarse_mm = H.nf * L.NQ + L.NQ;
+    L.Binv = P->alloc<double>((size_t)L.N * L.coarse_mm * L.coarse_mm);
+  }
+}
+
+void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
+  const int64_t elems = fac_elems(L.H, L.N, L.NQ, prec);
+  const size_t need = (size_t)elems * (prec == STWR_FP32 ? 4 : 8);
+  if (L.fac && L.fac_bytes >= need) {
+    // offsets depend on the precision's panel width
+  } else {
+    if (L.fac) {
+      P->release(L.fac);
+      L.fac = nullptr;
+    }
+    const size_t extra = need > L.fac_budgeted ? need - L.fac_budgeted : 0;
+    {
+      std::lock_guard<std::mutex> g(P->ctx->mu);
+      const uint64_t budget = P->ctx->budget;
+      if (budget && P->ctx->in_use + extra > budget)
+        throw StwrError(STWR_ERR_BUDGET, "patch factors exceed the HBM budget");
+      P->ctx->in_use += extra;
+    }
+    P->bytes += extra;
+    L.fac_budgeted += extra;
+    L.fac = P->alloc<char>(need);
+    L.fac_bytes = need;
+  }
+  L.fac_off.assign(L.H.nv + 1, 0);
+  for (int v = 0; v < L.H.nv; ++v) {
+    const int m = (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ;
+    L.fac_off[v + 1] = L.fac_off[v] + (int64_t)L.N * m * round_up(m, vw_of(prec));
+  }
+  HIPCHK(hipMemcpyAsync(L.d_fac_off, L.fac_off.data(), L.fac_off.size() * 8, hipMemcpyHostToDevice, P->s()));
+}
+
+// ---------------------------------------------------------------------------
+// Small host helpers
+Level& level_at(stwr_problem* P, int l) {
+  if (l < 0 || l >= (int)P->lv.size()) throw StwrError(STWR_ERR_ARG, "level out of range");
+  return P->lv[l];
+}
+
+void check_status_flag(stwr_problem* P, const char* what) {
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, P->dstatus, sizeof(int), hipMemcpyDeviceToHost, P->s()));
+  HIPCHK(hipStreamSynchronize(P->s()));
+  if (h) {
+    int z = 0;
+    HIPCHK(hipMemcpy(P->dstatus, &z, sizeof(int), hipMemcpyHostToDevice));
+    throw StwrError(STWR_ERR_SINGULAR, std::string(what) + ": zero or non-finite pivot");
+  }
+}
+
+double dot_host(stwr_problem* P, int64_t n, const double* x, const double* y) {
+  HIPCHK(launch_mdot(n, 1, x, 0, y, P->partial, P->dscal, P->s()));
+  double h = 0.0;
+  HIPCHK(hipMemcpyAsync(&h, P->dscal, 8, hipMemcpyDeviceToHost, P->s()));
+  HIPCHK(hipStreamSynchronize(P->s()));
+  return h;
+}
+
+double norm_host(stwr_problem* P, int64_t n, const double* x) {
+  const double v = dot_host(P, n, x, x);
+  if (!std::isfinite(v)) throw StwrError(STWR_ERR_NONFINITE, "non-finite norm");
+  return std::sqrt(v);
+}
+
+void spmv(stwr_problem* P, int l, const double* x, const double* b, double* y) {
+  Level& L = P->lv[l];
+  KernelMark mark(P->ctx, 1);
+  HIPCHK(launch_spmv(L.view, L.Jv, L.Mv, P->tab.e0, P->tab.e1, x, b, y, P->s()));
+}
+
+void project(stwr_problem* P, int l, double* x) {
+  Level& L = P->lv[l];
+  HIPCHK(launch_pressure_project(L.H.nf, L.H.po, L.N * L.NQ, x, P->dscal + 256, P->s()));
+}
+
+void require_factor(stwr_problem* P, int l) {
+  if (!P->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+  if (l >= (int)P->lv.size() - 1) throw StwrError(STWR_ERR_ARG, "the coarsest level has no smoother");
+  if (P->lv[l].fac_prec < 0) throw StwrError(STWR_ERR_STATE, "patch factors missing (call stwr_patch_factor)");
+}
+
+void patch_factor(stwr_problem* P, int l, int prec) {
+  if (!P->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+  if (l >= (int)P->lv.size() - 1) throw StwrError(STWR_ERR_ARG, "the coarsest level has no smoother");
+  if (prec != STWR_FP32 && prec != STWR_FP64) throw StwrError(STWR_ERR_ARG, "bad precision");
+  Level& L = P->lv[l];
+  ensure_factor_storage(P, L, prec);
+  HIPCHK(launch_patch_factor(L.view, L.pview, L.Jv, prec, L.fac, P->dstatus, P->s()));
+  HIPCHK(launch_patch_mass(L.view, L.pview, L.Mv, L.Mp, P->s()));
+  L.fac_prec = prec;
+  check_status_flag(P, "patch factorization");
+}
+
+void patch_apply(stwr_problem* P, int l, const double* r, double* z) {
+  require_factor(P, l);
+  Level& L = P->lv[l];
+  HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, r, L.Y, P->s()));
+  HIPCHK(launch_patch_gather(L.view, L.pview, L.Y, 0, 0.0, 0.0, z, nullptr, nullptr, P->s()));
+}
+
+// Chebyshev-accelerated relaxation (three-term recurrence over [a, bnd]).
+void relax(stwr_problem* P, int l, const double* b, double* x, int n_steps, double a, double bnd,
+           bool x_is_zero) {
+  require_factor(P, l);
+  Level& L = P->lv[l];
+  const double theta = 0.5 * (a + bnd), delta = 0.5 * (bnd - a);
+  double rho_old = 0.0;
+  for (int k = 0; k < n_steps; ++k) {
+    const double* r = L.r;
+    if (k == 0 && x_is_zero) r = b;   // b - A 0 = b exactly
+    else spmv(P, l, x, b, L.r);
+    {
+      KernelMark mark(P->ctx, 0);
+      HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, r, L.Y, P->s()));
+    }
+    double c1, c2, rho;
+    if (k == 0) {
+      rho = delta / theta;
+      c1 = 0.0;
+      c2 = 1.0 / theta;
+    } else {
+      rho = 1.0 / (2.0 * theta / delta - rho_old);
+      c1 = rho * rho_old;
+      c2 = 2.0 * rho / delta;
+    }
+    {
+      KernelMark mark(P->ctx, 2);
+      HIPCHK(launch_patch_gather(L.view, L.pview, L.Y, 1, c1, c2, nullptr, L.d, x, P->s()));
+    }
+    rho_old = rho;
+  }
+}
+
+void coarse_solve(stwr_problem* P, const double* b, double* x) {
+  if (!P->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+  Level& C = P->lv.back();
+  HIPCHK(launch_coarse_solve(C.view, C.Binv, C.Mv, P->tab.e0, P->tab.e1, b, x, P->s()));
+}
+
+void vcycle(stwr_problem* P, const double* b0, double* x0) {
+  const int L = (int)P->lv.size();
+  const stwr_solver_opts& o = P->opts;
+  for (int l = 0; l + 1 < L; ++l)
+    if (!P->lv[l].has_lambda || P->lv[l].fac_prec < 0)
+      throw StwrError(STWR_ERR_STATE, "smoothers not set up (call stwr_setup_smoothers)");
+  std::vector<const double*> bs(L);
+  std::vector<double*> xs(L);
+  for (int l = 0; l < L; ++l) {
+    bs[l] = l == 0 ? b0 : P->lv[l].b;
+    xs[l] = l == 0 ? x0 : P->lv[l].x;
+  }
+  if (L == 1) {
+    coarse_solve(P, bs[0], xs[0]);
+    return;
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    Level& Lv = P->lv[l];
+    HIPCHK(launch_fill(Lv.n_st, 0.0, xs[l], P->s()));
+    const double lam = Lv.lambda;
+    relax(P, l, bs[l], xs[l], o.nu_pre, o.cheb_lo * lam, o.cheb_hi * lam, true);
+    spmv(P, l, xs[l], bs[l], Lv.r);
+    Level& Cv = P->lv[l + 1];
+    HIPCHK(launch_transfer(Cv.H.nf, Cv.N * Cv.NQ, Lv.R_ptr, Lv.R_col, Lv.R_val, Lv.r, P->lv[l + 1].b, 0, P->s()));
+  }
+  coarse_solve(P, bs[L - 1], xs[L - 1]);
+  for (int l = L - 2; l >= 0; --l) {
+    Level& Lv = P->lv[l];
+    HIPCHK(launch_transfer(Lv.H.nf, Lv.N * Lv.NQ, Lv.P_ptr, Lv.P_col, Lv.P_val, xs[l + 1], xs[l], 1, P->s()));
+    const double lam = Lv.lambda;
+    relax(P, l, bs[l], xs[l], o.nu_post, o.cheb_lo * lam, o.cheb_hi * lam, false);
+  }
+}
+
+// Eigenvalues of a small real upper-Hessenberg matrix by shifted complex QR
+// iterations (Wilkinson shifts, deflation at the bottom).
+std::vector<std::complex<double>> hessenberg_eigs(std::vector<double> Hr, int m) {
+  using C = std::complex<double>;
+  std::vector<C> A(m * m);
+  for (int i = 0; i < m * m; ++i) A[i] = Hr[i];
+  auto at = [&](int i, int j) -> C& { return A[i * m + j]; };
+  std::vector<C> eig;
+  int n = m;
+  int iter = 0;
+  while (n > 0) {
+    if (n == 1) { eig.push_back(at(0, 0)); break; }
+    const double sub = std::abs(at(n - 1, n - 2));
+    const double scale = std::abs(at(n - 1, n - 1)) + std::abs(at(n - 2, n - 2));
+    if (sub <= 1e-15 * (scale > 0 ? scale : 1.0) || iter > 500) {
+      eig.push_back(at(n - 1, n - 1));
+      --n;
+      iter = 0;
+      continue;
+    }
+    // Wilkinson shift from the trailing 2x2 block
+    const C a = at(n - 2, n - 2), b = at(n - 2, n - 1), c = at(n - 1, n - 2), d = at(n - 1, n - 1);
+    const C tr = a + d, det = a * d - b * c;
+    const C disc = std::sqrt(tr * tr - 4.0 * det);
+    const C l1 = 0.5 * (tr + disc), l2 = 0.5 * (tr - disc);
+    C mu = std::abs(l1 - d) < std::abs(l2 - d) ? l1 : l2;
+    if (iter % 11 == 10) mu += C(sub, 0.0);   // exceptional shift
+    for (int i = 0; i < n; ++i) at(i, i) -= mu;
+    std::vector<C> cs(n - 1), sn(n - 1);
+    for (int k = 0; k < n - 1; ++k) {
+      const C x = at(k, k), y = at(k + 1, k);
+      const double r = std::sqrt(std::norm(x) + std::norm(y));
+      C cc = 1.0, ss = 0.0;
+      if (r > 0.0) { cc = x / r; ss = y / r; }
+      cs[k] = cc; sn[k] = ss;
+      for (int j = k; j < n; ++j) {
+        const C u = at(k, j), v = at(k + 1, j);
+        at(k, j) = std::conj(cc) * u + std::conj(ss) * v;
+        at(k + 1, j) = -ss * u + cc * v;
+      }
+    }
+    for (int k = 0; k < n - 1; ++k) {
+      const C cc = cs[k], ss = sn[k];
+      for (int i = 0; i <= std::min(k + 1, n - 1); ++i) {
+        const C u = at(i, k), v = at(i, k + 1);
+        at(i, k) = u * cc + v * ss;
+        at(i, k + 1) = -u * std::conj(ss) + v * std::conj(cc);
+      }
+    }
+    for (int i = 0; i < n; ++i) at(i, i) += mu;
+    ++iter;
+  }
+  return eig;
+}
+
+double eig_estimate(stwr_problem* P, int l) {
+  require_factor(P, l);
+  Level& L = P->lv[l];
+  const int steps = P->opts.eig_steps;
+  const int64_t n = L.n_st;
+  const int64_t ld = P->lv[0].n_st;
+  if (steps + 1 > P->restart + 1 + P->restart) throw StwrError(STWR_ERR_ARG, "eig_steps exceeds workspace");
+  // basis vectors live in the FGMRES workspace (V then Z)
+  auto vec = [&](int j) -> double* { return j <= P->restart ? P->V + j * ld : P->Z + (j - P->restart - 1) * ld; };
+  HIPCHK(launch_start_vector(n, vec(0), P->s()));
+  const double nv0 = norm_host(P, n, vec(0));
+  HIPCHK(launch_axpby(n, 1.0 / nv0, vec(0), 0.0, vec(0), P->s()));
+  std::vector<double> H((steps + 1) * steps, 0.0);
+  int m = steps;
+  std::vector<double> hcol(steps + 2);
+  for (int j = 0; j < steps; ++j) {
+    double* w = vec(j + 1);
+    spmv(P, l, vec(j), nullptr, L.r);
+    patch_apply(P, l, L.r, w);
+    for (int i = 0; i <= j; ++i) {
+      HIPCHK(launch_mdot(n, 1, vec(i), 0, w, P->partial, P->dscal + i, P->s()));
+      HIPCHK(launch_axpy_dev(n, P->dscal + i, -1.0, vec(i), w, P->s()));
+    }
+    HIPCHK(launch_mdot(n, 1, w, 0, w, P->partial, P->dscal + j + 1, P->s()));
+    HIPCHK(hipMemcpyAsync(hcol.data(), P->dscal, (j + 2) * 8, hipMemcpyDeviceToHost, P->s()));
+    HIPCHK(hipStreamSynchronize(P->s()));
+    for (int i = 0; i <= j; ++i) H[i * steps + j] = hcol[i];
+    const double h = std::sqrt(hcol[j + 1]);
+    if (!std::isfinite(h)) throw StwrError(STWR_ERR_NONFINITE, "eigen-estimate produced a non-finite value");
+    H[(j + 1) * steps + j] = h;
+    if (h <= 1e-14 * std::fabs(H[0])) { m = j + 1; break; }
+    HIPCHK(launch_axpby(n, 1.0 / h, w, 0.0, w, P->s()));
+  }
+  std::vector<double> Hm(m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) Hm[i * m + j] = H[i * steps + j];
+  auto ev = hessenberg_eigs(Hm, m);
+  double lam = -1e300;
+  for (auto& e : ev) lam = std::max(lam, e.real());
+  L.lambda = lam;
+  L.has_lambda = true;
+  return lam;
+}
+
+void assemble(stwr_problem* P, const double* U) {
+  const int L = (int)P->lv.size();
+  for (int l = 0; l < L; ++l) {
+    Level& Lv = P->lv[l];
+    const double* Ul = U;
+    if (l > 0) {
+      Level& F = P->lv[l - 1];
+      const double* src = l == 1 ? U : F.d;
+      HIPCHK(launch_gather(Lv.H.nf, Lv.N * Lv.NQ, F.Tr.inject.empty() ? nullptr : F.inject, src, Lv.d, P->s()));
+      Ul = Lv.d;
+    }
+    HIPCHK(launch_fill((int64_t)Lv.view.nnz * Lv.N * Lv.NQ * Lv.NQ, 0.0, Lv.Jv, P->s()));
+    HIPCHK(launch_fill(Lv.view.nnz, 0.0, Lv.Mv, P->s()));
+    HIPCHK(launch_assemble_jacobian(Lv.view, P->d_tab, P->mms, Ul, Lv.Jv, Lv.Mv, P->s()));
+    Lv.fac_prec = -1;
+    Lv.has_lambda = false;
+  }
+  Level& C = P->lv.back();
+  HIPCHK(launch_fill((int64_t)C.N * C.coarse_mm * C.coarse_mm, 0.0, C.Binv, P->s()));
+  HIPCHK(launch_coarse_build(C.view, C.Jv, C.Binv, P->s()));
+  HIPCHK(launch_dense_inverse(C.N, C.coarse_mm, C.Binv, P->dstatus, P->s()));
+  check_status_flag(P, "coarse factorization");
+  P->assembled = true;
+}
+
+void setup_smoothers(stwr_problem* P) {
+  for (int l = 0; l + 1 < (int)P->lv.size(); ++l) {
+    patch_factor(P, l, P->opts.smoother_prec);
+    eig_estimate(P, l);
+  }
+}
+
+// Right-preconditioned restarted FGMRES with modified Gram-Schmidt.
+void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* its_out, double* rel_out) {
+  const stwr_solver_opts& o = P->opts;
+  Level& L0 = P->lv[0];
+  const int64_t n = L0.n_st;
+  const int m = P->restart;
+  HIPCHK(launch_fill(n, 0.0, x, P->s()));
+  const double bnorm = norm_host(P, n, b);
+  int its = 0;
+  double rel = 0.0;
+  if (bnorm == 0.0) { if (its_out) *its_out = 0; if (rel_out) *rel_out = 0.0; return; }
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
+  auto V = [&](int j) { return P->V + j * n; };
+  auto Z = [&](int j) { return P->Z + j * n; };
+  bool done = false;
+  while (!done) {
+    spmv(P, 0, x, b, V(0));
+    const double beta = norm_host(P, n, V(0));
+    rel = beta / bnorm;
+    if (beta <= o.gmres_rtol * bnorm || its >= o.gmres_maxit) break;
+    HIPCHK(launch_axpby(n, 1.0 / beta, V(0), 0.0, V(0), P->s()));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      vcycle(P, V(j), Z(j));
+      project(P, 0, Z(j));
+      spmv(P, 0, Z(j), nullptr, V(j + 1));
+      for (int i = 0; i <= j; ++i) {
+        HIPCHK(launch_mdot(n, 1, V(i), 0, V(j + 1), P->partial, P->dscal + i, P->s()));
+        HIPCHK(launch_axpy_dev(n, P->dscal + i, -1.0, V(i), V(j + 1), P->s()));
+      }
+      HIPCHK(launch_mdot(n, 1, V(j + 1), 0, V(j + 1), P->partial, P->dscal + j + 1, P->s()));
+      HIPCHK(hipMemcpyAsync(hcol.data(), P->dscal, (j + 2) * 8, hipMemcpyDeviceToHost, P->s()));
+      HIPCHK(hipStreamSynchronize(P->s()));
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
+      const double hn = std::sqrt(hcol[j + 1]);
+      if (!std::isfinite(hn)) throw StwrError(STWR_ERR_NONFINITE, "FGMRES produced a non-finite value");
+      H[(j + 1) * m + j] = hn;
+      if (hn != 0.0) HIPCHK(launch_axpby(n, 1.0 / hn, V(j + 1), 0.0, V(j + 1), P->s()));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+        H[i * m + j] = t;
+      }
+      const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+      cs[j] = H[j * m + j] / den;
+      sn[j] = H[(j + 1) * m + j] / den;
+      H[j * m + j] = den;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      k = j + 1;
+      rel = std::fabs(g[j + 1]) / bnorm;
+      if (std::fabs(g[j + 1]) <= o.gmres_rtol * bnorm || its >= o.gmres_maxit) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < k; ++c) s -= H[i * m + c] * y[c];
+      y[i] = s / H[i * m + i];
+    }
+    HIPCHK(hipMemcpyAsync(P->dscal, y.data(), k * 8, hipMemcpyHostToDevice, P->s()));
+    HIPCHK(launch_gemv_cols(n, k, P->Z, n, P->dscal, x, P->s()));
+    HIPCHK(hipStreamSynchronize(P->s()));
+    if (std::fabs(g[k]) <= o.gmres_rtol * bnorm || its >= o.gmres_maxit) done = true;
+  }
+  HIPCHK(hipStreamSynchronize(P->s()));
+  if (its_out) *its_out = its;
+  if (rel_out) *rel_out = rel;
+  (void)st;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int32_t stwr_default_opts(stwr_solver_opts* o) {
+  if (!o) return STWR_ERR_ARG;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->cheb_lo = 0.25;
+  o->cheb_hi = 1.05;
+  o->eig_steps = 10;
+  o->smoother_prec = STWR_FP64;
+  o->gmres_restart = 30;
+  o->gmres_maxit = 200;
+  o->gmres_rtol = 1e-10;
+  o->newton_maxit = 20;
+  o->newton_rtol = 1e-10;
+  return STWR_OK;
+}
+
+int32_t stwr_ctx_create(int32_t device, void* hip_stream, uint64_t hbm_budget, stwr_ctx** out) {
+  return guarded(nullptr, [&]() -> int32_t {
+    if (!out) throw StwrError(STWR_ERR_ARG, "null output");
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) throw StwrError(STWR_ERR_ARG, "bad device index");
+    HIPCHK(hipSetDevice(device));
+    auto* c = new stwr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = hbm_budget;
+    *out = c;
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_ctx_destroy(stwr_ctx* ctx) {
+  delete ctx;
+  return STWR_OK;
+}
+
+int32_t stwr_ctx_set_stream(stwr_ctx* ctx, void* hip_stream) {
+  if (!ctx) return STWR_ERR_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return STWR_OK;
+}
+
+const char* stwr_last_error(const stwr_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : g_tls_error.c_str();
+}
+
+int32_t stwr_ctx_bytes_in_use(const stwr_ctx* ctx, uint64_t* bytes) {
+  if (!ctx || !bytes) return STWR_ERR_ARG;
+  *bytes = ctx->in_use;
+  return STWR_OK;
+}
+
+int32_t stwr_ctx_set_timing(stwr_ctx* ctx, int32_t enable) {
+  if (!ctx) return STWR_ERR_ARG;
+  ctx->timing = enable != 0;
+  return STWR_OK;
+}
+
+int32_t stwr_ctx_kernel_times(stwr_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return STWR_ERR_ARG;
+  return guarded(ctx, [&]() -> int32_t {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) {
+      double tot = 0.0;
+      for (auto& pr : ctx->marks[k]) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, pr.first, pr.second));
+        tot += t;
+        ctx->pool.push_back(pr.first);
+        ctx->pool.push_back(pr.second);
+      }
+      ms[k] = tot;
+      launches[k] = (int64_t)ctx->marks[k].size();
+      ctx->marks[k].clear();
+    }
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_problem_bytes(const stwr_problem_desc* desc, const stwr_solver_opts* opts, uint64_t* bytes) {
+  return guarded(nullptr, [&]() -> int32_t {
+    check_desc(desc);
+    check_opts(opts);
+    if (!bytes) throw StwrError(STWR_ERR_ARG, "null output");
+    std::vector<Level> lv;
+    build_levels(desc, lv);
+    *bytes = plan_bytes(desc, opts, lv);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_mesh_info(int32_t mesh_n, int64_t* out) {
+  return guarded(nullptr, [&]() -> int32_t {
+    if (!out || mesh_n < 1) throw StwrError(STWR_ERR_ARG, "bad arguments");
+    HostLevel H;
+    build_level(mesh_n, H);
+    std::memset(out, 0, 52 * sizeof(int64_t));
+    out[0] = H.nf;
+    out[1] = H.nn;
+    out[2] = H.nv;
+    out[3] = H.nc;
+    out[4] = H.row_ptr[H.nf];
+    out[5] = H.nv;
+    out[6] = (int64_t)H.patch_dofs.size();
+    int mx = 0;
+    for (int v = 0; v < H.nv; ++v) {
+      const int nb = H.patch_ptr[v + 1] - H.patch_ptr[v];
+      mx = std::max(mx, nb);
+      if (nb < 40) out[12 + nb]++;
+    }
+    out[7] = mx;
+    // nonzeros of the patch of the vertex nearest the centre
+    const int c = H.n1 / 2;
+    const int v = c + H.n1 * c;
+    const int s0 = H.patch_ptr[v], nb = H.patch_ptr[v + 1] - s0, nbu = H.patch_nbu[v];
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) {
+        if (H.patch_nz[H.patch_nz_off[v] + (int64_t)i * nb + j] < 0) continue;
+        if (i < nbu && j < nbu) out[8]++;
+        else if (i < nbu) out[9]++;
+        else if (j < nbu) out[10]++;
+      }
+    int distinct = 0;
+    for (int k = 0; k < 40; ++k) distinct += out[12 + k] > 0;
+    out[11] = distinct;
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const stwr_solver_opts* opts,
+                            stwr_problem** out) {
+  return guarded(ctx, [&]() -> int32_t {
+    if (!ctx || !out) throw StwrError(STWR_ERR_ARG, "null argument");
+    check_desc(desc);
+    check_opts(opts);
+    HIPCHK(hipSetDevice(ctx->device));
+    std::unique_ptr<stwr_problem> P(new stwr_problem());
+    P->ctx = ctx;
+    P->desc = *desc;
+    P->opts = *opts;
+    P->psi_ab.assign(desc->psi_ab, desc->psi_ab + 2 * desc->n_psi_modes);
+    P->psi_coef.assign(desc->psi_coef, desc->psi_coef + 3 * desc->n_psi_modes);
+    P->p_ab.assign(desc->p_ab, desc->p_ab + 2 * desc->n_p_modes);
+    P->p_coef.assign(desc->p_coef, desc->p_coef + 3 * desc->n_p_modes);
+    P->desc.psi_ab = nullptr; P->desc.psi_coef = nullptr; P->desc.p_ab = nullptr; P->desc.p_coef = nullptr;
+    build_levels(desc, P->lv);
+    const uint64_t need = plan_bytes(desc, opts, P->lv);
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      if (ctx->budget && ctx->in_use + need > ctx->budget)
+        throw StwrError(STWR_ERR_BUDGET, "problem needs " + std::to_string(need) + " bytes; budget left " +
+                                             std::to_string(ctx->budget - ctx->in_use));
+      ctx->in_use += need;
+    }
+    P->bytes = need;
+    try {
+      build_ref_tables(desc->q, P->tab);
+      P->d_tab = P->alloc<RefTables>(1);
+      HIPCHK(hipMemcpy(P->d_tab, &P->tab, sizeof(RefTables), hipMemcpyHostToDevice));
+      P->mms.n_psi = desc->n_psi_modes;
+      P->mms.n_p = desc->n_p_modes;
+      P->mms.psi_ab = P->upload(P->psi_ab);
+      P->mms.psi_coef = P->upload(P->psi_coef);
+      P->mms.p_ab = P->upload(P->p_ab);
+      P->mms.p_coef = P->upload(P->p_coef);
+      P->mms.reynolds = desc->reynolds;
+      const int L = (int)P->lv.size();
+      for (int l = 0; l < L; ++l) upload_level(P.get(), P->lv[l], l == L - 1);
+      for (int l = 0; l + 1 < L; ++l)
+        P->lv[l].fac_budgeted = (size_t)fac_elems(P->lv[l].H, P->lv[l].N, P->lv[l].NQ, opts->smoother_prec) *
+                                (opts->smoother_prec == STWR_FP32 ? 4 : 8);
+      for (int l = 0; l + 1 < L; ++l) P->lv[l].inject = P->upload(P->lv[l].Tr.inject);
+      P->restart = opts->gmres_restart;
+      const int64_t n0 = P->lv[0].n_st;
+      P->V = P->alloc<double>((size_t)(P->restart + 1) * n0);
+      P->Z = P->alloc<double>((size_t)P->restart * n0);
+      P->dscal = P->alloc<double>(256 + (size_t)desc->n_slabs * (desc->q + 1));
+      P->partial = P->alloc<double>(256 * 256);
+      P->dstatus = P->alloc<int>(4);
+      HIPCHK(hipMemset(P->dstatus, 0, 4 * sizeof(int)));
+      // host copies no longer needed on the device side can be dropped
+      for (auto& Lv : P->lv) {
+        std::vector<int>().swap(Lv.H.cell_nz);
+        std::vector<int>().swap(Lv.H.patch_nz);
+        std::vector<int>().swap(Lv.H.dof_slot);
+      }
+    } catch (...) {
+      for (auto& b : P->bufs) (void)hipFree(b.p);
+      P->bufs.clear();
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->in_use -= need;
+      throw;
+    }
+    *out = P.release();
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_problem_destroy(stwr_problem* p) {
+  if (!p) return STWR_OK;
+  (void)hipStreamSynchronize(p->s());
+  for (auto& b : p->bufs) (void)hipFree(b.p);
+  {
+    std::lock_guard<std::mutex> g(p->ctx->mu);
+    p->ctx->in_use -= std::min(p->ctx->in_use, p->bytes);
+  }
+  delete p;
+  return STWR_OK;
+}
+
+int32_t stwr_problem_sizes(const stwr_problem* p, int32_t level, int64_t* n_st, int64_t* n_spatial_free,
+                           int32_t* n_patches) {
+  if (!p || level < 0 || level >= (int)p->lv.size()) return STWR_ERR_ARG;
+  const Level& L = p->lv[level];
+  if (n_st) *n_st = L.n_st;
+  if (n_spatial_free) *n_spatial_free = L.H.nf;
+  if (n_patches) *n_patches = L.H.nv;
+  return STWR_OK;
+}
+
+int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    check_opts(opts);
+    if (opts->gmres_restart != p->restart) throw StwrError(STWR_ERR_ARG, "gmres_restart is fixed at creation");
+    if (opts->smoother_prec != p->opts.smoother_prec)
+      for (auto& L : p->lv) { L.fac_prec = -1; L.has_lambda = false; }
+    p->opts = *opts;
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_nonlinear_residual(stwr_problem* p, const double* U, double* F) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!U || !F) throw StwrError(STWR_ERR_ARG, "null vector");
+    Level& L = p->lv[0];
+    HIPCHK(launch_fill(L.n_st, 0.0, F, p->s()));
+    HIPCHK(launch_assemble_residual(L.view, p->d_tab, p->mms, U, F, p->s()));
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_assemble(stwr_problem* p, const double* U) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!U) throw StwrError(STWR_ERR_ARG, "null vector");
+    assemble(p, U);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_get_operator(stwr_problem* p, int32_t level, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                          double* values, double* mass) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    Level& L = level_at(p, level);
+    const int64_t nz = L.view.nnz;
+    if (nnz) *nnz = nz;
+    if (row_ptr) std::memcpy(row_ptr, L.H.row_ptr.data(), (L.H.nf + 1) * sizeof(int));
+    if (col) std::memcpy(col, L.H.col.data(), nz * sizeof(int));
+    if (values || mass) {
+      if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+      if (values) HIPCHK(hipMemcpyAsync(values, L.Jv, (size_t)nz * L.N * L.NQ * L.NQ * 8, hipMemcpyDeviceToHost, p->s()));
+      if (mass) HIPCHK(hipMemcpyAsync(mass, L.Mv, (size_t)nz * 8, hipMemcpyDeviceToHost, p->s()));
+      HIPCHK(hipStreamSynchronize(p->s()));
+    }
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_apply(stwr_problem* p, int32_t level, const double* x, double* y) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    if (!x || !y) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+    spmv(p, level, x, nullptr, y);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_residual(stwr_problem* p, int32_t level, const double* b, const double* x, double* r) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    if (!x || !b || !r) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+    spmv(p, level, x, b, r);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_patch_factor(stwr_problem* p, int32_t level, int32_t prec) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    patch_factor(p, level, prec);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_patch_apply(stwr_problem* p, int32_t level, const double* r, double* z) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    if (!r || !z) throw StwrError(STWR_ERR_ARG, "null vector");
+    patch_apply(p, level, r, z);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_eig_estimate(stwr_problem* p, int32_t level, double* lambda) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    const double lam = eig_estimate(p, level);
+    if (lambda) *lambda = lam;
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_relax(stwr_problem* p, int32_t level, const double* b, double* x, int32_t n_steps, double a,
+                   double bnd) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    if (!b || !x || n_steps < 0 || !(bnd > a) || !(a > 0.0)) throw StwrError(STWR_ERR_ARG, "bad relax arguments");
+    relax(p, level, b, x, n_steps, a, bnd, false);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_restrict(stwr_problem* p, int32_t fine_level, const double* rf, double* rc) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (fine_level < 0 || fine_level + 1 >= (int)p->lv.size()) throw StwrError(STWR_ERR_ARG, "level out of range");
+    if (!rf || !rc) throw StwrError(STWR_ERR_ARG, "null vector");
+    Level& F = p->lv[fine_level];
+    Level& C = p->lv[fine_level + 1];
+    HIPCHK(launch_transfer(C.H.nf, C.N * C.NQ, F.R_ptr, F.R_col, F.R_val, rf, rc, 0, p->s()));
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_prolong_add(stwr_problem* p, int32_t fine_level, const double* ec, double* xf) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (fine_level < 0 || fine_level + 1 >= (int)p->lv.size()) throw StwrError(STWR_ERR_ARG, "level out of range");
+    if (!ec || !xf) throw StwrError(STWR_ERR_ARG, "null vector");
+    Level& F = p->lv[fine_level];
+    HIPCHK(launch_transfer(F.H.nf, F.N * F.NQ, F.P_ptr, F.P_col, F.P_val, ec, xf, 1, p->s()));
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_coarse_solve(stwr_problem* p, const double* b, double* x) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!b || !x) throw StwrError(STWR_ERR_ARG, "null vector");
+    coarse_solve(p, b, x);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_setup_smoothers(stwr_problem* p) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    setup_smoothers(p);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_vcycle(stwr_problem* p, const double* b, double* x) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!b || !x) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+    vcycle(p, b, x);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_project_pressure(stwr_problem* p, int32_t level, double* x) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    level_at(p, level);
+    if (!x) throw StwrError(STWR_ERR_ARG, "null vector");
+    project(p, level, x);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* stats) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!b || !x) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
+    int its = 0;
+    double rel = 0.0;
+    const double t0 = now_s();
+    fgmres(p, b, x, stats, &its, &rel);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->linear_its_total = its;
+      stats->linear_its[0] = its;
+      stats->final_rel_residual = rel;
+      stats->solve_seconds = now_s() - t0;
+      for (int l = 0; l < (int)p->lv.size() && l < STWR_MAX_LEVELS; ++l) stats->lambda[l] = p->lv[l].lambda;
+    }
+    if (rel > p->opts.gmres_rtol) return fail(p->ctx, STWR_ERR_NOT_CONVERGED, "FGMRES reached its iteration limit");
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!U) throw StwrError(STWR_ERR_ARG, "null vector");
+    const stwr_solver_opts& o = p->opts;
+    Level& L0 = p->lv[0];
+    const int64_t n = L0.n_st;
+    // F lives in L0.b, the correction in L0.x (both level-0 work vectors are
+    // free outside V-cycles, which take their level-0 vectors from FGMRES).
+    double* F = L0.b;
+    double* dU = L0.x;
+    stwr_stats local{};
+    stwr_stats& st = stats ? *stats : local;
+    std::memset(&st, 0, sizeof(st));
+    auto resid = [&]() {
+      HIPCHK(launch_fill(n, 0.0, F, p->s()));
+      HIPCHK(launch_assemble_residual(L0.view, p->d_tab, p->mms, U, F, p->s()));
+      return norm_host(p, n, F);
+    };
+    double f = resid();
+    const double f0 = f;
+    st.fnorm[0] = f;
+    int k = 0;
+    bool converged = f0 == 0.0;
+    for (; k < o.newton_maxit && !converged; ++k) {
+      const double ts = now_s();
+      assemble(p, U);
+      setup_smoothers(p);
+      st.setup_seconds += now_s() - ts;
+      // F is recomputed after the update, so it can hold the right-hand side -F
+      HIPCHK(launch_axpby(n, -1.0, F, 0.0, F, p->s()));
+      int its = 0;
+      double rel = 0.0;
+      const double tk = now_s();
+      fgmres(p, F, dU, &st, &its, &rel);
+      st.solve_seconds += now_s() - tk;
+      HIPCHK(launch_axpby(n, 1.0, dU, 1.0, U, p->s()));
+      st.linear_its[k] = its;
+      st.linear_its_total += its;
+      f = resid();
+      st.fnorm[k + 1] = f;
+      converged = f <= o.newton_rtol * f0;
+    }
+    st.newton_its = k;
+    for (int l = 0; l < (int)p->lv.size() && l < STWR_MAX_LEVELS; ++l) st.lambda[l] = p->lv[l].lambda;
+    if (!converged) return fail(p->ctx, STWR_ERR_NOT_CONVERGED, "Newton reached its iteration limit");
+    return STWR_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,371 @@
+// Space-time assembly of Taylor-Hood P2-P1 x DG(q) Navier-Stokes on gfx950
+// (Sec. 2, eq. nsfem with forcing; upwind jump of eq. dgintime).
+//
+// One 64-lane workgroup per (cell, slab).  The workgroup stages the cell's
+// nodal values, its physical basis gradients and the fields at the
+// 25 x (q+3) space-time quadrature points in LDS; lanes then own local matrix
+// (or vector) entries and add them into the global space-time operator with
+// FP64 atomics.  Values of the operator are stored per spatial nonzero k as
+// Jv[((k * N + n) * NQ + a) * NQ + b] (test temporal node a, trial node b);
+// Mv[k] holds the velocity mass matrix, which is all the jump coupling of
+// slab n to slab n-1 needs (-e0 e1^T (x) M).
+//
+// Pressure convention: the momentum equation is tested as -(P, div psi) and
+// the continuity equation as -(div U, chi).  Boundary velocities are the
+// exact velocity at the temporal nodes; the value entering slab 0 from the
+// left is the P2 interpolant of the velocity at t = 0.
+#include "device.h"
+
+namespace stwr {
+
+namespace {
+
+struct ModeSums {
+  double px, py, pxx, pxy, pyy, pxt, pyt, lapx, lapy;
+};
+
+// Stream-function derivative sums of the manufactured solution at (t, x, y).
+__device__ ModeSums psi_sums(const MmsDev& m, double t, double x, double y) {
+  ModeSums s{};
+  for (int k = 0; k < m.n_psi; ++k) {
+    const double A = M_PI * m.psi_ab[2 * k], B = M_PI * m.psi_ab[2 * k + 1];
+    const double c = m.psi_coef[3 * k], w = m.psi_coef[3 * k + 1], th = m.psi_coef[3 * k + 2];
+    double sx, cx, sy, cy, st, ct;
+    sincos(A * x, &sx, &cx);
+    sincos(B * y, &sy, &cy);
+    sincos(w * t + th, &st, &ct);
+    const double psx = c * A * cx * sy, psy = c * B * sx * cy;
+    s.px += psx * ct;
+    s.py += psy * ct;
+    s.pxx -= c * A * A * sx * sy * ct;
+    s.pyy -= c * B * B * sx * sy * ct;
+    s.pxy += c * A * B * cx * cy * ct;
+    s.pxt -= psx * w * st;
+    s.pyt -= psy * w * st;
+    // each mode is an eigenfunction of the Laplacian: lap(psi_m) = -(A^2 + B^2) psi_m
+    const double k2 = A * A + B * B;
+    s.lapx -= k2 * psy * ct;   // lap(u_x) = lap(psi_y)
+    s.lapy += k2 * psx * ct;   // lap(u_y) = -lap(psi_x)
+  }
+  return s;
+}
+
+__device__ void exact_velocity(const MmsDev& m, double t, double x, double y, double& ux, double& uy) {
+  ux = 0.0;
+  uy = 0.0;
+  for (int k = 0; k < m.n_psi; ++k) {
+    const double A = M_PI * m.psi_ab[2 * k], B = M_PI * m.psi_ab[2 * k + 1];
+    const double c = m.psi_coef[3 * k], w = m.psi_coef[3 * k + 1], th = m.psi_coef[3 * k + 2];
+    const double tau = cos(w * t + th);
+    ux += c * B * sin(A * x) * cos(B * y) * tau;
+    uy -= c * A * cos(A * x) * sin(B * y) * tau;
+  }
+}
+
+__device__ void forcing(const MmsDev& m, double t, double x, double y, double& fx, double& fy) {
+  const ModeSums s = psi_sums(m, t, x, y);
+  const double ux = s.py, uy = -s.px;
+  const double convx = ux * s.pxy + uy * s.pyy;
+  const double convy = -ux * s.pxx - uy * s.pxy;
+  double gpx = 0.0, gpy = 0.0;
+  for (int k = 0; k < m.n_p; ++k) {
+    const double A = M_PI * m.p_ab[2 * k], B = M_PI * m.p_ab[2 * k + 1];
+    const double d = m.p_coef[3 * k], w = m.p_coef[3 * k + 1], th = m.p_coef[3 * k + 2];
+    const double tau = cos(w * t + th);
+    gpx -= d * A * sin(A * x) * cos(B * y) * tau;
+    gpy -= d * B * cos(A * x) * sin(B * y) * tau;
+  }
+  fx = s.pyt + m.reynolds * convx - s.lapx + gpx;
+  fy = -s.pxt + m.reynolds * convy - s.lapy + gpy;
+}
+
+// Cell geometry: inverse Jacobian (row-major 2x2), |det| and vertex 0.
+__device__ void cell_geometry(const LevelView& L, int c, double inv[4], double& adet, double v0[2],
+                              double Jc[4]) {
+  const int a = L.cells[3 * c], b = L.cells[3 * c + 1], d = L.cells[3 * c + 2];
+  const double ax = (a % L.n1) * L.h, ay = (a / L.n1) * L.h;
+  const double bx = (b % L.n1) * L.h, by = (b / L.n1) * L.h;
+  const double dx = (d % L.n1) * L.h, dy = (d / L.n1) * L.h;
+  Jc[0] = bx - ax; Jc[1] = dx - ax;   // column 0 = v1 - v0, column 1 = v2 - v0
+  Jc[2] = by - ay; Jc[3] = dy - ay;
+  const double det = Jc[0] * Jc[3] - Jc[1] * Jc[2];
+  inv[0] = Jc[3] / det; inv[1] = -Jc[1] / det;
+  inv[2] = -Jc[2] / det; inv[3] = Jc[0] / det;
+  adet = fabs(det);
+  v0[0] = ax; v0[1] = ay;
+}
+
+// Shared staging common to both kernels.
+template <int NQ>
+struct CellStage {
+  double ul[2][6][NQ];            // velocity nodal values (free or Dirichlet)
+  double gN[kQx][6][2];           // physical P2 gradients
+  double wdet[kQx];
+  double xp[kQx][2];              // physical quadrature points
+  double uq[kMaxG][kQx][2];
+  double gq[kMaxG][kQx][2][2];    // [comp][d/dx_k]
+};
+
+template <int NQ>
+__device__ void stage_cell(const LevelView& L, const RefTables* __restrict__ T, const MmsDev& mms,
+                           const double* __restrict__ U, int c, int n, CellStage<NQ>& S) {
+  const int tid = threadIdx.x;
+  __shared__ double inv_s[4], adet_s, v0_s[2], J_s[4];
+  if (tid == 0) {
+    double inv[4], adet, v0[2], Jc[4];
+    cell_geometry(L, c, inv, adet, v0, Jc);
+    for (int k = 0; k < 4; ++k) { inv_s[k] = inv[k]; J_s[k] = Jc[k]; }
+    adet_s = adet;
+    v0_s[0] = v0[0]; v0_s[1] = v0[1];
+  }
+  if (tid < 12 * NQ) {
+    const int comp = tid / (6 * NQ), i = (tid / NQ) % 6, a = tid % NQ;
+    const int node = L.cell_p2[6 * c + i];
+    const int k = L.node_free[node];
+    double v;
+    if (k >= 0) {
+      v = U[((int64_t)(2 * k + comp) * L.N + n) * NQ + a];
+    } else {
+      const double t = (n + T->tnode[a]) * L.dt;
+      const double x = (node % L.n2) * 0.5 * L.h, y = (node / L.n2) * 0.5 * L.h;
+      double ux, uy;
+      exact_velocity(mms, t, x, y, ux, uy);
+      v = comp == 0 ? ux : uy;
+    }
+    S.ul[comp][i][a] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kQx * 6; e += 64) {
+    const int x = e / 6, i = e % 6;
+    for (int k = 0; k < 2; ++k)
+      S.gN[x][i][k] = T->dN2[x][i][0] * inv_s[0 * 2 + k] + T->dN2[x][i][1] * inv_s[1 * 2 + k];
+  }
+  if (tid < kQx) {
+    S.wdet[tid] = T->wq[tid] * adet_s;
+    S.xp[tid][0] = v0_s[0] + J_s[0] * T->xq[tid][0] + J_s[1] * T->xq[tid][1];
+    S.xp[tid][1] = v0_s[1] + J_s[2] * T->xq[tid][0] + J_s[3] * T->xq[tid][1];
+  }
+  __syncthreads();
+  const int G = T->G;
+  for (int e = tid; e < G * kQx; e += 64) {
+    const int g = e / kQx, x = e % kQx;
+    for (int comp = 0; comp < 2; ++comp) {
+      double u = 0.0, gx = 0.0, gy = 0.0;
+      for (int i = 0; i < 6; ++i) {
+        double ui = 0.0;
+        for (int b = 0; b < NQ; ++b) ui += T->Phi[g][b] * S.ul[comp][i][b];
+        u += ui * T->N2[x][i];
+        gx += ui * S.gN[x][i][0];
+        gy += ui * S.gN[x][i][1];
+      }
+      S.uq[g][x][comp] = u;
+      S.gq[g][x][comp][0] = gx;
+      S.gq[g][x][comp][1] = gy;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NQ>
+__global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* __restrict__ T,
+                                                 MmsDev mms, const double* __restrict__ U,
+                                                 double* __restrict__ Jv, double* __restrict__ Mv) {
+  const int c = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  __shared__ CellStage<NQ> S;
+  stage_cell<NQ>(L, T, mms, U, c, n, S);
+  const int G = T->G;
+  const double dt = L.dt, R = mms.reynolds;
+  const int* nzc = L.cell_nz + (int64_t)225 * c;
+  if (tid < 36) {
+    const int i = tid / 6, j = tid % 6;
+    double Mij = 0.0, Kij = 0.0;
+    double c1[kMaxG], c2[kMaxG][2][2];
+    for (int g = 0; g < G; ++g) {
+      c1[g] = 0.0;
+      c2[g][0][0] = c2[g][0][1] = c2[g][1][0] = c2[g][1][1] = 0.0;
+    }
+    for (int x = 0; x < kQx; ++x) {
+      const double w = S.wdet[x], Ni = T->N2[x][i], Nj = T->N2[x][j];
+      Mij += w * Ni * Nj;
+      Kij += w * (S.gN[x][i][0] * S.gN[x][j][0] + S.gN[x][i][1] * S.gN[x][j][1]);
+      for (int g = 0; g < G; ++g) {
+        c1[g] += w * Ni * (S.uq[g][x][0] * S.gN[x][j][0] + S.uq[g][x][1] * S.gN[x][j][1]);
+        const double wnn = w * Ni * Nj;
+        for (int ci = 0; ci < 2; ++ci)
+          for (int cj = 0; cj < 2; ++cj) c2[g][ci][cj] += wnn * S.gq[g][x][ci][cj];
+      }
+    }
+    for (int a = 0; a < NQ; ++a)
+      for (int b = 0; b < NQ; ++b) {
+        double C1 = 0.0, C2[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int g = 0; g < G; ++g) {
+          const double cw = T->wg[g] * T->Phi[g][a] * T->Phi[g][b];
+          C1 += cw * c1[g];
+          for (int ci = 0; ci < 2; ++ci)
+            for (int cj = 0; cj < 2; ++cj) C2[ci][cj] += cw * c2[g][ci][cj];
+        }
+        const double diag = T->T[a][b] * Mij + dt * T->W[a][b] * Kij + dt * R * C1;
+        for (int ci = 0; ci < 2; ++ci)
+          for (int cj = 0; cj < 2; ++cj) {
+            const int nz = nzc[15 * (6 * ci + i) + 6 * cj + j];
+            if (nz < 0) continue;
+            const double v = dt * R * C2[ci][cj] + (ci == cj ? diag : 0.0);
+            atomicAdd(&Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
+          }
+      }
+    if (n == 0) {
+      for (int ci = 0; ci < 2; ++ci) {
+        const int nz = nzc[15 * (6 * ci + i) + 6 * ci + j];
+        if (nz >= 0) atomicAdd(&Mv[nz], Mij);
+      }
+    }
+  } else if (tid < 54) {
+    const int t = tid - 36, j = t / 6, i = t % 6;   // pressure j, velocity node i
+    double B[2] = {0.0, 0.0};
+    for (int x = 0; x < kQx; ++x) {
+      const double w = S.wdet[x] * T->N1[x][j];
+      B[0] += w * S.gN[x][i][0];
+      B[1] += w * S.gN[x][i][1];
+    }
+    for (int a = 0; a < NQ; ++a)
+      for (int b = 0; b < NQ; ++b)
+        for (int ci = 0; ci < 2; ++ci) {
+          const double v = -dt * T->W[a][b] * B[ci];
+          const int nz1 = nzc[15 * (6 * ci + i) + 12 + j];
+          if (nz1 >= 0) atomicAdd(&Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
+          const int nz2 = nzc[15 * (12 + j) + 6 * ci + i];
+          if (nz2 >= 0) atomicAdd(&Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
+        }
+  }
+}
+
+template <int NQ>
+__global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* __restrict__ T,
+                                                 MmsDev mms, const double* __restrict__ U,
+                                                 double* __restrict__ F) {
+  const int c = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  __shared__ CellStage<NQ> S;
+  __shared__ double pl[3][NQ];
+  __shared__ double prev[2][6];
+  __shared__ double dq[kMaxG][kQx][2], pq[kMaxG][kQx], fq[kMaxG][kQx][2];
+  __shared__ double jq[kQx][2];   // U(s=0) - U_{n-1}(1) at the quadrature points
+  stage_cell<NQ>(L, T, mms, U, c, n, S);
+  const int G = T->G;
+  if (tid < 3 * NQ) {
+    const int j = tid / NQ, a = tid % NQ;
+    pl[j][a] = U[((int64_t)(L.po + L.cells[3 * c + j]) * L.N + n) * NQ + a];
+  } else if (tid >= 32 && tid < 44) {
+    const int comp = (tid - 32) / 6, i = (tid - 32) % 6;
+    const int node = L.cell_p2[6 * c + i];
+    const int k = L.node_free[node];
+    const double x = (node % L.n2) * 0.5 * L.h, y = (node / L.n2) * 0.5 * L.h;
+    double v = 0.0;
+    if (n == 0) {
+      double ux, uy;
+      exact_velocity(mms, 0.0, x, y, ux, uy);
+      v = comp == 0 ? ux : uy;
+    } else {
+      for (int b = 0; b < NQ; ++b) {
+        double vb;
+        if (k >= 0) {
+          vb = U[((int64_t)(2 * k + comp) * L.N + n - 1) * NQ + b];
+        } else {
+          double ux, uy;
+          exact_velocity(mms, (n - 1 + T->tnode[b]) * L.dt, x, y, ux, uy);
+          vb = comp == 0 ? ux : uy;
+        }
+        v += T->e1[b] * vb;
+      }
+    }
+    prev[comp][i] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < G * kQx; e += 64) {
+    const int g = e / kQx, x = e % kQx;
+    for (int comp = 0; comp < 2; ++comp) {
+      double d = 0.0;
+      for (int i = 0; i < 6; ++i) {
+        double ui = 0.0;
+        for (int b = 0; b < NQ; ++b) ui += T->dPhi[g][b] * S.ul[comp][i][b];
+        d += ui * T->N2[x][i];
+      }
+      dq[g][x][comp] = d;
+    }
+    double p = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      double pj = 0.0;
+      for (int b = 0; b < NQ; ++b) pj += T->Phi[g][b] * pl[j][b];
+      p += pj * T->N1[x][j];
+    }
+    pq[g][x] = p;
+    double fx, fy;
+    forcing(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], fx, fy);
+    fq[g][x][0] = fx;
+    fq[g][x][1] = fy;
+  }
+  if (tid < kQx) {
+    for (int comp = 0; comp < 2; ++comp) {
+      double u0 = 0.0, up = 0.0;
+      for (int i = 0; i < 6; ++i) {
+        double ui = 0.0;
+        for (int b = 0; b < NQ; ++b) ui += T->e0[b] * S.ul[comp][i][b];
+        u0 += ui * T->N2[tid][i];
+        up += prev[comp][i] * T->N2[tid][i];
+      }
+      jq[tid][comp] = u0 - up;
+    }
+  }
+  __syncthreads();
+  const double dt = L.dt, R = mms.reynolds;
+  if (tid < 12 * NQ) {
+    const int comp = tid / (6 * NQ), i = (tid / NQ) % 6, a = tid % NQ;
+    double acc = 0.0;
+    for (int g = 0; g < G; ++g) {
+      double sg = 0.0;
+      for (int x = 0; x < kQx; ++x) {
+        const double conv = S.uq[g][x][0] * S.gq[g][x][comp][0] + S.uq[g][x][1] * S.gq[g][x][comp][1];
+        const double val = dq[g][x][comp] + dt * (R * conv - fq[g][x][comp]);
+        const double grd = S.gq[g][x][comp][0] * S.gN[x][i][0] + S.gq[g][x][comp][1] * S.gN[x][i][1]
+                         - pq[g][x] * S.gN[x][i][comp];
+        sg += S.wdet[x] * (val * T->N2[x][i] + dt * grd);
+      }
+      acc += T->wg[g] * T->Phi[g][a] * sg;
+    }
+    double jmp = 0.0;
+    for (int x = 0; x < kQx; ++x) jmp += S.wdet[x] * jq[x][comp] * T->N2[x][i];
+    acc += T->e0[a] * jmp;
+    const int dof = L.cell_dofs[15 * c + 6 * comp + i];
+    if (dof >= 0) atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], acc);
+  } else if (tid >= 32 && tid < 32 + 3 * NQ) {
+    const int j = (tid - 32) / NQ, a = (tid - 32) % NQ;
+    double acc = 0.0;
+    for (int g = 0; g < G; ++g) {
+      double sg = 0.0;
+      for (int x = 0; x < kQx; ++x)
+        sg += S.wdet[x] * (S.gq[g][x][0][0] + S.gq[g][x][1][1]) * T->N1[x][j];
+      acc += T->wg[g] * T->Phi[g][a] * sg;
+    }
+    const int dof = L.po + L.cells[3 * c + j];
+    atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
+                                    const double* U, double* Jv, double* Mv, hipStream_t s) {
+  dim3 grid(L.nc, L.N);
+  if (L.NQ == 1) hipLaunchKernelGGL(k_jacobian<1>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
+  else hipLaunchKernelGGL(k_jacobian<2>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_residual(const LevelView& L, const RefTables* tab, MmsDev mms,
+                                    const double* U, double* F, hipStream_t s) {
+  dim3 grid(L.nc, L.N);
+  if (L.NQ == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(64), 0, s, L, tab, mms, U, F);
+  else hipLaunchKernelGGL(k_residual<2>, grid, dim3(64), 0, s, L, tab, mms, U, F);
+  return hipGetLastError();
+}
+
+}  // namespace stwr

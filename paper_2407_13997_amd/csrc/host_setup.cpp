@@ -1,0 +1,336 @@
+// Host construction of levels, patches, transfers and reference tables.
+#include "host_setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+namespace stwr {
+
+// ---------------------------------------------------------------------------
+// Quadrature: Gauss-Legendre nodes by Newton iteration on the three-term
+// recurrence of the Legendre polynomials, mapped to [0, 1].
+void gauss_legendre01(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    // ascending order on [0, 1]
+    x[n - 1 - i] = 0.5 * (z + 1.0);
+    w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2) P'^2) scaled by 1/2
+  }
+}
+
+static void p2_eval(double xi, double eta, double* v, double (*g)[2]) {
+  const double l[3] = {1.0 - xi - eta, xi, eta};
+  const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+  for (int i = 0; i < 3; ++i) {
+    v[i] = l[i] * (2.0 * l[i] - 1.0);
+    if (g) for (int k = 0; k < 2; ++k) g[i][k] = (4.0 * l[i] - 1.0) * dl[i][k];
+  }
+  const int e[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+  for (int m = 0; m < 3; ++m) {
+    int a = e[m][0], b = e[m][1];
+    v[3 + m] = 4.0 * l[a] * l[b];
+    if (g) for (int k = 0; k < 2; ++k) g[3 + m][k] = 4.0 * (l[b] * dl[a][k] + l[a] * dl[b][k]);
+  }
+}
+
+static void p1_eval(double xi, double eta, double* v) {
+  v[0] = 1.0 - xi - eta;
+  v[1] = xi;
+  v[2] = eta;
+}
+
+void build_ref_tables(int q, RefTables& t) {
+  if (q < 0 || q > 1) throw std::invalid_argument("q must be 0 or 1");
+  double u[5], wu[5];
+  gauss_legendre01(5, u, wu);
+  int k = 0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j, ++k) {
+      t.xq[k][0] = u[i];
+      t.xq[k][1] = u[j] * (1.0 - u[i]);
+      t.wq[k] = wu[i] * wu[j] * (1.0 - u[i]);
+    }
+  const double dl1[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+  for (int x = 0; x < kQx; ++x) {
+    p2_eval(t.xq[x][0], t.xq[x][1], t.N2[x], t.dN2[x]);
+    p1_eval(t.xq[x][0], t.xq[x][1], t.N1[x]);
+    for (int i = 0; i < 3; ++i)
+      for (int d = 0; d < 2; ++d) t.dN1[x][i][d] = dl1[i][d];
+  }
+  t.NQ = q + 1;
+  t.G = q + 3;
+  gauss_legendre01(t.G, t.sg, t.wg);
+  // right Gauss-Radau nodes of the slab: {1} or {1/3, 1}
+  if (q == 0) t.tnode[0] = 1.0;
+  else { t.tnode[0] = 1.0 / 3.0; t.tnode[1] = 1.0; }
+  auto lag = [&](int a, double s, double* d) {
+    double v = 1.0, dv = 0.0;
+    for (int b = 0; b < t.NQ; ++b) {
+      if (b == a) continue;
+      double den = t.tnode[a] - t.tnode[b];
+      dv = dv * (s - t.tnode[b]) / den + v / den;
+      v *= (s - t.tnode[b]) / den;
+    }
+    if (d) *d = dv;
+    return v;
+  };
+  for (int g = 0; g < t.G; ++g)
+    for (int a = 0; a < t.NQ; ++a) t.Phi[g][a] = lag(a, t.sg[g], &t.dPhi[g][a]);
+  for (int a = 0; a < t.NQ; ++a) {
+    t.e0[a] = lag(a, 0.0, nullptr);
+    t.e1[a] = lag(a, 1.0, nullptr);
+  }
+  for (int a = 0; a < t.NQ; ++a)
+    for (int b = 0; b < t.NQ; ++b) {
+      double T = t.e0[a] * t.e0[b], W = 0.0;
+      for (int g = 0; g < t.G; ++g) {
+        T += t.wg[g] * t.Phi[g][a] * t.dPhi[g][b];
+        W += t.wg[g] * t.Phi[g][a] * t.Phi[g][b];
+      }
+      t.T[a][b] = T;
+      t.W[a][b] = W;
+    }
+}
+
+// ---------------------------------------------------------------------------
+void build_level(int M, HostLevel& L) {
+  if (M < 1) throw std::invalid_argument("mesh size must be positive");
+  L.M = M;
+  L.n1 = M + 1;
+  L.n2 = 2 * M + 1;
+  L.nv = L.n1 * L.n1;
+  L.nc = 2 * M * M;
+  L.nn = L.n2 * L.n2;
+  L.nfn = (L.n2 - 2) * (L.n2 - 2);
+  L.po = 2 * L.nfn;
+  L.nf = L.po + L.nv;
+  const int n1 = L.n1, n2 = L.n2;
+  L.cells.resize(3 * L.nc);
+  L.cell_p2.resize(6 * L.nc);
+  for (int j = 0; j < M; ++j)
+    for (int i = 0; i < M; ++i) {
+      int a = i + n1 * j, b = i + 1 + n1 * j, c = i + n1 * (j + 1), d = i + 1 + n1 * (j + 1);
+      int c0 = 2 * (i + M * j);
+      int tri[2][3] = {{a, b, c}, {d, c, b}};
+      for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < 3; ++k) L.cells[3 * (c0 + s) + k] = tri[s][k];
+    }
+  auto vnode = [&](int v) { return 2 * (v % n1) + n2 * 2 * (v / n1); };
+  for (int c = 0; c < L.nc; ++c) {
+    int g[3];
+    for (int k = 0; k < 3; ++k) g[k] = vnode(L.cells[3 * c + k]);
+    auto mid = [&](int x, int y) {
+      return (g[x] % n2 + g[y] % n2) / 2 + n2 * ((g[x] / n2 + g[y] / n2) / 2);
+    };
+    int* cp = &L.cell_p2[6 * c];
+    cp[0] = g[0]; cp[1] = g[1]; cp[2] = g[2];
+    cp[3] = mid(1, 2); cp[4] = mid(0, 2); cp[5] = mid(0, 1);
+  }
+  L.node_free.assign(L.nn, -1);
+  for (int gj = 1; gj < n2 - 1; ++gj)
+    for (int gi = 1; gi < n2 - 1; ++gi) L.node_free[gi + n2 * gj] = (gi - 1) + (n2 - 2) * (gj - 1);
+  L.cell_dofs.resize(15 * L.nc);
+  for (int c = 0; c < L.nc; ++c) {
+    int* d = &L.cell_dofs[15 * c];
+    for (int i = 0; i < 6; ++i) {
+      int k = L.node_free[L.cell_p2[6 * c + i]];
+      d[i] = k >= 0 ? 2 * k : -1;
+      d[6 + i] = k >= 0 ? 2 * k + 1 : -1;
+    }
+    for (int i = 0; i < 3; ++i) d[12 + i] = L.po + L.cells[3 * c + i];
+  }
+  // CSR pattern: DoF pairs that share a cell
+  std::vector<std::vector<int>> rows(L.nf);
+  for (int c = 0; c < L.nc; ++c) {
+    const int* d = &L.cell_dofs[15 * c];
+    for (int I = 0; I < 15; ++I) {
+      if (d[I] < 0) continue;
+      for (int J = 0; J < 15; ++J)
+        if (d[J] >= 0) rows[d[I]].push_back(d[J]);
+    }
+  }
+  L.row_ptr.assign(L.nf + 1, 0);
+  for (int r = 0; r < L.nf; ++r) {
+    auto& v = rows[r];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    L.row_ptr[r + 1] = L.row_ptr[r] + (int)v.size();
+  }
+  L.col.resize(L.row_ptr[L.nf]);
+  for (int r = 0; r < L.nf; ++r) std::copy(rows[r].begin(), rows[r].end(), L.col.begin() + L.row_ptr[r]);
+  rows.clear();
+  rows.shrink_to_fit();
+  auto find_nz = [&](int r, int c) -> int {
+    auto b = L.col.begin() + L.row_ptr[r], e = L.col.begin() + L.row_ptr[r + 1];
+    auto it = std::lower_bound(b, e, c);
+    return (it != e && *it == c) ? int(it - L.col.begin()) : -1;
+  };
+  L.cell_nz.resize((size_t)225 * L.nc);
+  for (int c = 0; c < L.nc; ++c) {
+    const int* d = &L.cell_dofs[15 * c];
+    for (int I = 0; I < 15; ++I)
+      for (int J = 0; J < 15; ++J)
+        L.cell_nz[(size_t)225 * c + 15 * I + J] = (d[I] >= 0 && d[J] >= 0) ? find_nz(d[I], d[J]) : -1;
+  }
+  // Vanka+star patches: every free velocity DoF on the closure of the vertex
+  // star, plus the pressure DoF of the vertex.
+  std::vector<std::vector<int>> inc(L.nv);
+  for (int c = 0; c < L.nc; ++c)
+    for (int k = 0; k < 3; ++k) inc[L.cells[3 * c + k]].push_back(c);
+  L.patch_ptr.assign(L.nv + 1, 0);
+  L.patch_nbu.assign(L.nv, 0);
+  L.patch_dofs.clear();
+  for (int v = 0; v < L.nv; ++v) {
+    std::vector<int> d;
+    for (int c : inc[v])
+      for (int i = 0; i < 6; ++i) {
+        int k = L.node_free[L.cell_p2[6 * c + i]];
+        if (k >= 0) { d.push_back(2 * k); d.push_back(2 * k + 1); }
+      }
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    L.patch_nbu[v] = (int)d.size();
+    d.push_back(L.po + v);
+    L.patch_dofs.insert(L.patch_dofs.end(), d.begin(), d.end());
+    L.patch_ptr[v + 1] = (int)L.patch_dofs.size();
+  }
+  L.patch_nz_off.assign(L.nv + 1, 0);
+  for (int v = 0; v < L.nv; ++v) {
+    int64_t nb = L.patch_ptr[v + 1] - L.patch_ptr[v];
+    L.patch_nz_off[v + 1] = L.patch_nz_off[v] + nb * nb;
+  }
+  L.patch_nz.resize(L.patch_nz_off[L.nv]);
+  for (int v = 0; v < L.nv; ++v) {
+    int s = L.patch_ptr[v], nb = L.patch_ptr[v + 1] - s;
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j)
+        L.patch_nz[L.patch_nz_off[v] + (int64_t)i * nb + j] = find_nz(L.patch_dofs[s + i], L.patch_dofs[s + j]);
+  }
+  // transpose: DoF -> slots
+  const int ns = (int)L.patch_dofs.size();
+  L.slot_patch.resize(ns);
+  for (int v = 0; v < L.nv; ++v)
+    for (int s = L.patch_ptr[v]; s < L.patch_ptr[v + 1]; ++s) L.slot_patch[s] = v;
+  L.dof_ptr.assign(L.nf + 1, 0);
+  for (int s = 0; s < ns; ++s) L.dof_ptr[L.patch_dofs[s] + 1]++;
+  for (int r = 0; r < L.nf; ++r) L.dof_ptr[r + 1] += L.dof_ptr[r];
+  L.dof_slot.resize(ns);
+  std::vector<int> fill(L.dof_ptr.begin(), L.dof_ptr.end() - 1);
+  for (int s = 0; s < ns; ++s) L.dof_slot[fill[L.patch_dofs[s]]++] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Nested interpolation: the coarse P2 (P1) function is evaluated at each fine
+// free node (vertex); the coarse cell is found from the structured layout.
+static void locate(const HostLevel& C, double x, double y, int& cell, double& xi, double& eta) {
+  const int M = C.M;
+  const double h = 1.0 / M;
+  int i = std::min((int)std::floor(x / h), M - 1);
+  int j = std::min((int)std::floor(y / h), M - 1);
+  double fx = x / h - i, fy = y / h - j;
+  if (fx + fy <= 1.0 + 1e-12) {
+    cell = 2 * (i + M * j);
+    xi = fx; eta = fy;
+  } else {
+    cell = 2 * (i + M * j) + 1;
+    xi = 1.0 - fx; eta = 1.0 - fy;
+  }
+}
+
+void build_transfer(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
+  if (F.M != 2 * C.M) throw std::invalid_argument("transfer needs a factor-2 refinement");
+  std::vector<std::vector<std::pair<int, double>>> rows(F.nf);
+  const double hf2 = 0.5 / F.M;
+  for (int g = 0; g < F.nn; ++g) {
+    int k = F.node_free[g];
+    if (k < 0) continue;
+    double x = (g % F.n2) * hf2, y = (g / F.n2) * hf2;
+    int cell; double xi, eta;
+    locate(C, x, y, cell, xi, eta);
+    double v[6];
+    p2_eval(xi, eta, v, nullptr);
+    for (int i = 0; i < 6; ++i) {
+      if (std::fabs(v[i]) < 1e-14) continue;
+      int kc = C.node_free[C.cell_p2[6 * cell + i]];
+      if (kc < 0) continue;
+      rows[2 * k].push_back({2 * kc, v[i]});
+      rows[2 * k + 1].push_back({2 * kc + 1, v[i]});
+    }
+  }
+  const double hf = 1.0 / F.M;
+  for (int vf = 0; vf < F.nv; ++vf) {
+    double x = (vf % F.n1) * hf, y = (vf / F.n1) * hf;
+    int cell; double xi, eta;
+    locate(C, x, y, cell, xi, eta);
+    double v[3];
+    p1_eval(xi, eta, v);
+    for (int i = 0; i < 3; ++i) {
+      if (std::fabs(v[i]) < 1e-14) continue;
+      rows[F.po + vf].push_back({C.po + C.cells[3 * cell + i], v[i]});
+    }
+  }
+  T.p_ptr.assign(F.nf + 1, 0);
+  T.p_col.clear();
+  T.p_val.clear();
+  for (int r = 0; r < F.nf; ++r) {
+    auto& e = rows[r];
+    std::sort(e.begin(), e.end());
+    for (auto& pr : e) { T.p_col.push_back(pr.first); T.p_val.push_back(pr.second); }
+    T.p_ptr[r + 1] = (int)T.p_col.size();
+  }
+  // transpose
+  T.r_ptr.assign(C.nf + 1, 0);
+  for (int c : T.p_col) T.r_ptr[c + 1]++;
+  for (int r = 0; r < C.nf; ++r) T.r_ptr[r + 1] += T.r_ptr[r];
+  T.r_col.resize(T.p_col.size());
+  T.r_val.resize(T.p_col.size());
+  std::vector<int> fill(T.r_ptr.begin(), T.r_ptr.end() - 1);
+  for (int r = 0; r < F.nf; ++r)
+    for (int k = T.p_ptr[r]; k < T.p_ptr[r + 1]; ++k) {
+      int c = T.p_col[k];
+      T.r_col[fill[c]] = r;
+      T.r_val[fill[c]] = T.p_val[k];
+      fill[c]++;
+    }
+  // injection: coarse node (a, b) on the coarse node grid is fine node (2a, 2b)
+  T.inject.assign(C.nf, -1);
+  for (int g = 0; g < C.nn; ++g) {
+    int kc = C.node_free[g];
+    if (kc < 0) continue;
+    int gf = 2 * (g % C.n2) + F.n2 * 2 * (g / C.n2);
+    int kf = F.node_free[gf];
+    T.inject[2 * kc] = 2 * kf;
+    T.inject[2 * kc + 1] = 2 * kf + 1;
+  }
+  for (int v = 0; v < C.nv; ++v) {
+    int vf = 2 * (v % C.n1) + F.n1 * 2 * (v / C.n1);
+    T.inject[C.po + v] = F.po + vf;
+  }
+}
+
+}  // namespace stwr

@@ -1,0 +1,74 @@
+// Host-side construction of one space-time level: structured triangle-split
+// mesh, Taylor-Hood P2-P1 free-DoF numbering, CSR sparsity pattern, cell and
+// patch index maps (Vanka+star patches, Sec. 3), nested-grid transfer
+// stencils (P = I (x) blockdiag(P_u, P_phi), Sec. 3) and the quadrature and
+// temporal reference tables.  Pure C++: no device calls.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace stwr {
+
+constexpr int kQx = 25;       // spatial quadrature points (5x5 collapsed Gauss rule)
+constexpr int kMaxG = 6;      // temporal Gauss points (q + 3)
+constexpr int kMaxNQ = 2;     // temporal nodes per slab (q <= 1)
+constexpr int kMaxNb = 39;    // spatial DoFs in a Vanka+star patch (interior)
+constexpr int kMaxNbu = 38;   // velocity DoFs in a patch
+
+// Reference tables consumed by the assembly kernels (plain doubles so the
+// struct can be copied to device memory as is).
+struct RefTables {
+  double xq[kQx][2];
+  double wq[kQx];
+  double N2[kQx][6];
+  double dN2[kQx][6][2];
+  double N1[kQx][3];
+  double dN1[kQx][3][2];
+  int G;                    // temporal Gauss points
+  int NQ;                   // q + 1
+  double sg[kMaxG], wg[kMaxG];
+  double Phi[kMaxG][kMaxNQ], dPhi[kMaxG][kMaxNQ];
+  double e0[kMaxNQ], e1[kMaxNQ], tnode[kMaxNQ];
+  double T[kMaxNQ][kMaxNQ];  // int phi_b' phi_a + phi_b(0) phi_a(0)
+  double W[kMaxNQ][kMaxNQ];  // int phi_a phi_b
+};
+
+void build_ref_tables(int q, RefTables& t);
+void gauss_legendre01(int n, double* x, double* w);
+
+struct HostLevel {
+  int M = 0, n1 = 0, n2 = 0;
+  int nv = 0, nc = 0, nn = 0;
+  int nfn = 0, nf = 0, po = 0;   // free P2 nodes, free DoFs, pressure offset
+  std::vector<int> cells;        // nc x 3 vertex ids
+  std::vector<int> cell_p2;      // nc x 6 P2 node ids (3 vertices, edges opposite v0, v1, v2)
+  std::vector<int> cell_dofs;    // nc x 15: 6 ux, 6 uy, 3 p (-1 = Dirichlet)
+  std::vector<int> node_free;    // nn: free node index or -1
+  std::vector<int> row_ptr, col; // CSR over free DoFs
+  std::vector<int> cell_nz;      // nc x 15 x 15: CSR position or -1
+  std::vector<int> patch_ptr;    // nv + 1
+  std::vector<int> patch_dofs;   // sum nb, sorted (velocity DoFs, then the vertex pressure)
+  std::vector<int> patch_nbu;    // nv: velocity DoFs per patch
+  std::vector<int64_t> patch_nz_off;  // nv + 1: offsets into patch_nz (sum nb^2)
+  std::vector<int> patch_nz;     // nb x nb CSR positions per patch (-1 = structural zero)
+  std::vector<int> dof_ptr;      // nf + 1: transpose map, DoF -> patch slots
+  std::vector<int> dof_slot;     // positions in patch_dofs that hold the DoF
+  std::vector<int> slot_patch;   // sum nb: patch owning each slot
+};
+
+void build_level(int M, HostLevel& L);
+
+// Prolongation from coarse (M/2) to fine (M) in free-DoF numbering, stored by
+// fine rows (P) and by coarse rows (R = P^T).  Injection map: coarse free DoF
+// -> fine free DoF at the same node.
+struct HostTransfer {
+  std::vector<int> p_ptr, p_col;
+  std::vector<double> p_val;
+  std::vector<int> r_ptr, r_col;
+  std::vector<double> r_val;
+  std::vector<int> inject;   // coarse nf
+};
+
+void build_transfer(const HostLevel& fine, const HostLevel& coarse, HostTransfer& T);
+
+}  // namespace stwr

@@ -1,0 +1,434 @@
+// Space-time operator application, grid transfers, Krylov vector kernels and
+// the coarsest-level direct solve on gfx950.
+//
+// Vector layout: [free DoF][slab][temporal node], so one DoF's N * NQ values
+// are contiguous and a lane per (row, slab) reads its row's coefficients
+// Jv[k][n][.][.] coalesced across consecutive slabs.
+#include "device.h"
+
+namespace stwr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// y = A x or y = b - A x for the space-time operator of one level:
+// block diagonal part from Jv, plus the jump coupling of slab n to slab n-1,
+// -e0 (x) (M * (e1 . x_{n-1})), on velocity rows.
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_spmv(int nf, int N, const int* __restrict__ rp,
+                                                 const int* __restrict__ col,
+                                                 const double* __restrict__ Jv,
+                                                 const double* __restrict__ Mv, double e00,
+                                                 double e01, double e10, double e11,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (int64_t)nf * N) return;
+  const int i = (int)(t / N), n = (int)(t % N);
+  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  double acc[NQ];
+  for (int a = 0; a < NQ; ++a) acc[a] = 0.0;
+  double jump = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = col[k];
+    const double* xv = x + ((int64_t)j * N + n) * NQ;
+    const double* v = Jv + ((int64_t)k * N + n) * NQ * NQ;
+    double xb[NQ];
+    for (int bb = 0; bb < NQ; ++bb) xb[bb] = xv[bb];
+    for (int a = 0; a < NQ; ++a)
+      for (int bb = 0; bb < NQ; ++bb) acc[a] += v[a * NQ + bb] * xb[bb];
+    if (n > 0) {
+      const double m = Mv[k];
+      if (m != 0.0) {
+        double xl = 0.0;
+        for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xv[bb - NQ];
+        jump += m * xl;
+      }
+    }
+  }
+  double* yo = y + t * NQ;
+  for (int a = 0; a < NQ; ++a) {
+    const double out = acc[a] - e0[a] * jump;
+    yo[a] = b ? b[t * NQ + a] - out : out;
+  }
+}
+
+// y[r][t] (+)= sum_k val[k] x[col[k]][t]  (nt values per row)
+__global__ __launch_bounds__(kBlock) void k_transfer(int n_rows, int nt, const int* __restrict__ ptr,
+                                                     const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ y, int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)n_rows * nt) return;
+  const int r = (int)(e / nt), t = (int)(e % nt);
+  double acc = 0.0;
+  for (int k = ptr[r]; k < ptr[r + 1]; ++k) acc += val[k] * x[(int64_t)col[k] * nt + t];
+  y[e] = accumulate ? y[e] + acc : acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(int n, int nt, const int* __restrict__ map,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)n * nt) return;
+  const int r = (int)(e / nt), t = (int)(e % nt);
+  y[e] = x[(int64_t)map[r] * nt + t];
+}
+
+__device__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kBlock / 64; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+constexpr int kDotBlocks = 256;
+
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(int64_t n, const double* __restrict__ X,
+                                                         int64_t ldx, const double* __restrict__ y,
+                                                         double* __restrict__ partial) {
+  const int k = blockIdx.y;
+  const double* xk = X + k * ldx;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)kDotBlocks * kBlock)
+    s += xk[e] * y[e];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[k * kDotBlocks + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mdot_final(const double* __restrict__ partial,
+                                                       double* __restrict__ out) {
+  const int k = blockIdx.x;
+  double s = block_sum(partial[k * kDotBlocks + threadIdx.x]);
+  if (threadIdx.x == 0) out[k] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy_dev(int64_t n, const double* __restrict__ coef,
+                                                     double scale, const double* __restrict__ x,
+                                                     double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) y[e] += scale * coef[0] * x[e];
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, double a, const double* x, double b,
+                                                  double* y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) y[e] = (b == 0.0 ? 0.0 : b * y[e]) + a * x[e];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_dev(int64_t n, const double* __restrict__ num,
+                                                      int invert, const double* x, double* y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) y[e] = invert ? x[e] / num[0] : x[e] * num[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double v, double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) y[e] = v;
+}
+
+// v[i] = frac(0.6180339887498949 i) - 0.5, the fixed Arnoldi start vector
+__global__ __launch_bounds__(kBlock) void k_start_vector(int64_t n, double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) {
+    const double v = (double)e * 0.6180339887498949;
+    y[e] = (v - floor(v)) - 0.5;
+  }
+}
+
+// mean of the pressure DoFs per (slab, temporal node) column t
+__global__ __launch_bounds__(kBlock) void k_pmean(int nf, int po, int nt, const double* __restrict__ x,
+                                                  double* __restrict__ mean) {
+  const int t = blockIdx.x;
+  double s = 0.0;
+  for (int i = po + threadIdx.x; i < nf; i += kBlock) s += x[(int64_t)i * nt + t];
+  s = block_sum(s);
+  if (threadIdx.x == 0) mean[t] = s / (nf - po);
+}
+
+__global__ __launch_bounds__(kBlock) void k_psub(int nf, int po, int nt, double* __restrict__ x,
+                                                 const double* __restrict__ mean) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)(nf - po) * nt) return;
+  const int t = (int)(e % nt);
+  x[(int64_t)po * nt + e] -= mean[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemv_cols(int64_t n, int k, const double* __restrict__ Z,
+                                                      int64_t ldz, const double* __restrict__ yv,
+                                                      double* __restrict__ x) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < k; ++j) acc += Z[j * ldz + e] * yv[j];
+  x[e] += acc;
+}
+
+// Dense bordered slab blocks of the coarsest level: B_n = [J_nn C; C^T 0],
+// C = one indicator column of the pressure DoFs per temporal node.
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N,
+                                                         const int* __restrict__ rp,
+                                                         const int* __restrict__ col,
+                                                         const double* __restrict__ Jv,
+                                                         double* __restrict__ B) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (int64_t)nf * N) return;
+  const int i = (int)(t / N), n = (int)(t % N);
+  const int m = nf * NQ, mm = m + NQ;
+  double* Bn = B + (int64_t)n * mm * mm;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = col[k];
+    const double* v = Jv + ((int64_t)k * N + n) * NQ * NQ;
+    for (int a = 0; a < NQ; ++a)
+      for (int b = 0; b < NQ; ++b) Bn[(int64_t)(i * NQ + a) * mm + j * NQ + b] = v[a * NQ + b];
+  }
+  if (i >= po) {
+    for (int a = 0; a < NQ; ++a) {
+      Bn[(int64_t)(i * NQ + a) * mm + m + a] = 1.0;
+      Bn[(int64_t)(m + a) * mm + i * NQ + a] = 1.0;
+    }
+  }
+}
+
+constexpr int kMaxCoarse = 2048;
+
+// In-place Gauss-Jordan inversion with partial pivoting of B[blockIdx.x]
+// (m x m, row-major, global memory), one workgroup per matrix.
+__global__ __launch_bounds__(kBlock) void k_dense_inverse(int m, double* __restrict__ Ball,
+                                                          int* __restrict__ status) {
+  double* B = Ball + (int64_t)blockIdx.x * m * m;
+  __shared__ int perm[kMaxCoarse];
+  __shared__ double colk[kMaxCoarse];
+  __shared__ double rv[kBlock / 64];
+  __shared__ int ri[kBlock / 64];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < m; ++k) {
+    double best = -1.0;
+    int bi = m;
+    for (int i = k + tid; i < m; i += kBlock) {
+      const double v = fabs(B[(int64_t)i * m + k]);
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = rv[0];
+      int p = ri[0];
+      for (int w = 1; w < kBlock / 64; ++w)
+        if (rv[w] > b || (rv[w] == b && ri[w] < p)) { b = rv[w]; p = ri[w]; }
+      if (!(b > 0.0) || !isfinite(b) || p >= m) {
+        status[0] = 1;
+        p = k;
+      }
+      piv_s = p;
+      perm[k] = p;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != k)
+      for (int j = tid; j < m; j += kBlock) {
+        const double a = B[(int64_t)k * m + j];
+        B[(int64_t)k * m + j] = B[(int64_t)p * m + j];
+        B[(int64_t)p * m + j] = a;
+      }
+    __syncthreads();
+    const double pv = B[(int64_t)k * m + k];
+    __syncthreads();
+    for (int j = tid; j < m; j += kBlock)
+      B[(int64_t)k * m + j] = (j == k ? 1.0 : B[(int64_t)k * m + j]) / pv;
+    for (int i = tid; i < m; i += kBlock) colk[i] = B[(int64_t)i * m + k];
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)m * m; e += kBlock) {
+      const int i = (int)(e / m), j = (int)(e % m);
+      if (i == k) continue;
+      const double f = colk[i];
+      if (j == k) B[e] = -f * B[(int64_t)k * m + k];
+      else B[e] -= f * B[(int64_t)k * m + j];
+    }
+    __syncthreads();
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < m; i += kBlock) {
+        const double a = B[(int64_t)i * m + k];
+        B[(int64_t)i * m + k] = B[(int64_t)i * m + p];
+        B[(int64_t)i * m + p] = a;
+      }
+    __syncthreads();
+  }
+}
+
+// Forward block substitution over the slabs of the coarsest level with the
+// inverted bordered slab blocks; one workgroup walks the slabs in order.
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
+                                                         const int* __restrict__ rp,
+                                                         const int* __restrict__ col,
+                                                         const double* __restrict__ Mv, double e00,
+                                                         double e01, double e10, double e11,
+                                                         const double* __restrict__ Binv,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ x) {
+  __shared__ double g[kMaxCoarse];
+  const int m = nf * NQ, mm = m + NQ;
+  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  const int tid = threadIdx.x;
+  for (int n = 0; n < N; ++n) {
+    for (int r = tid; r < m; r += kBlock) {
+      const int i = r / NQ, a = r % NQ;
+      double v = b[((int64_t)i * N + n) * NQ + a];
+      if (n > 0 && i < po) {
+        double jump = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          const double mk = Mv[k];
+          if (mk == 0.0) continue;
+          const double* xv = x + ((int64_t)col[k] * N + n - 1) * NQ;
+          double xl = 0.0;
+          for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xv[bb];
+          jump += mk * xl;
+        }
+        v += e0[a] * jump;
+      }
+      g[r] = v;
+    }
+    if (tid < NQ) g[m + tid] = 0.0;
+    __syncthreads();
+    const double* Bn = Binv + (int64_t)n * mm * mm;
+    for (int r = tid; r < m; r += kBlock) {
+      double acc = 0.0;
+      for (int c = 0; c < mm; ++c) acc += Bn[(int64_t)r * mm + c] * g[c];
+      const int i = r / NQ, a = r % NQ;
+      x[((int64_t)i * N + n) * NQ + a] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, const double* e0,
+                       const double* e1, const double* x, const double* b, double* y,
+                       hipStream_t s) {
+  const int64_t n = (int64_t)L.nf * L.N;
+  const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
+  if (L.NQ == 1)
+    hipLaunchKernelGGL(k_spmv<1>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.N, L.row_ptr, L.col,
+                       Jv, Mv, e0[0], e01, e1[0], e11, x, b, y);
+  else
+    hipLaunchKernelGGL(k_spmv<2>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.N, L.row_ptr, L.col,
+                       Jv, Mv, e0[0], e01, e1[0], e11, x, b, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(int n_rows, int nt, const int* ptr, const int* col, const double* val,
+                           const double* x, double* y, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_transfer, dim3(nblk((int64_t)n_rows * nt)), dim3(kBlock), 0, s, n_rows, nt,
+                     ptr, col, val, x, y, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int n, int nt, const int* map, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(nblk((int64_t)n * nt)), dim3(kBlock), 0, s, n, nt, map, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdot(int64_t n, int nvec, const double* X, int64_t ldx, const double* y,
+                       double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot_partial, dim3(kDotBlocks, nvec), dim3(kBlock), 0, s, n, X, ldx, y,
+                     partial);
+  hipLaunchKernelGGL(k_mdot_final, dim3(nvec), dim3(kBlock), 0, s, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dev(int64_t n, const double* coef, double scale, const double* x, double* y,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n)), dim3(kBlock), 0, s, n, coef, scale, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_dev(int64_t n, const double* num, int invert, const double* x, double* y,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_dev, dim3(nblk(n)), dim3(kBlock), 0, s, n, num, invert, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kBlock), 0, s, n, v, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_vector(int64_t n, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_vector, dim3(nblk(n)), dim3(kBlock), 0, s, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_pressure_project(int nf, int po, int nt, double* x, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_pmean, dim3(nt), dim3(kBlock), 0, s, nf, po, nt, x, work);
+  hipLaunchKernelGGL(k_psub, dim3(nblk((int64_t)(nf - po) * nt)), dim3(kBlock), 0, s, nf, po, nt, x,
+                     work);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_cols(int64_t n, int k, const double* Z, int64_t ldz, const double* y,
+                            double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_cols, dim3(nblk(n)), dim3(kBlock), 0, s, n, k, Z, ldz, y, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, hipStream_t s) {
+  const int64_t n = (int64_t)L.nf * L.N;
+  if (L.NQ == 1)
+    hipLaunchKernelGGL(k_coarse_build<1>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
+                       L.row_ptr, L.col, Jv, B);
+  else
+    hipLaunchKernelGGL(k_coarse_build<2>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
+                       L.row_ptr, L.col, Jv, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, hipStream_t s) {
+  if (m > kMaxCoarse) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dense_inverse, dim3(nmat), dim3(kBlock), 0, s, m, B, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const double* Mv,
+                               const double* e0, const double* e1, const double* b, double* x,
+                               hipStream_t s) {
+  if (L.nf * L.NQ + L.NQ > kMaxCoarse) return hipErrorInvalidValue;
+  const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
+  if (L.NQ == 1)
+    hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.row_ptr,
+                       L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);
+  else
+    hipLaunchKernelGGL(k_coarse_solve<2>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.row_ptr,
+                       L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);
+  return hipGetLastError();
+}
+
+}  // namespace stwr
