@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--vcycles", type=int, default=3)
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -154,23 +155,33 @@ def main():
 
     # algorithmic bytes of one patch-sweep launch: every (patch, slab) inverse
     # block once, the residual of every patch DoF once per slab, the patch
-    # outputs once; see DESIGN for the derivation
+    # outputs once
     s_f = 4 if prec == binding.FP32 else 8
-    H = None
     sweep_ms, sweep_n = kt["sweep"]
     info_bytes = patch_sweep_bytes(prob, s_f)
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
     achieved = info_bytes / (sweep_avg_ms * 1e-3) / 1e9
 
     # one full V(2,2) cycle on all levels (outside the timed region)
-    P.setup_smoothers()
-    vx = P.vec()
-    torch.cuda.synchronize()
-    tv = time.perf_counter()
-    for _ in range(args.vcycles):
-        P.vcycle(b, vx)
-    torch.cuda.synchronize()
-    vc_ms = (time.perf_counter() - tv) / args.vcycles * 1e3
+    vc_ms = None
+    if args.vcycles > 0:
+        P.setup_smoothers()
+        vx = P.vec()
+        torch.cuda.synchronize()
+        tv = time.perf_counter()
+        for _ in range(args.vcycles):
+            P.vcycle(b, vx)
+        torch.cuda.synchronize()
+        vc_ms = (time.perf_counter() - tv) / args.vcycles * 1e3
+    if args.copy_calibration_gib > 0:
+        # a plain device copy of known size, for scaling hardware byte counters
+        nb = int(args.copy_calibration_gib * (1 << 30)) // 8
+        src = torch.ones(nb, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nb * 8} bytes done")
+        del src, dst
 
     out = {
         "metric": "space-time DoFs relaxed/s per WR sweep",
@@ -191,7 +202,9 @@ def main():
                    "levels": args.levels, "st_dofs": n_st, "patches": n_patch,
                    "smoother_prec": args.prec, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (profiled_traffic() if (args.mesh, args.slabs, args.prec) == (128, 64, "fp32")
+                                 else None),
                      "kernel": "k_patch_sweep", "avg_ms": sweep_avg_ms,
                      "algorithmic_bytes": info_bytes},
         "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
@@ -205,6 +218,28 @@ def main():
     print(json.dumps(out), flush=True)
     P.close()
     ctx.close()
+
+
+PROFILE = os.path.join(ROOT, "profiles", "k_patch_sweep_ns_p2p1_dg1_m128_n64_re1000.md")
+
+
+def profiled_traffic() -> int | None:
+    """HBM bytes per k_patch_sweep launch from the committed rocprofv3 byte
+    counters, only while the kernel source is the one that was profiled."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    src = open(os.path.join(ROOT, "paper_2407_13997_amd", "csrc", "patch.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    rec_sha = rec_bytes = None
+    for line in text.splitlines():
+        if line.startswith("patch.hip sha256 (first 16 hex):"):
+            rec_sha = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            rec_bytes = int(line.split(":", 1)[1].strip())
+    return rec_bytes if (rec_sha == sha and rec_bytes) else None
 
 
 def patch_sweep_bytes(prob, s_f: int) -> int:

@@ -230,12 +230,19 @@ void check_opts(const stwr_solver_opts* o) {
 int vw_of(int prec) { return prec == STWR_FP32 ? 4 : 2; }
 int round_up(int m, int w) { return (m + w - 1) / w * w; }
 
+// Elements of one stored inverse slab block of size m (see the patch kernels:
+// P = ceil(m / VW) panels; rows past 64 are split over four lanes each).
+int64_t block_elems(int m, int VW) {
+  const int P = (m + VW - 1) / VW, r1 = std::min(m, 64), r2 = m - r1, K2 = (P + 3) / 4;
+  return (int64_t)P * r1 * VW + (r2 > 0 ? (int64_t)K2 * 4 * r2 * VW : 0);
+}
+
 // Element count of the factor storage of one level at a precision.
 int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
   int64_t tot = 0;
   for (int v = 0; v < H.nv; ++v) {
     const int m = (H.patch_ptr[v + 1] - H.patch_ptr[v]) * NQ;
-    tot += (int64_t)N * m * round_up(m, vw_of(prec));
+    tot += (int64_t)N * block_elems(m, vw_of(prec));
   }
   return tot;
 }
@@ -381,7 +388,7 @@ void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
   L.fac_off.assign(L.H.nv + 1, 0);
   for (int v = 0; v < L.H.nv; ++v) {
     const int m = (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ;
-    L.fac_off[v + 1] = L.fac_off[v] + (int64_t)L.N * m * round_up(m, vw_of(prec));
+    L.fac_off[v + 1] = L.fac_off[v] + (int64_t)L.N * block_elems(m, vw_of(prec));
   }
   HIPCHK(hipMemcpyAsync(L.d_fac_off, L.fac_off.data(), L.fac_off.size() * 8, hipMemcpyHostToDevice, P->s()));
 }

@@ -4,10 +4,11 @@
 // * k_patch_factor: one workgroup per (patch, slab) gathers the slab block
 //   A_{v,n} = R_v J_n R_v^T (nb' = nb (q+1) rows, nb <= 39) from the assembled
 //   operator into LDS and inverts it in place by Gauss-Jordan elimination with
-//   partial pivoting, in FP64 or FP32.  The inverse is stored in column panels
-//   of VW = 16 / sizeof(T) columns: element (r, c) of a block sits at
-//   (c / VW) * (m * VW) + r * VW + c % VW, so a wavefront whose lane r reads a
-//   16-byte vector of row r touches one contiguous 1 KB segment.
+//   partial pivoting, in FP64 or FP32.  The inverse is stored for a 64-lane
+//   wavefront (see block_offset): columns are grouped in panels of
+//   VW = 16 / sizeof(T); rows 0..63 are one row per lane, panel-major, and the
+//   rows past 64 (at most 14) are split over four lanes each, so every 16-byte
+//   vector load of a wavefront reads one contiguous segment and no lane idles.
 // * k_patch_sweep: one wavefront per patch walks the slabs in order (forward
 //   block substitution): gather the residual of the patch DoFs, add the jump
 //   coupling e0 (x) (M_v * (e1 . y_{n-1})), multiply by the stored inverse and
@@ -37,6 +38,23 @@ struct Vec<double> {
 };
 
 __host__ __device__ inline int round_up(int m, int w) { return (m + w - 1) / w * w; }
+
+// Layout of one inverted m x m slab block for the sweep wavefront.
+//   P  = ceil(m / VW) column panels, r1 = min(m, 64) lane rows, r2 = m - r1.
+//   Region 1: (panel q, row r < r1) at (q * r1 + r) * VW.
+//   Region 2: row 64 + rr is handled by lanes 4 rr + s (s = 0..3), which take
+//   panels s, s + 4, s + 8, ...: (k, lane) at P r1 VW + (k * 4 r2 + lane) * VW
+//   for k < K2 = ceil(P / 4).  Padding columns and panels hold zeros.
+struct BlockShape {
+  int m, P, r1, r2, K2, S;
+  __host__ __device__ BlockShape(int m_, int VW) : m(m_) {
+    P = (m + VW - 1) / VW;
+    r1 = m < 64 ? m : 64;
+    r2 = m - r1;
+    K2 = (P + 3) / 4;
+    S = P * r1 * VW + (r2 > 0 ? K2 * 4 * r2 * VW : 0);
+  }
+};
 
 template <int NQ, typename T>
 __global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, PatchView P,
@@ -120,11 +138,23 @@ __global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, Patch
       }
     __syncthreads();
   }
-  const int CP = round_up(m, VW);
-  T* out = fac + P.fac_off[p] + (int64_t)n * m * CP;
-  for (int e = tid; e < m * CP; e += kFacThreads) {
-    const int panel = e / (m * VW), rem = e % (m * VW);
-    const int r = rem / VW, c = panel * VW + rem % VW;
+  const BlockShape sh(m, VW);
+  T* out = fac + P.fac_off[p] + (int64_t)n * sh.S;
+  const int R1 = sh.P * sh.r1 * VW;
+  for (int e = tid; e < sh.S; e += kFacThreads) {
+    int r, c;
+    if (e < R1) {
+      const int q = e / (sh.r1 * VW), rem = e % (sh.r1 * VW);
+      r = rem / VW;
+      c = q * VW + rem % VW;
+    } else {
+      const int e2 = e - R1;
+      const int k = e2 / (4 * sh.r2 * VW), rem = e2 % (4 * sh.r2 * VW);
+      const int lane = rem / VW;
+      const int q = (lane & 3) + 4 * k;
+      r = 64 + lane / 4;
+      c = q < sh.P ? q * VW + rem % VW : m;
+    }
     out[e] = c < m ? A[r][c] : (T)0;
   }
 }
@@ -143,6 +173,17 @@ __global__ __launch_bounds__(256) void k_patch_mass(PatchView P, const double* _
   }
 }
 
+template <typename V, typename T>
+__device__ inline T dotv(const V& w, const T* g) {
+  if constexpr (sizeof(V) / sizeof(T) == 4) return w.x * g[0] + w.y * g[1] + w.z * g[2] + w.w * g[3];
+  else return w.x * g[0] + w.y * g[1];
+}
+
+// One wavefront per patch.  Per slab: issue every load of the slab's inverse
+// block at once (the block does not depend on the previous slab), then form
+// the right-hand side g = r_n + e0 (x) (M_v ylast) in LDS while the loads are
+// in flight, then the matrix-vector product.  The residual values of slab
+// n + 1 are loaded one slab ahead.
 template <int NQ, typename T>
 __global__ __launch_bounds__(64) void k_patch_sweep(LevelView L, PatchView P, const T* __restrict__ fac,
                                                     const double* __restrict__ Mp, double e00,
@@ -151,61 +192,104 @@ __global__ __launch_bounds__(64) void k_patch_sweep(LevelView L, PatchView P, co
                                                     double* __restrict__ Y) {
   constexpr int MAXM = kMaxNb * NQ;
   constexpr int VW = Vec<T>::W;
+  constexpr int MAXP = (MAXM + VW - 1) / VW;
+  constexpr int MAXK2 = (MAXP + 3) / 4;
+  constexpr bool kTwo = MAXM > 64;
   using V = typename Vec<T>::type;
   __shared__ int dofs[kMaxNb];
   __shared__ double Ms[kMaxNbu * kMaxNbu];
-  __shared__ T g[MAXM + 4];
-  __shared__ double ys[MAXM];
+  __shared__ T g[MAXP * VW + 64];
+  __shared__ double ys[MAXM + 64];
   __shared__ double ylast[kMaxNbu];
   const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
-  const int p = blockIdx.x, tid = threadIdx.x;
+  const int p = blockIdx.x, lane = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0, nbu = P.patch_nbu[p];
-  const int m = nb * NQ, CP = round_up(m, VW), N = L.N;
-  for (int i = tid; i < nb; i += 64) dofs[i] = P.patch_dofs[s0 + i];
+  const int m = nb * NQ, N = L.N;
+  const BlockShape sh(m, VW);
+  for (int i = lane; i < nb; i += 64) dofs[i] = P.patch_dofs[s0 + i];
   const double* mp = Mp + P.mp_off[p];
-  for (int e = tid; e < nbu * nbu; e += 64) Ms[e] = mp[e];
-  for (int i = tid; i < nbu; i += 64) ylast[i] = 0.0;
+  for (int e = lane; e < nbu * nbu; e += 64) Ms[e] = mp[e];
+  for (int i = lane; i < nbu; i += 64) ylast[i] = 0.0;
   __syncthreads();
   const T* Ab = fac + P.fac_off[p];
   double* yout = Y + P.y_off[p];
+  // the (at most two) rows whose right-hand side this lane forms
+  const int rowA = lane, rowB = lane + 64;
+  const bool hasA = rowA < m, hasB = kTwo && rowB < m;
+  const int64_t baseA = hasA ? (int64_t)dofs[rowA / NQ] * N * NQ + rowA % NQ : 0;
+  const int64_t baseB = hasB ? (int64_t)dofs[rowB / NQ] * N * NQ + rowB % NQ : 0;
+  double rA = hasA ? r[baseA] : 0.0, rB = hasB ? r[baseB] : 0.0;
+  const int R1 = sh.P * sh.r1 * VW;
+  const int quarter = lane & 3;
   for (int n = 0; n < N; ++n) {
-    for (int row = tid; row < CP; row += 64) {
-      T v = (T)0;
-      if (row < m) {
-        const int i = row / NQ, a = row % NQ;
-        double rv = r[((int64_t)dofs[i] * N + n) * NQ + a];
-        if (n > 0 && i < nbu) {
-          double acc = 0.0;
-          for (int j = 0; j < nbu; ++j) acc += Ms[i * nbu + j] * ylast[j];
-          rv += e0[a] * acc;
-        }
-        v = (T)rv;
+    const T* blk = Ab + (int64_t)n * sh.S;
+    V a1[MAXP];
+    V a2[kTwo ? MAXK2 : 1];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q)
+      if (q < sh.P && lane < sh.r1) a1[q] = *reinterpret_cast<const V*>(blk + (q * sh.r1 + lane) * VW);
+    if constexpr (kTwo) {
+#pragma unroll
+      for (int k = 0; k < MAXK2; ++k)
+        if (k < sh.K2 && lane < 4 * sh.r2)
+          a2[k] = *reinterpret_cast<const V*>(blk + R1 + (k * 4 * sh.r2 + lane) * VW);
+    }
+    double rA_next = 0.0, rB_next = 0.0;
+    if (n + 1 < N) {
+      if (hasA) rA_next = r[baseA + (int64_t)(n + 1) * NQ];
+      if (hasB) rB_next = r[baseB + (int64_t)(n + 1) * NQ];
+    }
+    double gA = rA, gB = rB;
+    if (n > 0) {
+      if (hasA && rowA / NQ < nbu) {
+        const double* mrow = Ms + (rowA / NQ) * nbu;
+        double acc = 0.0;
+        for (int j = 0; j < nbu; ++j) acc += mrow[j] * ylast[j];
+        gA += e0[rowA % NQ] * acc;
       }
-      g[row] = v;
+      if (hasB && rowB / NQ < nbu) {
+        const double* mrow = Ms + (rowB / NQ) * nbu;
+        double acc = 0.0;
+        for (int j = 0; j < nbu; ++j) acc += mrow[j] * ylast[j];
+        gB += e0[rowB % NQ] * acc;
+      }
+    }
+    if (rowA < sh.P * VW) g[rowA] = hasA ? (T)gA : (T)0;
+    if (rowB < sh.P * VW) g[rowB] = hasB ? (T)gB : (T)0;
+    __syncthreads();
+    T acc1 = (T)0;
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q)
+      if (q < sh.P) acc1 += dotv<V, T>(a1[q], g + q * VW);
+    if (lane < sh.r1) {
+      ys[lane] = (double)acc1;
+      yout[(int64_t)n * m + lane] = (double)acc1;
+    }
+    if constexpr (kTwo) {
+      T acc2 = (T)0;
+#pragma unroll
+      for (int k = 0; k < MAXK2; ++k) {
+        const int q = quarter + 4 * k;
+        if (k < sh.K2 && q < sh.P) acc2 += dotv<V, T>(a2[k], g + q * VW);
+      }
+      acc2 += __shfl_xor(acc2, 1);
+      acc2 += __shfl_xor(acc2, 2);
+      if (lane < 4 * sh.r2 && quarter == 0) {
+        const int row = 64 + lane / 4;
+        ys[row] = (double)acc2;
+        yout[(int64_t)n * m + row] = (double)acc2;
+      }
     }
     __syncthreads();
-    const T* An = Ab + (int64_t)n * m * CP;
-    for (int row = tid; row < m; row += 64) {
-      T acc = (T)0;
-      for (int pc = 0; pc < CP / VW; ++pc) {
-        const V w = *reinterpret_cast<const V*>(An + (int64_t)pc * m * VW + row * VW);
-        if constexpr (VW == 4) {
-          acc += w.x * g[pc * 4] + w.y * g[pc * 4 + 1] + w.z * g[pc * 4 + 2] + w.w * g[pc * 4 + 3];
-        } else {
-          acc += w.x * g[pc * 2] + w.y * g[pc * 2 + 1];
-        }
-      }
-      ys[row] = (double)acc;
-      yout[(int64_t)n * m + row] = (double)acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < nbu; i += 64) {
+    for (int i = lane; i < nbu; i += 64) {
       double v = 0.0;
       for (int b = 0; b < NQ; ++b) v += e1[b] * ys[i * NQ + b];
       ylast[i] = v;
     }
     __syncthreads();
+    rA = rA_next;
+    rB = rB_next;
   }
 }
 

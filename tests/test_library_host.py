@@ -1,0 +1,91 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol the header
+declares, and its host-built structure matches the paper's closed-form
+counts (Sec. 3.1, App. A.1) and the oracle's independent construction."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def lib():
+    from paper_2407_13997_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libstwr.so is not built (run __graft_entry__.build())")
+    return binding
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "stwr.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(stwr_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    b = lib()
+    L = b.load()
+    names = declared_symbols()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(b.EXPORTED) == names
+
+
+@pytest.mark.parametrize("M", [2, 4, 8, 16])
+def test_mesh_info_counts(M):
+    b = lib()
+    info = b.mesh_info(M)
+    n_free, nn, nv, nc = info[:4]
+    assert nn == (2 * M + 1) ** 2 and nv == (M + 1) ** 2 and nc == 2 * M * M
+    assert n_free == 2 * (2 * M - 1) ** 2 + (M + 1) ** 2
+    Mx = M + 1
+    assert 2 * nn + nv == 3 * (Mx - 1) ** 2 + (4 * (Mx - 1) ** 2 + 6 * (Mx - 1)) + 2 * (Mx - 1) ** 2 + 4 * (Mx - 1) + 3
+    assert info[5] == nv
+    hist = info[12:52]
+    assert hist.sum() == nv
+    if M >= 4:
+        # interior patch: 39 DoFs, 652 + 2 x 38 = 728 nonzeros (App. A.1)
+        assert info[7] == 39
+        assert (info[8], info[9], info[10]) == (652, 38, 38)
+        assert info[8] + info[9] + info[10] == 12 + 96 + 240 + 252 + 128
+        assert hist[39] == (M - 3) ** 2
+
+
+def test_host_patches_match_oracle():
+    b = lib()
+    from oracle.mesh import Mesh
+    for M in (4, 8):
+        P = Mesh(M).patches()
+        hist = np.bincount([len(p) for p in P], minlength=40)
+        assert np.array_equal(b.mesh_info(M)[12:52], hist)
+        assert b.mesh_info(M)[6] == sum(len(p) for p in P)
+
+
+def test_problem_bytes_and_argument_checks():
+    b = lib()
+    import stwr_workloads as w
+    p0 = b.problem_bytes(w.config_problem(0))
+    p1 = b.problem_bytes(w.config_problem(1))
+    assert 0 < p0 < p1
+    o = b.default_opts()
+    o.smoother_prec = b.FP32
+    assert b.problem_bytes(w.config_problem(1), o) < p1
+    bad = w.config_problem(0)
+    bad.q = 3
+    with pytest.raises(b.StwrError) as e:
+        b.problem_bytes(bad)
+    assert e.value.code == -1
+    bad = w.config_problem(0)
+    bad.n_levels = 4   # 4 / 2^3 is not a mesh
+    with pytest.raises(b.StwrError):
+        b.problem_bytes(bad)
+
+
+def test_null_handles_are_rejected():
+    L = lib().load()
+    assert L.stwr_problem_sizes(None, 0, None, None, None) == -1
+    assert L.stwr_apply(None, 0, None, None) == -1
+    assert L.stwr_ctx_set_timing(None, 1) == -1
+    assert L.stwr_problem_destroy(None) == 0
