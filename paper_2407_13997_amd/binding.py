@@ -81,11 +81,13 @@ class StwrError(RuntimeError):
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load the library; raises if it has not been built."""
+def load(path: str | None = None):
+    """Load the library (``STWR_LIBRARY`` overrides the in-tree path); raises if
+    it has not been built."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("STWR_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with python -m paper_2407_13997_amd.build")
     lib = ctypes.CDLL(path)

@@ -230,12 +230,9 @@ void check_opts(const stwr_solver_opts* o) {
 int vw_of(int prec) { return prec == STWR_FP32 ? 4 : 2; }
 int round_up(int m, int w) { return (m + w - 1) / w * w; }
 
-// Elements of one stored inverse slab block of size m (see the patch kernels:
-// P = ceil(m / VW) panels; rows past 64 are split over four lanes each).
-int64_t block_elems(int m, int VW) {
-  const int P = (m + VW - 1) / VW, r1 = std::min(m, 64), r2 = m - r1, K2 = (P + 3) / 4;
-  return (int64_t)P * r1 * VW + (r2 > 0 ? (int64_t)K2 * 4 * r2 * VW : 0);
-}
+// Elements of one stored inverse slab block of size m (layout shared with the
+// patch kernels).
+int64_t block_elems(int m, int VW) { return BlockLayout(m, VW).size(); }
 
 // Element count of the factor storage of one level at a precision.
 int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
@@ -350,6 +347,13 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     pv.patch_nz_off = L.patch_nz_off; pv.patch_nz = L.patch_nz; pv.fac_off = L.d_fac_off;
     pv.y_off = L.d_y_off; pv.mp_off = L.d_mp_off; pv.dof_ptr = L.dof_ptr; pv.dof_slot = L.dof_slot;
     pv.slot_patch = L.slot_patch;
+    std::vector<int> order;
+    for (int v = 0; v < H.nv; ++v)
+      if (H.patch_ptr[v + 1] - H.patch_ptr[v] == kMaxNb) order.push_back(v);
+    pv.n_full = (int)order.size();
+    for (int v = 0; v < H.nv; ++v)
+      if (H.patch_ptr[v + 1] - H.patch_ptr[v] != kMaxNb) order.push_back(v);
+    pv.order = P->upload(order);
     L.P_ptr = P->upload(L.Tr.p_ptr);
     L.P_col = P->upload(L.Tr.p_col);
     L.P_val = P->upload(L.Tr.p_val);

@@ -47,6 +47,50 @@ struct PatchView {
   const int* dof_ptr;
   const int* dof_slot;
   const int* slot_patch;
+  const int* order;         // n_patch: interior (full-size) patches first, then the rest
+  int n_full;               // number of full-size patches at the front of order
+};
+
+// Storage of one inverted m x m slab block for the patch sweep, in T-typed
+// elements.  Columns are grouped in panels of VW = 16 / sizeof(T) (one 16-byte
+// vector); the panels are dealt to wavefronts, at most panels_per_wave each.
+// Inside wavefront w's share (PH_w panels): rows r < r1 = min(m, 64) hold
+// (panel ql, row r) at (ql * r1 + r) * VW, so lane r of a 16-byte load reads
+// one contiguous segment; rows 64 + rr (rr < r2 = m - r1) are split over four
+// lanes 4 rr + s, lane s taking local panels s, s + 4, ..., stored as (k, lane)
+// at PH_w r1 VW + (k * 4 r2 + lane) * VW, k < ceil(PH_w / 4).  Padding is zero.
+// FP32 blocks (at most 20 panels) go to one wavefront; FP64 blocks are dealt
+// ten panels per wavefront.
+__host__ __device__ constexpr int panels_per_wave(int vw) { return vw == 4 ? 20 : 10; }
+
+struct BlockLayout {
+  int m, VW, P, r1, r2, waves, ppw;
+  __host__ __device__ BlockLayout(int m_, int vw_) : m(m_), VW(vw_) {
+    ppw = panels_per_wave(VW);
+    P = (m + VW - 1) / VW;
+    r1 = m < 64 ? m : 64;
+    r2 = m - r1;
+    waves = (P + ppw - 1) / ppw;
+  }
+  __host__ __device__ int panels(int w) const {
+    const int p = P - w * ppw;
+    return p < 0 ? 0 : (p > ppw ? ppw : p);
+  }
+  __host__ __device__ int k2(int w) const { return r2 > 0 ? (panels(w) + 3) / 4 : 0; }
+  __host__ __device__ int share(int w) const { return (panels(w) * r1 + k2(w) * 4 * r2) * VW; }
+  __host__ __device__ int offset(int w) const {
+    int o = 0;
+    for (int v = 0; v < w; ++v) o += share(v);
+    return o;
+  }
+  __host__ __device__ int size() const { return offset(waves); }
+  // element offset of (r, c), r, c < m
+  __host__ __device__ int at(int r, int c) const {
+    const int q = c / VW, w = q / ppw, ql = q % ppw;
+    if (r < r1) return offset(w) + (ql * r1 + r) * VW + c % VW;
+    const int lane = (r - 64) * 4 + ql % 4, k = ql / 4;
+    return offset(w) + panels(w) * r1 * VW + (k * 4 * r2 + lane) * VW + c % VW;
+  }
 };
 
 // ---- assembly ---------------------------------------------------------------

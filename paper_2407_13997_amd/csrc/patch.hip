@@ -39,23 +39,6 @@ struct Vec<double> {
 
 __host__ __device__ inline int round_up(int m, int w) { return (m + w - 1) / w * w; }
 
-// Layout of one inverted m x m slab block for the sweep wavefront.
-//   P  = ceil(m / VW) column panels, r1 = min(m, 64) lane rows, r2 = m - r1.
-//   Region 1: (panel q, row r < r1) at (q * r1 + r) * VW.
-//   Region 2: row 64 + rr is handled by lanes 4 rr + s (s = 0..3), which take
-//   panels s, s + 4, s + 8, ...: (k, lane) at P r1 VW + (k * 4 r2 + lane) * VW
-//   for k < K2 = ceil(P / 4).  Padding columns and panels hold zeros.
-struct BlockShape {
-  int m, P, r1, r2, K2, S;
-  __host__ __device__ BlockShape(int m_, int VW) : m(m_) {
-    P = (m + VW - 1) / VW;
-    r1 = m < 64 ? m : 64;
-    r2 = m - r1;
-    K2 = (P + 3) / 4;
-    S = P * r1 * VW + (r2 > 0 ? K2 * 4 * r2 * VW : 0);
-  }
-};
-
 template <int NQ, typename T>
 __global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, PatchView P,
                                                               const double* __restrict__ Jv,
@@ -138,24 +121,13 @@ __global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, Patch
       }
     __syncthreads();
   }
-  const BlockShape sh(m, VW);
-  T* out = fac + P.fac_off[p] + (int64_t)n * sh.S;
-  const int R1 = sh.P * sh.r1 * VW;
-  for (int e = tid; e < sh.S; e += kFacThreads) {
-    int r, c;
-    if (e < R1) {
-      const int q = e / (sh.r1 * VW), rem = e % (sh.r1 * VW);
-      r = rem / VW;
-      c = q * VW + rem % VW;
-    } else {
-      const int e2 = e - R1;
-      const int k = e2 / (4 * sh.r2 * VW), rem = e2 % (4 * sh.r2 * VW);
-      const int lane = rem / VW;
-      const int q = (lane & 3) + 4 * k;
-      r = 64 + lane / 4;
-      c = q < sh.P ? q * VW + rem % VW : m;
-    }
-    out[e] = c < m ? A[r][c] : (T)0;
+  const BlockLayout lay(m, VW);
+  T* out = fac + P.fac_off[p] + (int64_t)n * lay.size();
+  for (int e = tid; e < lay.size(); e += kFacThreads) out[e] = (T)0;
+  __syncthreads();
+  for (int e = tid; e < m * m; e += kFacThreads) {
+    const int r = e / m, c = e % m;
+    out[lay.at(r, c)] = A[r][c];
   }
 }
 
@@ -179,118 +151,281 @@ __device__ inline T dotv(const V& w, const T* g) {
   else return w.x * g[0] + w.y * g[1];
 }
 
-// One wavefront per patch.  Per slab: issue every load of the slab's inverse
-// block at once (the block does not depend on the previous slab), then form
-// the right-hand side g = r_n + e0 (x) (M_v ylast) in LDS while the loads are
-// in flight, then the matrix-vector product.  The residual values of slab
-// n + 1 are loaded one slab ahead.
-template <int NQ, typename T>
-__global__ __launch_bounds__(64) void k_patch_sweep(LevelView L, PatchView P, const T* __restrict__ fac,
-                                                    const double* __restrict__ Mp, double e00,
-                                                    double e01, double e10, double e11,
-                                                    const double* __restrict__ r,
-                                                    double* __restrict__ Y) {
+// FP32 sweep, one wavefront per patch (every FP32 block fits one wavefront's
+// registers).  The right-hand side stays distributed, one value per lane
+// (rows lane and 64 + lane); the lane-per-row part of the product broadcasts
+// it with v_readlane into scalar operands, so it needs neither LDS nor
+// replicated registers, and only the rows past 64 read it from LDS.  All
+// loads of a slab block are issued before the right-hand side is formed;
+// the residual values of slab n + 1 are loaded one slab ahead.  The jump
+// coupling works in FP32 from a transposed copy of the patch mass block
+// (conflict-free LDS reads).  FULL = true
+// is the interior patch (nb = 39), whose sizes are all compile-time
+// constants; FULL = false handles the smaller boundary patches.  Panels past
+// a block's last one re-read its last panel: their columns meet zeros of
+// the right-hand side, so they add nothing.
+template <int NQ, bool FULL>
+__global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P, int first,
+                                                       const float* __restrict__ fac,
+                                                       const double* __restrict__ Mp, double e00,
+                                                       double e01, const double* __restrict__ r,
+                                                       double* __restrict__ Y) {
+  constexpr int MAXM = kMaxNb * NQ;
+  constexpr int VW = 4;
+  constexpr int MAXP = (MAXM + VW - 1) / VW;   // 10 or 20 panels
+  constexpr int K2 = (MAXP + 3) / 4;
+  constexpr bool kTwo = MAXM > 64;
+  constexpr int R1F = MAXM < 64 ? MAXM : 64, R2F = MAXM - R1F;
+  __shared__ int dofs[kMaxNb];
+  __shared__ float MsT[kMaxNbu * kMaxNbu];     // patch mass block, transposed
+  __shared__ float g[MAXP * VW + 4];
+  __shared__ float ylast[kMaxNbu];
+  __shared__ float mj[kMaxNbu];
+  const float e0[2] = {(float)e00, (float)e01};
+  const int p = P.order[first + blockIdx.x], lane = threadIdx.x;
+  const int s0 = P.patch_ptr[p];
+  const int nb = FULL ? kMaxNb : P.patch_ptr[p + 1] - s0;
+  const int nbu = FULL ? kMaxNbu : P.patch_nbu[p];
+  const int m = nb * NQ, N = L.N;
+  const BlockLayout lay(m, VW);
+  const int PH = FULL ? MAXP : lay.P;
+  const int r1 = FULL ? R1F : lay.r1, r2 = FULL ? R2F : lay.r2;
+  const int nk2 = FULL ? (R2F > 0 ? K2 : 0) : lay.k2(0);
+  const int S = FULL ? (MAXP * R1F + (R2F > 0 ? K2 * 4 * R2F : 0)) * VW : lay.size();
+  for (int i = lane; i < nb; i += 64) dofs[i] = P.patch_dofs[s0 + i];
+  const double* mp = Mp + P.mp_off[p];
+  for (int e = lane; e < nbu * nbu; e += 64) MsT[(e % nbu) * nbu + e / nbu] = (float)mp[e];
+  for (int i = lane; i < kMaxNbu; i += 64) mj[i] = 0.0f;
+  for (int i = lane; i < MAXP * VW + 4; i += 64) g[i] = 0.0f;
+  __syncthreads();
+  const float* Ab = fac + P.fac_off[p];
+  double* yout = Y + P.y_off[p];
+  const unsigned row1 = lane < r1 ? lane : 0;
+  const unsigned base1 = row1 * VW, step1 = r1 * VW;
+  const unsigned lane2 = lane < 4 * r2 ? lane : 0;
+  const unsigned base2 = PH * r1 * VW + lane2 * VW, step2 = 4 * r2 * VW;
+  const int lastq = PH - 1, lastk = nk2 > 0 ? nk2 - 1 : 0;
+  const int rowA = lane, rowB = lane + 64;
+  const bool hasA = rowA < m, hasB = kTwo && rowB < m;
+  const int64_t bA = hasA ? (int64_t)dofs[rowA / NQ] * N * NQ + rowA % NQ : 0;
+  const int64_t bB = hasB ? (int64_t)dofs[rowB / NQ] * N * NQ + rowB % NQ : 0;
+  const int iA = rowA / NQ, iB = rowB / NQ;
+  const int quarter = lane & 3;
+  float4 a1[MAXP];
+  float4 a2[kTwo ? K2 : 1];
+  auto issue = [&](int n) {
+    const float* blk = Ab + (int64_t)n * S;
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+      const unsigned qq = FULL ? q : (q < lastq ? q : lastq);
+      a1[q] = *reinterpret_cast<const float4*>(blk + base1 + qq * step1);
+    }
+    if constexpr (kTwo) {
+#pragma unroll
+      for (int k = 0; k < K2; ++k) {
+        const unsigned kk = FULL ? k : (k < lastk ? k : lastk);
+        a2[k] = *reinterpret_cast<const float4*>(blk + base2 + kk * step2);
+      }
+    }
+  };
+  double rA = hasA ? r[bA] : 0.0, rB = hasB ? r[bB] : 0.0;
+  for (int n = 0; n < N; ++n) {
+    issue(n);
+    const double rAn = (hasA && n + 1 < N) ? r[bA + (int64_t)(n + 1) * NQ] : 0.0;
+    const double rBn = (hasB && n + 1 < N) ? r[bB + (int64_t)(n + 1) * NQ] : 0.0;
+    float gA = 0.0f, gB = 0.0f;
+    if (hasA) gA = (float)rA + ((n > 0 && iA < nbu) ? e0[rowA % NQ] * mj[iA] : 0.0f);
+    if (hasB) gB = (float)rB + ((n > 0 && iB < nbu) ? e0[rowB % NQ] * mj[iB] : 0.0f);
+    if constexpr (kTwo) {
+      g[rowA] = gA;
+      if (rowB < MAXP * VW) g[rowB] = gB;
+    }
+    // rows r < r1: g broadcast lane by lane
+    float acc1 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int col = 4 * q + c;
+        const float gc = col < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gA), col))
+                                  : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gB), col - 64));
+        acc1 += (c == 0 ? a1[q].x : c == 1 ? a1[q].y : c == 2 ? a1[q].z : a1[q].w) * gc;
+      }
+      // keep each panel's broadcasts next to their use (bounded scalar registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    float acc2 = 0.0f;
+    if constexpr (kTwo) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < K2; ++k) {
+        const float* gq = g + (quarter + 4 * k) * VW;
+        acc2 += a2[k].x * gq[0] + a2[k].y * gq[1] + a2[k].z * gq[2] + a2[k].w * gq[3];
+      }
+      acc2 += __shfl_xor(acc2, 1);
+      acc2 += __shfl_xor(acc2, 2);
+    }
+    if (lane < r1) {
+      yout[(int64_t)n * m + lane] = (double)acc1;
+      if (lane % NQ == NQ - 1) ylast[lane / NQ] = acc1;
+    }
+    if constexpr (kTwo) {
+      if (lane < 4 * r2 && quarter == 0) {
+        const int row = 64 + lane / 4;
+        yout[(int64_t)n * m + row] = (double)acc2;
+        if (row % NQ == NQ - 1) ylast[row / NQ] = acc2;
+      }
+    }
+    __syncthreads();
+    // jump coupling of the next slab: mj = M_v y_n(end of slab); the slab end
+    // value is the last temporal node (right Radau nodes)
+    if (lane < nbu) {
+      float acc = 0.0f;
+#pragma unroll 8
+      for (int j = 0; j < nbu; ++j) acc += MsT[j * nbu + lane] * ylast[j];
+      mj[lane] = acc;
+    }
+    __syncthreads();
+    rA = rAn;
+    rB = rBn;
+  }
+}
+
+// One workgroup per patch, WAVES wavefronts, each owning at most
+// kPanelsPerWave column panels of every slab block (see BlockLayout).  The
+// slabs are walked in order (forward block substitution).  Software pipeline:
+// while slab n is formed and multiplied, the block of slab n + 1 is already in
+// flight into a second register set (every load is unconditional, with
+// clamped addresses, so the wait counts leave the prefetch outstanding), and
+// the residual values of slab n + 1 are loaded too.  The jump coupling
+// mj = M_v (e1 . y_{n-1}) is formed once per velocity DoF at the end of the
+// previous slab.
+template <int NQ, typename T, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchView P,
+                                                            const T* __restrict__ fac,
+                                                            const double* __restrict__ Mp,
+                                                            double e00, double e01, double e10,
+                                                            double e11, const double* __restrict__ r,
+                                                            double* __restrict__ Y) {
   constexpr int MAXM = kMaxNb * NQ;
   constexpr int VW = Vec<T>::W;
   constexpr int MAXP = (MAXM + VW - 1) / VW;
-  constexpr int MAXK2 = (MAXP + 3) / 4;
+  constexpr int PW = panels_per_wave(VW);
+  constexpr int K2 = (PW + 3) / 4;
   constexpr bool kTwo = MAXM > 64;
   using V = typename Vec<T>::type;
   __shared__ int dofs[kMaxNb];
   __shared__ double Ms[kMaxNbu * kMaxNbu];
-  __shared__ T g[MAXP * VW + 64];
-  __shared__ double ys[MAXM + 64];
-  __shared__ double ylast[kMaxNbu];
+  __shared__ T g[WAVES * PW * VW];
+  __shared__ double part[WAVES][MAXM];
+  __shared__ double ys[MAXM];
+  __shared__ double mj[kMaxNbu];
   const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
-  const int p = blockIdx.x, lane = threadIdx.x;
+  const int p = blockIdx.x, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0, nbu = P.patch_nbu[p];
   const int m = nb * NQ, N = L.N;
-  const BlockShape sh(m, VW);
-  for (int i = lane; i < nb; i += 64) dofs[i] = P.patch_dofs[s0 + i];
+  const BlockLayout lay(m, VW);
+  const int PH = lay.panels(w), r1 = lay.r1, r2 = lay.r2;
+  for (int i = tid; i < nb; i += 64 * WAVES) dofs[i] = P.patch_dofs[s0 + i];
   const double* mp = Mp + P.mp_off[p];
-  for (int e = lane; e < nbu * nbu; e += 64) Ms[e] = mp[e];
-  for (int i = lane; i < nbu; i += 64) ylast[i] = 0.0;
+  for (int e = tid; e < nbu * nbu; e += 64 * WAVES) Ms[e] = mp[e];
+  for (int i = tid; i < kMaxNbu; i += 64 * WAVES) mj[i] = 0.0;
+  for (int i = tid; i < WAVES * PW * VW; i += 64 * WAVES) g[i] = (T)0;
   __syncthreads();
+  const int S = lay.size();
   const T* Ab = fac + P.fac_off[p];
   double* yout = Y + P.y_off[p];
-  // the (at most two) rows whose right-hand side this lane forms
-  const int rowA = lane, rowB = lane + 64;
-  const bool hasA = rowA < m, hasB = kTwo && rowB < m;
-  const int64_t baseA = hasA ? (int64_t)dofs[rowA / NQ] * N * NQ + rowA % NQ : 0;
-  const int64_t baseB = hasB ? (int64_t)dofs[rowB / NQ] * N * NQ + rowB % NQ : 0;
-  double rA = hasA ? r[baseA] : 0.0, rB = hasB ? r[baseB] : 0.0;
-  const int R1 = sh.P * sh.r1 * VW;
+  // this lane's load offsets inside a block (clamped to valid elements)
+  const int wbase = lay.offset(w);
+  const int row1 = lane < r1 ? lane : 0;
+  const int off2 = wbase + PH * r1 * VW;
+  const int lane2 = lane < 4 * r2 ? lane : 0;
+  // element offsets: region 1 = base1 + q * step1 (q < PH), region 2 = base2 + k * step2
+  const int base1 = wbase + row1 * VW, step1 = r1 * VW;
+  const int base2 = off2 + lane2 * VW, step2 = 4 * r2 * VW, nk2 = lay.k2(w);
+#define O1(q) ((q) < PH ? base1 + (q) * step1 : 0)
+#define O2(k) ((kTwo && (k) < nk2) ? base2 + (k) * step2 : 0)
+  // the row whose right-hand side this thread forms
+  const bool hasRow = tid < m;
+  const int64_t rbase = hasRow ? (int64_t)dofs[tid / NQ] * N * NQ + tid % NQ : 0;
+  const int ia = tid / NQ, aa = tid % NQ;
+  V cur1[PW], nxt1[PW], cur2[K2], nxt2[K2];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) cur1[q] = *reinterpret_cast<const V*>(Ab + O1(q));
+  if constexpr (kTwo) {
+#pragma unroll
+    for (int k = 0; k < K2; ++k) cur2[k] = *reinterpret_cast<const V*>(Ab + O2(k));
+  }
+  double rcur = hasRow ? r[rbase] : 0.0;
   const int quarter = lane & 3;
   for (int n = 0; n < N; ++n) {
-    const T* blk = Ab + (int64_t)n * sh.S;
-    V a1[MAXP];
-    V a2[kTwo ? MAXK2 : 1];
+    const T* nblk = Ab + (int64_t)(n + 1 < N ? n + 1 : n) * S;
 #pragma unroll
-    for (int q = 0; q < MAXP; ++q)
-      if (q < sh.P && lane < sh.r1) a1[q] = *reinterpret_cast<const V*>(blk + (q * sh.r1 + lane) * VW);
+    for (int q = 0; q < PW; ++q) nxt1[q] = *reinterpret_cast<const V*>(nblk + O1(q));
     if constexpr (kTwo) {
 #pragma unroll
-      for (int k = 0; k < MAXK2; ++k)
-        if (k < sh.K2 && lane < 4 * sh.r2)
-          a2[k] = *reinterpret_cast<const V*>(blk + R1 + (k * 4 * sh.r2 + lane) * VW);
+      for (int k = 0; k < K2; ++k) nxt2[k] = *reinterpret_cast<const V*>(nblk + O2(k));
     }
-    double rA_next = 0.0, rB_next = 0.0;
-    if (n + 1 < N) {
-      if (hasA) rA_next = r[baseA + (int64_t)(n + 1) * NQ];
-      if (hasB) rB_next = r[baseB + (int64_t)(n + 1) * NQ];
+    const double rnext = (hasRow && n + 1 < N) ? r[rbase + (int64_t)(n + 1) * NQ] : 0.0;
+    if (hasRow) {
+      double gv = rcur;
+      if (n > 0 && ia < nbu) gv += e0[aa] * mj[ia];
+      g[tid] = (T)gv;
     }
-    double gA = rA, gB = rB;
-    if (n > 0) {
-      if (hasA && rowA / NQ < nbu) {
-        const double* mrow = Ms + (rowA / NQ) * nbu;
-        double acc = 0.0;
-        for (int j = 0; j < nbu; ++j) acc += mrow[j] * ylast[j];
-        gA += e0[rowA % NQ] * acc;
-      }
-      if (hasB && rowB / NQ < nbu) {
-        const double* mrow = Ms + (rowB / NQ) * nbu;
-        double acc = 0.0;
-        for (int j = 0; j < nbu; ++j) acc += mrow[j] * ylast[j];
-        gB += e0[rowB % NQ] * acc;
-      }
-    }
-    if (rowA < sh.P * VW) g[rowA] = hasA ? (T)gA : (T)0;
-    if (rowB < sh.P * VW) g[rowB] = hasB ? (T)gB : (T)0;
     __syncthreads();
+    // this wavefront's share of y = A_n^{-1} g
+    const T* gw = g + w * PW * VW;
     T acc1 = (T)0;
 #pragma unroll
-    for (int q = 0; q < MAXP; ++q)
-      if (q < sh.P) acc1 += dotv<V, T>(a1[q], g + q * VW);
-    if (lane < sh.r1) {
-      ys[lane] = (double)acc1;
-      yout[(int64_t)n * m + lane] = (double)acc1;
+    for (int q = 0; q < PW; ++q) {
+      const T d = dotv<V, T>(cur1[q], gw + q * VW);
+      acc1 += q < PH ? d : (T)0;
     }
+    if (lane < r1) part[w][lane] = (double)acc1;
     if constexpr (kTwo) {
       T acc2 = (T)0;
 #pragma unroll
-      for (int k = 0; k < MAXK2; ++k) {
-        const int q = quarter + 4 * k;
-        if (k < sh.K2 && q < sh.P) acc2 += dotv<V, T>(a2[k], g + q * VW);
+      for (int k = 0; k < K2; ++k) {
+        const int ql = quarter + 4 * k;
+        const T d = dotv<V, T>(cur2[k], gw + (ql < PW ? ql : 0) * VW);
+        acc2 += ql < PH ? d : (T)0;
       }
       acc2 += __shfl_xor(acc2, 1);
       acc2 += __shfl_xor(acc2, 2);
-      if (lane < 4 * sh.r2 && quarter == 0) {
-        const int row = 64 + lane / 4;
-        ys[row] = (double)acc2;
-        yout[(int64_t)n * m + row] = (double)acc2;
+      if (lane < 4 * r2 && quarter == 0) part[w][64 + lane / 4] = (double)acc2;
+    }
+    __syncthreads();
+    if (hasRow) {
+      double y = 0.0;
+#pragma unroll
+      for (int v = 0; v < WAVES; ++v) y += v < lay.waves ? part[v][tid] : 0.0;
+      ys[tid] = y;
+      yout[(int64_t)n * m + tid] = y;
+    }
+    __syncthreads();
+    if (tid < nbu) {
+      const double* mrow = Ms + tid * nbu;
+      double acc = 0.0;
+#pragma unroll 2
+      for (int j = 0; j < nbu; ++j) {
+        double yl = 0.0;
+        for (int b = 0; b < NQ; ++b) yl += e1[b] * ys[j * NQ + b];
+        acc += mrow[j] * yl;
       }
+      mj[tid] = acc;
     }
     __syncthreads();
-    for (int i = lane; i < nbu; i += 64) {
-      double v = 0.0;
-      for (int b = 0; b < NQ; ++b) v += e1[b] * ys[i * NQ + b];
-      ylast[i] = v;
+#pragma unroll
+    for (int q = 0; q < PW; ++q) cur1[q] = nxt1[q];
+    if constexpr (kTwo) {
+#pragma unroll
+      for (int k = 0; k < K2; ++k) cur2[k] = nxt2[k];
     }
-    __syncthreads();
-    rA = rA_next;
-    rB = rB_next;
+    rcur = rnext;
   }
+#undef O1
+#undef O2
 }
 
 template <int NQ>
@@ -349,13 +484,22 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, double* Y, hipStream_t s) {
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
-  dim3 grid(P.n_patch), block(64);
+  dim3 grid(P.n_patch);
+  // wavefronts per patch = panels of the largest block / kPanelsPerWave
   if (prec == 1) {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, float>), grid, block, 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
-    else hipLaunchKernelGGL((k_patch_sweep<2, float>), grid, block, 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
+    // the FP32 kernel reads the slab end value as the last temporal node
+    if (e1[L.NQ - 1] != 1.0 || (L.NQ > 1 && e1[0] != 0.0)) return hipErrorInvalidValue;
+    const int nfull = P.n_full, nrest = P.n_patch - P.n_full;
+    if (L.NQ == 1) {
+      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<1, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, Y);
+      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<1, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, Y);
+    } else {
+      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<2, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, Y);
+      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<2, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, Y);
+    }
   } else {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double>), grid, block, 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
-    else hipLaunchKernelGGL((k_patch_sweep<2, double>), grid, block, 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
+    else hipLaunchKernelGGL((k_patch_sweep<2, double, 4>), grid, dim3(256), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
   }
   return hipGetLastError();
 }
