@@ -63,10 +63,12 @@ class Level:
 
     def dirichlet_full(self):
         """Exact velocity at every P2 node and temporal node: (nn, N, nq) x 2."""
-        t = self.node_times()[None, :, :]
-        x = self.mesh.nxy[:, 0][:, None, None]
-        y = self.mesh.nxy[:, 1][:, None, None]
-        return self.mms.velocity(t, x, y)
+        if getattr(self, "_dir", None) is None:
+            t = self.node_times()[None, :, :]
+            x = self.mesh.nxy[:, 0][:, None, None]
+            y = self.mesh.nxy[:, 1][:, None, None]
+            self._dir = self.mms.velocity(t, x, y)
+        return self._dir
 
     def initial_full(self):
         """P2 interpolant of the velocity at t = 0 on every node: (nn,) x 2."""

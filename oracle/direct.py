@@ -19,21 +19,28 @@ import scipy.sparse.linalg as spla
 
 
 def solve_slab_by_slab(level, tol=1e-13, maxit=30):
+    """Newton per slab until ||F_n|| <= tol * max(1, ||U_n||) or it stalls at
+    rounding level (no decrease by a factor 2 once below 1e-10 relative)."""
     nf, N, nq = level.n_free, level.N, level.nq
     st = N * nq
     po = level.mesh.p_offset
     x = np.zeros((nf, N, nq))
-    C = sp.lil_matrix((nf * nq, nq))
-    for a in range(nq):
-        for i in range(po, nf):
-            C[i * nq + a, a] = 1.0
-    C = C.tocsr()
+    rows = (np.arange(po, nf)[:, None] * nq + np.arange(nq)[None, :]).ravel()
+    cols = np.tile(np.arange(nq), nf - po)
+    C = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(nf * nq, nq))
     for n in range(N):
         idx = (np.arange(nf)[:, None] * st + n * nq + np.arange(nq)[None, :]).ravel()
+        f0 = None
+        fprev = None
         for it in range(maxit):
             F = level.residual(x, slabs=[n]).ravel()[idx]
-            if np.linalg.norm(F) <= tol * max(1.0, np.linalg.norm(x[:, n, :])):
+            fn = np.linalg.norm(F)
+            f0 = fn if f0 is None else f0
+            if fn <= tol * max(1.0, np.linalg.norm(x[:, n, :])):
                 break
+            if fprev is not None and fn <= 1e-10 * f0 and fn > 0.5 * fprev:
+                break
+            fprev = fn
             J = level.jacobian(x, slabs=[n])
             Jn = J[idx][:, idx]
             B = sp.bmat([[Jn, C], [C.T, None]], format="csc")

@@ -123,6 +123,9 @@ struct Level {
   double *P_val = nullptr, *R_val = nullptr;
   double *r = nullptr, *d = nullptr, *x = nullptr, *b = nullptr;
   double* Binv = nullptr;   // coarsest only
+  double* gbuf = nullptr;   // coarsest only: right-hand side of one slab
+  int* perm = nullptr;      // coarsest only: pivot rows of the slab inverses
+  double* colbuf = nullptr; // coarsest only: pivot columns of the slab inverses
   int coarse_mm = 0;
 };
 
@@ -266,7 +269,7 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
     b += (uint64_t)H.patch_dofs.size() * N * NQ * 8;                    // Y
   } else {
     const int64_t mm = (int64_t)H.nf * NQ + NQ;
-    b += (uint64_t)N * mm * mm * 8;
+    b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8;
   }
   if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
   return b;
@@ -363,6 +366,9 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   } else {
     L.coarse_mm = H.nf * L.NQ + L.NQ;
     L.Binv = P->alloc<double>((size_t)L.N * L.coarse_mm * L.coarse_mm);
+    L.gbuf = P->alloc<double>((size_t)L.coarse_mm);
+    L.perm = P->alloc<int>((size_t)L.N * L.coarse_mm);
+    L.colbuf = P->alloc<double>((size_t)L.N * L.coarse_mm);
   }
 }
 
@@ -501,7 +507,7 @@ void relax(stwr_problem* P, int l, const double* b, double* x, int n_steps, doub
 void coarse_solve(stwr_problem* P, const double* b, double* x) {
   if (!P->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
   Level& C = P->lv.back();
-  HIPCHK(launch_coarse_solve(C.view, C.Binv, C.Mv, P->tab.e0, P->tab.e1, b, x, P->s()));
+  HIPCHK(launch_coarse_solve(C.view, C.Binv, C.Mv, P->tab.e0, P->tab.e1, b, x, C.gbuf, P->s()));
 }
 
 void vcycle(stwr_problem* P, const double* b0, double* x0) {
@@ -657,7 +663,7 @@ void assemble(stwr_problem* P, const double* U) {
   Level& C = P->lv.back();
   HIPCHK(launch_fill((int64_t)C.N * C.coarse_mm * C.coarse_mm, 0.0, C.Binv, P->s()));
   HIPCHK(launch_coarse_build(C.view, C.Jv, C.Binv, P->s()));
-  HIPCHK(launch_dense_inverse(C.N, C.coarse_mm, C.Binv, P->dstatus, P->s()));
+  HIPCHK(launch_dense_inverse(C.N, C.coarse_mm, C.Binv, P->dstatus, C.perm, C.colbuf, P->s()));
   check_status_flag(P, "coarse factorization");
   P->assembled = true;
 }
@@ -670,7 +676,9 @@ void setup_smoothers(stwr_problem* P) {
 }
 
 // Right-preconditioned restarted FGMRES with modified Gram-Schmidt.
-void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* its_out, double* rel_out) {
+// Stops when ||r|| <= max(rtol ||b||, atol).
+void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* its_out, double* rel_out,
+            double atol = 0.0) {
   const stwr_solver_opts& o = P->opts;
   Level& L0 = P->lv[0];
   const int64_t n = L0.n_st;
@@ -680,6 +688,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
   int its = 0;
   double rel = 0.0;
   if (bnorm == 0.0) { if (its_out) *its_out = 0; if (rel_out) *rel_out = 0.0; return; }
+  const double target = std::max(o.gmres_rtol * bnorm, atol);
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
   auto V = [&](int j) { return P->V + j * n; };
   auto Z = [&](int j) { return P->Z + j * n; };
@@ -688,7 +697,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
     spmv(P, 0, x, b, V(0));
     const double beta = norm_host(P, n, V(0));
     rel = beta / bnorm;
-    if (beta <= o.gmres_rtol * bnorm || its >= o.gmres_maxit) break;
+    if (beta <= target || its >= o.gmres_maxit) break;
     HIPCHK(launch_axpby(n, 1.0 / beta, V(0), 0.0, V(0), P->s()));
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -724,7 +733,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
       ++its;
       k = j + 1;
       rel = std::fabs(g[j + 1]) / bnorm;
-      if (std::fabs(g[j + 1]) <= o.gmres_rtol * bnorm || its >= o.gmres_maxit) break;
+      if (std::fabs(g[j + 1]) <= target || its >= o.gmres_maxit) break;
     }
     for (int i = k - 1; i >= 0; --i) {
       double s = g[i];
@@ -734,7 +743,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
     HIPCHK(hipMemcpyAsync(P->dscal, y.data(), k * 8, hipMemcpyHostToDevice, P->s()));
     HIPCHK(launch_gemv_cols(n, k, P->Z, n, P->dscal, x, P->s()));
     HIPCHK(hipStreamSynchronize(P->s()));
-    if (std::fabs(g[k]) <= o.gmres_rtol * bnorm || its >= o.gmres_maxit) done = true;
+    if (std::fabs(g[k]) <= target || its >= o.gmres_maxit) done = true;
   }
   HIPCHK(hipStreamSynchronize(P->s()));
   if (its_out) *its_out = its;
@@ -1197,7 +1206,9 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
       int its = 0;
       double rel = 0.0;
       const double tk = now_s();
-      fgmres(p, F, dU, &st, &its, &rel);
+      // absolute floor of the linear solve: three orders below the Newton
+      // target (a relative tolerance alone would chase rounding once F is tiny)
+      fgmres(p, F, dU, &st, &its, &rel, 1e-3 * o.newton_rtol * f0);
       st.solve_seconds += now_s() - tk;
       HIPCHK(launch_axpby(n, 1.0, dU, 1.0, U, p->s()));
       st.linear_its[k] = its;

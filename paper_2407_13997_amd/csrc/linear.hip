@@ -275,6 +275,92 @@ __global__ __launch_bounds__(kBlock) void k_dense_inverse(int m, double* __restr
   }
 }
 
+// Large dense inverses (m > 512): Gauss-Jordan with partial pivoting spread
+// over the chip, one elimination step per pair of launches.  k_gj_pivot (one
+// workgroup per matrix) picks the pivot of column k, swaps it into row k,
+// scales row k and saves column k; k_gj_update applies the rank-1 update to
+// every other row of every matrix; k_gj_unpermute undoes the column order.
+__global__ __launch_bounds__(kBlock) void k_gj_pivot(int m, int k, double* __restrict__ Ball,
+                                                     int* __restrict__ perm,
+                                                     double* __restrict__ colbuf,
+                                                     int* __restrict__ status) {
+  double* B = Ball + (int64_t)blockIdx.x * m * m;
+  __shared__ double rv[kBlock / 64];
+  __shared__ int ri[kBlock / 64];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bi = m;
+  for (int i = k + tid; i < m; i += kBlock) {
+    const double v = fabs(B[(int64_t)i * m + k]);
+    if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+  }
+  if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
+  __syncthreads();
+  if (tid == 0) {
+    double b = rv[0];
+    int p = ri[0];
+    for (int w = 1; w < kBlock / 64; ++w)
+      if (rv[w] > b || (rv[w] == b && ri[w] < p)) { b = rv[w]; p = ri[w]; }
+    if (!(b > 0.0) || !isfinite(b) || p >= m) {
+      status[0] = 1;
+      p = k;
+    }
+    piv_s = p;
+    perm[(int64_t)blockIdx.x * m + k] = p;
+  }
+  __syncthreads();
+  const int p = piv_s;
+  if (p != k)
+    for (int j = tid; j < m; j += kBlock) {
+      const double a = B[(int64_t)k * m + j];
+      B[(int64_t)k * m + j] = B[(int64_t)p * m + j];
+      B[(int64_t)p * m + j] = a;
+    }
+  __syncthreads();
+  const double pv = B[(int64_t)k * m + k];
+  __syncthreads();
+  for (int j = tid; j < m; j += kBlock)
+    B[(int64_t)k * m + j] = (j == k ? 1.0 : B[(int64_t)k * m + j]) / pv;
+  double* col = colbuf + (int64_t)blockIdx.x * m;
+  for (int i = tid; i < m; i += kBlock) col[i] = B[(int64_t)i * m + k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gj_update(int m, int k, double* __restrict__ Ball,
+                                                      const double* __restrict__ colbuf) {
+  double* B = Ball + (int64_t)blockIdx.y * m * m;
+  const double* col = colbuf + (int64_t)blockIdx.y * m;
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  if (i == k) return;
+  const double f = col[i];
+  if (j == k) B[e] = -f * B[(int64_t)k * m + k];
+  else B[e] -= f * B[(int64_t)k * m + j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gj_unpermute(int m, double* __restrict__ Ball,
+                                                         const int* __restrict__ perm) {
+  double* B = Ball + (int64_t)blockIdx.y * m * m;
+  const int* pm = perm + (int64_t)blockIdx.y * m;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m) return;
+  double* row = B + (int64_t)i * m;
+  for (int k = m - 1; k >= 0; --k) {
+    const int p = pm[k];
+    if (p != k) {
+      const double a = row[k];
+      row[k] = row[p];
+      row[p] = a;
+    }
+  }
+}
+
 // Forward block substitution over the slabs of the coarsest level with the
 // inverted bordered slab blocks; one workgroup walks the slabs in order.
 template <int NQ>
@@ -318,6 +404,58 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
       x[((int64_t)i * N + n) * NQ + a] = acc;
     }
     __syncthreads();
+  }
+}
+
+// Large coarsest levels: one slab at a time, with the right-hand side
+// g = b_n + e0 (x) (M (e1 . x_{n-1})) formed by one kernel and the product with
+// the inverted bordered block by another, many workgroups each.
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, int n,
+                                                       const int* __restrict__ rp,
+                                                       const int* __restrict__ col,
+                                                       const double* __restrict__ Mv, double e00,
+                                                       double e01, double e10, double e11,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ g) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int m = nf * NQ;
+  if (r >= m + NQ) return;
+  if (r >= m) { g[r] = 0.0; return; }
+  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  const int i = r / NQ, a = r % NQ;
+  double v = b[((int64_t)i * N + n) * NQ + a];
+  if (n > 0 && i < po) {
+    double jump = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const double mk = Mv[k];
+      if (mk == 0.0) continue;
+      const double* xv = x + ((int64_t)col[k] * N + n - 1) * NQ;
+      double xl = 0.0;
+      for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xv[bb];
+      jump += mk * xl;
+    }
+    v += e0[a] * jump;
+  }
+  g[r] = v;
+}
+
+// 16 rows per workgroup, 16 lanes per row.
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(int nf, int N, int n, int mm,
+                                                        const double* __restrict__ Bn,
+                                                        const double* __restrict__ g,
+                                                        double* __restrict__ x) {
+  const int row = blockIdx.x * 16 + threadIdx.x / 16, l = threadIdx.x % 16;
+  const int m = nf * NQ;
+  double acc = 0.0;
+  if (row < m)
+    for (int c = l; c < mm; c += 16) acc += Bn[(int64_t)row * mm + c] * g[c];
+  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  if (row < m && l == 0) {
+    const int i = row / NQ, a = row % NQ;
+    x[((int64_t)i * N + n) * NQ + a] = acc;
   }
 }
 
@@ -411,17 +549,42 @@ hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, 
   return hipGetLastError();
 }
 
-hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, hipStream_t s) {
+hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
+                                double* colbuf, hipStream_t s) {
   if (m > kMaxCoarse) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dense_inverse, dim3(nmat), dim3(kBlock), 0, s, m, B, status);
+  if (m <= 512) {
+    hipLaunchKernelGGL(k_dense_inverse, dim3(nmat), dim3(kBlock), 0, s, m, B, status);
+    return hipGetLastError();
+  }
+  const dim3 gu(nblk((int64_t)m * m), nmat), gp(nblk(m), nmat);
+  for (int k = 0; k < m; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(nmat), dim3(kBlock), 0, s, m, k, B, perm, colbuf, status);
+    hipLaunchKernelGGL(k_gj_update, gu, dim3(kBlock), 0, s, m, k, B, colbuf);
+  }
+  hipLaunchKernelGGL(k_gj_unpermute, gp, dim3(kBlock), 0, s, m, B, perm);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const double* Mv,
                                const double* e0, const double* e1, const double* b, double* x,
-                               hipStream_t s) {
-  if (L.nf * L.NQ + L.NQ > kMaxCoarse) return hipErrorInvalidValue;
+                               double* gbuf, hipStream_t s) {
+  const int mm = L.nf * L.NQ + L.NQ;
+  if (mm > kMaxCoarse) return hipErrorInvalidValue;
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
+  if (mm > 512) {
+    const unsigned gr = nblk(mm), gg = (unsigned)((L.nf * L.NQ + 15) / 16);
+    for (int n = 0; n < L.N; ++n) {
+      const double* Bn = Binv + (int64_t)n * mm * mm;
+      if (L.NQ == 1) {
+        hipLaunchKernelGGL(k_coarse_rhs<1>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
+        hipLaunchKernelGGL(k_coarse_gemv<1>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
+      } else {
+        hipLaunchKernelGGL(k_coarse_rhs<2>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
+        hipLaunchKernelGGL(k_coarse_gemv<2>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
+      }
+    }
+    return hipGetLastError();
+  }
   if (L.NQ == 1)
     hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.row_ptr,
                        L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);

@@ -57,12 +57,16 @@ def draw_modes(seed: int, n_psi: int = 4, n_p: int = 3, max_wave: int = 4,
                omega: float = math.pi):
     """Draw manufactured-solution modes with numpy's default_rng(seed).
 
-    a, b ~ U{1..max_wave}; c ~ N(0,1); th ~ U[0, 2 pi); (al, be) ~ U{0..4}^2
+    a, b ~ U{1..max_wave}; c = N(0,1) / (pi sqrt(a^2 + b^2)) (so each mode's
+    velocity has an N(0,1) amplitude); th ~ U[0, 2 pi); (al, be) ~ U{0..4}^2
     without (0,0); d ~ N(0,1); every temporal frequency is ``omega``.
     """
     rng = np.random.default_rng(seed)
     psi_ab = rng.integers(1, max_wave + 1, size=(n_psi, 2)).astype(np.int32)
-    c = rng.standard_normal(n_psi)
+    # N(0,1) amplitude of each mode's velocity: the stream-function coefficient
+    # is divided by pi * sqrt(a^2 + b^2), so |u_m| ~ |N(0,1)| as in the
+    # O(1)-velocity flows the Reynolds numbers refer to
+    c = rng.standard_normal(n_psi) / (np.pi * np.sqrt((psi_ab.astype(float) ** 2).sum(axis=1)))
     th = rng.uniform(0.0, 2.0 * math.pi, n_psi)
     psi_coef = np.stack([c, np.full(n_psi, omega), th], axis=1)
     p_ab = np.zeros((n_p, 2), dtype=np.int32)

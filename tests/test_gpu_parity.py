@@ -20,6 +20,10 @@ CASES = {
     "q1_m8_n1": dict(mesh_n=8, n_levels=2, q=1, n_slabs=1, reynolds=10.0, seed=12),
     "q0_m16_n5": dict(mesh_n=16, n_levels=3, q=0, n_slabs=5, reynolds=30.0, seed=13),
     "q0_m16_n5_re10": dict(mesh_n=16, n_levels=3, q=0, n_slabs=5, reynolds=10.0, seed=13),
+    # coarsest level 8x8: bordered slab blocks of 1064 (q=1) and 532 (q=0) rows,
+    # the chip-wide inverse and the per-slab coarse kernels
+    "q1_m16_L2_n3": dict(mesh_n=16, n_levels=2, q=1, n_slabs=3, reynolds=10.0, seed=14),
+    "q0_m8_L1_n6": dict(mesh_n=8, n_levels=1, q=0, n_slabs=6, reynolds=5.0, seed=15),
 }
 
 
@@ -210,7 +214,7 @@ def test_vcycle(case):
     assert e < 1e-12
 
 
-@pytest.mark.parametrize("case", ["q0_m4_n4", "q1_m8_n3", "q0_m16_n5_re10", "q1_m8_n1"])
+@pytest.mark.parametrize("case", ["q0_m4_n4", "q1_m8_n3", "q0_m16_n5_re10", "q1_m8_n1", "q1_m16_L2_n3"])
 def test_fgmres_solution(case):
     """Linear solve at the Newton start state (zero at the free DoFs), from a
     consistent right-hand side.  (At Re = 30 on the 16x16, q = 0, dt = 0.2 case
