@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--vcycles", type=int, default=3)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
     args = ap.parse_args()
@@ -212,11 +213,14 @@ def main():
         "vcycle_ms": vc_ms,
         "lambda_finest": lam,
     }
+    P.close()
+    if not args.no_serving:
+        out["serving"] = serving_benchmark()
+        log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
-    P.close()
     ctx.close()
 
 
@@ -240,6 +244,70 @@ def profiled_traffic() -> int | None:
         if line.startswith("traffic_bytes_per_launch:"):
             rec_bytes = int(line.split(":", 1)[1].strip())
     return rec_bytes if (rec_sha == sha and rec_bytes) else None
+
+
+def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:
+    """Solves/s and latency of independent Newton solves, plain (FP64 smoother,
+    one at a time) vs served (FP32 smoother, continuous batching over `slots`
+    streams), on requests drawn from the uneven-batch distribution restricted
+    to meshes {8, 16, 32}, N in [8, 64], Re in [1, 100] so the run stays short."""
+    import numpy as np
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+
+    probs = w.batch_problems(n_req, seed0=2000, meshes=(8, 16, 32), slab_range=(8, 64),
+                             log10_re=(0.0, 2.0))
+
+    def opts(prec):
+        o = binding.default_opts()
+        o.smoother_prec = prec
+        o.newton_maxit = 12
+        return o
+
+    def closed_batch(prec, n_slots):
+        srv = binding.Server(0, n_slots=n_slots)
+        t0 = srv.now()
+        ids = [srv.submit(p, opts(prec)) for p in probs]
+        srv.wait(1200.0)
+        res = {r["id"]: r for r in srv.poll()}
+        srv.close()
+        span = max(r["end_time"] for r in res.values()) - t0
+        ok = [res[i] for i in ids if res[i]["status"] == 0]
+        lat = [r["end_time"] - r["submit_time"] for r in res.values()]
+        return {"solves": len(ok), "makespan_s": span, "solves_per_s": len(ok) / span,
+                "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99))}, [res[i] for i in ids]
+
+    log(f"[bench] serving: {n_req} requests, plain FP64 x1 slot")
+    plain, rp = closed_batch(0, 1)
+    log(f"[bench] serving: FP32 x{slots} slots")
+    served, rs = closed_batch(1, slots)
+    errs = [float(np.linalg.norm(a["solution"] - b["solution"]) / max(np.linalg.norm(a["solution"]), 1e-300))
+            for a, b in zip(rp, rs) if a["status"] == 0 and b["status"] == 0]
+    # open loop: Poisson arrivals at 70% of the served closed-batch rate
+    rate = 0.7 * served["solves_per_s"]
+    arr = w.arrival_times(rate, n_req, seed=3000)
+    srv = binding.Server(0, n_slots=slots)
+    t0 = srv.now()
+    for a, p in zip(arr, probs):
+        while srv.now() - t0 < a:
+            time.sleep(min(0.002, max(0.0, a - (srv.now() - t0))))
+        srv.submit(p, opts(1), want_solution=False)
+    srv.wait(1200.0)
+    res = srv.poll()
+    srv.close()
+    lat = [r["end_time"] - r["submit_time"] for r in res if r["status"] == 0]
+    return {
+        "requests": n_req,
+        "workload": "uneven batch: meshes {8,16,32}, N in [8,64], q in {0,1}, Re in [1,100], seeds 2000+",
+        "plain_fp64_serial": plain,
+        "served_fp32": dict(served, slots=slots),
+        "speedup_solves_per_s": served["solves_per_s"] / plain["solves_per_s"],
+        "max_rel_diff_served_vs_plain": max(errs) if errs else None,
+        "poisson": {"rate_per_s": rate, "completed": len(lat),
+                    "p50_latency_s": float(np.percentile(lat, 50)) if lat else None,
+                    "p99_latency_s": float(np.percentile(lat, 99)) if lat else None},
+    }
 
 
 def patch_sweep_bytes(prob, s_f: int) -> int:

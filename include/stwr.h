@@ -127,6 +127,11 @@ int32_t stwr_ctx_bytes_in_use(const stwr_ctx* ctx, uint64_t* bytes);
 int32_t stwr_ctx_set_timing(stwr_ctx* ctx, int32_t enable);
 int32_t stwr_ctx_kernel_times(stwr_ctx* ctx, double* ms, int64_t* launches);
 
+/* Allocate problem memory stream-ordered (hipMallocAsync/hipFreeAsync on the
+ * context's stream) instead of hipMalloc/hipFree, so that freeing a finished
+ * problem does not synchronise the device while other streams work. */
+int32_t stwr_ctx_set_alloc_mode(stwr_ctx* ctx, int32_t stream_ordered);
+
 /* ---- host-only queries (no device needed) ------------------------------ */
 /* Device bytes stwr_problem_create would allocate (factors at the chosen
  * precision, operators, maps, Krylov and smoother workspaces). */
@@ -212,6 +217,44 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats);
 
 /* Subtract the mean pressure per (slab, temporal node) from x (level l). */
 int32_t stwr_project_pressure(stwr_problem* p, int32_t level, double* x);
+
+/* ---- serving: continuous batching of independent solves ------------------
+ * A server owns n_slots workers, each with its own non-blocking HIP stream on
+ * `device`.  Submitted requests wait in FIFO order and are admitted when a
+ * worker is free and the request's device bytes (stwr_problem_bytes plus its
+ * solution vector) fit in hbm_budget minus the bytes of the solves in flight
+ * (0 = no bound); a request larger than the whole budget completes at once
+ * with STWR_ERR_BUDGET.  An admitted request is created, solved by
+ * stwr_newton_solve from the zero start, its solution copied to `host_out`
+ * (n_st doubles, or NULL to discard), and its memory released, so solves of
+ * different sizes overlap on the device.  Times are seconds on the server's
+ * steady clock (stwr_server_now). */
+typedef struct stwr_server stwr_server;
+
+typedef struct {
+  int64_t id;
+  int32_t status;              /* stwr_status of the solve */
+  int32_t newton_its, linear_its;
+  int32_t slot;                /* worker that ran it (-1 if rejected) */
+  double submit_time, start_time, end_time;
+  double fnorm_ratio;          /* final ||F|| / ||F_0|| */
+  uint64_t bytes;              /* device bytes reserved for it */
+} stwr_result;
+
+int32_t stwr_server_create(int32_t device, int32_t n_slots, uint64_t hbm_budget,
+                           stwr_server** out);
+/* desc/opts are copied; host_out must stay valid until the result is polled. */
+int32_t stwr_server_submit(stwr_server* s, const stwr_problem_desc* desc,
+                           const stwr_solver_opts* opts, double* host_out, int64_t* id_out);
+/* Move up to max_results finished results into `results`; *n_out = count. */
+int32_t stwr_server_poll(stwr_server* s, stwr_result* results, int32_t max_results,
+                         int32_t* n_out);
+/* Block until every submitted request has finished or timeout_s elapses
+ * (returns STWR_ERR_STATE on timeout). */
+int32_t stwr_server_wait(stwr_server* s, double timeout_s);
+int32_t stwr_server_now(const stwr_server* s, double* t);
+/* Finishes the requests in flight, drops the queued ones, joins the workers. */
+int32_t stwr_server_destroy(stwr_server* s);
 
 #ifdef __cplusplus
 }

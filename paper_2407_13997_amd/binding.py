@@ -30,6 +30,8 @@ EXPORTED = [
     "stwr_relax", "stwr_restrict", "stwr_prolong_add", "stwr_coarse_solve",
     "stwr_setup_smoothers", "stwr_vcycle", "stwr_fgmres", "stwr_newton_solve",
     "stwr_project_pressure", "stwr_ctx_set_timing", "stwr_ctx_kernel_times",
+    "stwr_ctx_set_alloc_mode", "stwr_server_create", "stwr_server_submit", "stwr_server_poll",
+    "stwr_server_wait", "stwr_server_now", "stwr_server_destroy",
 ]
 
 
@@ -70,6 +72,17 @@ class Stats(ctypes.Structure):
                 "fnorm": list(self.fnorm[:k + 1]), "lambda": list(self.lambda_),
                 "final_rel_residual": self.final_rel_residual,
                 "setup_seconds": self.setup_seconds, "solve_seconds": self.solve_seconds}
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("newton_its", ctypes.c_int32),
+                ("linear_its", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("submit_time", ctypes.c_double), ("start_time", ctypes.c_double),
+                ("end_time", ctypes.c_double), ("fnorm_ratio", ctypes.c_double),
+                ("bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class StwrError(RuntimeError):
@@ -124,6 +137,14 @@ def load(path: str | None = None):
         "stwr_project_pressure": [P, i32, V],
         "stwr_ctx_set_timing": [P, i32],
         "stwr_ctx_kernel_times": [P, ctypes.POINTER(f64), ctypes.POINTER(i64)],
+        "stwr_ctx_set_alloc_mode": [P, i32],
+        "stwr_server_create": [i32, i32, u64, ctypes.POINTER(P)],
+        "stwr_server_submit": [P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolverOpts), V,
+                               ctypes.POINTER(i64)],
+        "stwr_server_poll": [P, ctypes.POINTER(Result), i32, ctypes.POINTER(i32)],
+        "stwr_server_wait": [P, f64],
+        "stwr_server_now": [P, ctypes.POINTER(f64)],
+        "stwr_server_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -340,3 +361,56 @@ class Problem:
         if rc != STWR_OK and not (allow_unconverged and rc == -7):
             self.ctx.check(rc)
         return st.as_dict()
+
+
+class Server:
+    """Continuous-batching solve server (stwr_server_*): n_slots workers with
+    their own HIP streams, FIFO admission by HBM budget."""
+
+    def __init__(self, device: int = 0, n_slots: int = 4, hbm_budget: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        rc = self.lib.stwr_server_create(device, n_slots, hbm_budget, ctypes.byref(h))
+        if rc != STWR_OK:
+            raise StwrError(rc, "stwr_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, prob, opts: SolverOpts | None = None, want_solution: bool = True) -> int:
+        d, keep = make_desc(prob)
+        opts = opts or default_opts()
+        out = np.zeros(prob.n_st) if want_solution else None
+        rid = ctypes.c_int64()
+        rc = self.lib.stwr_server_submit(self.h, ctypes.byref(d), ctypes.byref(opts),
+                                         None if out is None else out.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(rid))
+        if rc != STWR_OK:
+            raise StwrError(rc, "stwr_server_submit failed")
+        self._keep[rid.value] = out
+        return rid.value
+
+    def poll(self, max_results: int = 256):
+        buf = (Result * max_results)()
+        n = ctypes.c_int32()
+        rc = self.lib.stwr_server_poll(self.h, buf, max_results, ctypes.byref(n))
+        if rc != STWR_OK:
+            raise StwrError(rc, "stwr_server_poll failed")
+        out = []
+        for i in range(n.value):
+            d = buf[i].as_dict()
+            d["solution"] = self._keep.pop(d["id"], None)
+            out.append(d)
+        return out
+
+    def wait(self, timeout_s: float = 600.0) -> bool:
+        return self.lib.stwr_server_wait(self.h, timeout_s) == STWR_OK
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        self.lib.stwr_server_now(self.h, ctypes.byref(t))
+        return t.value
+
+    def close(self):
+        if self.h:
+            self.lib.stwr_server_destroy(self.h)
+            self.h = None

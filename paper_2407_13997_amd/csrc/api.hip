@@ -48,6 +48,8 @@ struct stwr_ctx {
   uint64_t in_use = 0;
   std::string last_error;
   std::mutex mu;
+  // stream-ordered allocation (server workers: no device-wide sync on free)
+  bool stream_alloc = false;
   // kernel timing: event pairs recorded around launches of each class
   bool timing = false;
   std::vector<hipEvent_t> pool;
@@ -157,21 +159,30 @@ struct stwr_problem {
   T* alloc(size_t count) {
     if (count == 0) count = 1;
     void* ptr = nullptr;
-    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-    if (e != hipSuccess) throw StwrError(STWR_ERR_OOM, "hipMalloc failed for " + std::to_string(count * sizeof(T)) + " bytes");
+    hipError_t e = ctx->stream_alloc ? hipMallocAsync(&ptr, count * sizeof(T), ctx->stream)
+                                     : hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) throw StwrError(STWR_ERR_OOM, "device allocation failed for " + std::to_string(count * sizeof(T)) + " bytes");
     bufs.push_back({ptr, count * sizeof(T)});
     return (T*)ptr;
   }
+  // copies on the context's stream and waits, so the host vector may go away
   template <typename T>
   T* upload(const std::vector<T>& v) {
     T* d = alloc<T>(v.size());
-    if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!v.empty()) {
+      HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
     return d;
+  }
+  void free_one(void* ptr) {
+    if (ctx->stream_alloc) (void)hipFreeAsync(ptr, ctx->stream);
+    else (void)hipFree(ptr);
   }
   void release(void* ptr) {
     for (auto it = bufs.begin(); it != bufs.end(); ++it)
       if (it->p == ptr) {
-        (void)hipFree(it->p);
+        free_one(it->p);
         bufs.erase(it);
         return;
       }
@@ -416,7 +427,8 @@ void check_status_flag(stwr_problem* P, const char* what) {
   HIPCHK(hipStreamSynchronize(P->s()));
   if (h) {
     int z = 0;
-    HIPCHK(hipMemcpy(P->dstatus, &z, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(P->dstatus, &z, sizeof(int), hipMemcpyHostToDevice, P->s()));
+    HIPCHK(hipStreamSynchronize(P->s()));
     throw StwrError(STWR_ERR_SINGULAR, std::string(what) + ": zero or non-finite pivot");
   }
 }
@@ -809,6 +821,12 @@ int32_t stwr_ctx_bytes_in_use(const stwr_ctx* ctx, uint64_t* bytes) {
   return STWR_OK;
 }
 
+int32_t stwr_ctx_set_alloc_mode(stwr_ctx* ctx, int32_t stream_ordered) {
+  if (!ctx) return STWR_ERR_ARG;
+  ctx->stream_alloc = stream_ordered != 0;
+  return STWR_OK;
+}
+
 int32_t stwr_ctx_set_timing(stwr_ctx* ctx, int32_t enable) {
   if (!ctx) return STWR_ERR_ARG;
   ctx->timing = enable != 0;
@@ -915,7 +933,8 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
     try {
       build_ref_tables(desc->q, P->tab);
       P->d_tab = P->alloc<RefTables>(1);
-      HIPCHK(hipMemcpy(P->d_tab, &P->tab, sizeof(RefTables), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpyAsync(P->d_tab, &P->tab, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
       P->mms.n_psi = desc->n_psi_modes;
       P->mms.n_p = desc->n_p_modes;
       P->mms.psi_ab = P->upload(P->psi_ab);
@@ -936,7 +955,8 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
       P->dscal = P->alloc<double>(256 + (size_t)desc->n_slabs * (desc->q + 1));
       P->partial = P->alloc<double>(256 * 256);
       P->dstatus = P->alloc<int>(4);
-      HIPCHK(hipMemset(P->dstatus, 0, 4 * sizeof(int)));
+      HIPCHK(hipMemsetAsync(P->dstatus, 0, 4 * sizeof(int), ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
       // host copies no longer needed on the device side can be dropped
       for (auto& Lv : P->lv) {
         std::vector<int>().swap(Lv.H.cell_nz);
@@ -944,7 +964,7 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
         std::vector<int>().swap(Lv.H.dof_slot);
       }
     } catch (...) {
-      for (auto& b : P->bufs) (void)hipFree(b.p);
+      for (auto& b : P->bufs) P->free_one(b.p);
       P->bufs.clear();
       std::lock_guard<std::mutex> g(ctx->mu);
       ctx->in_use -= need;
@@ -958,7 +978,8 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
 int32_t stwr_problem_destroy(stwr_problem* p) {
   if (!p) return STWR_OK;
   (void)hipStreamSynchronize(p->s());
-  for (auto& b : p->bufs) (void)hipFree(b.p);
+  for (auto& b : p->bufs) p->free_one(b.p);
+  if (p->ctx->stream_alloc) (void)hipStreamSynchronize(p->s());
   {
     std::lock_guard<std::mutex> g(p->ctx->mu);
     p->ctx->in_use -= std::min(p->ctx->in_use, p->bytes);

@@ -114,17 +114,19 @@ def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,
 
 
 def batch_problems(n: int = 64, seed0: int = 2000, meshes=(8, 16, 32, 64),
-                   slab_range=(8, 128)) -> list:
+                   slab_range=(8, 128), log10_re=(0.0, 3.0)) -> list:
     """The uneven batch: mesh ~ U{meshes}, N ~ U[slab_range], q ~ U{0,1},
-    R = 10**U[0,3]; problem j uses seed seed0 + j; levels go down to 4x4."""
+    R = 10**U[log10_re]; problem j uses seed seed0 + j.  Levels go down to an
+    8x8 coarsest mesh (4x4 for the 8x8 mesh)."""
     out = []
     for j in range(n):
         rng = np.random.default_rng(seed0 + j)
         m = int(rng.choice(meshes))
         nsl = int(rng.integers(slab_range[0], slab_range[1] + 1))
         q = int(rng.integers(0, 2))
-        re = float(10.0 ** rng.uniform(0.0, 3.0))
-        levels = int(round(math.log2(m / 4))) + 1
+        re = float(10.0 ** rng.uniform(log10_re[0], log10_re[1]))
+        coarsest = 8 if m >= 16 else 4
+        levels = int(round(math.log2(m / coarsest))) + 1
         modes = draw_modes(seed0 + j, 4, 3, 4)
         out.append(Problem(m, levels, q, nsl, 1.0, re, *modes, seed=seed0 + j))
     return out
