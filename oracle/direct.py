@@ -18,9 +18,10 @@ import scipy.sparse.linalg as spla
 
 
 
-def solve_slab_by_slab(level, tol=1e-13, maxit=30):
-    """Newton per slab until ||F_n|| <= tol * max(1, ||U_n||) or it stalls at
-    rounding level (no decrease by a factor 2 once below 1e-10 relative)."""
+def solve_slab_by_slab(level, tol=0.0, maxit=40, info=None):
+    """Newton per slab until ||F_n|| <= tol * max(1, ||U_n||) or, by default,
+    until it reaches its rounding floor (no decrease by a factor 2 once below
+    1e-10 relative).  ``info`` (a list) receives each slab's final ||F_n||."""
     nf, N, nq = level.n_free, level.N, level.nq
     st = N * nq
     po = level.mesh.p_offset
@@ -40,12 +41,16 @@ def solve_slab_by_slab(level, tol=1e-13, maxit=30):
                 break
             if fprev is not None and fn <= 1e-10 * f0 and fn > 0.5 * fprev:
                 break
+            if fn == 0.0:
+                break
             fprev = fn
             J = level.jacobian(x, slabs=[n])
             Jn = J[idx][:, idx]
             B = sp.bmat([[Jn, C], [C.T, None]], format="csc")
             d = spla.spsolve(B, np.concatenate([-F, np.zeros(nq)]))[: nf * nq]
             x[:, n, :] += d.reshape(nf, nq)
+        if info is not None:
+            info.append(float(fn))
     return x
 
 

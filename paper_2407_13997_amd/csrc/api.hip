@@ -128,6 +128,7 @@ struct Level {
   double* gbuf = nullptr;   // coarsest only: right-hand side of one slab
   int* perm = nullptr;      // coarsest only: pivot rows of the slab inverses
   double* colbuf = nullptr; // coarsest only: pivot columns of the slab inverses
+  double* rbuf = nullptr;   // coarsest only: panel rows for the blocked inverse
   int coarse_mm = 0;
 };
 
@@ -280,7 +281,7 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
     b += (uint64_t)H.patch_dofs.size() * N * NQ * 8;                    // Y
   } else {
     const int64_t mm = (int64_t)H.nf * NQ + NQ;
-    b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8;
+    b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8 + (mm > 512 ? (uint64_t)N * 32 * mm * 8 : 0);
   }
   if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
   return b;
@@ -380,6 +381,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     L.gbuf = P->alloc<double>((size_t)L.coarse_mm);
     L.perm = P->alloc<int>((size_t)L.N * L.coarse_mm);
     L.colbuf = P->alloc<double>((size_t)L.N * L.coarse_mm);
+    if (L.coarse_mm > 512) L.rbuf = P->alloc<double>((size_t)L.N * 32 * L.coarse_mm);
   }
 }
 
@@ -675,7 +677,7 @@ void assemble(stwr_problem* P, const double* U) {
   Level& C = P->lv.back();
   HIPCHK(launch_fill((int64_t)C.N * C.coarse_mm * C.coarse_mm, 0.0, C.Binv, P->s()));
   HIPCHK(launch_coarse_build(C.view, C.Jv, C.Binv, P->s()));
-  HIPCHK(launch_dense_inverse(C.N, C.coarse_mm, C.Binv, P->dstatus, C.perm, C.colbuf, P->s()));
+  HIPCHK(launch_dense_inverse(C.N, C.coarse_mm, C.Binv, P->dstatus, C.perm, C.colbuf, C.rbuf, P->s()));
   check_status_flag(P, "coarse factorization");
   P->assembled = true;
 }

@@ -139,9 +139,10 @@ hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, const dou
 
 // ---- coarsest level ---------------------------------------------------------------
 hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, hipStream_t s);
-// perm: nmat * m ints, colbuf: nmat * m doubles of workspace (used when m > 512)
+// perm: nmat * m ints, colbuf: nmat * m doubles, rbuf: nmat * 32 * m doubles of
+// workspace (used when m > 512; rbuf = NULL selects the unblocked form)
 hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
-                                double* colbuf, hipStream_t s);
+                                double* colbuf, double* rbuf, hipStream_t s);
 // gbuf: nf (q+1) + q + 1 doubles of workspace (used for large coarsest levels)
 hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const double* Mv,
                                const double* e0, const double* e1, const double* b, double* x,

@@ -361,6 +361,143 @@ __global__ __launch_bounds__(kBlock) void k_gj_unpermute(int m, double* __restri
   }
 }
 
+// Blocked form for the largest coarse blocks: column panels of kGjPanel.
+// The elimination steps of a panel compose to a transform that differs from
+// the identity only in the panel columns (which the in-place steps leave
+// holding it), so the other columns only need the panel's row swaps and one
+// rank-kGjPanel update A += W R with W = (panel columns - selector) and R the
+// panel rows of those columns: one pass over each matrix per panel instead of
+// one per column.
+constexpr int kGjPanel = 32;
+
+__global__ __launch_bounds__(kBlock) void k_bgj_panel(int m, int k0, int k1, double* __restrict__ Ball,
+                                                      int* __restrict__ perm,
+                                                      double* __restrict__ colbuf,
+                                                      int* __restrict__ status) {
+  double* B = Ball + (int64_t)blockIdx.x * m * m;
+  double* col = colbuf + (int64_t)blockIdx.x * m;
+  __shared__ double rv[kBlock / 64];
+  __shared__ int ri[kBlock / 64];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x, b = k1 - k0;
+  for (int k = k0; k < k1; ++k) {
+    double best = -1.0;
+    int bi = m;
+    for (int i = k + tid; i < m; i += kBlock) {
+      const double v = fabs(B[(int64_t)i * m + k]);
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = rv[0];
+      int p = ri[0];
+      for (int w = 1; w < kBlock / 64; ++w)
+        if (rv[w] > bb || (rv[w] == bb && ri[w] < p)) { bb = rv[w]; p = ri[w]; }
+      if (!(bb > 0.0) || !isfinite(bb) || p >= m) {
+        status[0] = 1;
+        p = k;
+      }
+      piv_s = p;
+      perm[(int64_t)blockIdx.x * m + k] = p;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != k && tid < b) {
+      const int j = k0 + tid;
+      const double a = B[(int64_t)k * m + j];
+      B[(int64_t)k * m + j] = B[(int64_t)p * m + j];
+      B[(int64_t)p * m + j] = a;
+    }
+    __syncthreads();
+    const double pv = B[(int64_t)k * m + k];
+    __syncthreads();
+    if (tid < b) {
+      const int j = k0 + tid;
+      B[(int64_t)k * m + j] = (j == k ? 1.0 : B[(int64_t)k * m + j]) / pv;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kBlock) col[i] = B[(int64_t)i * m + k];
+    __syncthreads();
+    for (int e = tid; e < m * b; e += kBlock) {
+      const int i = e / b, j = k0 + e % b;
+      if (i == k) continue;
+      const double f = col[i];
+      if (j == k) B[(int64_t)i * m + j] = -f * B[(int64_t)k * m + k];
+      else B[(int64_t)i * m + j] -= f * B[(int64_t)k * m + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Row swaps of the panel applied to every non-panel column, then the panel
+// rows of those columns copied to R (kGjPanel x m per matrix).
+__global__ __launch_bounds__(kBlock) void k_bgj_swap(int m, int k0, int k1, double* __restrict__ Ball,
+                                                     const int* __restrict__ perm,
+                                                     double* __restrict__ Rall) {
+  double* B = Ball + (int64_t)blockIdx.y * m * m;
+  const int* pm = perm + (int64_t)blockIdx.y * m;
+  double* R = Rall + (int64_t)blockIdx.y * kGjPanel * m;
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= m || (j >= k0 && j < k1)) return;
+  for (int k = k0; k < k1; ++k) {
+    const int p = pm[k];
+    if (p != k) {
+      const double a = B[(int64_t)k * m + j];
+      B[(int64_t)k * m + j] = B[(int64_t)p * m + j];
+      B[(int64_t)p * m + j] = a;
+    }
+  }
+  for (int k = k0; k < k1; ++k) R[(int64_t)(k - k0) * m + j] = B[(int64_t)k * m + j];
+}
+
+// A[i][j] += sum_t W[i][t] R[t][j] over non-panel columns j, in 64 x 64 tiles.
+__global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, double* __restrict__ Ball,
+                                                       const double* __restrict__ Rall) {
+  double* B = Ball + (int64_t)blockIdx.z * m * m;
+  const double* R = Rall + (int64_t)blockIdx.z * kGjPanel * m;
+  __shared__ double Ws[64][kGjPanel + 1];
+  __shared__ double Rs[kGjPanel][64 + 1];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64, tid = threadIdx.x, b = k1 - k0;
+  if (j0 + 64 > k0 && j0 < k1 && j0 >= k0 && j0 + 64 <= k1) return;   // tile inside the panel
+  for (int e = tid; e < 64 * kGjPanel; e += kBlock) {
+    const int r = e / kGjPanel, t = e % kGjPanel, i = i0 + r;
+    double w = 0.0;
+    if (i < m && t < b) w = B[(int64_t)i * m + k0 + t] - (i == k0 + t ? 1.0 : 0.0);
+    Ws[r][t] = w;
+  }
+  for (int e = tid; e < kGjPanel * 64; e += kBlock) {
+    const int t = e / 64, c = e % 64, j = j0 + c;
+    Rs[t][c] = (t < b && j < m) ? R[(int64_t)t * m + j] : 0.0;
+  }
+  __syncthreads();
+  const int tr = tid / 16, tc = tid % 16;   // 4 x 4 outputs per thread
+  double acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  for (int t = 0; t < kGjPanel; ++t) {
+    double wv[4], rv4[4];
+    for (int a = 0; a < 4; ++a) wv[a] = Ws[tr + 16 * a][t];
+    for (int c = 0; c < 4; ++c) rv4[c] = Rs[t][tc + 16 * c];
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) acc[a][c] += wv[a] * rv4[c];
+  }
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + tr + 16 * a;
+    if (i >= m) continue;
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + tc + 16 * c;
+      if (j >= m || (j >= k0 && j < k1)) continue;
+      B[(int64_t)i * m + j] += acc[a][c];
+    }
+  }
+}
+
 // Forward block substitution over the slabs of the coarsest level with the
 // inverted bordered slab blocks; one workgroup walks the slabs in order.
 template <int NQ>
@@ -550,16 +687,27 @@ hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, 
 }
 
 hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
-                                double* colbuf, hipStream_t s) {
+                                double* colbuf, double* rbuf, hipStream_t s) {
   if (m > kMaxCoarse) return hipErrorInvalidValue;
   if (m <= 512) {
     hipLaunchKernelGGL(k_dense_inverse, dim3(nmat), dim3(kBlock), 0, s, m, B, status);
     return hipGetLastError();
   }
-  const dim3 gu(nblk((int64_t)m * m), nmat), gp(nblk(m), nmat);
-  for (int k = 0; k < m; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(nmat), dim3(kBlock), 0, s, m, k, B, perm, colbuf, status);
-    hipLaunchKernelGGL(k_gj_update, gu, dim3(kBlock), 0, s, m, k, B, colbuf);
+  if (!rbuf) {
+    const dim3 gu(nblk((int64_t)m * m), nmat), gp(nblk(m), nmat);
+    for (int k = 0; k < m; ++k) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3(nmat), dim3(kBlock), 0, s, m, k, B, perm, colbuf, status);
+      hipLaunchKernelGGL(k_gj_update, gu, dim3(kBlock), 0, s, m, k, B, colbuf);
+    }
+    hipLaunchKernelGGL(k_gj_unpermute, gp, dim3(kBlock), 0, s, m, B, perm);
+    return hipGetLastError();
+  }
+  const dim3 gs(nblk(m), nmat), gt((m + 63) / 64, (m + 63) / 64, nmat), gp(nblk(m), nmat);
+  for (int k0 = 0; k0 < m; k0 += kGjPanel) {
+    const int k1 = k0 + kGjPanel < m ? k0 + kGjPanel : m;
+    hipLaunchKernelGGL(k_bgj_panel, dim3(nmat), dim3(kBlock), 0, s, m, k0, k1, B, perm, colbuf, status);
+    hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf);
+    hipLaunchKernelGGL(k_bgj_update, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
   }
   hipLaunchKernelGGL(k_gj_unpermute, gp, dim3(kBlock), 0, s, m, B, perm);
   return hipGetLastError();
