@@ -245,9 +245,10 @@ void check_opts(const stwr_solver_opts* o) {
 int vw_of(int prec) { return prec == STWR_FP32 ? 4 : 2; }
 int round_up(int m, int w) { return (m + w - 1) / w * w; }
 
-// Elements of one stored inverse slab block of size m (layout shared with the
-// patch kernels).
-int64_t block_elems(int m, int VW) { return BlockLayout(m, VW).size(); }
+// Elements reserved for one stored inverse slab block of size m (layout shared
+// with the patch kernels), rounded up to 256 bytes so that every block, and so
+// every 1 KiB wavefront load inside it, starts on a cache-line boundary.
+int64_t block_elems(int m, int VW) { return round_up(BlockLayout(m, VW).size(), 16 * VW); }
 
 // Element count of the factor storage of one level at a precision.
 int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
@@ -408,11 +409,14 @@ void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
     L.fac = P->alloc<char>(need);
     L.fac_bytes = need;
   }
+  // [slab][patch] order: the patches resident at one time (which start
+  // together and advance at similar rates) read from a few compact regions
   L.fac_off.assign(L.H.nv + 1, 0);
   for (int v = 0; v < L.H.nv; ++v) {
     const int m = (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ;
-    L.fac_off[v + 1] = L.fac_off[v] + (int64_t)L.N * block_elems(m, vw_of(prec));
+    L.fac_off[v + 1] = L.fac_off[v] + block_elems(m, vw_of(prec));
   }
+  L.pview.slab_stride = L.fac_off[L.H.nv];
   HIPCHK(hipMemcpyAsync(L.d_fac_off, L.fac_off.data(), L.fac_off.size() * 8, hipMemcpyHostToDevice, P->s()));
 }
 

@@ -41,7 +41,8 @@ struct PatchView {
   const int* patch_nbu;
   const int64_t* patch_nz_off;
   const int* patch_nz;
-  const int64_t* fac_off;   // n_patch + 1, element offsets of each patch's N blocks
+  const int64_t* fac_off;   // n_patch + 1, element offset of each patch's block inside a slab
+  int64_t slab_stride;      // elements of one slab's blocks (all patches): blocks are [slab][patch]
   const int64_t* y_off;     // n_patch + 1, offsets into the patch output buffer
   const int64_t* mp_off;    // n_patch + 1, offsets of the patch mass blocks
   const int* dof_ptr;

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, Patch
     __syncthreads();
   }
   const BlockLayout lay(m, VW);
-  T* out = fac + P.fac_off[p] + (int64_t)n * lay.size();
+  T* out = fac + P.fac_off[p] + (int64_t)n * P.slab_stride;
   for (int e = tid; e < lay.size(); e += kFacThreads) out[e] = (T)0;
   __syncthreads();
   for (int e = tid; e < m * m; e += kFacThreads) {
@@ -157,9 +157,9 @@ __device__ inline T dotv(const V& w, const T* g) {
 // it with v_readlane into scalar operands, so it needs neither LDS nor
 // replicated registers, and only the rows past 64 read it from LDS.  All
 // loads of a slab block are issued before the right-hand side is formed;
-// the residual values of slab n + 1 are loaded one slab ahead.  The jump
-// coupling works in FP32 from a transposed copy of the patch mass block
-// (conflict-free LDS reads).  FULL = true
+// the residual values are staged a cache line (16 / (q+1) slabs) at a time.
+// The jump coupling works in FP32 from a transposed copy of the patch mass
+// block (conflict-free LDS reads).  FULL = true
 // is the interior patch (nb = 39), whose sizes are all compile-time
 // constants; FULL = false handles the smaller boundary patches.  Panels past
 // a block's last one re-read its last panel: their columns meet zeros of
@@ -181,6 +181,10 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
   __shared__ float g[MAXP * VW + 4];
   __shared__ float ylast[kMaxNbu];
   __shared__ float mj[kMaxNbu];
+  // residual of the current chunk of CH slabs (one 128-byte line of a DoF's
+  // values), so each line is fetched once instead of once per slab
+  constexpr int CH = 16 / NQ;
+  __shared__ float rch[CH][2 * 64];
   const float e0[2] = {(float)e00, (float)e01};
   const int p = P.order[first + blockIdx.x], lane = threadIdx.x;
   const int s0 = P.patch_ptr[p];
@@ -199,6 +203,7 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
   for (int i = lane; i < MAXP * VW + 4; i += 64) g[i] = 0.0f;
   __syncthreads();
   const float* Ab = fac + P.fac_off[p];
+  const int64_t SS = P.slab_stride;
   double* yout = Y + P.y_off[p];
   const unsigned row1 = lane < r1 ? lane : 0;
   const unsigned base1 = row1 * VW, step1 = r1 * VW;
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
   float4 a1[MAXP];
   float4 a2[kTwo ? K2 : 1];
   auto issue = [&](int n) {
-    const float* blk = Ab + (int64_t)n * S;
+    const float* blk = Ab + (int64_t)n * SS;
 #pragma unroll
     for (int q = 0; q < MAXP; ++q) {
       const unsigned qq = FULL ? q : (q < lastq ? q : lastq);
@@ -228,14 +233,20 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
       }
     }
   };
-  double rA = hasA ? r[bA] : 0.0, rB = hasB ? r[bB] : 0.0;
   for (int n = 0; n < N; ++n) {
     issue(n);
-    const double rAn = (hasA && n + 1 < N) ? r[bA + (int64_t)(n + 1) * NQ] : 0.0;
-    const double rBn = (hasB && n + 1 < N) ? r[bB + (int64_t)(n + 1) * NQ] : 0.0;
+    const int s = n % CH;
+    if (s == 0) {
+      // each lane stages only its own rows: no barrier needed
+      for (int t = 0; t < CH; ++t) {
+        const bool in = n + t < N;
+        rch[t][lane] = (hasA && in) ? (float)r[bA + (int64_t)(n + t) * NQ] : 0.0f;
+        if (kTwo) rch[t][64 + lane] = (hasB && in) ? (float)r[bB + (int64_t)(n + t) * NQ] : 0.0f;
+      }
+    }
     float gA = 0.0f, gB = 0.0f;
-    if (hasA) gA = (float)rA + ((n > 0 && iA < nbu) ? e0[rowA % NQ] * mj[iA] : 0.0f);
-    if (hasB) gB = (float)rB + ((n > 0 && iB < nbu) ? e0[rowB % NQ] * mj[iB] : 0.0f);
+    if (hasA) gA = rch[s][lane] + ((n > 0 && iA < nbu) ? e0[rowA % NQ] * mj[iA] : 0.0f);
+    if (hasB) gB = rch[s][64 + lane] + ((n > 0 && iB < nbu) ? e0[rowB % NQ] * mj[iB] : 0.0f);
     if constexpr (kTwo) {
       g[rowA] = gA;
       if (rowB < MAXP * VW) g[rowB] = gB;
@@ -286,8 +297,6 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
       mj[lane] = acc;
     }
     __syncthreads();
-    rA = rAn;
-    rB = rBn;
   }
 }
 
@@ -333,7 +342,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   for (int i = tid; i < kMaxNbu; i += 64 * WAVES) mj[i] = 0.0;
   for (int i = tid; i < WAVES * PW * VW; i += 64 * WAVES) g[i] = (T)0;
   __syncthreads();
-  const int S = lay.size();
+  const int64_t S = P.slab_stride;
   const T* Ab = fac + P.fac_off[p];
   double* yout = Y + P.y_off[p];
   // this lane's load offsets inside a block (clamped to valid elements)
