@@ -312,8 +312,9 @@ def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:
 
 def patch_sweep_bytes(prob, s_f: int) -> int:
     """Algorithmic bytes of one patch-sweep launch on the finest level:
-    sum over patches of N (m^2 s_f + 8 m + 8 m), m = (q+1) nb the slab block size:
-    the inverse block, the residual gather and the patch output per slab."""
+    sum over patches of N (m^2 s_f + 8 m + s_f m), m = (q+1) nb the slab block
+    size: the inverse block, the FP64 residual gather and the patch output
+    (in the smoother's precision) per slab."""
     from paper_2407_13997_amd import binding
     info = binding.mesh_info(prob.mesh_n)
     hist = info[12:52]
@@ -321,7 +322,7 @@ def patch_sweep_bytes(prob, s_f: int) -> int:
     tot = 0
     for nb, cnt in enumerate(hist):
         m = nb * nq
-        tot += int(cnt) * prob.n_slabs * (m * m * s_f + 16 * m)
+        tot += int(cnt) * prob.n_slabs * (m * m * s_f + 8 * m + s_f * m)
     return tot
 
 

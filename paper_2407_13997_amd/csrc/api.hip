@@ -260,6 +260,11 @@ int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
   return tot;
 }
 
+// Doubles reserved for one patch's outputs (nb DoFs x N slabs x (q+1)
+// nodes), rounded up to whole 128-byte lines so every patch's outputs start
+// on a line boundary.
+int64_t y_elems(int nb, int N, int NQ) { return ((int64_t)nb * N * NQ + 15) / 16 * 16; }
+
 struct Plan {
   uint64_t bytes = 0;
 };
@@ -279,7 +284,8 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
     int64_t mp = 0;
     for (int v = 0; v < H.nv; ++v) mp += (int64_t)H.patch_nbu[v] * H.patch_nbu[v];
     b += (uint64_t)mp * 8;
-    b += (uint64_t)H.patch_dofs.size() * N * NQ * 8;                    // Y
+    for (int v = 0; v < H.nv; ++v)                                      // Y
+      b += (uint64_t)y_elems(H.patch_ptr[v + 1] - H.patch_ptr[v], N, NQ) * 8;
   } else {
     const int64_t mm = (int64_t)H.nf * NQ + NQ;
     b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8 + (mm > 512 ? (uint64_t)N * 32 * mm * 8 : 0);
@@ -351,7 +357,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     L.mp_off.assign(H.nv + 1, 0);
     for (int p = 0; p < H.nv; ++p) {
       const int nb = H.patch_ptr[p + 1] - H.patch_ptr[p];
-      L.y_off[p + 1] = L.y_off[p] + (int64_t)nb * L.N * L.NQ;
+      L.y_off[p + 1] = L.y_off[p] + y_elems(nb, L.N, L.NQ);
       L.mp_off[p + 1] = L.mp_off[p] + (int64_t)H.patch_nbu[p] * H.patch_nbu[p];
     }
     L.d_y_off = P->upload(L.y_off);
@@ -486,7 +492,7 @@ void patch_apply(stwr_problem* P, int l, const double* r, double* z) {
   require_factor(P, l);
   Level& L = P->lv[l];
   HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, r, L.Y, P->s()));
-  HIPCHK(launch_patch_gather(L.view, L.pview, L.Y, 0, 0.0, 0.0, z, nullptr, nullptr, P->s()));
+  HIPCHK(launch_patch_gather(L.view, L.pview, L.fac_prec, L.Y, 0, 0.0, 0.0, z, nullptr, nullptr, P->s()));
 }
 
 // Chebyshev-accelerated relaxation (three-term recurrence over [a, bnd]).
@@ -516,7 +522,7 @@ void relax(stwr_problem* P, int l, const double* b, double* x, int n_steps, doub
     }
     {
       KernelMark mark(P->ctx, 2);
-      HIPCHK(launch_patch_gather(L.view, L.pview, L.Y, 1, c1, c2, nullptr, L.d, x, P->s()));
+      HIPCHK(launch_patch_gather(L.view, L.pview, L.fac_prec, L.Y, 1, c1, c2, nullptr, L.d, x, P->s()));
     }
     rho_old = rho;
   }

@@ -130,12 +130,14 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
                                int prec, void* fac, int* status, hipStream_t s);
 hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const double* Mv,
                              double* Mp, hipStream_t s);
+// Y: patch outputs, FP64 at element offset y_off[p] (prec 0), or FP32 at
+// element offset 2 y_off[p] (prec 1); the buffer holds y_off[n_patch] doubles.
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
-                              const double* r, double* Y, hipStream_t s);
+                              const double* r, void* Y, hipStream_t s);
 // mode 0: z = sum; mode 1: d = c1 d + c2 sum, x += d.
-hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, const double* Y, int mode,
-                               double c1, double c2, double* z, double* d, double* x,
+hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,
+                               int mode, double c1, double c2, double* z, double* d, double* x,
                                hipStream_t s);
 
 // ---- coarsest level ---------------------------------------------------------------

@@ -155,56 +155,80 @@ __device__ inline T dotv(const V& w, const T* g) {
 // registers).  The right-hand side stays distributed, one value per lane
 // (rows lane and 64 + lane); the lane-per-row part of the product broadcasts
 // it with v_readlane into scalar operands, so it needs neither LDS nor
-// replicated registers, and only the rows past 64 read it from LDS.  All
-// loads of a slab block are issued before the right-hand side is formed;
-// the residual values are staged a cache line (16 / (q+1) slabs) at a time.
-// The jump coupling works in FP32 from a transposed copy of the patch mass
-// block (conflict-free LDS reads).  FULL = true
-// is the interior patch (nb = 39), whose sizes are all compile-time
-// constants; FULL = false handles the smaller boundary patches.  Panels past
-// a block's last one re-read its last panel: their columns meet zeros of
-// the right-hand side, so they add nothing.
+// replicated registers, and only the rows past 64 read it from LDS.
+// Software pipeline: the loads of slab n + 1's block are issued as soon as
+// slab n's product has consumed its registers, so they are in flight while
+// slab n's output is stored and the jump coupling is formed; every load is
+// unconditional (clamped addresses), so the wait counts leave them
+// outstanding.  The residual is staged a 128-byte line (16 / (q+1) slabs) of
+// every patch DoF at a time, with one batch of coalesced loads issued ahead
+// of a block.  The outputs are FP32 (they are computed in FP32, so nothing
+// is lost; the gather widens them), collected in LDS for 32 / (q+1) slabs
+// and written as whole 128-byte lines: writes interleaved with the block
+// stream cost HBM time far beyond their share of the bytes, so they are
+// kept few and full.  The blocks are read once per sweep and are loaded
+// nontemporal, so they do not push the residual and output lines out of L2.  The jump coupling works in FP32 from the scalar patch mass
+// block: the velocity mass couples equal components only, with the same
+// scalar block for both, and the patch velocity DoFs come in (x, y) pairs of
+// a node.  FULL = true is the interior patch (nb = 39), whose sizes are all
+// compile-time constants; FULL = false handles the smaller boundary patches.
+// Panels past a block's last one re-read its last panel: their columns meet
+// zeros of the right-hand side, so they add nothing.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline float4 load_stream(const float* p) {
+  const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+
 template <int NQ, bool FULL>
 __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P, int first,
                                                        const float* __restrict__ fac,
                                                        const double* __restrict__ Mp, double e00,
                                                        double e01, const double* __restrict__ r,
-                                                       double* __restrict__ Y) {
+                                                       float* __restrict__ Y) {
   constexpr int MAXM = kMaxNb * NQ;
   constexpr int VW = 4;
   constexpr int MAXP = (MAXM + VW - 1) / VW;   // 10 or 20 panels
   constexpr int K2 = (MAXP + 3) / 4;
   constexpr bool kTwo = MAXM > 64;
   constexpr int R1F = MAXM < 64 ? MAXM : 64, R2F = MAXM - R1F;
+  constexpr int kLine = 16;                    // doubles in one 128-byte line
+  constexpr int CH = kLine / NQ;               // slabs per residual line
+  constexpr int RL = (kMaxNb * kLine + 63) / 64;   // residual loads per lane and line
+  constexpr int kMaxNn = kMaxNbu / 2;          // velocity nodes of a patch
+  constexpr int RW = kTwo ? 128 : 64;
   __shared__ int dofs[kMaxNb];
-  __shared__ float MsT[kMaxNbu * kMaxNbu];     // patch mass block, transposed
+  __shared__ float MsT[kMaxNn * kMaxNn];       // scalar patch mass block, transposed
   __shared__ float g[MAXP * VW + 4];
   __shared__ float ylast[kMaxNbu];
   __shared__ float mj[kMaxNbu];
-  // residual of the current chunk of CH slabs (one 128-byte line of a DoF's
-  // values), so each line is fetched once instead of once per slab
-  constexpr int CH = 16 / NQ;
-  __shared__ float rch[CH][2 * 64];
+  __shared__ float rch[CH][RW];                // residual of the current CH slabs
+  constexpr int YCH = 2 * CH;                  // slabs per 128-byte line of FP32 outputs
+  __shared__ float ych[YCH * MAXM];            // outputs of the current YCH slabs
+  constexpr int YL = (YCH * MAXM + 255) / 256; // 16-byte output stores per lane and line
   const float e0[2] = {(float)e00, (float)e01};
   const int p = P.order[first + blockIdx.x], lane = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = FULL ? kMaxNb : P.patch_ptr[p + 1] - s0;
   const int nbu = FULL ? kMaxNbu : P.patch_nbu[p];
+  const int nn = nbu / 2;
   const int m = nb * NQ, N = L.N;
   const BlockLayout lay(m, VW);
   const int PH = FULL ? MAXP : lay.P;
   const int r1 = FULL ? R1F : lay.r1, r2 = FULL ? R2F : lay.r2;
   const int nk2 = FULL ? (R2F > 0 ? K2 : 0) : lay.k2(0);
-  const int S = FULL ? (MAXP * R1F + (R2F > 0 ? K2 * 4 * R2F : 0)) * VW : lay.size();
   for (int i = lane; i < nb; i += 64) dofs[i] = P.patch_dofs[s0 + i];
   const double* mp = Mp + P.mp_off[p];
-  for (int e = lane; e < nbu * nbu; e += 64) MsT[(e % nbu) * nbu + e / nbu] = (float)mp[e];
+  for (int e = lane; e < nn * nn; e += 64) {
+    const int i = e / nn, j = e % nn;
+    MsT[j * nn + i] = (float)mp[2 * i * nbu + 2 * j];
+  }
   for (int i = lane; i < kMaxNbu; i += 64) mj[i] = 0.0f;
   for (int i = lane; i < MAXP * VW + 4; i += 64) g[i] = 0.0f;
   __syncthreads();
   const float* Ab = fac + P.fac_off[p];
   const int64_t SS = P.slab_stride;
-  double* yout = Y + P.y_off[p];
+  float* yout = Y + 2 * P.y_off[p];   // FP32 outputs at the byte offset of the FP64 layout
   const unsigned row1 = lane < r1 ? lane : 0;
   const unsigned base1 = row1 * VW, step1 = r1 * VW;
   const unsigned lane2 = lane < 4 * r2 ? lane : 0;
@@ -212,41 +236,73 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
   const int lastq = PH - 1, lastk = nk2 > 0 ? nk2 - 1 : 0;
   const int rowA = lane, rowB = lane + 64;
   const bool hasA = rowA < m, hasB = kTwo && rowB < m;
-  const int64_t bA = hasA ? (int64_t)dofs[rowA / NQ] * N * NQ + rowA % NQ : 0;
-  const int64_t bB = hasB ? (int64_t)dofs[rowB / NQ] * N * NQ + rowB % NQ : 0;
   const int iA = rowA / NQ, iB = rowB / NQ;
   const int quarter = lane & 3;
+  const int nq = N * NQ;
+  const int nel = nb * kLine;
   float4 a1[MAXP];
   float4 a2[kTwo ? K2 : 1];
+  double rv[RL];
   auto issue = [&](int n) {
     const float* blk = Ab + (int64_t)n * SS;
 #pragma unroll
     for (int q = 0; q < MAXP; ++q) {
       const unsigned qq = FULL ? q : (q < lastq ? q : lastq);
-      a1[q] = *reinterpret_cast<const float4*>(blk + base1 + qq * step1);
+      a1[q] = load_stream(blk + base1 + qq * step1);
     }
     if constexpr (kTwo) {
 #pragma unroll
       for (int k = 0; k < K2; ++k) {
         const unsigned kk = FULL ? k : (k < lastk ? k : lastk);
-        a2[k] = *reinterpret_cast<const float4*>(blk + base2 + kk * step2);
+        a2[k] = load_stream(blk + base2 + kk * step2);
       }
     }
   };
-  for (int n = 0; n < N; ++n) {
-    issue(n);
-    const int s = n % CH;
-    if (s == 0) {
-      // each lane stages only its own rows: no barrier needed
-      for (int t = 0; t < CH; ++t) {
-        const bool in = n + t < N;
-        rch[t][lane] = (hasA && in) ? (float)r[bA + (int64_t)(n + t) * NQ] : 0.0f;
-        if (kTwo) rch[t][64 + lane] = (hasB && in) ? (float)r[bB + (int64_t)(n + t) * NQ] : 0.0f;
+  // line of CH slabs from slab n0 (a multiple of CH) of every patch DoF:
+  // element id = 16 d + j of the chunk is value j of DoF d's line
+  auto stage_issue = [&](int n0) {
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      int id = i * 64 + lane;
+      id = id < nel ? id : nel - 1;
+      int e = n0 * NQ + (id & (kLine - 1));
+      e = e < nq ? e : nq - 1;
+      rv[i] = r[(int64_t)dofs[id >> 4] * nq + e];
+    }
+  };
+  auto stage_store = [&]() {
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const int id = i * 64 + lane, j = id & (kLine - 1);
+      if (id < nel) rch[j / NQ][(id >> 4) * NQ + j % NQ] = (float)rv[i];
+    }
+  };
+  // outputs of slabs n0 .. n0 + ns - 1 (n0 a multiple of YCH), four a lane;
+  // the chunk starts on a line boundary (the output region is line-aligned
+  // and a chunk of YCH slabs is nb whole lines)
+  auto flush = [&](int n0, int ns) {
+    const int elems = ns * m;
+    float* yo = yout + (int64_t)n0 * m;
+#pragma unroll
+    for (int i = 0; i < YL; ++i) {
+      const int e = 4 * (i * 64 + lane);
+      if (e + 3 < elems) {
+        *reinterpret_cast<float4*>(yo + e) = make_float4(ych[e], ych[e + 1], ych[e + 2], ych[e + 3]);
+      } else {
+        for (int j = e; j < elems; ++j) yo[j] = ych[j];
       }
     }
+  };
+  if (N > 0) {
+    stage_issue(0);
+    issue(0);
+    stage_store();
+  }
+  for (int n = 0; n < N; ++n) {
+    const int s = n % CH;
     float gA = 0.0f, gB = 0.0f;
     if (hasA) gA = rch[s][lane] + ((n > 0 && iA < nbu) ? e0[rowA % NQ] * mj[iA] : 0.0f);
-    if (hasB) gB = rch[s][64 + lane] + ((n > 0 && iB < nbu) ? e0[rowB % NQ] * mj[iB] : 0.0f);
+    if (kTwo && hasB) gB = rch[s][RW - 64 + lane] + ((n > 0 && iB < nbu) ? e0[rowB % NQ] * mj[iB] : 0.0f);
     if constexpr (kTwo) {
       g[rowA] = gA;
       if (rowB < MAXP * VW) g[rowB] = gB;
@@ -276,14 +332,25 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
       acc2 += __shfl_xor(acc2, 1);
       acc2 += __shfl_xor(acc2, 2);
     }
+    // the block registers are free: start the next slab's loads (the last
+    // slab re-reads its own block, an L2 hit, so the loads stay unconditional).
+    // The empty asm pins the products here: without it the compiler sinks
+    // them to their stores, past the loads, and needs a second register set.
+    asm volatile("" : "+v"(acc1), "+v"(acc2) : : "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    const bool line = n + 1 < N && (n + 1) % CH == 0;
+    if (line) stage_issue(n + 1);
+    issue(n + 1 < N ? n + 1 : n);
+    __builtin_amdgcn_sched_barrier(0);
+    const int sy = n % YCH;
     if (lane < r1) {
-      yout[(int64_t)n * m + lane] = (double)acc1;
+      ych[sy * m + lane] = acc1;
       if (lane % NQ == NQ - 1) ylast[lane / NQ] = acc1;
     }
     if constexpr (kTwo) {
       if (lane < 4 * r2 && quarter == 0) {
         const int row = 64 + lane / 4;
-        yout[(int64_t)n * m + row] = (double)acc2;
+        ych[sy * m + row] = acc2;
         if (row % NQ == NQ - 1) ylast[row / NQ] = acc2;
       }
     }
@@ -291,11 +358,14 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
     // jump coupling of the next slab: mj = M_v y_n(end of slab); the slab end
     // value is the last temporal node (right Radau nodes)
     if (lane < nbu) {
+      const int a = lane >> 1, c = lane & 1;
       float acc = 0.0f;
-#pragma unroll 8
-      for (int j = 0; j < nbu; ++j) acc += MsT[j * nbu + lane] * ylast[j];
+#pragma unroll 4
+      for (int k = 0; k < nn; ++k) acc += MsT[k * nn + a] * ylast[2 * k + c];
       mj[lane] = acc;
     }
+    if (sy == YCH - 1 || n == N - 1) flush(n - sy, sy + 1);
+    if (line) stage_store();
     __syncthreads();
   }
 }
@@ -437,9 +507,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
 #undef O2
 }
 
-template <int NQ>
+// Y: FP64 patch outputs at y_off, or FP32 ones at twice y_off (same bytes)
+template <int NQ, typename TY>
 __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P,
-                                                      const double* __restrict__ Y, int mode,
+                                                      const TY* __restrict__ Y, int mode,
                                                       double c1, double c2, double* __restrict__ z,
                                                       double* __restrict__ d, double* __restrict__ x) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -452,8 +523,8 @@ __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P
     const int p = P.slot_patch[s];
     const int s0 = P.patch_ptr[p];
     const int m = (P.patch_ptr[p + 1] - s0) * NQ;
-    const double* yp = Y + P.y_off[p] + (int64_t)n * m + (s - s0) * NQ;
-    for (int a = 0; a < NQ; ++a) acc[a] += yp[a];
+    const TY* yp = Y + (sizeof(TY) == 4 ? 2 : 1) * P.y_off[p] + (int64_t)n * m + (s - s0) * NQ;
+    for (int a = 0; a < NQ; ++a) acc[a] += (double)yp[a];
   }
   const int64_t o = t * NQ;
   if (mode == 0) {
@@ -491,7 +562,7 @@ hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const doubl
 
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
-                              const double* r, double* Y, hipStream_t s) {
+                              const double* r, void* Y, hipStream_t s) {
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
   dim3 grid(P.n_patch);
   // wavefronts per patch = panels of the largest block / kPanelsPerWave
@@ -500,26 +571,33 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
     if (e1[L.NQ - 1] != 1.0 || (L.NQ > 1 && e1[0] != 0.0)) return hipErrorInvalidValue;
     const int nfull = P.n_full, nrest = P.n_patch - P.n_full;
     if (L.NQ == 1) {
-      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<1, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, Y);
-      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<1, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, Y);
+      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<1, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
+      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<1, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
     } else {
-      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<2, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, Y);
-      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<2, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, Y);
+      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<2, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
+      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<2, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
     }
   } else {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
-    else hipLaunchKernelGGL((k_patch_sweep<2, double, 4>), grid, dim3(256), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, Y);
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+    else hipLaunchKernelGGL((k_patch_sweep<2, double, 4>), grid, dim3(256), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, const double* Y, int mode,
-                               double c1, double c2, double* z, double* d, double* x,
+hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,
+                               int mode, double c1, double c2, double* z, double* d, double* x,
                                hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (L.NQ == 1) hipLaunchKernelGGL(k_patch_gather<1>, grid, block, 0, s, L.nf, L.N, P, Y, mode, c1, c2, z, d, x);
-  else hipLaunchKernelGGL(k_patch_gather<2>, grid, block, 0, s, L.nf, L.N, P, Y, mode, c1, c2, z, d, x);
+  if (prec == 1) {
+    const float* Yf = (const float*)Y;
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_gather<1, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
+    else hipLaunchKernelGGL((k_patch_gather<2, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
+  } else {
+    const double* Yd = (const double*)Y;
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_gather<1, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x);
+    else hipLaunchKernelGGL((k_patch_gather<2, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x);
+  }
   return hipGetLastError();
 }
 
