@@ -39,6 +39,14 @@ struct Vec<double> {
 
 __host__ __device__ inline int round_up(int m, int w) { return (m + w - 1) / w * w; }
 
+// 16-byte nontemporal load of streamed data (read once per sweep): it does
+// not displace the reused residual and output lines from L2
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline float4 load_stream(const float* p) {
+  const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+
 template <int NQ, typename T>
 __global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, PatchView P,
                                                               const double* __restrict__ Jv,
@@ -174,12 +182,6 @@ __device__ inline T dotv(const V& w, const T* g) {
 // compile-time constants; FULL = false handles the smaller boundary patches.
 // Panels past a block's last one re-read its last panel: their columns meet
 // zeros of the right-hand side, so they add nothing.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-__device__ inline float4 load_stream(const float* p) {
-  const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
-  return make_float4(t.x, t.y, t.z, t.w);
-}
-
 template <int NQ, bool FULL>
 __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P, int first,
                                                        const float* __restrict__ fac,
