@@ -159,6 +159,20 @@ int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts);
  * nodes; the initial value is the P2 interpolant of the velocity at t = 0. */
 int32_t stwr_nonlinear_residual(stwr_problem* p, const double* U, double* F);
 
+/* Space-time velocity L2 error of U against the manufactured velocity,
+ * sqrt(sum_n int_{I_n} ||u - U||^2 dt) (the error measure of the paper's
+ * convergence tables, Sec. 5), by the residual's quadrature rules.  U: device
+ * vector of length n_st(0); err: host scalar (the call synchronises).  The
+ * sum has a fixed order, so repeated calls give identical results. */
+int32_t stwr_velocity_l2_error(stwr_problem* p, const double* U, double* err);
+
+/* Full nodal space-time vector from a free one (adds the Dirichlet values):
+ * full = [ux at every P2 node][uy at every P2 node][p at every vertex], each
+ * row [slab][temporal node]; P2 nodes number i + (2M+1) j on the (2M+1)^2
+ * grid of the mesh, vertices i + (M+1) j.  Length
+ * (2 (2M+1)^2 + (M+1)^2) N (q+1); device pointers, caller-owned. */
+int32_t stwr_expand(stwr_problem* p, const double* U, double* full);
+
 /* Jacobian dF/dU at U (level 0 vector) on every level: the iterate is
  * injected to the coarse nodes and each level rediscretised; also factors
  * the coarsest level (bordered by one zero-mean pressure constraint per

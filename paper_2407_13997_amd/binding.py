@@ -25,7 +25,8 @@ EXPORTED = [
     "stwr_default_opts", "stwr_ctx_create", "stwr_ctx_destroy", "stwr_ctx_set_stream",
     "stwr_last_error", "stwr_ctx_bytes_in_use", "stwr_problem_bytes", "stwr_mesh_info",
     "stwr_problem_create", "stwr_problem_destroy", "stwr_problem_sizes", "stwr_set_opts",
-    "stwr_nonlinear_residual", "stwr_assemble", "stwr_get_operator", "stwr_apply",
+    "stwr_nonlinear_residual", "stwr_velocity_l2_error", "stwr_expand", "stwr_assemble",
+    "stwr_get_operator", "stwr_apply",
     "stwr_residual", "stwr_patch_factor", "stwr_patch_apply", "stwr_eig_estimate",
     "stwr_relax", "stwr_restrict", "stwr_prolong_add", "stwr_coarse_solve",
     "stwr_setup_smoothers", "stwr_vcycle", "stwr_fgmres", "stwr_newton_solve",
@@ -119,6 +120,8 @@ def load(path: str | None = None):
         "stwr_problem_sizes": [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)],
         "stwr_set_opts": [P, ctypes.POINTER(SolverOpts)],
         "stwr_nonlinear_residual": [P, V, V],
+        "stwr_velocity_l2_error": [P, V, ctypes.POINTER(f64)],
+        "stwr_expand": [P, V, V],
         "stwr_assemble": [P, V],
         "stwr_get_operator": [P, i32, ctypes.POINTER(i64), V, V, V, V],
         "stwr_apply": [P, i32, V, V],
@@ -292,6 +295,23 @@ class Problem:
 
     def nonlinear_residual(self, U, F):
         self.ctx.check(self.lib.stwr_nonlinear_residual(self.h, _ptr(U), _ptr(F)))
+
+    def velocity_l2_error(self, U) -> float:
+        err = ctypes.c_double()
+        self.ctx.check(self.lib.stwr_velocity_l2_error(self.h, _ptr(U), ctypes.byref(err)))
+        return err.value
+
+    def full_length(self) -> int:
+        M = self.prob.mesh_n
+        return (2 * (2 * M + 1) ** 2 + (M + 1) ** 2) * self.prob.n_slabs * (self.prob.q + 1)
+
+    def expand(self, U, full=None):
+        """Full nodal vector (ux, uy at every P2 node, p at every vertex)."""
+        import torch
+        if full is None:
+            full = torch.empty(self.full_length(), dtype=torch.float64, device=U.device)
+        self.ctx.check(self.lib.stwr_expand(self.h, _ptr(U), _ptr(full)))
+        return full
 
     def assemble(self, U):
         self.ctx.check(self.lib.stwr_assemble(self.h, _ptr(U)))

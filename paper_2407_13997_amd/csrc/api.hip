@@ -1033,6 +1033,31 @@ int32_t stwr_nonlinear_residual(stwr_problem* p, const double* U, double* F) {
   });
 }
 
+int32_t stwr_velocity_l2_error(stwr_problem* p, const double* U, double* err) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!U || !err) throw StwrError(STWR_ERR_ARG, "null pointer");
+    Level& L = p->lv[0];
+    // per-(cell, slab) partial sums in the finest level's residual buffer
+    // (nc N <= n_st), the total in the scalar buffer
+    HIPCHK(launch_velocity_error(L.view, p->d_tab, p->mms, U, L.r, p->dscal, p->s()));
+    double h = 0.0;
+    HIPCHK(hipMemcpyAsync(&h, p->dscal, 8, hipMemcpyDeviceToHost, p->s()));
+    HIPCHK(hipStreamSynchronize(p->s()));
+    *err = std::sqrt(h);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_expand(stwr_problem* p, const double* U, double* full) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!U || !full) throw StwrError(STWR_ERR_ARG, "null vector");
+    HIPCHK(launch_expand(p->lv[0].view, p->d_tab, p->mms, U, full, p->s()));
+    return STWR_OK;
+  });
+}
+
 int32_t stwr_assemble(stwr_problem* p, const double* U) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {

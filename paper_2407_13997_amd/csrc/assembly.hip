@@ -350,7 +350,97 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
   }
 }
 
+// Space-time velocity L2 error (Sec. 5, the error norm of the convergence
+// tables): part[n * nc + c] = int_{I_n} int_c |u - U|^2, by the residual's
+// quadrature (q + 3 Gauss points in time, the 25-point rule in space).
+// The per-workgroup sum runs in a fixed tree, so the result is deterministic.
+template <int NQ>
+__global__ __launch_bounds__(64) void k_velocity_error(LevelView L, const RefTables* __restrict__ T,
+                                                       MmsDev mms, const double* __restrict__ U,
+                                                       double* __restrict__ part) {
+  const int c = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  __shared__ CellStage<NQ> S;
+  __shared__ double red[64];
+  stage_cell<NQ>(L, T, mms, U, c, n, S);
+  double acc = 0.0;
+  for (int e = tid; e < T->G * kQx; e += 64) {
+    const int g = e / kQx, x = e % kQx;
+    double ux, uy;
+    exact_velocity(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], ux, uy);
+    const double dx = ux - S.uq[g][x][0], dy = uy - S.uq[g][x][1];
+    acc += T->wg[g] * S.wdet[x] * (dx * dx + dy * dy);
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) part[(int64_t)n * L.nc + c] = L.dt * red[0];
+}
+
+// out[0] = sum of part[0 .. n), one workgroup, fixed summation order.
+__global__ __launch_bounds__(256) void k_sum(int64_t n, const double* __restrict__ part,
+                                             double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Full nodal vector from a free one: [ux: nn][N][NQ], [uy: nn][N][NQ],
+// [p: nv][N][NQ]; Dirichlet velocity values are the exact velocity at the
+// node and temporal node (the boundary data of the problem).
+__global__ __launch_bounds__(256) void k_expand(LevelView L, const RefTables* __restrict__ T,
+                                                MmsDev mms, const double* __restrict__ U,
+                                                double* __restrict__ full) {
+  const int64_t nn = (int64_t)L.n2 * L.n2, nv = (int64_t)L.n1 * L.n1;
+  const int64_t nt = (int64_t)L.N * L.NQ;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (2 * nn + nv) * nt) return;
+  const int64_t row = e / nt, tt = e % nt;
+  double v;
+  if (row < 2 * nn) {
+    const int comp = (int)(row / nn), node = (int)(row % nn);
+    const int k = L.node_free[node];
+    if (k >= 0) {
+      v = U[(int64_t)(2 * k + comp) * nt + tt];
+    } else {
+      const int n = (int)(tt / L.NQ), a = (int)(tt % L.NQ);
+      double ux, uy;
+      exact_velocity(mms, (n + T->tnode[a]) * L.dt, (node % L.n2) * 0.5 * L.h,
+                     (node / L.n2) * 0.5 * L.h, ux, uy);
+      v = comp == 0 ? ux : uy;
+    }
+  } else {
+    v = U[(L.po + (row - 2 * nn)) * nt + tt];
+  }
+  full[e] = v;
+}
+
 }  // namespace
+
+hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDev mms,
+                                 const double* U, double* part, double* out, hipStream_t s) {
+  dim3 grid(L.nc, L.N);
+  if (L.NQ == 1) hipLaunchKernelGGL(k_velocity_error<1>, grid, dim3(64), 0, s, L, tab, mms, U, part);
+  else hipLaunchKernelGGL(k_velocity_error<2>, grid, dim3(64), 0, s, L, tab, mms, U, part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (int64_t)L.nc * L.N, part, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, const double* U,
+                         double* full, hipStream_t s) {
+  const int64_t n = ((int64_t)2 * L.n2 * L.n2 + (int64_t)L.n1 * L.n1) * L.N * L.NQ;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L, tab, mms, U, full);
+  return hipGetLastError();
+}
 
 hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
                                     const double* U, double* Jv, double* Mv, hipStream_t s) {

@@ -99,6 +99,12 @@ hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, Mm
                                     const double* U, double* Jv, double* Mv, hipStream_t s);
 hipError_t launch_assemble_residual(const LevelView& L, const RefTables* tab, MmsDev mms,
                                     const double* U, double* F, hipStream_t s);
+// out[0] = squared space-time velocity L2 error; part: nc * N doubles of workspace
+hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDev mms,
+                                 const double* U, double* part, double* out, hipStream_t s);
+// full: (2 nn + nv) N NQ doubles (ux, uy at every P2 node, p at every vertex)
+hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, const double* U,
+                         double* full, hipStream_t s);
 
 // ---- linear algebra ----------------------------------------------------------
 hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, const double* e0,

@@ -65,6 +65,37 @@ def test_nonlinear_residual(case):
 
 
 @pytest.mark.parametrize("case", list(CASES))
+def test_velocity_l2_error(case):
+    """Space-time velocity L2 error against the manufactured velocity, by the
+    same quadrature on both sides; the device sum has a fixed order."""
+    prob, G, H, U, Ud = setup_case(case)
+    L0 = H.levels[0]
+    e1 = G.velocity_l2_error(Ud)
+    e2 = G.velocity_l2_error(Ud)
+    eo = L0.velocity_l2_error(U.reshape(L0.n_free, L0.N, L0.nq))
+    log(f"[l2 error] {case} gpu={e1:.15e} oracle={eo:.15e}")
+    assert e1 == e2
+    assert abs(e1 - eo) <= 1e-12 * eo
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_expand_full_vector(case):
+    """Free vector plus Dirichlet data at every P2 node and temporal node."""
+    prob, G, H, U, Ud = setup_case(case)
+    L0 = H.levels[0]
+    ux, uy, p = L0.full_state(U.reshape(L0.n_free, L0.N, L0.nq))
+    ref = np.concatenate([ux.ravel(), uy.ravel(), p.ravel()])
+    full = to_host(G.expand(Ud))
+    fr = np.concatenate([L0.mesh.node_free >= 0] * 2)
+    nt = L0.N * L0.nq
+    free_mask = np.concatenate([np.repeat(fr, nt), np.ones(p.size, dtype=bool)])
+    log(f"[expand] {case} len={full.size} rel={rel(full, ref):.2e}")
+    assert full.size == ref.size
+    assert np.array_equal(full[free_mask], ref[free_mask])      # copied values
+    assert np.max(np.abs(full - ref)) <= 1e-14 * max(np.max(np.abs(ref)), 1.0)
+
+
+@pytest.mark.parametrize("case", list(CASES))
 def test_jacobian_entries_all_levels(case):
     prob, G, H, U, Ud = setup_case(case)
     for l, lev in enumerate(H.levels):
