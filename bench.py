@@ -206,7 +206,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (profiled_traffic() if (args.mesh, args.slabs, args.prec) == (128, 64, "fp32")
                                  else None),
-                     "kernel": "k_patch_sweep", "avg_ms": sweep_avg_ms,
+                     "kernel": ("k_patch_sweep_f32 (interior + boundary launches)" if prec == binding.FP32
+                                else "k_patch_sweep"), "avg_ms": sweep_avg_ms,
                      "algorithmic_bytes": info_bytes},
         "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "setup_s": {"assemble_all_levels": t_asm, "factor_finest": t_fac, "eig_estimate": t_eig},
@@ -224,12 +225,13 @@ def main():
     ctx.close()
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_patch_sweep_ns_p2p1_dg1_m128_n64_re1000.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_patch_sweep_f32_ns_p2p1_dg1_m128_n64_re1000.md")
 
 
 def profiled_traffic() -> int | None:
-    """HBM bytes per k_patch_sweep launch from the committed rocprofv3 byte
-    counters, only while the kernel source is the one that was profiled."""
+    """HBM bytes of one FP32 patch sweep (its interior and boundary launches)
+    from the committed rocprofv3 byte counters, only while the kernel source is
+    the one that was profiled."""
     import hashlib
     try:
         text = open(PROFILE).read()
