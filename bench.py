@@ -106,7 +106,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    prob = w.config_problem(4)
+    prob = w.named_problem(w.LARGE)
     if (args.mesh, args.slabs, args.levels) != (128, 64, 6):
         prob = w.Problem(args.mesh, args.levels, 1, args.slabs, 1.0, 1000.0,
                          prob.psi_ab, prob.psi_coef, prob.p_ab, prob.p_coef, seed=prob.seed)
@@ -197,7 +197,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 patch factors/solves, f64 residual/update",
         "data": "synthetic manufactured solution (seeded Fourier modes)",
-        "config": {"workload": f"{w.CONFIG_NAMES.get(4)} finest-level WR sweep" if args.mesh == 128
+        "config": {"workload": f"{w.LARGE} finest-level WR sweep" if args.mesh == 128
                    else f"ns_p2p1_dg1_m{args.mesh}_n{args.slabs} finest-level WR sweep",
                    "mesh": args.mesh, "q": 1, "slabs": args.slabs, "reynolds": 1000.0,
                    "levels": args.levels, "st_dofs": n_st, "patches": n_patch,

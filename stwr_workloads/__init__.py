@@ -24,8 +24,8 @@ import math
 
 import numpy as np
 
-__all__ = ["Problem", "draw_modes", "config_problem", "batch_problems",
-           "arrival_times", "CONFIG_NAMES"]
+__all__ = ["Problem", "draw_modes", "named_problem", "batch_problems",
+           "arrival_times", "WORKLOADS", "SMOKE", "MEDIUM", "LARGE"]
 
 
 @dataclasses.dataclass
@@ -83,26 +83,26 @@ def draw_modes(seed: int, n_psi: int = 4, n_p: int = 3, max_wave: int = 4,
             np.ascontiguousarray(p_ab), np.ascontiguousarray(p_coef))
 
 
-CONFIG_NAMES = {
-    0: "ns_p2p1_dg0_m4_n4_re1",
-    1: "ns_p2p1_dg1_m32_n32_re100",
-    4: "ns_p2p1_dg1_m128_n64_re1000",
+# The fixed single-solve workloads, by name: (mesh, levels, q, slabs, Re,
+# stream-function modes, highest wave number, base seed); seed = base + index.
+WORKLOADS = {
+    "ns_p2p1_dg0_m4_n4_re1": (4, 2, 0, 4, 1.0, 4, 4, 0),
+    "ns_p2p1_dg1_m32_n32_re100": (32, 4, 1, 32, 100.0, 4, 4, 1000),
+    "ns_p2p1_dg1_m128_n64_re1000": (128, 6, 1, 64, 1000.0, 16, 8, 4000),
 }
+SMOKE = "ns_p2p1_dg0_m4_n4_re1"
+MEDIUM = "ns_p2p1_dg1_m32_n32_re100"
+LARGE = "ns_p2p1_dg1_m128_n64_re1000"
 
 
-def config_problem(config: int, index: int = 0) -> Problem:
-    """The fixed single-solve workloads (configs 0, 1 and 4); seed = 1000*config + index."""
-    seed = 1000 * config + index
-    if config == 0:
-        modes = draw_modes(seed, 4, 3, 4)
-        return Problem(4, 2, 0, 4, 1.0, 1.0, *modes, seed=seed)
-    if config == 1:
-        modes = draw_modes(seed, 4, 3, 4)
-        return Problem(32, 4, 1, 32, 1.0, 100.0, *modes, seed=seed)
-    if config == 4:
-        modes = draw_modes(seed, 16, 3, 8)
-        return Problem(128, 6, 1, 64, 1.0, 1000.0, *modes, seed=seed)
-    raise ValueError(f"no fixed workload for config {config}")
+def named_problem(name: str, index: int = 0) -> Problem:
+    """One of the fixed workloads (4x4 smoke solve, 32x32 solve, 128x128 sweep)."""
+    if name not in WORKLOADS:
+        raise ValueError(f"no fixed workload named {name}")
+    mesh, levels, q, slabs, re, n_psi, wave, base = WORKLOADS[name]
+    seed = base + index
+    modes = draw_modes(seed, n_psi, 3, wave)
+    return Problem(mesh, levels, q, slabs, 1.0, re, *modes, seed=seed)
 
 
 def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,

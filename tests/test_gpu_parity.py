@@ -272,13 +272,13 @@ def test_fgmres_solution(case):
     assert abs(st["linear_total"] - its) <= 1
 
 
-def test_newton_config0_matches_exact_discrete_solution():
-    """Config 0: FP64 GPU Newton (one step and to convergence) against the
+def test_newton_m4_matches_exact_discrete_solution():
+    """4x4, DG(0), 4 slabs, Re 1: FP64 GPU Newton (one step and to convergence) against the
     oracle's Newton step and its all-at-once exact discrete solution."""
     torch_cuda()
     from oracle.direct import solve_all_at_once
     from oracle.multigrid import Options, newton_solve
-    prob = w.config_problem(0)
+    prob = w.named_problem(w.SMOKE)
     G = gpu_problem(prob, nu_pre=1, nu_post=1, newton_maxit=1)
     U = G.vec()
     st = G.newton_solve(U, allow_unconverged=True)

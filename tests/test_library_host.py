@@ -66,18 +66,18 @@ def test_host_patches_match_oracle():
 def test_problem_bytes_and_argument_checks():
     b = lib()
     import stwr_workloads as w
-    p0 = b.problem_bytes(w.config_problem(0))
-    p1 = b.problem_bytes(w.config_problem(1))
+    p0 = b.problem_bytes(w.named_problem(w.SMOKE))
+    p1 = b.problem_bytes(w.named_problem(w.MEDIUM))
     assert 0 < p0 < p1
     o = b.default_opts()
     o.smoother_prec = b.FP32
-    assert b.problem_bytes(w.config_problem(1), o) < p1
-    bad = w.config_problem(0)
+    assert b.problem_bytes(w.named_problem(w.MEDIUM), o) < p1
+    bad = w.named_problem(w.SMOKE)
     bad.q = 3
     with pytest.raises(b.StwrError) as e:
         b.problem_bytes(bad)
     assert e.value.code == -1
-    bad = w.config_problem(0)
+    bad = w.named_problem(w.SMOKE)
     bad.n_levels = 4   # 4 / 2^3 is not a mesh
     with pytest.raises(b.StwrError):
         b.problem_bytes(bad)

@@ -76,9 +76,9 @@ def test_block_lower_bidiagonal_with_jump_coupling(q):
                 assert not np.any(B)
 
 
-def test_three_routes_agree_config0():
+def test_three_routes_agree_m4():
     """R1 (Newton-FGMRES-WRMG), R2 (slab by slab) and R3 (all-at-once LU)."""
-    p = w.config_problem(0)
+    p = w.named_problem(w.SMOKE)
     x1, stats, H = newton_solve(p, Options(nu_pre=1, nu_post=1))
     L0 = H.levels[0]
     x2 = solve_slab_by_slab(L0)
