@@ -137,16 +137,19 @@ def main():
     torch.cuda.synchronize()
     ctx.set_timing(True)
     ctx.kernel_times()   # reset
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps (the library works on torch's
+    # current stream), so the per-step distribution comes with the total
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
+    ev[0].record()
+    for k in range(args.steps):
         P.relax(0, b, x, 1, a, bnd)
-    stop.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(stop)
+    ms_total = ev[0].elapsed_time(ev[-1])
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
     kt = ctx.kernel_times()
     ctx.set_timing(False)
     ms_step = ms_total / args.steps
@@ -209,6 +212,7 @@ def main():
                      "kernel": ("k_patch_sweep_f32 (interior + boundary launches)" if prec == binding.FP32
                                 else "k_patch_sweep"), "avg_ms": sweep_avg_ms,
                      "algorithmic_bytes": info_bytes},
+        "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "setup_s": {"assemble_all_levels": t_asm, "factor_finest": t_fac, "eig_estimate": t_eig},
         "vcycle_ms": vc_ms,

@@ -465,6 +465,16 @@ __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, do
   __shared__ double Rs[kGjPanel][64 + 1];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64, tid = threadIdx.x, b = k1 - k0;
   if (j0 + 64 > k0 && j0 < k1 && j0 >= k0 && j0 + 64 <= k1) return;   // tile inside the panel
+  const int tr = tid / 16, tc = tid % 16;   // 4 x 4 outputs per thread
+  // this thread's outputs, loaded first (clamped addresses, so every load is
+  // issued at once and their latency overlaps the staging below)
+  double bo[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = min(i0 + tr + 16 * a, m - 1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bo[a][c] = B[(int64_t)i * m + min(j0 + tc + 16 * c, m - 1)];
+  }
   for (int e = tid; e < 64 * kGjPanel; e += kBlock) {
     const int r = e / kGjPanel, t = e % kGjPanel, i = i0 + r;
     double w = 0.0;
@@ -476,10 +486,10 @@ __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, do
     Rs[t][c] = (t < b && j < m) ? R[(int64_t)t * m + j] : 0.0;
   }
   __syncthreads();
-  const int tr = tid / 16, tc = tid % 16;   // 4 x 4 outputs per thread
   double acc[4][4];
   for (int a = 0; a < 4; ++a)
     for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+#pragma unroll 4
   for (int t = 0; t < kGjPanel; ++t) {
     double wv[4], rv4[4];
     for (int a = 0; a < 4; ++a) wv[a] = Ws[tr + 16 * a][t];
@@ -493,8 +503,146 @@ __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, do
     for (int c = 0; c < 4; ++c) {
       const int j = j0 + tc + 16 * c;
       if (j >= m || (j >= k0 && j < k1)) continue;
-      B[(int64_t)i * m + j] += acc[a][c];
+      B[(int64_t)i * m + j] = bo[a][c] + acc[a][c];
     }
+  }
+}
+
+// Register-resident panel of the blocked Gauss-Jordan inverse, for m <= 512 RP:
+// thread t keeps the panel segments (kGjPanel columns) of rows t + 512 r,
+// r < RP, in registers for the whole panel, so a column step costs a few LDS
+// exchanges instead of a pass over the panel in memory.  After each step the
+// segments rotate left by one column, so the active column is always
+// register 0 and every register index is static; after b steps position j
+// holds panel column (j + b) mod kGjPanel.  Per element the arithmetic and
+// the pivot choice (largest magnitude, ties to the smaller row) are those of
+// k_bgj_panel.
+constexpr int kPanelThreads = 512;
+template <int RP>
+__global__ __launch_bounds__(kPanelThreads) void k_bgj_panel_reg(int m, int k0, int k1,
+                                                                 double* __restrict__ Ball,
+                                                                 int* __restrict__ perm,
+                                                                 int* __restrict__ status) {
+  constexpr int T = kPanelThreads, NW = T / 64, PB = kGjPanel;
+  double* B = Ball + (int64_t)blockIdx.x * m * m;
+  int* pm = perm + (int64_t)blockIdx.x * m;
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
+  __shared__ double swp[2][PB];
+  __shared__ double prow[PB];
+  const int tid = threadIdx.x, b = k1 - k0;
+  double a[RP][PB];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int i = tid + T * r;
+#pragma unroll
+    for (int j = 0; j < PB; ++j) a[r][j] = (i < m && j < b) ? B[(int64_t)i * m + k0 + j] : 0.0;
+  }
+  for (int kk = 0; kk < b; ++kk) {
+    const int k = k0 + kk;
+    // pivot: largest |a| in column k among rows >= k
+    double best = -1.0;
+    int bi = m;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int i = tid + T * r;
+      const double v = (i >= k && i < m) ? fabs(a[r][0]) : -1.0;
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
+    __syncthreads();
+    double bb = rv[0];
+    int p = ri[0];
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > bb || (rv[w] == bb && ri[w] < p)) { bb = rv[w]; p = ri[w]; }
+    if (!(bb > 0.0) || !isfinite(bb) || p >= m) {
+      if (tid == 0) status[0] = 1;
+      p = k;
+    }
+    if (tid == 0) pm[k] = p;
+    // swap rows k and p of the panel (uniform branch)
+    if (p != k) {
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int i = tid + T * r;
+        if (i == p)
+#pragma unroll
+          for (int j = 0; j < PB; ++j) swp[0][j] = a[r][j];
+        if (i == k)
+#pragma unroll
+          for (int j = 0; j < PB; ++j) swp[1][j] = a[r][j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int i = tid + T * r;
+        if (i == k)
+#pragma unroll
+          for (int j = 0; j < PB; ++j) a[r][j] = swp[0][j];
+        if (i == p)
+#pragma unroll
+          for (int j = 0; j < PB; ++j) a[r][j] = swp[1][j];
+      }
+    }
+    // scale the pivot row: the pivot entry becomes 1 / pivot
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      if (tid + T * r == k) {
+        const double pv = a[r][0];
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+          a[r][j] = (j == 0 ? 1.0 : a[r][j]) / pv;
+          prow[j] = a[r][j];
+        }
+      }
+    }
+    __syncthreads();
+    // eliminate column k from every other row (column by column, so each
+    // pivot-row value is read from LDS just before its use), then rotate
+    double f[RP];
+    bool live[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int i = tid + T * r;
+      live[r] = i < m && i != k;
+      f[r] = a[r][0];
+    }
+    {
+      const double p0 = prow[0];
+#pragma unroll
+      for (int r = 0; r < RP; ++r)
+        if (live[r]) a[r][0] = -f[r] * p0;
+    }
+#pragma unroll
+    for (int j = 1; j < PB; ++j) {
+      const double pj = prow[j];
+#pragma unroll
+      for (int r = 0; r < RP; ++r)
+        if (live[r]) a[r][j] = a[r][j] - f[r] * pj;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const double t0 = a[r][0];
+#pragma unroll
+      for (int j = 0; j + 1 < PB; ++j) a[r][j] = a[r][j + 1];
+      a[r][PB - 1] = t0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int i = tid + T * r;
+    if (i < m)
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        const int c = (j + b) % PB;
+        if (c < b) B[(int64_t)i * m + k0 + c] = a[r][j];
+      }
   }
 }
 
@@ -578,19 +726,24 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, in
   g[r] = v;
 }
 
-// 16 rows per workgroup, 16 lanes per row.
+// x_n = (inverse slab block) g, one wavefront per row, four rows per
+// workgroup; every lane issues all its loads of the row before reducing.
 template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_coarse_gemv(int nf, int N, int n, int mm,
                                                         const double* __restrict__ Bn,
                                                         const double* __restrict__ g,
                                                         double* __restrict__ x) {
-  const int row = blockIdx.x * 16 + threadIdx.x / 16, l = threadIdx.x % 16;
+  const int row = blockIdx.x * (kBlock / 64) + threadIdx.x / 64, l = threadIdx.x % 64;
   const int m = nf * NQ;
+  if (row >= m) return;
+  const double* br = Bn + (int64_t)row * mm;
   double acc = 0.0;
-  if (row < m)
-    for (int c = l; c < mm; c += 16) acc += Bn[(int64_t)row * mm + c] * g[c];
-  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-  if (row < m && l == 0) {
+  int c = l;
+  for (; c + 192 < mm; c += 256)
+    acc += br[c] * g[c] + br[c + 64] * g[c + 64] + br[c + 128] * g[c + 128] + br[c + 192] * g[c + 192];
+  for (; c < mm; c += 64) acc += br[c] * g[c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (l == 0) {
     const int i = row / NQ, a = row % NQ;
     x[((int64_t)i * N + n) * NQ + a] = acc;
   }
@@ -705,7 +858,12 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
   const dim3 gs(nblk(m), nmat), gt((m + 63) / 64, (m + 63) / 64, nmat), gp(nblk(m), nmat);
   for (int k0 = 0; k0 < m; k0 += kGjPanel) {
     const int k1 = k0 + kGjPanel < m ? k0 + kGjPanel : m;
-    hipLaunchKernelGGL(k_bgj_panel, dim3(nmat), dim3(kBlock), 0, s, m, k0, k1, B, perm, colbuf, status);
+    if (m <= kPanelThreads * 2)
+      hipLaunchKernelGGL(k_bgj_panel_reg<2>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+    else if (m <= kPanelThreads * 3)
+      hipLaunchKernelGGL(k_bgj_panel_reg<3>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+    else
+      hipLaunchKernelGGL(k_bgj_panel, dim3(nmat), dim3(kBlock), 0, s, m, k0, k1, B, perm, colbuf, status);
     hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf);
     hipLaunchKernelGGL(k_bgj_update, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
   }
@@ -720,7 +878,7 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
   if (mm > kMaxCoarse) return hipErrorInvalidValue;
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
   if (mm > 512) {
-    const unsigned gr = nblk(mm), gg = (unsigned)((L.nf * L.NQ + 15) / 16);
+    const unsigned gr = nblk(mm), gg = (unsigned)((L.nf * L.NQ + kBlock / 64 - 1) / (kBlock / 64));
     for (int n = 0; n < L.N; ++n) {
       const double* Bn = Binv + (int64_t)n * mm * mm;
       if (L.NQ == 1) {
