@@ -694,7 +694,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
 
 // Large coarsest levels: one slab at a time, with the right-hand side
 // g = b_n + e0 (x) (M (e1 . x_{n-1})) formed by one kernel and the product with
-// the inverted bordered block by another, many workgroups each.
+// the inverted bordered block by another, many workgroups each.  The
+// right-hand side takes 16 lanes per row, each summing every 16th nonzero of
+// the row's mass entries.
 template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, int n,
                                                        const int* __restrict__ rp,
@@ -704,26 +706,30 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, in
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ g) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int r = blockIdx.x * (kBlock / 16) + threadIdx.x / 16, l = threadIdx.x % 16;
   const int m = nf * NQ;
   if (r >= m + NQ) return;
-  if (r >= m) { g[r] = 0.0; return; }
+  if (r >= m) {
+    if (l == 0) g[r] = 0.0;
+    return;
+  }
   const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
   const int i = r / NQ, a = r % NQ;
-  double v = b[((int64_t)i * N + n) * NQ + a];
-  if (n > 0 && i < po) {
-    double jump = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      const double mk = Mv[k];
-      if (mk == 0.0) continue;
+  const bool jumps = n > 0 && i < po;
+  double jump = 0.0;
+  if (jumps) {
+    for (int k = rp[i] + l; k < rp[i + 1]; k += 16) {
       const double* xv = x + ((int64_t)col[k] * N + n - 1) * NQ;
       double xl = 0.0;
       for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xv[bb];
-      jump += mk * xl;
+      jump += Mv[k] * xl;
     }
-    v += e0[a] * jump;
   }
-  g[r] = v;
+  for (int off = 8; off > 0; off >>= 1) jump += __shfl_xor(jump, off, 16);
+  if (l == 0) {
+    const double v = b[((int64_t)i * N + n) * NQ + a];
+    g[r] = jumps ? v + e0[a] * jump : v;
+  }
 }
 
 // x_n = (inverse slab block) g, one wavefront per row, four rows per
@@ -878,7 +884,8 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
   if (mm > kMaxCoarse) return hipErrorInvalidValue;
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
   if (mm > 512) {
-    const unsigned gr = nblk(mm), gg = (unsigned)((L.nf * L.NQ + kBlock / 64 - 1) / (kBlock / 64));
+    const unsigned gr = (unsigned)((mm + kBlock / 16 - 1) / (kBlock / 16));
+    const unsigned gg = (unsigned)((L.nf * L.NQ + kBlock / 64 - 1) / (kBlock / 64));
     for (int n = 0; n < L.N; ++n) {
       const double* Bn = Binv + (int64_t)n * mm * mm;
       if (L.NQ == 1) {

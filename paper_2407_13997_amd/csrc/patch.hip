@@ -181,13 +181,31 @@ __device__ inline T dotv(const V& w, const T* g) {
 // a node.  FULL = true is the interior patch (nb = 39), whose sizes are all
 // compile-time constants; FULL = false handles the smaller boundary patches.
 // Panels past a block's last one re-read its last panel: their columns meet
-// zeros of the right-hand side, so they add nothing.
+// zeros of the right-hand side, so they add nothing.  Both forms run in one
+// launch (interior patches first), so on small meshes the boundary patches
+// overlap the interior ones instead of following them.
+template <int NQ>
+struct SweepF32Lds {
+  static constexpr int MAXM = kMaxNb * NQ;
+  static constexpr int MAXP = (MAXM + 3) / 4;
+  static constexpr int CH = 16 / NQ;           // slabs per 128-byte residual line
+  static constexpr int RW = MAXM > 64 ? 128 : 64;
+  static constexpr int kMaxNn = kMaxNbu / 2;   // velocity nodes of a patch
+  int dofs[kMaxNb];
+  float MsT[kMaxNn * kMaxNn];                  // scalar patch mass block, transposed
+  float g[MAXP * 4 + 4];
+  float ylast[kMaxNbu];
+  float mj[kMaxNbu];
+  float rch[CH][RW];                           // residual of the current CH slabs
+  float ych[2 * CH * MAXM];                    // outputs of the current 2 CH slabs
+};
+
 template <int NQ, bool FULL>
-__global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P, int first,
-                                                       const float* __restrict__ fac,
-                                                       const double* __restrict__ Mp, double e00,
-                                                       double e01, const double* __restrict__ r,
-                                                       float* __restrict__ Y) {
+__device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchView& P, const int p,
+                                                const float* __restrict__ fac,
+                                                const double* __restrict__ Mp, const double e00,
+                                                const double e01, const double* __restrict__ r,
+                                                float* __restrict__ Y, SweepF32Lds<NQ>& S) {
   constexpr int MAXM = kMaxNb * NQ;
   constexpr int VW = 4;
   constexpr int MAXP = (MAXM + VW - 1) / VW;   // 10 or 20 panels
@@ -197,19 +215,18 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
   constexpr int kLine = 16;                    // doubles in one 128-byte line
   constexpr int CH = kLine / NQ;               // slabs per residual line
   constexpr int RL = (kMaxNb * kLine + 63) / 64;   // residual loads per lane and line
-  constexpr int kMaxNn = kMaxNbu / 2;          // velocity nodes of a patch
   constexpr int RW = kTwo ? 128 : 64;
-  __shared__ int dofs[kMaxNb];
-  __shared__ float MsT[kMaxNn * kMaxNn];       // scalar patch mass block, transposed
-  __shared__ float g[MAXP * VW + 4];
-  __shared__ float ylast[kMaxNbu];
-  __shared__ float mj[kMaxNbu];
-  __shared__ float rch[CH][RW];                // residual of the current CH slabs
+  int* dofs = S.dofs;
+  float* MsT = S.MsT;
+  float* g = S.g;
+  float* ylast = S.ylast;
+  float* mj = S.mj;
+  float (*rch)[RW] = S.rch;
   constexpr int YCH = 2 * CH;                  // slabs per 128-byte line of FP32 outputs
-  __shared__ float ych[YCH * MAXM];            // outputs of the current YCH slabs
+  float* ych = S.ych;
   constexpr int YL = (YCH * MAXM + 255) / 256; // 16-byte output stores per lane and line
   const float e0[2] = {(float)e00, (float)e01};
-  const int p = P.order[first + blockIdx.x], lane = threadIdx.x;
+  const int lane = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = FULL ? kMaxNb : P.patch_ptr[p + 1] - s0;
   const int nbu = FULL ? kMaxNbu : P.patch_nbu[p];
@@ -370,6 +387,18 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
     if (line) stage_store();
     __syncthreads();
   }
+}
+
+template <int NQ>
+__global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P,
+                                                       const float* __restrict__ fac,
+                                                       const double* __restrict__ Mp, double e00,
+                                                       double e01, const double* __restrict__ r,
+                                                       float* __restrict__ Y) {
+  __shared__ SweepF32Lds<NQ> S;
+  const int p = P.order[blockIdx.x];
+  if ((int)blockIdx.x < P.n_full) sweep_f32_patch<NQ, true>(L, P, p, fac, Mp, e00, e01, r, Y, S);
+  else sweep_f32_patch<NQ, false>(L, P, p, fac, Mp, e00, e01, r, Y, S);
 }
 
 // One workgroup per patch, WAVES wavefronts, each owning at most
@@ -571,13 +600,10 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
   if (prec == 1) {
     // the FP32 kernel reads the slab end value as the last temporal node
     if (e1[L.NQ - 1] != 1.0 || (L.NQ > 1 && e1[0] != 0.0)) return hipErrorInvalidValue;
-    const int nfull = P.n_full, nrest = P.n_patch - P.n_full;
     if (L.NQ == 1) {
-      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<1, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
-      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<1, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
+      hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
     } else {
-      if (nfull) hipLaunchKernelGGL((k_patch_sweep_f32<2, true>), dim3(nfull), dim3(64), 0, s, L, P, 0, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
-      if (nrest) hipLaunchKernelGGL((k_patch_sweep_f32<2, false>), dim3(nrest), dim3(64), 0, s, L, P, nfull, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
+      hipLaunchKernelGGL(k_patch_sweep_f32<2>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
     }
   } else {
     if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
