@@ -79,7 +79,12 @@ typedef struct {
 
 /* Solver options (Sec. 3 and 4.2).  stwr_default_opts fills V(2,2),
  * Chebyshev [0.25, 1.05] * lam, 10 estimation steps, FP64 smoother,
- * FGMRES(30) with rtol 1e-10 and 200 iterations, Newton rtol 1e-10, 20 steps. */
+ * FGMRES(30) with rtol 1e-10 and 200 iterations, Newton rtol 1e-10, 20 steps,
+ * and vcycle_graph = 1: the V-cycle is captured once into a HIP graph (on the
+ * problem's stream, re-captured when the smoothers or options change) and
+ * replayed for every application, with results identical to the launched
+ * form; the graph's input and output vectors add 2 n_st(0) doubles to the
+ * problem.  0 launches the kernels one by one. */
 typedef struct {
   int32_t nu_pre, nu_post;
   double cheb_lo, cheb_hi;
@@ -89,6 +94,7 @@ typedef struct {
   double gmres_rtol;
   int32_t newton_maxit;
   double newton_rtol;
+  int32_t vcycle_graph;        /* 1: replay a captured HIP graph of the V-cycle; 0: launch */
 } stwr_solver_opts;
 
 #define STWR_MAX_NEWTON 64

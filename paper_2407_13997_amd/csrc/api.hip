@@ -153,6 +153,12 @@ struct stwr_problem {
   double *dscal = nullptr, *partial = nullptr;
   int* dstatus = nullptr;
   int* hstatus_pinned = nullptr;
+  // captured V-cycle: its executable graph, the state it was captured for,
+  // and its fixed input/output vectors
+  hipGraphExec_t vc_exec = nullptr;
+  std::vector<double> vc_sig;
+  double *vc_in = nullptr, *vc_out = nullptr;
+  hipStream_t vc_stream = nullptr;   // capture stream (the context's may be the null stream)
 
   hipStream_t s() const { return ctx->stream; }
 
@@ -238,7 +244,7 @@ void check_opts(const stwr_solver_opts* o) {
   if (o->nu_pre < 0 || o->nu_post < 0 || o->eig_steps < 1 || o->eig_steps > 64 || o->gmres_restart < 1 ||
       o->gmres_restart > 200 || o->gmres_maxit < 1 || o->newton_maxit < 0 || o->newton_maxit > STWR_MAX_NEWTON ||
       (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
-      !(o->cheb_lo > 0.0))
+      !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1))
     throw StwrError(STWR_ERR_ARG, "invalid solver options");
 }
 
@@ -313,6 +319,7 @@ uint64_t plan_bytes(const stwr_problem_desc* d, const stwr_solver_opts* o, const
     b += level_bytes(lv[l].H, l + 1 < L ? &lv[l].Tr : nullptr, d->n_slabs, d->q + 1, o->smoother_prec, l == L - 1);
   const int64_t n0 = lv[0].n_st;
   b += (uint64_t)(2 * o->gmres_restart + 1) * n0 * 8;
+  if (o->vcycle_graph) b += (uint64_t)2 * n0 * 8;                       // graph input, output
   b += (uint64_t)(256 + 4) * 256 * 8 + sizeof(RefTables) + 4096;
   return b;
 }
@@ -568,6 +575,73 @@ void vcycle(stwr_problem* P, const double* b0, double* x0) {
   }
 }
 
+// What a captured V-cycle depends on beyond device memory contents: the
+// Chebyshev intervals, the smoother precisions and factor storage, the
+// smoothing counts.
+std::vector<double> vcycle_signature(stwr_problem* P) {
+  const stwr_solver_opts& o = P->opts;
+  std::vector<double> s = {(double)o.nu_pre, (double)o.nu_post, o.cheb_lo, o.cheb_hi};
+  for (const Level& L : P->lv) {
+    s.push_back(L.lambda);
+    s.push_back((double)L.fac_prec);
+    s.push_back((double)(uintptr_t)L.fac);
+  }
+  return s;
+}
+
+void drop_vcycle_graph(stwr_problem* P) {
+  if (P->vc_exec) (void)hipGraphExecDestroy(P->vc_exec);
+  P->vc_exec = nullptr;
+  P->vc_sig.clear();
+}
+
+// x = V-cycle(b).  With vcycle_graph the cycle is captured once and replayed
+// on the context's stream between a copy into its input and out of its
+// output.  Capture runs on a stream of the problem's own (thread-local mode,
+// so other threads' streams are not affected), with the context's stream
+// pointed at it while the launches are recorded.
+void vcycle_apply(stwr_problem* P, const double* b, double* x) {
+  if (!P->opts.vcycle_graph || P->ctx->timing) {
+    vcycle(P, b, x);
+    return;
+  }
+  const int64_t n0 = P->lv[0].n_st;
+  std::vector<double> sig = vcycle_signature(P);
+  if (!P->vc_exec || sig != P->vc_sig) {
+    drop_vcycle_graph(P);
+    if (!P->vc_in) {
+      P->vc_in = P->alloc<double>(n0);
+      P->vc_out = P->alloc<double>(n0);
+    }
+    if (!P->vc_stream) HIPCHK(hipStreamCreateWithFlags(&P->vc_stream, hipStreamNonBlocking));
+    // the capture stream starts after everything already queued on the context's
+    HIPCHK(hipStreamSynchronize(P->s()));
+    hipStream_t saved = P->ctx->stream;
+    HIPCHK(hipStreamBeginCapture(P->vc_stream, hipStreamCaptureModeThreadLocal));
+    P->ctx->stream = P->vc_stream;
+    hipGraph_t g = nullptr;
+    try {
+      vcycle(P, P->vc_in, P->vc_out);
+    } catch (...) {
+      P->ctx->stream = saved;
+      if (hipStreamEndCapture(P->vc_stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    P->ctx->stream = saved;
+    HIPCHK(hipStreamEndCapture(P->vc_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&P->vc_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      P->vc_exec = nullptr;
+      HIPCHK(e);
+    }
+    P->vc_sig = sig;
+  }
+  HIPCHK(hipMemcpyAsync(P->vc_in, b, n0 * sizeof(double), hipMemcpyDeviceToDevice, P->s()));
+  HIPCHK(hipGraphLaunch(P->vc_exec, P->s()));
+  HIPCHK(hipMemcpyAsync(x, P->vc_out, n0 * sizeof(double), hipMemcpyDeviceToDevice, P->s()));
+}
+
 // Eigenvalues of a small real upper-Hessenberg matrix by shifted complex QR
 // iterations (Wilkinson shifts, deflation at the bottom).
 std::vector<std::complex<double>> hessenberg_eigs(std::vector<double> Hr, int m) {
@@ -727,7 +801,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      vcycle(P, V(j), Z(j));
+      vcycle_apply(P, V(j), Z(j));
       project(P, 0, Z(j));
       spmv(P, 0, Z(j), nullptr, V(j + 1));
       for (int i = 0; i <= j; ++i) {
@@ -793,6 +867,7 @@ int32_t stwr_default_opts(stwr_solver_opts* o) {
   o->gmres_rtol = 1e-10;
   o->newton_maxit = 20;
   o->newton_rtol = 1e-10;
+  o->vcycle_graph = 1;
   return STWR_OK;
 }
 
@@ -990,6 +1065,8 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
 int32_t stwr_problem_destroy(stwr_problem* p) {
   if (!p) return STWR_OK;
   (void)hipStreamSynchronize(p->s());
+  drop_vcycle_graph(p);
+  if (p->vc_stream) (void)hipStreamDestroy(p->vc_stream);
   for (auto& b : p->bufs) p->free_one(b.p);
   if (p->ctx->stream_alloc) (void)hipStreamSynchronize(p->s());
   {
@@ -1193,7 +1270,7 @@ int32_t stwr_vcycle(stwr_problem* p, const double* b, double* x) {
   return guarded(p->ctx, [&]() -> int32_t {
     if (!b || !x) throw StwrError(STWR_ERR_ARG, "null vector");
     if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
-    vcycle(p, b, x);
+    vcycle_apply(p, b, x);
     return STWR_OK;
   });
 }

@@ -245,6 +245,55 @@ def test_vcycle(case):
     assert e < 1e-12
 
 
+@pytest.mark.parametrize("case", ["q1_m8_n3", "q1_m16_L2_n3", "q0_m8_L1_n6"])
+def test_vcycle_graph_replays_match_launched(case):
+    """The captured V-cycle against the launched one, bit for bit, over
+    several replays with other work and synchronisations between them, and
+    re-captured after the smoothers change."""
+    torch = torch_cuda()
+    from paper_2407_13997_amd import binding
+    prob, G, H, U, Ud = setup_case(case)
+    G.setup_smoothers()
+    n = H.levels[0].n_st
+    bs = [to_dev(seeded(n, 300 + k)) for k in range(3)]
+
+    def run(graph, b):
+        o = binding.SolverOpts()
+        ctypes_copy(G.opts, o)
+        o.vcycle_graph = graph
+        G.set_opts(o)
+        x = G.vec(0)
+        G.vcycle(b, x)
+        torch.cuda.synchronize()
+        return to_host(x)
+
+    ref = [run(0, b) for b in bs]
+    for rep in range(3):
+        for k, b in enumerate(bs):
+            got = run(1, b)
+            log(f"[vcycle graph] {case} replay {rep} rhs {k} max|diff|={np.max(np.abs(got - ref[k])):.1e}")
+            assert np.array_equal(got, ref[k])
+            # eager work between replays
+            y = G.vec(0)
+            G.apply(0, b, y)
+            torch.cuda.synchronize()
+    # new smoother state (re-estimated eigenvalues after a re-assembly at a
+    # different iterate): the graph is captured again
+    G.assemble(to_dev(0.5 * to_host(Ud)))
+    G.setup_smoothers()
+    ref2 = run(0, bs[0])
+    got2 = run(1, bs[0])
+    assert np.array_equal(got2, ref2)
+    assert not np.array_equal(ref2, ref[0])
+    G.assemble(Ud)
+    G.setup_smoothers()
+
+
+def ctypes_copy(src, dst):
+    for name, _ in src._fields_:
+        setattr(dst, name, getattr(src, name))
+
+
 @pytest.mark.parametrize("case", ["q0_m4_n4", "q1_m8_n3", "q0_m16_n5_re10", "q1_m8_n1", "q1_m16_L2_n3"])
 def test_fgmres_solution(case):
     """Linear solve at the Newton start state (zero at the free DoFs), from a
