@@ -232,7 +232,9 @@ int32_t stwr_vcycle(stwr_problem* p, const double* b, double* x);
 int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* stats);
 
 /* Newton's method from the U given (zero = the standard start), in place:
- * assemble, factor, estimate, FGMRES, U += dU, until ||F|| <= rtol ||F_0||. */
+ * assemble, factor, estimate, FGMRES, U += dU, until ||F|| <= rtol ||F_0||.
+ * Full steps; STWR_ERR_NOT_CONVERGED after newton_maxit steps, or as soon as
+ * ||F|| exceeds 100 ||F_0|| (divergence), with stats filled either way. */
 int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats);
 
 /* Subtract the mean pressure per (slab, temporal node) from x (level l). */

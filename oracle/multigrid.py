@@ -216,4 +216,7 @@ def newton_solve(prob, opts=None, max_newton=None, x0=None):
         stats["newton"] += 1
         stats["linear"].append(its)
         stats["fnorm"].append(np.linalg.norm(F))
+        if stats["fnorm"][-1] > 1e2 * f0:     # divergence: stop (full steps, no line search)
+            stats["diverged"] = True
+            break
     return x, stats, H

@@ -108,6 +108,7 @@ struct Level {
   LevelView view{};
   PatchView pview{};
   int fac_prec = -1;      // precision of the current factors, -1 = none
+  int fac_layout = -1;    // precision whose panel layout the (zeroed) storage holds
   size_t fac_budgeted = 0;  // factor bytes already charged to the context
   double lambda = 0.0;
   bool has_lambda = false;
@@ -376,12 +377,18 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     pv.patch_nz_off = L.patch_nz_off; pv.patch_nz = L.patch_nz; pv.fac_off = L.d_fac_off;
     pv.y_off = L.d_y_off; pv.mp_off = L.d_mp_off; pv.dof_ptr = L.dof_ptr; pv.dof_slot = L.dof_slot;
     pv.slot_patch = L.slot_patch;
-    std::vector<int> order;
-    for (int v = 0; v < H.nv; ++v)
-      if (H.patch_ptr[v + 1] - H.patch_ptr[v] == kMaxNb) order.push_back(v);
-    pv.n_full = (int)order.size();
-    for (int v = 0; v < H.nv; ++v)
-      if (H.patch_ptr[v + 1] - H.patch_ptr[v] != kMaxNb) order.push_back(v);
+    // patches by decreasing size (stable): the interior ones (nb = 39)
+    // first, then the blocks larger than a wavefront's 64 rows
+    std::vector<int> order(H.nv);
+    for (int v = 0; v < H.nv; ++v) order[v] = v;
+    auto nb_of = [&](int v) { return H.patch_ptr[v + 1] - H.patch_ptr[v]; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nb_of(x) > nb_of(y); });
+    pv.n_full = 0;
+    pv.n_big = 0;
+    for (int v : order) {
+      pv.n_full += nb_of(v) == kMaxNb;
+      pv.n_big += nb_of(v) * L.NQ > 64;
+    }
     pv.order = P->upload(order);
     L.P_ptr = P->upload(L.Tr.p_ptr);
     L.P_col = P->upload(L.Tr.p_col);
@@ -421,6 +428,14 @@ void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
     L.fac_budgeted += extra;
     L.fac = P->alloc<char>(need);
     L.fac_bytes = need;
+    L.fac_layout = -1;
+  }
+  // the panel layout's padding must read as zero; the factor kernel writes
+  // every entry but never the padding, so clear the storage whenever its
+  // layout (the precision) changes
+  if (L.fac_layout != prec) {
+    HIPCHK(hipMemsetAsync(L.fac, 0, L.fac_bytes, P->s()));
+    L.fac_layout = prec;
   }
   // [slab][patch] order: the patches resident at one time (which start
   // together and advance at similar rates) read from a few compact regions
@@ -1307,6 +1322,9 @@ int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* sta
   });
 }
 
+// Newton stops as diverged once ||F|| exceeds this multiple of ||F_0||.
+constexpr double kNewtonDiverged = 1e2;
+
 int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
@@ -1351,10 +1369,16 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
       f = resid();
       st.fnorm[k + 1] = f;
       converged = f <= o.newton_rtol * f0;
+      if (f > kNewtonDiverged * f0) {   // full steps that leave the basin: give up early
+        ++k;
+        break;
+      }
     }
     st.newton_its = k;
     for (int l = 0; l < (int)p->lv.size() && l < STWR_MAX_LEVELS; ++l) st.lambda[l] = p->lv[l].lambda;
-    if (!converged) return fail(p->ctx, STWR_ERR_NOT_CONVERGED, "Newton reached its iteration limit");
+    if (!converged)
+      return fail(p->ctx, STWR_ERR_NOT_CONVERGED,
+                  f > kNewtonDiverged * f0 ? "Newton diverged" : "Newton reached its iteration limit");
     return STWR_OK;
   });
 }

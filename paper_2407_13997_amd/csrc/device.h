@@ -48,8 +48,9 @@ struct PatchView {
   const int* dof_ptr;
   const int* dof_slot;
   const int* slot_patch;
-  const int* order;         // n_patch: interior (full-size) patches first, then the rest
+  const int* order;         // n_patch, by decreasing size: interior (full-size) patches first
   int n_full;               // number of full-size patches at the front of order
+  int n_big;                // number of patches with (q+1) nb > 64 at the front of order
 };
 
 // Storage of one inverted m x m slab block for the patch sweep, in T-typed

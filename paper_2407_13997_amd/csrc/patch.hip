@@ -22,7 +22,6 @@ namespace stwr {
 
 namespace {
 
-constexpr int kFacThreads = 256;
 
 template <typename T>
 struct Vec;
@@ -47,95 +46,201 @@ __device__ inline float4 load_stream(const float* p) {
   return make_float4(t.x, t.y, t.z, t.w);
 }
 
-template <int NQ, typename T>
-__global__ __launch_bounds__(kFacThreads) void k_patch_factor(LevelView L, PatchView P,
-                                                              const double* __restrict__ Jv,
-                                                              T* __restrict__ fac,
-                                                              int* __restrict__ status) {
+// Inverse of one (patch, slab) block by Gauss-Jordan elimination with
+// partial pivoting, held in registers: thread t owns rows t + TPB r (r < RPL),
+// each a full row of MAXM entries.  After each step the rows rotate left by
+// one column, so the active column is always register 0 and every register
+// index is static; after m steps position j holds column (j + m) mod MAXM
+// (columns past m are zero padding and stay zero).  A step is a pivot search
+// (wavefront reduction, plus LDS across wavefronts when TPB > 64), a row swap
+// and the broadcast of the scaled pivot row through LDS, and the elimination
+// in registers.  The column permutation of the pivoting is applied while
+// writing the inverse out in the sweep's panel layout.  Per element the
+// arithmetic and the pivot choice (largest magnitude, ties to the smaller
+// row) are those of the textbook in-place Gauss-Jordan inverse.
+template <int NQ, typename T, int TPB, int RPL>
+__global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, int first,
+                                                      const double* __restrict__ Jv,
+                                                      T* __restrict__ fac, int* __restrict__ status) {
   constexpr int MAXM = kMaxNb * NQ;
+  constexpr int NW = TPB / 64;
   constexpr int VW = Vec<T>::W;
-  __shared__ T A[MAXM][MAXM + 1];
-  __shared__ T colk[MAXM];
+  // row buffers padded to whole 16-byte vectors
+  constexpr int RV = 16 / sizeof(T), MP = (MAXM + RV - 1) / RV * RV;
+  using V16 = typename Vec<T>::type;
+  __shared__ __align__(16) T prow[MP];
+  __shared__ __align__(16) T swp[2][MP];
+  __shared__ T rv[NW];
+  __shared__ int ri[NW];
   __shared__ int perm[MAXM];
-  __shared__ T rv[kFacThreads / 64];
-  __shared__ int ri[kFacThreads / 64];
-  __shared__ int piv_s;
-  const int p = blockIdx.x / L.N, n = blockIdx.x % L.N;
+  __shared__ int ofs1[MAXM], ofs2[MAXM];
+  const int p = P.order[first + blockIdx.x / L.N], n = blockIdx.x % L.N;
   const int tid = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0;
   const int m = nb * NQ;
   const int* nzp = P.patch_nz + P.patch_nz_off[p];
-  for (int e = tid; e < m * m; e += kFacThreads) {
-    const int r = e / m, c = e % m;
-    const int i = r / NQ, a = r % NQ, j = c / NQ, b = c % NQ;
-    const int k = nzp[i * nb + j];
-    A[r][c] = k >= 0 ? (T)Jv[(((int64_t)k * L.N + n) * NQ + a) * NQ + b] : (T)0;
+  T a[RPL][MAXM];
+  // row r of the registers to / from an LDS row buffer, 16 bytes at a time
+  auto put = [&](T* dst, int r) {
+#pragma unroll
+    for (int j = 0; j < MP; j += RV) {
+      V16 v;
+      T* e = reinterpret_cast<T*>(&v);
+#pragma unroll
+      for (int t = 0; t < RV; ++t) e[t] = j + t < MAXM ? a[r][j + t] : (T)0;
+      *reinterpret_cast<V16*>(dst + j) = v;
+    }
+  };
+  auto get = [&](const T* src, int r) {
+#pragma unroll
+    for (int j = 0; j < MP; j += RV) {
+      const V16 v = *reinterpret_cast<const V16*>(src + j);
+      const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int t = 0; t < RV; ++t)
+        if (j + t < MAXM) a[r][j + t] = e[t];
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = tid + TPB * r;
+    const int ii = i < m ? i : 0;
+    const int* nzr = nzp + (ii / NQ) * nb;
+#pragma unroll
+    for (int c = 0; c < MAXM; ++c) {
+      T v = (T)0;
+      if (i < m && c < m) {
+        const int k = nzr[c / NQ];
+        if (k >= 0) v = (T)Jv[(((int64_t)k * L.N + n) * NQ + ii % NQ) * NQ + c % NQ];
+      }
+      a[r][c] = v;
+    }
   }
-  __syncthreads();
   for (int k = 0; k < m; ++k) {
+    // pivot: largest |entry| of column k among rows >= k
     T best = (T)-1;
     int bi = m;
-    for (int i = k + tid; i < m; i += kFacThreads) {
-      const T v = fabs(A[i][k]);
-      if (v > best) { best = v; bi = i; }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = tid + TPB * r;
+      const T v = (i >= k && i < m) ? fabs(a[r][0]) : (T)-1;
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
     }
     for (int off = 32; off > 0; off >>= 1) {
       const T ov = __shfl_xor(best, off);
       const int oi = __shfl_xor(bi, off);
       if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
     }
-    if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      T b = rv[0];
-      int pi = ri[0];
-      for (int w = 1; w < kFacThreads / 64; ++w)
-        if (rv[w] > b || (rv[w] == b && ri[w] < pi)) { b = rv[w]; pi = ri[w]; }
-      if (!(b > (T)0) || !isfinite(b) || pi >= m) { status[0] = 1; pi = k; }
-      piv_s = pi;
-      perm[k] = pi;
+    if constexpr (NW > 1) {
+      if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
+      __syncthreads();
+      best = rv[0];
+      bi = ri[0];
+      for (int w = 1; w < NW; ++w)
+        if (rv[w] > best || (rv[w] == best && ri[w] < bi)) { best = rv[w]; bi = ri[w]; }
+    }
+    int pi = bi;
+    if (!(best > (T)0) || !isfinite(best) || pi >= m) {
+      if (tid == 0) status[0] = 1;
+      pi = k;
+    }
+    if (tid == 0) perm[k] = pi;
+    if (pi != k) {   // uniform: swap rows k and pi
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = tid + TPB * r;
+        if (i == pi) put(swp[0], r);
+        if (i == k) put(swp[1], r);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = tid + TPB * r;
+        if (i == k) get(swp[0], r);
+        if (i == pi) get(swp[1], r);
+      }
+    }
+    // scale the pivot row (its pivot entry becomes 1 / pivot) and publish it
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      if (tid + TPB * r == k) {
+        const T pv = a[r][0];
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) a[r][j] = (j == 0 ? (T)1 : a[r][j]) / pv;
+        put(prow, r);
+      }
     }
     __syncthreads();
-    const int pr = piv_s;
-    if (pr != k)
-      for (int j = tid; j < m; j += kFacThreads) {
-        const T t = A[k][j];
-        A[k][j] = A[pr][j];
-        A[pr][j] = t;
-      }
-    __syncthreads();
-    const T pv = A[k][k];
-    __syncthreads();
-    for (int j = tid; j < m; j += kFacThreads) A[k][j] = (j == k ? (T)1 : A[k][j]) / pv;
-    for (int i = tid; i < m; i += kFacThreads) colk[i] = A[i][k];
-    __syncthreads();
-    for (int e = tid; e < m * m; e += kFacThreads) {
-      const int i = e / m, j = e % m;
-      if (i == k) continue;
-      const T f = colk[i];
-      if (j == k) A[i][j] = -f * A[k][k];
-      else A[i][j] -= f * A[k][j];
+    // eliminate column k from the other rows, one column at a time so that
+    // each pivot-row value is read just before its use; then rotate
+    T f[RPL];
+    bool live[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = tid + TPB * r;
+      live[r] = i < m && i != k;
+      f[r] = a[r][0];
     }
-    __syncthreads();
-  }
-  for (int k = m - 1; k >= 0; --k) {
-    const int pr = perm[k];
-    if (pr != k)
-      for (int i = tid; i < m; i += kFacThreads) {
-        const T t = A[i][k];
-        A[i][k] = A[i][pr];
-        A[i][pr] = t;
+    {
+      const T p0 = prow[0];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        if (live[r]) a[r][0] = -f[r] * p0;
+    }
+#pragma unroll
+    for (int j0 = 0; j0 < MP; j0 += RV) {
+      const V16 v = *reinterpret_cast<const V16*>(prow + j0);
+      const T* pj = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int t = 0; t < RV; ++t) {
+        const int j = j0 + t;
+        if (j >= 1 && j < MAXM) {
+#pragma unroll
+          for (int r = 0; r < RPL; ++r)
+            if (live[r]) a[r][j] -= f[r] * pj[t];
+        }
       }
-    __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const T t0 = a[r][0];
+#pragma unroll
+      for (int j = 0; j + 1 < MAXM; ++j) a[r][j] = a[r][j + 1];
+      a[r][MAXM - 1] = t0;
+    }
   }
+  // undo the column permutation of the pivoting (the swaps (k, perm[k])
+  // applied to the columns for k = m-1 .. 0): each thread follows its
+  // columns through the swaps, then records the panel-layout offsets of
+  // their destination (rows < 64 and rows >= 64)
   const BlockLayout lay(m, VW);
-  T* out = fac + P.fac_off[p] + (int64_t)n * P.slab_stride;
-  for (int e = tid; e < lay.size(); e += kFacThreads) out[e] = (T)0;
   __syncthreads();
-  for (int e = tid; e < m * m; e += kFacThreads) {
-    const int r = e / m, c = e % m;
-    out[lay.at(r, c)] = A[r][c];
+  for (int c = tid; c < m; c += TPB) {
+    int pos = c;
+    for (int k = m - 1; k >= 0; --k) {
+      const int pk = perm[k];
+      if (pos == k) pos = pk;
+      else if (pos == pk) pos = k;
+    }
+    ofs1[c] = lay.at(0, pos);
+    ofs2[c] = m > 64 ? lay.at(64, pos) : 0;
+  }
+  // the padding of the layout is zeroed once when the storage is allocated;
+  // every entry is written here
+  T* out = fac + P.fac_off[p] + (int64_t)n * P.slab_stride;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = tid + TPB * r;
+    if (i < m) {
+      const int rofs = i < 64 ? i * VW : (i - 64) * 4 * VW;
+#pragma unroll
+      for (int q = 0; q < MAXM; ++q) {
+        const int c = (q + m) % MAXM;
+        if (c < m) out[(i < 64 ? ofs1[c] : ofs2[c]) + rofs] = a[r][q];
+      }
+    }
   }
 }
 
@@ -573,13 +678,26 @@ __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P
 
 hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const double* Jv, int prec,
                                void* fac, int* status, hipStream_t s) {
-  dim3 grid((unsigned)P.n_patch * L.N), block(kFacThreads);
+  // blocks larger than 64 rows (the front of the patch order) take two rows
+  // per lane (FP32) or two wavefronts (FP64); the others one row per lane
+  const int big = L.NQ == 2 ? P.n_big : 0, small = P.n_patch - big;
+  const dim3 gb((unsigned)big * L.N), gs((unsigned)small * L.N);
   if (prec == 1) {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, float>), grid, block, 0, s, L, P, Jv, (float*)fac, status);
-    else hipLaunchKernelGGL((k_patch_factor<2, float>), grid, block, 0, s, L, P, Jv, (float*)fac, status);
+    float* f = (float*)fac;
+    if (L.NQ == 1) {
+      hipLaunchKernelGGL((k_patch_factor<1, float, 64, 1>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+    } else {
+      if (big) hipLaunchKernelGGL((k_patch_factor<2, float, 64, 2>), gb, dim3(64), 0, s, L, P, 0, Jv, f, status);
+      if (small) hipLaunchKernelGGL((k_patch_factor<2, float, 64, 1>), gs, dim3(64), 0, s, L, P, big, Jv, f, status);
+    }
   } else {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, double>), grid, block, 0, s, L, P, Jv, (double*)fac, status);
-    else hipLaunchKernelGGL((k_patch_factor<2, double>), grid, block, 0, s, L, P, Jv, (double*)fac, status);
+    double* f = (double*)fac;
+    if (L.NQ == 1) {
+      hipLaunchKernelGGL((k_patch_factor<1, double, 64, 1>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+    } else {
+      if (big) hipLaunchKernelGGL((k_patch_factor<2, double, 128, 1>), gb, dim3(128), 0, s, L, P, 0, Jv, f, status);
+      if (small) hipLaunchKernelGGL((k_patch_factor<2, double, 64, 1>), gs, dim3(64), 0, s, L, P, big, Jv, f, status);
+    }
   }
   return hipGetLastError();
 }
