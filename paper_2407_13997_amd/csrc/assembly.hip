@@ -170,7 +170,9 @@ template <int NQ>
 __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* __restrict__ T,
                                                  MmsDev mms, const double* __restrict__ U,
                                                  double* __restrict__ Jv, double* __restrict__ Mv) {
-  const int c = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  // one workgroup per (cell, slab), slab fastest: consecutive workgroups
+  // update the same operator lines (each holds several slabs of a nonzero)
+  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ CellStage<NQ> S;
   stage_cell<NQ>(L, T, mms, U, c, n, S);
   const int G = T->G;
@@ -243,7 +245,8 @@ template <int NQ>
 __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* __restrict__ T,
                                                  MmsDev mms, const double* __restrict__ U,
                                                  double* __restrict__ F) {
-  const int c = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  // slab fastest, as in k_jacobian
+  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ CellStage<NQ> S;
   __shared__ double pl[3][NQ];
   __shared__ double prev[2][6];
@@ -444,7 +447,7 @@ hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, c
 
 hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
                                     const double* U, double* Jv, double* Mv, hipStream_t s) {
-  dim3 grid(L.nc, L.N);
+  dim3 grid((unsigned)((int64_t)L.nc * L.N));
   if (L.NQ == 1) hipLaunchKernelGGL(k_jacobian<1>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
   else hipLaunchKernelGGL(k_jacobian<2>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
   return hipGetLastError();
@@ -452,7 +455,7 @@ hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, Mm
 
 hipError_t launch_assemble_residual(const LevelView& L, const RefTables* tab, MmsDev mms,
                                     const double* U, double* F, hipStream_t s) {
-  dim3 grid(L.nc, L.N);
+  dim3 grid((unsigned)((int64_t)L.nc * L.N));
   if (L.NQ == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(64), 0, s, L, tab, mms, U, F);
   else hipLaunchKernelGGL(k_residual<2>, grid, dim3(64), 0, s, L, tab, mms, U, F);
   return hipGetLastError();
