@@ -295,7 +295,7 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
       b += (uint64_t)y_elems(H.patch_ptr[v + 1] - H.patch_ptr[v], N, NQ) * 8;
   } else {
     const int64_t mm = (int64_t)H.nf * NQ + NQ;
-    b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8 + (mm > 512 ? (uint64_t)N * 32 * mm * 8 : 0);
+    b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8 + (mm > kCoarseSmall ? (uint64_t)N * 32 * mm * 8 : 0);
   }
   if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
   return b;
@@ -402,7 +402,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     L.gbuf = P->alloc<double>((size_t)L.coarse_mm);
     L.perm = P->alloc<int>((size_t)L.N * L.coarse_mm);
     L.colbuf = P->alloc<double>((size_t)L.N * L.coarse_mm);
-    if (L.coarse_mm > 512) L.rbuf = P->alloc<double>((size_t)L.N * 32 * L.coarse_mm);
+    if (L.coarse_mm > kCoarseSmall) L.rbuf = P->alloc<double>((size_t)L.N * 32 * L.coarse_mm);
   }
 }
 

@@ -148,9 +148,12 @@ hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec,
                                hipStream_t s);
 
 // ---- coarsest level ---------------------------------------------------------------
+// Bordered slab blocks of at most this order are inverted and applied by one
+// workgroup; larger ones by the blocked, chip-wide kernels.
+constexpr int kCoarseSmall = 64;
 hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, hipStream_t s);
 // perm: nmat * m ints, colbuf: nmat * m doubles, rbuf: nmat * 32 * m doubles of
-// workspace (used when m > 512; rbuf = NULL selects the unblocked form)
+// workspace (used when m > kCoarseSmall; rbuf = NULL selects the unblocked form)
 hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
                                 double* colbuf, double* rbuf, hipStream_t s);
 // gbuf: nf (q+1) + q + 1 doubles of workspace (used for large coarsest levels)

@@ -275,7 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_inverse(int m, double* __restr
   }
 }
 
-// Large dense inverses (m > 512): Gauss-Jordan with partial pivoting spread
+// Dense inverses over kCoarseSmall rows when no panel workspace is given
+// (rbuf = NULL): Gauss-Jordan with partial pivoting spread
 // over the chip, one elimination step per pair of launches.  k_gj_pivot (one
 // workgroup per matrix) picks the pivot of column k, swaps it into row k,
 // scales row k and saves column k; k_gj_update applies the rank-1 update to
@@ -848,7 +849,7 @@ hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, 
 hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
                                 double* colbuf, double* rbuf, hipStream_t s) {
   if (m > kMaxCoarse) return hipErrorInvalidValue;
-  if (m <= 512) {
+  if (m <= kCoarseSmall) {
     hipLaunchKernelGGL(k_dense_inverse, dim3(nmat), dim3(kBlock), 0, s, m, B, status);
     return hipGetLastError();
   }
@@ -864,7 +865,9 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
   const dim3 gs(nblk(m), nmat), gt((m + 63) / 64, (m + 63) / 64, nmat), gp(nblk(m), nmat);
   for (int k0 = 0; k0 < m; k0 += kGjPanel) {
     const int k1 = k0 + kGjPanel < m ? k0 + kGjPanel : m;
-    if (m <= kPanelThreads * 2)
+    if (m <= kPanelThreads)
+      hipLaunchKernelGGL(k_bgj_panel_reg<1>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+    else if (m <= kPanelThreads * 2)
       hipLaunchKernelGGL(k_bgj_panel_reg<2>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else if (m <= kPanelThreads * 3)
       hipLaunchKernelGGL(k_bgj_panel_reg<3>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
@@ -883,7 +886,7 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
   const int mm = L.nf * L.NQ + L.NQ;
   if (mm > kMaxCoarse) return hipErrorInvalidValue;
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
-  if (mm > 512) {
+  if (mm > kCoarseSmall) {
     const unsigned gr = (unsigned)((mm + kBlock / 16 - 1) / (kBlock / 16));
     const unsigned gg = (unsigned)((L.nf * L.NQ + kBlock / 64 - 1) / (kBlock / 64));
     for (int n = 0; n < L.N; ++n) {
