@@ -25,7 +25,7 @@ import math
 import numpy as np
 
 __all__ = ["Problem", "draw_modes", "named_problem", "batch_problems",
-           "arrival_times", "WORKLOADS", "SMOKE", "MEDIUM", "LARGE"]
+           "arrival_times", "seeded_vector", "WORKLOADS", "SMOKE", "MEDIUM", "LARGE"]
 
 
 @dataclasses.dataclass
@@ -136,3 +136,9 @@ def arrival_times(rate: float, n: int, seed: int = 3000) -> np.ndarray:
     """Poisson arrivals: cumulative sums of exponential gaps with mean 1/rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def seeded_vector(n: int, seed: int) -> np.ndarray:
+    """n standard normal values from numpy's default generator with this seed
+    (a right-hand side or residual for tests and references)."""
+    return np.random.default_rng(seed).standard_normal(n)
