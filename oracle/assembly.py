@@ -30,12 +30,12 @@ from .mesh import Mesh
 class Level:
     """One space-time level: a spatial mesh times the fixed temporal mesh."""
 
-    def __init__(self, M, q, n_slabs, t_final, mms):
+    def __init__(self, M, q, n_slabs, t_final, mms, nodes="radau"):
         self.mesh = Mesh(M)
         self.q, self.N, self.nq = q, n_slabs, q + 1
         self.T = t_final
         self.dt = t_final / n_slabs
-        self.tb = SlabBasis(q)
+        self.tb = SlabBasis(q, nodes)
         self.mms = mms
         self.R = mms.R
         m = self.mesh

@@ -80,3 +80,53 @@ class MMS:
         fx = d["yt"] + self.R * conv_x - lap_x + px
         fy = -d["xt"] + self.R * conv_y - lap_y + py
         return fx, fy
+
+
+class Chorin:
+    """The Chorin test problem (Sec. 2, Definition of the Chorin test problem):
+    on the unit square the velocity
+
+        u = (-cos(pi x) sin(pi y), sin(pi x) cos(pi y)) exp(-2 pi^2 t)
+
+    with full Dirichlet data from u, initial value u(0).  Its pressure, in the
+    sign convention above (strong form + grad p), is
+    p = -(R / 4) (cos(2 pi x) + cos(2 pi y)) exp(-4 pi^2 t): the printed
+    pressure carries a factor pi and the opposite sign (the sign is the one
+    the printed weak form implies); with this p the pair solves the equations
+    with no forcing (u_t = lap u, R (u.grad)u = -grad p), so the forcing is
+    zero.  The velocity does not depend on R."""
+
+    def __init__(self, reynolds):
+        self.R = float(reynolds)
+
+    @staticmethod
+    def _fields(t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float),
+                                      np.asarray(y, float))
+        return t, x, y
+
+    def velocity(self, t, x, y):
+        t, x, y = self._fields(t, x, y)
+        e = np.exp(-2.0 * PI * PI * t)
+        return -np.cos(PI * x) * np.sin(PI * y) * e, np.sin(PI * x) * np.cos(PI * y) * e
+
+    def pressure(self, t, x, y):
+        t, x, y = self._fields(t, x, y)
+        return -0.25 * self.R * (np.cos(2 * PI * x) + np.cos(2 * PI * y)) * np.exp(-4.0 * PI * PI * t)
+
+    def pressure_grad(self, t, x, y):
+        t, x, y = self._fields(t, x, y)
+        e = np.exp(-4.0 * PI * PI * t)
+        return 0.5 * PI * self.R * np.sin(2 * PI * x) * e, 0.5 * PI * self.R * np.sin(2 * PI * y) * e
+
+    def forcing(self, t, x, y):
+        t, x, y = self._fields(t, x, y)
+        return np.zeros(t.shape), np.zeros(t.shape)
+
+
+def make_flow(prob):
+    """The exact solution of a problem: the manufactured modes, or the Chorin
+    problem when prob.flow == 1."""
+    if getattr(prob, "flow", 0) == 1:
+        return Chorin(prob.reynolds)
+    return MMS(prob.psi_ab, prob.psi_coef, prob.p_ab, prob.p_coef, prob.reynolds)

@@ -19,7 +19,7 @@ import numpy as np
 import scipy.linalg as la
 
 from .assembly import Level
-from .mms import MMS
+from .mms import make_flow
 from .smoother import PatchSmoother, chebyshev, eig_estimate
 from .transfer import spacetime_prolongation, inject_full
 
@@ -83,8 +83,9 @@ class CoarseSolver:
 class Hierarchy:
     def __init__(self, prob, opts=None):
         self.opts = opts or Options()
-        self.mms = MMS(prob.psi_ab, prob.psi_coef, prob.p_ab, prob.p_coef, prob.reynolds)
-        self.levels = [Level(prob.mesh_n >> l, prob.q, prob.n_slabs, prob.t_final, self.mms)
+        self.mms = make_flow(prob)
+        nodes = "gauss" if getattr(prob, "nodes", 0) == 1 else "radau"
+        self.levels = [Level(prob.mesh_n >> l, prob.q, prob.n_slabs, prob.t_final, self.mms, nodes)
                        for l in range(prob.n_levels)]
         L0 = self.levels[0]
         self.P = [spacetime_prolongation(self.levels[l].mesh, self.levels[l + 1].mesh,

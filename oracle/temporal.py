@@ -1,9 +1,13 @@
 """Upwind DG(q) in time on one slab (Sec. 2, Defs. DG notation and temporal
 discretisation, eq. dgintime).
 
-Reading of the paper (it does not name the temporal nodes): the Lagrange basis
-of each slab sits on the right Gauss-Radau points of [0, 1] (q=0: {1};
-q=1: {1/3, 1}), so the slab end value is the last nodal value.  The +/- limit
+Reading of the paper (it does not name the temporal nodes): by default the
+Lagrange basis of each slab sits on the right Gauss-Radau points of [0, 1]
+(q=0: {1}; q=1: {1/3, 1}), so the slab end value is the last nodal value.
+The nodes also fix where the Dirichlet data is interpolated in time, the only
+place they change the discrete solution; the Gauss-Legendre points
+(nodes="gauss") are the other family offered (with them the Chorin error table
+of Sec. 4.2 is reproduced).  The +/- limit
 notation of the paper's definition is read in the standard upwind sense:
 psi_n^+ is the value at t_n from inside slab n, Y_n^- the value at t_n from
 inside slab n-1 (this is what makes the space-time system block lower
@@ -56,9 +60,14 @@ class SlabBasis:
     matrices T_ab = int phi_b' phi_a + phi_b(0) phi_a(0) and W_ab = int phi_a phi_b.
     """
 
-    def __init__(self, q):
+    def __init__(self, q, nodes="radau"):
         self.q = q
-        self.nodes = radau_right_nodes(q)
+        if nodes == "radau":
+            self.nodes = radau_right_nodes(q)
+        elif nodes == "gauss":
+            self.nodes = gauss_01(q + 1)[0]
+        else:
+            raise ValueError(f"unknown temporal nodes {nodes!r}")
         self.sg, self.wg = gauss_01(q + 3)
         self.Phi, self.dPhi = lagrange(self.nodes, self.sg)
         self.e0 = lagrange(self.nodes, [0.0])[0][0]

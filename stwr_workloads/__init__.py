@@ -25,7 +25,8 @@ import math
 import numpy as np
 
 __all__ = ["Problem", "draw_modes", "named_problem", "batch_problems",
-           "arrival_times", "seeded_vector", "WORKLOADS", "SMOKE", "MEDIUM", "LARGE"]
+           "arrival_times", "seeded_vector", "chorin_problem", "WORKLOADS", "SMOKE", "MEDIUM",
+           "LARGE"]
 
 
 @dataclasses.dataclass
@@ -42,6 +43,8 @@ class Problem:
     p_ab: np.ndarray
     p_coef: np.ndarray
     seed: int = 0
+    flow: int = 0          # 0: the manufactured modes; 1: the Chorin test problem (modes unused)
+    nodes: int = 0         # temporal nodes: 0 right Gauss-Radau, 1 Gauss-Legendre
 
     @property
     def n_free_spatial(self) -> int:
@@ -103,6 +106,17 @@ def named_problem(name: str, index: int = 0) -> Problem:
     seed = base + index
     modes = draw_modes(seed, n_psi, 3, wave)
     return Problem(mesh, levels, q, slabs, 1.0, re, *modes, seed=seed)
+
+
+def chorin_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int, reynolds: float = 10.0,
+                   t_final: float = 0.1, nodes: int = 1) -> Problem:
+    """The Chorin test problem on [0, t_final] (the paper's runs: 80 x 80 mesh
+    from a 10 x 10 base, 4 levels, R = 10, t in [0, 0.1], N = 10, 20, 40),
+    with Gauss-Legendre temporal nodes by default (nodes=0: right Radau)."""
+    none_i = np.zeros((0, 2), dtype=np.int64)
+    none_f = np.zeros((0, 3))
+    return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, none_i, none_f, none_i, none_f,
+                   seed=0, flow=1, nodes=nodes)
 
 
 def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,

@@ -37,16 +37,23 @@ def test_radau_nodes():
     assert np.allclose(SlabBasis(2).nodes, [(4 - math.sqrt(6)) / 10, (4 + math.sqrt(6)) / 10, 1.0])
 
 
+@pytest.mark.parametrize("nodes", ["radau", "gauss"])
 @pytest.mark.parametrize("z", [-0.3, -2.0, -17.5, 0.4])
-def test_dg_slab_map_is_radau_iia_stability_function(z):
+def test_dg_slab_map_is_radau_iia_stability_function(z, nodes):
     """y' = lam y over one slab with z = lam dt: the DG(q) end value is
-    R(z) y0 with R the (q, q+1) Pade approximant (Radau IIA)."""
-    r0 = SlabBasis(0)
+    R(z) y0 with R the (q, q+1) Pade approximant (Radau IIA), whichever
+    Lagrange nodes span the slab's polynomials."""
+    r0 = SlabBasis(0, nodes)
     R0 = r0.e1 @ np.linalg.solve(r0.T - z * r0.W, r0.e0)
     assert R0 == pytest.approx(1.0 / (1.0 - z), rel=1e-13)
-    r1 = SlabBasis(1)
+    r1 = SlabBasis(1, nodes)
     R1 = r1.e1 @ np.linalg.solve(r1.T - z * r1.W, r1.e0)
     assert R1 == pytest.approx((1 + z / 3) / (1 - 2 * z / 3 + z * z / 6), rel=1e-13)
+
+
+def test_gauss_nodes():
+    assert np.allclose(SlabBasis(0, "gauss").nodes, [0.5])
+    assert np.allclose(SlabBasis(1, "gauss").nodes, [(3 - math.sqrt(3)) / 6, (3 + math.sqrt(3)) / 6])
 
 
 def test_p2_basis_nodal_and_partition():
