@@ -75,7 +75,27 @@ typedef struct {
   const double* psi_coef;
   const int32_t* p_ab;
   const double* p_coef;
+  int32_t flow;   /* STWR_FLOW_MODES: the modes above; STWR_FLOW_CHORIN: see below */
+  int32_t temporal_nodes;  /* STWR_NODES_RADAU (default) or STWR_NODES_GAUSS, see below */
 } stwr_problem_desc;
+
+/* flow = STWR_FLOW_CHORIN selects the Chorin test problem of Sec. 2 (the mode
+ * arrays are then ignored and may be empty): velocity
+ *   u = (-cos(pi x) sin(pi y), sin(pi x) cos(pi y)) exp(-2 pi^2 t),
+ * full Dirichlet data and initial value from u, and no forcing (u with the
+ * pressure -(R/4)(cos 2 pi x + cos 2 pi y) exp(-4 pi^2 t) solves the equations). */
+#define STWR_FLOW_MODES 0
+#define STWR_FLOW_CHORIN 1
+
+/* Lagrange nodes of the DG(q) basis on each slab (Sec. 2 leaves them
+ * unnamed).  They fix the times at which the Dirichlet data is interpolated,
+ * the only place they change the discrete solution.  STWR_NODES_RADAU: right
+ * Gauss-Radau points ({1}; {1/3, 1}), the slab end value is the last nodal
+ * value.  STWR_NODES_GAUSS: Gauss-Legendre points ({1/2}; (3 -+ sqrt 3)/6),
+ * with which the Chorin error table of Sec. 4.2 is reproduced.  Vectors hold
+ * the nodal values in either case. */
+#define STWR_NODES_RADAU 0
+#define STWR_NODES_GAUSS 1
 
 /* Solver options (Sec. 3 and 4.2).  stwr_default_opts fills V(2,2),
  * Chebyshev [0.25, 1.05] * lam, 10 estimation steps, FP64 smoother,

@@ -43,7 +43,8 @@ class ProblemDesc(ctypes.Structure):
                 ("n_p_modes", ctypes.c_int32), ("psi_ab", ctypes.POINTER(ctypes.c_int32)),
                 ("psi_coef", ctypes.POINTER(ctypes.c_double)),
                 ("p_ab", ctypes.POINTER(ctypes.c_int32)),
-                ("p_coef", ctypes.POINTER(ctypes.c_double))]
+                ("p_coef", ctypes.POINTER(ctypes.c_double)), ("flow", ctypes.c_int32),
+                ("temporal_nodes", ctypes.c_int32)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -176,7 +177,8 @@ def make_desc(prob):
                     psi_ab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                     psi_coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     p_ab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                    p_coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                    p_coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    int(getattr(prob, "flow", 0)), int(getattr(prob, "nodes", 0)))
     return d, (psi_ab, psi_coef, p_ab, p_coef)
 
 

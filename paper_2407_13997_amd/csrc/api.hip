@@ -232,6 +232,9 @@ void check_desc(const stwr_problem_desc* d) {
     throw StwrError(STWR_ERR_ARG, "mesh_n must be divisible by 2^(n_levels-1) with a coarsest mesh of >= 2");
   if (!(d->t_final > 0.0)) throw StwrError(STWR_ERR_ARG, "t_final must be positive");
   if (d->n_psi_modes < 0 || d->n_p_modes < 0) throw StwrError(STWR_ERR_ARG, "bad mode counts");
+  if (d->flow != STWR_FLOW_MODES && d->flow != STWR_FLOW_CHORIN) throw StwrError(STWR_ERR_ARG, "bad flow");
+  if (d->temporal_nodes != STWR_NODES_RADAU && d->temporal_nodes != STWR_NODES_GAUSS)
+    throw StwrError(STWR_ERR_ARG, "bad temporal nodes");
   if ((d->n_psi_modes > 0 && (!d->psi_ab || !d->psi_coef)) || (d->n_p_modes > 0 && (!d->p_ab || !d->p_coef)))
     throw StwrError(STWR_ERR_ARG, "null mode arrays");
   const int mc = d->mesh_n >> (d->n_levels - 1);
@@ -1033,7 +1036,7 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
     }
     P->bytes = need;
     try {
-      build_ref_tables(desc->q, P->tab);
+      build_ref_tables(desc->q, desc->temporal_nodes, P->tab);
       P->d_tab = P->alloc<RefTables>(1);
       HIPCHK(hipMemcpyAsync(P->d_tab, &P->tab, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1044,6 +1047,7 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
       P->mms.p_ab = P->upload(P->p_ab);
       P->mms.p_coef = P->upload(P->p_coef);
       P->mms.reynolds = desc->reynolds;
+      P->mms.flow = desc->flow;
       const int L = (int)P->lv.size();
       for (int l = 0; l < L; ++l) upload_level(P.get(), P->lv[l], l == L - 1);
       for (int l = 0; l + 1 < L; ++l)

@@ -53,6 +53,12 @@ __device__ ModeSums psi_sums(const MmsDev& m, double t, double x, double y) {
 __device__ void exact_velocity(const MmsDev& m, double t, double x, double y, double& ux, double& uy) {
   ux = 0.0;
   uy = 0.0;
+  if (m.flow == 1) {   // Chorin test problem (Sec. 2)
+    const double e = exp(-2.0 * M_PI * M_PI * t);
+    ux = -cos(M_PI * x) * sin(M_PI * y) * e;
+    uy = sin(M_PI * x) * cos(M_PI * y) * e;
+    return;
+  }
   for (int k = 0; k < m.n_psi; ++k) {
     const double A = M_PI * m.psi_ab[2 * k], B = M_PI * m.psi_ab[2 * k + 1];
     const double c = m.psi_coef[3 * k], w = m.psi_coef[3 * k + 1], th = m.psi_coef[3 * k + 2];
@@ -63,6 +69,11 @@ __device__ void exact_velocity(const MmsDev& m, double t, double x, double y, do
 }
 
 __device__ void forcing(const MmsDev& m, double t, double x, double y, double& fx, double& fy) {
+  if (m.flow == 1) {   // the Chorin velocity and pressure solve the equations unforced
+    fx = 0.0;
+    fy = 0.0;
+    return;
+  }
   const ModeSums s = psi_sums(m, t, x, y);
   const double ux = s.py, uy = -s.px;
   const double convx = ux * s.pxy + uy * s.pyy;

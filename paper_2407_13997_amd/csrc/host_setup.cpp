@@ -64,8 +64,9 @@ static void p1_eval(double xi, double eta, double* v) {
   v[2] = eta;
 }
 
-void build_ref_tables(int q, RefTables& t) {
+void build_ref_tables(int q, int nodes, RefTables& t) {
   if (q < 0 || q > 1) throw std::invalid_argument("q must be 0 or 1");
+  if (nodes != 0 && nodes != 1) throw std::invalid_argument("temporal nodes must be 0 or 1");
   double u[5], wu[5];
   gauss_legendre01(5, u, wu);
   int k = 0;
@@ -85,9 +86,15 @@ void build_ref_tables(int q, RefTables& t) {
   t.NQ = q + 1;
   t.G = q + 3;
   gauss_legendre01(t.G, t.sg, t.wg);
-  // right Gauss-Radau nodes of the slab: {1} or {1/3, 1}
-  if (q == 0) t.tnode[0] = 1.0;
-  else { t.tnode[0] = 1.0 / 3.0; t.tnode[1] = 1.0; }
+  if (nodes == 0) {
+    // right Gauss-Radau nodes of the slab: {1} or {1/3, 1}
+    if (q == 0) t.tnode[0] = 1.0;
+    else { t.tnode[0] = 1.0 / 3.0; t.tnode[1] = 1.0; }
+  } else {
+    // Gauss-Legendre nodes of the slab
+    double w[kMaxNQ];
+    gauss_legendre01(q + 1, t.tnode, w);
+  }
   auto lag = [&](int a, double s, double* d) {
     double v = 1.0, dv = 0.0;
     for (int b = 0; b < t.NQ; ++b) {

@@ -33,7 +33,8 @@ struct RefTables {
   double W[kMaxNQ][kMaxNQ];  // int phi_a phi_b
 };
 
-void build_ref_tables(int q, RefTables& t);
+// nodes: 0 right Gauss-Radau, 1 Gauss-Legendre (the slab's Lagrange nodes)
+void build_ref_tables(int q, int nodes, RefTables& t);
 void gauss_legendre01(int n, double* x, double* w);
 
 struct HostLevel {

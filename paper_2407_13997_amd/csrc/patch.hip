@@ -309,7 +309,8 @@ template <int NQ, bool FULL>
 __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchView& P, const int p,
                                                 const float* __restrict__ fac,
                                                 const double* __restrict__ Mp, const double e00,
-                                                const double e01, const double* __restrict__ r,
+                                                const double e01, const double e10,
+                                                const double e11, const double* __restrict__ r,
                                                 float* __restrict__ Y, SweepF32Lds<NQ>& S) {
   constexpr int MAXM = kMaxNb * NQ;
   constexpr int VW = 4;
@@ -330,7 +331,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   constexpr int YCH = 2 * CH;                  // slabs per 128-byte line of FP32 outputs
   float* ych = S.ych;
   constexpr int YL = (YCH * MAXM + 255) / 256; // 16-byte output stores per lane and line
-  const float e0[2] = {(float)e00, (float)e01};
+  const float e0[2] = {(float)e00, (float)e01}, e1[2] = {(float)e10, (float)e11};
   const int lane = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = FULL ? kMaxNb : P.patch_ptr[p + 1] - s0;
@@ -467,20 +468,25 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
     issue(n + 1 < N ? n + 1 : n);
     __builtin_amdgcn_sched_barrier(0);
     const int sy = n % YCH;
+    // slab end value of each DoF, sum_b e1[b] y(row of node b): the nodes of
+    // a DoF sit in adjacent lanes (rows < 64) or adjacent quads (rows >= 64)
+    float v1 = e1[lane % NQ] * acc1;
+    if constexpr (NQ == 2) v1 += __shfl_xor(v1, 1);
     if (lane < r1) {
       ych[sy * m + lane] = acc1;
-      if (lane % NQ == NQ - 1) ylast[lane / NQ] = acc1;
+      if (lane % NQ == NQ - 1) ylast[lane / NQ] = v1;
     }
     if constexpr (kTwo) {
+      const int row = 64 + lane / 4;
+      float v2 = e1[row % NQ] * acc2;
+      if constexpr (NQ == 2) v2 += __shfl_xor(v2, 4);
       if (lane < 4 * r2 && quarter == 0) {
-        const int row = 64 + lane / 4;
         ych[sy * m + row] = acc2;
-        if (row % NQ == NQ - 1) ylast[row / NQ] = acc2;
+        if (row % NQ == NQ - 1) ylast[row / NQ] = v2;
       }
     }
     __syncthreads();
-    // jump coupling of the next slab: mj = M_v y_n(end of slab); the slab end
-    // value is the last temporal node (right Radau nodes)
+    // jump coupling of the next slab: mj = M_v y_n(end of slab)
     if (lane < nbu) {
       const int a = lane >> 1, c = lane & 1;
       float acc = 0.0f;
@@ -498,12 +504,13 @@ template <int NQ>
 __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P,
                                                        const float* __restrict__ fac,
                                                        const double* __restrict__ Mp, double e00,
-                                                       double e01, const double* __restrict__ r,
+                                                       double e01, double e10, double e11,
+                                                       const double* __restrict__ r,
                                                        float* __restrict__ Y) {
   __shared__ SweepF32Lds<NQ> S;
   const int p = P.order[blockIdx.x];
-  if ((int)blockIdx.x < P.n_full) sweep_f32_patch<NQ, true>(L, P, p, fac, Mp, e00, e01, r, Y, S);
-  else sweep_f32_patch<NQ, false>(L, P, p, fac, Mp, e00, e01, r, Y, S);
+  if ((int)blockIdx.x < P.n_full) sweep_f32_patch<NQ, true>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
+  else sweep_f32_patch<NQ, false>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
 }
 
 // One workgroup per patch, WAVES wavefronts, each owning at most
@@ -716,12 +723,10 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
   dim3 grid(P.n_patch);
   // wavefronts per patch = panels of the largest block / kPanelsPerWave
   if (prec == 1) {
-    // the FP32 kernel reads the slab end value as the last temporal node
-    if (e1[L.NQ - 1] != 1.0 || (L.NQ > 1 && e1[0] != 0.0)) return hipErrorInvalidValue;
     if (L.NQ == 1) {
-      hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
+      hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     } else {
-      hipLaunchKernelGGL(k_patch_sweep_f32<2>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, r, (float*)Y);
+      hipLaunchKernelGGL(k_patch_sweep_f32<2>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     }
   } else {
     if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
