@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-context", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--vcycles", type=int, default=3)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
@@ -222,6 +223,9 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_benchmark()
         log(f"[bench] serving: {out['serving']}")
+    if not args.no_paper_context:
+        out["paper_context"] = paper_context()
+        log(f"[bench] paper context: {out['paper_context']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
@@ -250,6 +254,48 @@ def profiled_traffic() -> int | None:
         if line.startswith("traffic_bytes_per_launch:"):
             rec_bytes = int(line.split(":", 1)[1].strip())
     return rec_bytes if (rec_sha == sha and rec_bytes) else None
+
+
+# The paper's Chorin runs (Sec. 4.2 tables of errors, times and iterations;
+# 80 x 80 mesh, R = 10, t in [0, 0.1], P2-P1, FGMRES-WRMG with Eisenstat-Walker
+# tolerances, Newton to 1e-8; 8 Xeon cores at 1.7 GHz, Firedrake/PETSc).
+# The q = 1, N = 10 error is printed as 1.77e-3 and read as 1.77e-4.
+PAPER_CHORIN = {
+    (0, 10): (6.51e-3, 110.0, "4 (11)"), (0, 20): (3.32e-3, 395.3, "4 (11)"),
+    (0, 40): (1.70e-3, 2596.8, "4 (11)"), (1, 10): (1.77e-4, 432.2, "4 (12)"),
+    (1, 20): (4.60e-5, 1971.7, "4 (10)"), (1, 40): (1.18e-5, 13964.7, "4 (17)"),
+}
+
+
+def paper_context() -> list:
+    """The Chorin runs of the paper's tables on this GPU (Gauss-Legendre
+    temporal nodes, FP32 smoother, Newton to 1e-8, FGMRES rtol 1e-10): space-time
+    velocity error, Newton (linear) iterations and time to solution, beside the
+    paper's figures (context on other hardware, not a target)."""
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    ctx = binding.Context(0)
+    rows = []
+    for (q, N), (p_err, p_time, p_its) in sorted(PAPER_CHORIN.items()):
+        prob = w.chorin_problem(80, 4, q, N, nodes=1)
+        o = binding.default_opts()
+        o.smoother_prec = binding.FP32
+        o.newton_rtol = 1e-8
+        P = binding.Problem(ctx, prob, o)
+        U = P.vec()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = P.newton_solve(U)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = P.velocity_l2_error(U)
+        P.close()
+        rows.append({"q": q, "N": N, "st_dofs": prob.n_st, "error": err, "paper_error": p_err,
+                     "time_s": dt, "paper_time_s": p_time,
+                     "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
+    ctx.close()
+    return rows
 
 
 def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:
