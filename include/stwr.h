@@ -115,7 +115,14 @@ typedef struct {
   int32_t newton_maxit;
   double newton_rtol;
   int32_t vcycle_graph;        /* 1: replay a captured HIP graph of the V-cycle; 0: launch */
+  int32_t newton_ew;           /* 1: Eisenstat-Walker linear tolerances in Newton (see below) */
 } stwr_solver_opts;
+
+/* newton_ew = 1 replaces gmres_rtol in Newton's linear solves by Eisenstat and
+ * Walker's second forcing term (SIAM J. Sci. Comput. 17, 1996; the paper's
+ * Chorin and cavity runs use it): eta_0 = 0.3, then
+ * eta_k = (||F_k|| / ||F_{k-1}||)^((1+sqrt 5)/2), raised to eta_{k-1}^((1+sqrt 5)/2)
+ * when that exceeds 0.1, at most 0.9.  Default 0. */
 
 #define STWR_MAX_NEWTON 64
 #define STWR_MAX_LEVELS 16

@@ -36,6 +36,26 @@ class Options:
     gmres_rtol: float = 1e-10
     newton_maxit: int = 20
     newton_rtol: float = 1e-10
+    newton_ew: bool = False      # Eisenstat-Walker linear tolerances (see ew_forcing)
+
+
+# Eisenstat and Walker's second choice of forcing term (SIAM J. Sci. Comput.
+# 17, 1996): eta_k = gamma (||F_k|| / ||F_{k-1}||)^alpha, kept at least
+# gamma eta_{k-1}^alpha when that exceeds a threshold, and at most eta_max;
+# eta_0 given.  The paper cites the method without its parameters; these are
+# the defaults of the PETSc implementation it ran on.
+EW_ETA0, EW_ETA_MAX, EW_GAMMA, EW_ALPHA, EW_THRESHOLD = 0.3, 0.9, 1.0, (1 + 5 ** 0.5) / 2, 0.1
+
+
+def ew_forcing(k, fnorm, fnorm_prev, eta_prev):
+    """Relative tolerance of the k-th Newton linear solve."""
+    if k == 0:
+        return EW_ETA0
+    eta = EW_GAMMA * (fnorm / fnorm_prev) ** EW_ALPHA
+    safe = EW_GAMMA * eta_prev ** EW_ALPHA
+    if safe > EW_THRESHOLD:
+        eta = max(eta, safe)
+    return min(eta, EW_ETA_MAX)
 
 
 def project_pressure(level, v):
@@ -141,8 +161,9 @@ class Hierarchy:
         return self.relax(l, b, x, self.opts.nu_post)
 
 
-def fgmres(A, prec, b, rtol, restart, maxit, project=lambda v: v):
-    """Right-preconditioned restarted FGMRES with MGS; returns (x, iterations, history)."""
+def fgmres(A, prec, b, rtol, restart, maxit, project=lambda v: v, atol=0.0):
+    """Right-preconditioned restarted FGMRES with MGS, stopping when the
+    residual is at most max(rtol ||b||, atol); returns (x, iterations, history)."""
     n = b.size
     x = np.zeros(n)
     bnorm = np.linalg.norm(b)
@@ -154,7 +175,7 @@ def fgmres(A, prec, b, rtol, restart, maxit, project=lambda v: v):
         r = b - A @ x
         beta = np.linalg.norm(r)
         hist.append(beta / bnorm)
-        if beta <= rtol * bnorm or its >= maxit:
+        if beta <= max(rtol * bnorm, atol) or its >= maxit:
             break
         V = np.zeros((restart + 1, n))
         Z = np.zeros((restart, n))
@@ -186,7 +207,7 @@ def fgmres(A, prec, b, rtol, restart, maxit, project=lambda v: v):
             its += 1
             j_last = j
             hist.append(abs(g[j + 1]) / bnorm)
-            if abs(g[j + 1]) <= rtol * bnorm or its >= maxit:
+            if abs(g[j + 1]) <= max(rtol * bnorm, atol) or its >= maxit:
                 break
         k = j_last + 1
         y = la.solve_triangular(H[:k, :k], g[:k])
@@ -204,14 +225,23 @@ def newton_solve(prob, opts=None, max_newton=None, x0=None):
     x = L0.initial_guess().ravel() if x0 is None else np.array(x0, dtype=float).ravel()
     F = L0.residual(x.reshape(L0.n_free, L0.N, L0.nq)).ravel()
     f0 = np.linalg.norm(F)
-    stats = {"newton": 0, "linear": [], "fnorm": [f0]}
+    stats = {"newton": 0, "linear": [], "fnorm": [f0], "eta": []}
     maxit = o.newton_maxit if max_newton is None else max_newton
+    eta = None
     for k in range(maxit):
         if np.linalg.norm(F) <= o.newton_rtol * f0:
             break
         H.assemble(x)
-        dx, its, _ = fgmres(H.A[0], H.vcycle, -F, o.gmres_rtol, o.gmres_restart,
-                            o.gmres_maxit, lambda v: project_pressure(L0, v))
+        rtol = o.gmres_rtol
+        if o.newton_ew:
+            eta = ew_forcing(k, stats["fnorm"][-1], stats["fnorm"][-2] if k else f0, eta)
+            rtol = eta
+            stats["eta"].append(eta)
+        # absolute floor three orders below the Newton target: a relative
+        # tolerance alone would chase rounding once F is tiny
+        dx, its, _ = fgmres(H.A[0], H.vcycle, -F, rtol, o.gmres_restart,
+                            o.gmres_maxit, lambda v: project_pressure(L0, v),
+                            atol=1e-3 * o.newton_rtol * f0)
         x = x + dx
         F = L0.residual(x.reshape(L0.n_free, L0.N, L0.nq)).ravel()
         stats["newton"] += 1

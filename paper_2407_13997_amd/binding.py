@@ -53,7 +53,8 @@ class SolverOpts(ctypes.Structure):
                 ("eig_steps", ctypes.c_int32), ("smoother_prec", ctypes.c_int32),
                 ("gmres_restart", ctypes.c_int32), ("gmres_maxit", ctypes.c_int32),
                 ("gmres_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
-                ("newton_rtol", ctypes.c_double), ("vcycle_graph", ctypes.c_int32)]
+                ("newton_rtol", ctypes.c_double), ("vcycle_graph", ctypes.c_int32),
+                ("newton_ew", ctypes.c_int32)]
 
 
 MAX_NEWTON, MAX_LEVELS = 64, 16

@@ -248,7 +248,8 @@ void check_opts(const stwr_solver_opts* o) {
   if (o->nu_pre < 0 || o->nu_post < 0 || o->eig_steps < 1 || o->eig_steps > 64 || o->gmres_restart < 1 ||
       o->gmres_restart > 200 || o->gmres_maxit < 1 || o->newton_maxit < 0 || o->newton_maxit > STWR_MAX_NEWTON ||
       (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
-      !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1))
+      !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1) ||
+      (o->newton_ew != 0 && o->newton_ew != 1))
     throw StwrError(STWR_ERR_ARG, "invalid solver options");
 }
 
@@ -794,7 +795,7 @@ void setup_smoothers(stwr_problem* P) {
 // Right-preconditioned restarted FGMRES with modified Gram-Schmidt.
 // Stops when ||r|| <= max(rtol ||b||, atol).
 void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* its_out, double* rel_out,
-            double atol = 0.0) {
+            double atol = 0.0, double rtol = -1.0) {
   const stwr_solver_opts& o = P->opts;
   Level& L0 = P->lv[0];
   const int64_t n = L0.n_st;
@@ -804,7 +805,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
   int its = 0;
   double rel = 0.0;
   if (bnorm == 0.0) { if (its_out) *its_out = 0; if (rel_out) *rel_out = 0.0; return; }
-  const double target = std::max(o.gmres_rtol * bnorm, atol);
+  const double target = std::max((rtol >= 0.0 ? rtol : o.gmres_rtol) * bnorm, atol);
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
   auto V = [&](int j) { return P->V + j * n; };
   auto Z = [&](int j) { return P->Z + j * n; };
@@ -886,6 +887,7 @@ int32_t stwr_default_opts(stwr_solver_opts* o) {
   o->newton_maxit = 20;
   o->newton_rtol = 1e-10;
   o->vcycle_graph = 1;
+  o->newton_ew = 0;
   return STWR_OK;
 }
 
@@ -1329,6 +1331,20 @@ int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* sta
 // Newton stops as diverged once ||F|| exceeds this multiple of ||F_0||.
 constexpr double kNewtonDiverged = 1e2;
 
+// Eisenstat and Walker's second forcing term (SIAM J. Sci. Comput. 17, 1996):
+// eta_k = gamma (||F_k|| / ||F_{k-1}||)^alpha, kept at least
+// gamma eta_{k-1}^alpha when that exceeds a threshold, at most eta_max; the
+// parameters are the PETSc defaults (the paper cites the method only).
+double ew_forcing(int k, double f, double f_prev, double eta_prev) {
+  const double eta0 = 0.3, eta_max = 0.9, gamma = 1.0, threshold = 0.1;
+  const double alpha = 0.5 * (1.0 + std::sqrt(5.0));
+  if (k == 0) return eta0;
+  double eta = gamma * std::pow(f / f_prev, alpha);
+  const double safe = gamma * std::pow(eta_prev, alpha);
+  if (safe > threshold) eta = std::max(eta, safe);
+  return std::min(eta, eta_max);
+}
+
 int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
@@ -1353,6 +1369,7 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
     st.fnorm[0] = f;
     int k = 0;
     bool converged = f0 == 0.0;
+    double eta = 0.0;
     for (; k < o.newton_maxit && !converged; ++k) {
       const double ts = now_s();
       assemble(p, U);
@@ -1365,7 +1382,9 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
       const double tk = now_s();
       // absolute floor of the linear solve: three orders below the Newton
       // target (a relative tolerance alone would chase rounding once F is tiny)
-      fgmres(p, F, dU, &st, &its, &rel, 1e-3 * o.newton_rtol * f0);
+      double rtol = -1.0;   // options' gmres_rtol
+      if (o.newton_ew) rtol = eta = ew_forcing(k, f, k > 0 ? st.fnorm[k - 1] : f0, eta);
+      fgmres(p, F, dU, &st, &its, &rel, 1e-3 * o.newton_rtol * f0, rtol);
       st.solve_seconds += now_s() - tk;
       HIPCHK(launch_axpby(n, 1.0, dU, 1.0, U, p->s()));
       st.linear_its[k] = its;

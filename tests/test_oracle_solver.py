@@ -135,3 +135,23 @@ def test_mesh_independent_iterations():
         _, n, _ = fgmres(H.A[0], H.vcycle, -F, 1e-8, 30, 100, lambda v: project_pressure(L0, v))
         its.append(n)
     assert abs(its[1] - its[0]) <= 3 and max(its) <= 25, its
+
+
+def test_newton_with_eisenstat_walker_reaches_the_exact_solution():
+    """Newton with Eisenstat-Walker forcing terms (choice 2) converges to the
+    exact discrete solution (slab-by-slab direct route) like the fixed
+    tolerance does, with fewer linear iterations; the forcing terms start at
+    eta_0 and shrink as the residual ratio does."""
+    from oracle.direct import solve_slab_by_slab
+    from oracle.multigrid import newton_solve
+    p = w.small_problem(8, 2, 0, 3, 10.0, seed=31)
+    L = Level(8, 0, 3, 1.0, MMS(p.psi_ab, p.psi_coef, p.p_ab, p.p_coef, p.reynolds))
+    xs = solve_slab_by_slab(L).ravel()
+    x1, s1, _ = newton_solve(p, Options(newton_rtol=1e-12))
+    x2, s2, _ = newton_solve(p, Options(newton_rtol=1e-12, newton_ew=True))
+    assert np.linalg.norm(x1 - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert np.linalg.norm(x2 - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert sum(s2["linear"]) < sum(s1["linear"])
+    eta = s2["eta"]
+    assert eta[0] == 0.3 and all(0.0 < e <= 0.9 for e in eta)
+    assert eta[-1] < eta[0]
