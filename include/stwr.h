@@ -75,7 +75,7 @@ typedef struct {
   const double* psi_coef;
   const int32_t* p_ab;
   const double* p_coef;
-  int32_t flow;   /* STWR_FLOW_MODES: the modes above; STWR_FLOW_CHORIN: see below */
+  int32_t flow;   /* STWR_FLOW_MODES: the modes above; STWR_FLOW_CHORIN, STWR_FLOW_CAVITY: below */
   int32_t temporal_nodes;  /* STWR_NODES_RADAU (default) or STWR_NODES_GAUSS, see below */
 } stwr_problem_desc;
 
@@ -84,8 +84,14 @@ typedef struct {
  *   u = (-cos(pi x) sin(pi y), sin(pi x) cos(pi y)) exp(-2 pi^2 t),
  * full Dirichlet data and initial value from u, and no forcing (u with the
  * pressure -(R/4)(cos 2 pi x + cos 2 pi y) exp(-4 pi^2 t) solves the equations). */
+/* flow = STWR_FLOW_CAVITY selects the lid-driven cavity of Sec. 2: velocity
+ * (1, 0) on the open top side, zero on the other sides and at the two top
+ * corners, zero initial velocity (the lid moves from the first slab on), no
+ * forcing; there is no exact solution (stwr_velocity_l2_error then measures
+ * against the boundary data). */
 #define STWR_FLOW_MODES 0
 #define STWR_FLOW_CHORIN 1
+#define STWR_FLOW_CAVITY 2
 
 /* Lagrange nodes of the DG(q) basis on each slab (Sec. 2 leaves them
  * unnamed).  They fix the times at which the Dirichlet data is interpolated,

@@ -71,8 +71,12 @@ class Level:
         return self._dir
 
     def initial_full(self):
-        """P2 interpolant of the velocity at t = 0 on every node: (nn,) x 2."""
-        return self.mms.velocity(0.0, self.mesh.nxy[:, 0], self.mesh.nxy[:, 1])
+        """P2 interpolant of the initial velocity on every node: (nn,) x 2 (the
+        velocity at t = 0, unless the flow states its own initial value)."""
+        x, y = self.mesh.nxy[:, 0], self.mesh.nxy[:, 1]
+        if hasattr(self.mms, "initial_velocity"):
+            return self.mms.initial_velocity(x, y)
+        return self.mms.velocity(0.0, x, y)
 
     def full_state(self, x_free):
         """Full nodal arrays (ux, uy, p) from a free space-time vector (n_free, N, nq)."""

@@ -124,9 +124,40 @@ class Chorin:
         return np.zeros(t.shape), np.zeros(t.shape)
 
 
+class Cavity:
+    """The lid-driven cavity (Sec. 2, Definition of the lid-driven cavity):
+    velocity (1, 0) on the top side of the unit square, zero on the bottom,
+    left and right sides, no forcing, zero initial velocity.  Readings: the
+    two top corners belong to the no-slip sides (zero), and the lid is at
+    speed 1 from the first slab on (the initial value is zero everywhere, the
+    lid included).  There is no exact solution; ``velocity`` gives the
+    boundary data."""
+
+    def __init__(self, reynolds):
+        self.R = float(reynolds)
+
+    def velocity(self, t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float),
+                                      np.asarray(y, float))
+        lid = (y > 1.0 - 1e-12) & (x > 1e-12) & (x < 1.0 - 1e-12)
+        return np.where(lid, 1.0, 0.0), np.zeros(t.shape)
+
+    def initial_velocity(self, x, y):
+        x = np.asarray(x, float)
+        return np.zeros(x.shape), np.zeros(x.shape)
+
+    def forcing(self, t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float),
+                                      np.asarray(y, float))
+        return np.zeros(t.shape), np.zeros(t.shape)
+
+
 def make_flow(prob):
-    """The exact solution of a problem: the manufactured modes, or the Chorin
-    problem when prob.flow == 1."""
-    if getattr(prob, "flow", 0) == 1:
+    """The flow of a problem: the manufactured modes, the Chorin problem
+    (prob.flow == 1) or the lid-driven cavity (prob.flow == 2)."""
+    flow = getattr(prob, "flow", 0)
+    if flow == 1:
         return Chorin(prob.reynolds)
+    if flow == 2:
+        return Cavity(prob.reynolds)
     return MMS(prob.psi_ab, prob.psi_coef, prob.p_ab, prob.p_coef, prob.reynolds)

@@ -232,7 +232,8 @@ void check_desc(const stwr_problem_desc* d) {
     throw StwrError(STWR_ERR_ARG, "mesh_n must be divisible by 2^(n_levels-1) with a coarsest mesh of >= 2");
   if (!(d->t_final > 0.0)) throw StwrError(STWR_ERR_ARG, "t_final must be positive");
   if (d->n_psi_modes < 0 || d->n_p_modes < 0) throw StwrError(STWR_ERR_ARG, "bad mode counts");
-  if (d->flow != STWR_FLOW_MODES && d->flow != STWR_FLOW_CHORIN) throw StwrError(STWR_ERR_ARG, "bad flow");
+  if (d->flow != STWR_FLOW_MODES && d->flow != STWR_FLOW_CHORIN && d->flow != STWR_FLOW_CAVITY)
+    throw StwrError(STWR_ERR_ARG, "bad flow");
   if (d->temporal_nodes != STWR_NODES_RADAU && d->temporal_nodes != STWR_NODES_GAUSS)
     throw StwrError(STWR_ERR_ARG, "bad temporal nodes");
   if ((d->n_psi_modes > 0 && (!d->psi_ab || !d->psi_coef)) || (d->n_p_modes > 0 && (!d->p_ab || !d->p_coef)))

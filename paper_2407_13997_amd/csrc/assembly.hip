@@ -59,6 +59,10 @@ __device__ void exact_velocity(const MmsDev& m, double t, double x, double y, do
     uy = sin(M_PI * x) * cos(M_PI * y) * e;
     return;
   }
+  if (m.flow == 2) {   // lid-driven cavity: the lid is the open top side
+    if (y > 1.0 - 1e-12 && x > 1e-12 && x < 1.0 - 1e-12) ux = 1.0;
+    return;
+  }
   for (int k = 0; k < m.n_psi; ++k) {
     const double A = M_PI * m.psi_ab[2 * k], B = M_PI * m.psi_ab[2 * k + 1];
     const double c = m.psi_coef[3 * k], w = m.psi_coef[3 * k + 1], th = m.psi_coef[3 * k + 2];
@@ -68,8 +72,19 @@ __device__ void exact_velocity(const MmsDev& m, double t, double x, double y, do
   }
 }
 
+// Initial velocity: the velocity at t = 0, except for the cavity, which
+// starts at rest (the lid included).
+__device__ void initial_velocity(const MmsDev& m, double x, double y, double& ux, double& uy) {
+  if (m.flow == 2) {
+    ux = 0.0;
+    uy = 0.0;
+    return;
+  }
+  exact_velocity(m, 0.0, x, y, ux, uy);
+}
+
 __device__ void forcing(const MmsDev& m, double t, double x, double y, double& fx, double& fy) {
-  if (m.flow == 1) {   // the Chorin velocity and pressure solve the equations unforced
+  if (m.flow != 0) {   // the Chorin pair solves the equations unforced; the cavity has none
     fx = 0.0;
     fy = 0.0;
     return;
@@ -276,7 +291,7 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
     double v = 0.0;
     if (n == 0) {
       double ux, uy;
-      exact_velocity(mms, 0.0, x, y, ux, uy);
+      initial_velocity(mms, x, y, ux, uy);
       v = comp == 0 ? ux : uy;
     } else {
       for (int b = 0; b < NQ; ++b) {

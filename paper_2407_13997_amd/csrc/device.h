@@ -17,7 +17,7 @@ struct MmsDev {
   const int* p_ab;        // n_p x 2
   const double* p_coef;   // n_p x 3
   double reynolds;
-  int flow;               // 0: the modes; 1: the Chorin test problem (modes unused)
+  int flow;               // 0: the modes; 1: Chorin problem; 2: lid-driven cavity (modes unused)
 };
 
 // Read-only structure of one level on the device.

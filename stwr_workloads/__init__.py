@@ -24,8 +24,8 @@ import math
 
 import numpy as np
 
-__all__ = ["Problem", "draw_modes", "named_problem", "batch_problems",
-           "arrival_times", "seeded_vector", "chorin_problem", "WORKLOADS", "SMOKE", "MEDIUM",
+__all__ = ["Problem", "draw_modes", "named_problem", "batch_problems", "arrival_times",
+           "seeded_vector", "chorin_problem", "cavity_problem", "WORKLOADS", "SMOKE", "MEDIUM",
            "LARGE"]
 
 
@@ -43,7 +43,7 @@ class Problem:
     p_ab: np.ndarray
     p_coef: np.ndarray
     seed: int = 0
-    flow: int = 0          # 0: the manufactured modes; 1: the Chorin test problem (modes unused)
+    flow: int = 0          # 0: manufactured modes; 1: Chorin problem; 2: lid-driven cavity
     nodes: int = 0         # temporal nodes: 0 right Gauss-Radau, 1 Gauss-Legendre
 
     @property
@@ -117,6 +117,17 @@ def chorin_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int, reynolds: f
     none_f = np.zeros((0, 3))
     return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, none_i, none_f, none_i, none_f,
                    seed=0, flow=1, nodes=nodes)
+
+
+def cavity_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int, reynolds: float,
+                   t_final: float = 0.02, nodes: int = 1) -> Problem:
+    """The lid-driven cavity on [0, t_final] (the paper's runs: 40 x 40 and
+    80 x 80 meshes from a 10 x 10 base, R = 1, 10, 100, t in [0, 0.02],
+    N = 20), Gauss-Legendre temporal nodes by default."""
+    none_i = np.zeros((0, 2), dtype=np.int64)
+    none_f = np.zeros((0, 3))
+    return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, none_i, none_f, none_i, none_f,
+                   seed=0, flow=2, nodes=nodes)
 
 
 def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,

@@ -192,3 +192,30 @@ def test_chorin_error_matches_paper_table_with_gauss_nodes(N, paper):
         err[nodes] = lev.velocity_l2_error(x.reshape(lev.n_free, lev.N, lev.nq))
     assert abs(err["gauss"] / paper - 1.0) < 0.05
     assert err["radau"] / paper > 1.6
+
+
+def test_cavity_boundary_data_and_routes():
+    """Lid-driven cavity (Sec. 2): lid (1, 0) on the open top side, zero on the
+    other sides and at the top corners, zero initial value; the exact discrete
+    solution by the slab-by-slab route equals the all-at-once dense solve, and
+    Newton-FGMRES-WRMG reaches it."""
+    import stwr_workloads as ww
+    from oracle.assembly import Level
+    from oracle.direct import solve_all_at_once, solve_slab_by_slab
+    from oracle.mms import Cavity
+    from oracle.multigrid import Options, newton_solve
+    lev = Level(4, 1, 2, 0.02, Cavity(10.0), "gauss")
+    m = lev.mesh
+    bx, by = lev.dirichlet_full()
+    top = (m.nxy[:, 1] > 1 - 1e-12) & (m.nxy[:, 0] > 1e-12) & (m.nxy[:, 0] < 1 - 1e-12)
+    bnd = m.node_free < 0
+    assert np.all(bx[top] == 1.0) and np.all(by[bnd] == 0.0)
+    assert np.all(bx[bnd & ~top] == 0.0)
+    i0x, i0y = lev.initial_full()
+    assert not i0x.any() and not i0y.any()
+    x2 = solve_slab_by_slab(lev, tol=0.0).ravel()
+    x3 = solve_all_at_once(lev).ravel()
+    assert np.linalg.norm(x2 - x3) <= 1e-10 * np.linalg.norm(x3)
+    p = ww.cavity_problem(4, 2, 1, 2, 10.0)
+    x1, st, _ = newton_solve(p, Options(newton_rtol=1e-12))
+    assert np.linalg.norm(x1 - x3) <= 1e-9 * np.linalg.norm(x3)
