@@ -267,37 +267,63 @@ PAPER_CHORIN = {
 }
 
 
-def paper_context() -> list:
-    """The Chorin runs of the paper's tables on this GPU (Gauss-Legendre
-    temporal nodes, FP32 smoother, Newton to 1e-8 with Eisenstat-Walker linear
-    tolerances, as the paper ran them): space-time
-    velocity error, Newton (linear) iterations and time to solution, beside the
-    paper's figures (context on other hardware, not a target)."""
+# The paper's lid-driven cavity runs (Sec. 4.3, P2-P1 columns): (mesh, q, R)
+# -> (time to solution in s, "Newton (linear)" with Eisenstat-Walker
+# tolerances); 40 x 40 and 80 x 80 are its two and three refinements of the
+# 10 x 10 base mesh, N = 20, t in [0, 0.02].
+PAPER_CAVITY = {
+    (40, 1, 1.0): (432.8, "4 (10)"), (40, 1, 10.0): (434.2, "4 (10)"), (40, 1, 100.0): (456.6, "4 (13)"),
+    (40, 0, 1.0): (90.6, "4 (10)"), (40, 0, 10.0): (90.3, "4 (11)"), (40, 0, 100.0): (98.8, "4 (15)"),
+    (80, 1, 1.0): (1798.1, "4 (8)"), (80, 1, 10.0): (1782.4, "4 (8)"), (80, 1, 100.0): (1894.1, "4 (13)"),
+    (80, 0, 1.0): (347.7, "4 (8)"), (80, 0, 10.0): (348.9, "4 (8)"), (80, 0, 100.0): (381.9, "4 (12)"),
+}
+
+
+def _timed_newton(ctx, prob):
+    """Newton to 1e-8 with Eisenstat-Walker linear tolerances and the FP32
+    smoother, as the paper's runs were set; returns (stats, seconds, error)."""
     import torch
+    from paper_2407_13997_amd import binding
+    o = binding.default_opts()
+    o.smoother_prec = binding.FP32
+    o.newton_rtol = 1e-8
+    o.newton_ew = 1
+    P = binding.Problem(ctx, prob, o)
+    U = P.vec()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = P.newton_solve(U)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = P.velocity_l2_error(U) if prob.flow != 2 else None
+    P.close()
+    return st, dt, err
+
+
+def paper_context() -> dict:
+    """The Chorin and lid-driven cavity runs of the paper's tables on this GPU
+    (Gauss-Legendre temporal nodes, FP32 smoother, Newton to 1e-8 with
+    Eisenstat-Walker linear tolerances, as the paper ran them): space-time
+    velocity error (Chorin), Newton (linear) iterations and time to solution,
+    beside the paper's figures (context on other hardware, not a target)."""
     import stwr_workloads as w
     from paper_2407_13997_amd import binding
     ctx = binding.Context(0)
-    rows = []
+    chorin, cavity = [], []
     for (q, N), (p_err, p_time, p_its) in sorted(PAPER_CHORIN.items()):
         prob = w.chorin_problem(80, 4, q, N, nodes=1)
-        o = binding.default_opts()
-        o.smoother_prec = binding.FP32
-        o.newton_rtol = 1e-8
-        o.newton_ew = 1
-        P = binding.Problem(ctx, prob, o)
-        U = P.vec()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = P.newton_solve(U)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        err = P.velocity_l2_error(U)
-        P.close()
-        rows.append({"q": q, "N": N, "st_dofs": prob.n_st, "error": err, "paper_error": p_err,
-                     "time_s": dt, "paper_time_s": p_time,
-                     "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
+        st, dt, err = _timed_newton(ctx, prob)
+        chorin.append({"q": q, "N": N, "st_dofs": prob.n_st, "error": err, "paper_error": p_err,
+                       "time_s": dt, "paper_time_s": p_time,
+                       "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
+    for (M, q, R), (p_time, p_its) in sorted(PAPER_CAVITY.items()):
+        prob = w.cavity_problem(M, 3 if M == 40 else 4, q, 20, R)
+        st, dt, _ = _timed_newton(ctx, prob)
+        cavity.append({"mesh": M, "q": q, "R": R, "st_dofs": prob.n_st, "time_s": dt,
+                       "paper_time_s": p_time,
+                       "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
     ctx.close()
-    return rows
+    return {"chorin": chorin, "cavity": cavity}
 
 
 def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:

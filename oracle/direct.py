@@ -5,6 +5,11 @@
   by Newton with a sparse direct solve of the slab block bordered by the
   zero-mean pressure constraints (the timestepping view of Sec. 3, where the
   same discretisation is coupled over one time element at a time).
+* Space-time Newton with exact linear solves: each Newton correction solves
+  the whole space-time Jacobian system exactly, by forward substitution over
+  the slabs (the Jacobian is block lower bidiagonal in time) with a sparse
+  direct solve of each bordered slab block.  This is the direct-solver
+  comparison of Sec. 4.3, which counts Newton steps with direct linear solves.
 * R3, all at once: Newton on the whole space-time system with a dense LU of
   the bordered space-time Jacobian (the monolithic direct comparison of
   Sec. 4.1), for tiny meshes only.
@@ -72,3 +77,39 @@ def solve_all_at_once(level, tol=1e-13, maxit=30):
         d = la.solve(B, np.concatenate([-F, np.zeros(N * nq)]))[:n]
         x += d
     return x.reshape(nf, N, nq)
+
+
+def newton_exact_linear(level, rtol=1e-8, maxit=20):
+    """Newton on the whole space-time system, started from zero, with full
+    steps and exact linear solves, stopped once ||F|| <= rtol ||F_0||.
+    Returns (solution, [||F_k||])."""
+    nf, N, nq = level.n_free, level.N, level.nq
+    st = N * nq
+    po = level.mesh.p_offset
+    ns = nf * nq
+    rows = (np.arange(po, nf)[:, None] * nq + np.arange(nq)[None, :]).ravel()
+    cols = np.tile(np.arange(nq), nf - po)
+    C = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(ns, nq))
+    # slab-major order: slab n occupies rows n*ns .. (n+1)*ns of the permuted system
+    perm = np.concatenate([(np.arange(nf)[:, None] * st + n * nq + np.arange(nq)[None, :]).ravel()
+                           for n in range(N)])
+    x = np.zeros(nf * st)
+    fnorm = []
+    for _ in range(maxit + 1):
+        F = level.residual(x.reshape(nf, N, nq)).ravel()
+        fnorm.append(np.linalg.norm(F))
+        if fnorm[-1] <= rtol * fnorm[0]:
+            break
+        J = level.jacobian(x.reshape(nf, N, nq)).tocsr()[perm][:, perm].tocsr()
+        b = -F[perm]
+        d = np.zeros(nf * st)
+        for n in range(N):
+            r = slice(n * ns, (n + 1) * ns)
+            rhs = b[r]
+            if n > 0:
+                rhs = rhs - J[r, (n - 1) * ns:n * ns] @ d[(n - 1) * ns:n * ns]
+            B = sp.bmat([[J[r, r], C], [C.T, None]], format="csc")
+            d[r] = spla.spsolve(B, np.concatenate([rhs, np.zeros(nq)]))[:ns]
+        x[perm] += d
+    return x.reshape(nf, N, nq), fnorm
+
