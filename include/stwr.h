@@ -12,6 +12,8 @@
  *   transfers ............. Sec. 3, P = I (x) blockdiag(P_u, P_phi), R = P^T
  *   patch relaxation ...... Sec. 3 Vanka+star patches, eq. waveform_patch_solve
  *   Newton ................ Sec. 4.2
+ *   heat equation ......... Sec. 2, eq. heatfem; vertex-star patches, Sec. 3;
+ *                           FGMRES-WRMG runs of Sec. 4.1 (equation = STWR_EQ_HEAT)
  *
  * Conventions shared by every call
  * ---------------------------------
@@ -77,7 +79,26 @@ typedef struct {
   const double* p_coef;
   int32_t flow;   /* STWR_FLOW_MODES: the modes above; STWR_FLOW_CHORIN, STWR_FLOW_CAVITY: below */
   int32_t temporal_nodes;  /* STWR_NODES_RADAU (default) or STWR_NODES_GAUSS, see below */
+  int32_t equation;        /* STWR_EQ_NAVIER_STOKES (default) or STWR_EQ_HEAT, see below */
+  int32_t degree;          /* spatial degree k of the heat equation's P_k, 1..3 (else ignored) */
 } stwr_problem_desc;
+
+/* equation = STWR_EQ_HEAT selects the heat equation u_t - Laplace u = 0 of
+ * Sec. 2 (eq. heatfem) on the unit square with natural (homogeneous Neumann)
+ * boundary conditions, scalar continuous P_k in space (k = degree, 1..3) and
+ * DG(q) in time (q in {0, 1}), initial value the nodal interpolant of
+ * u_0 = sin(pi x) + cos(2 pi y) (the paper's runs, Sec. 4.1).  Reynolds
+ * number, modes and flow are ignored.  Every node of the (k M + 1)^2 lattice
+ * of spacing 1/(k M) is an unknown: node g = gi + (k M + 1) gj is DoF g, so
+ * n_free = (k M + 1)^2.  The smoother's patches are the vertex stars (Sec. 3:
+ * the vertex and the nodes interior to its incident edges and cells,
+ * 3k^2 - 3k + 1 DoFs at an interior vertex).  The operator is linear and
+ * assembled at creation; stwr_nonlinear_residual gives F(U) = A U - b with
+ * b = e0 (x) M U_0 on slab 0 (stwr_linear_rhs returns b), so
+ * stwr_fgmres(b) is the paper's solve and stwr_newton_solve converges in one
+ * step.  The coarsest level must satisfy (k M_c + 1)^2 (q + 1) <= 2048. */
+#define STWR_EQ_NAVIER_STOKES 0
+#define STWR_EQ_HEAT 1
 
 /* flow = STWR_FLOW_CHORIN selects the Chorin test problem of Sec. 2 (the mode
  * arrays are then ignored and may be empty): velocity
@@ -122,6 +143,8 @@ typedef struct {
   double newton_rtol;
   int32_t vcycle_graph;        /* 1: replay a captured HIP graph of the V-cycle; 0: launch */
   int32_t newton_ew;           /* 1: Eisenstat-Walker linear tolerances in Newton (see below) */
+  double gmres_atol;           /* stwr_fgmres also stops once ||r|| <= gmres_atol (default 0;
+                                  the paper's heat runs: rtol 1e-6, atol 1e-6) */
 } stwr_solver_opts;
 
 /* newton_ew = 1 replaces gmres_rtol in Newton's linear solves by Eisenstat and
@@ -195,27 +218,37 @@ int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts);
 
 /* Nonlinear space-time residual F(U) of eq. nsfem (level 0), U and F of
  * length n_st(0).  Boundary values are the exact velocity at the temporal
- * nodes; the initial value is the P2 interpolant of the velocity at t = 0. */
+ * nodes; the initial value is the P2 interpolant of the velocity at t = 0.
+ * Heat equation: F(U) = A U - b (eq. heatfem). */
 int32_t stwr_nonlinear_residual(stwr_problem* p, const double* U, double* F);
+
+/* b = -F(0), the right-hand side of the first Newton correction; for the
+ * heat equation the right-hand side of its linear system, e0 (x) M U_0 on
+ * slab 0 (eq. heatfem's jump term with U_0^- the initial value).  b: device
+ * vector of length n_st(0). */
+int32_t stwr_linear_rhs(stwr_problem* p, double* b);
 
 /* Space-time velocity L2 error of U against the manufactured velocity,
  * sqrt(sum_n int_{I_n} ||u - U||^2 dt) (the error measure of the paper's
  * convergence tables, Sec. 5), by the residual's quadrature rules.  U: device
  * vector of length n_st(0); err: host scalar (the call synchronises).  The
- * sum has a fixed order, so repeated calls give identical results. */
+ * sum has a fixed order, so repeated calls give identical results.
+ * STWR_ERR_STATE for the heat equation. */
 int32_t stwr_velocity_l2_error(stwr_problem* p, const double* U, double* err);
 
 /* Full nodal space-time vector from a free one (adds the Dirichlet values):
  * full = [ux at every P2 node][uy at every P2 node][p at every vertex], each
  * row [slab][temporal node]; P2 nodes number i + (2M+1) j on the (2M+1)^2
  * grid of the mesh, vertices i + (M+1) j.  Length
- * (2 (2M+1)^2 + (M+1)^2) N (q+1); device pointers, caller-owned. */
+ * (2 (2M+1)^2 + (M+1)^2) N (q+1); device pointers, caller-owned.
+ * STWR_ERR_STATE for the heat equation (every node is already free). */
 int32_t stwr_expand(stwr_problem* p, const double* U, double* full);
 
 /* Jacobian dF/dU at U (level 0 vector) on every level: the iterate is
  * injected to the coarse nodes and each level rediscretised; also factors
  * the coarsest level (bordered by one zero-mean pressure constraint per
- * temporal node).  Invalidates patch factors and eigen-estimates. */
+ * temporal node).  Invalidates patch factors and eigen-estimates.  Heat
+ * equation: rebuilds its (state-independent) operator; U is not read. */
 int32_t stwr_assemble(stwr_problem* p, const double* U);
 
 /* Copy of the assembled operator of a level (host memory): row_ptr
@@ -251,7 +284,8 @@ int32_t stwr_relax(stwr_problem* p, int32_t level, const double* b, double* x,
 int32_t stwr_restrict(stwr_problem* p, int32_t fine_level, const double* rf, double* rc);
 int32_t stwr_prolong_add(stwr_problem* p, int32_t fine_level, const double* ec, double* xf);
 
-/* Exact solve on the coarsest level; x has zero-mean pressure per temporal node. */
+/* Exact solve on the coarsest level; x has zero-mean pressure per temporal
+ * node (Navier-Stokes; the heat equation's slab blocks need no border). */
 int32_t stwr_coarse_solve(stwr_problem* p, const double* b, double* x);
 
 /* Factor every smoothed level at opts.smoother_prec and estimate lam on each. */
@@ -261,7 +295,9 @@ int32_t stwr_setup_smoothers(stwr_problem* p);
 int32_t stwr_vcycle(stwr_problem* p, const double* b, double* x);
 
 /* FGMRES(restart) on A_0 x = b, x starting at 0, right-preconditioned by one
- * V-cycle, constant pressure projected out of each preconditioned vector. */
+ * V-cycle, constant pressure projected out of each preconditioned vector
+ * (Navier-Stokes).  Stops when ||r|| <= max(gmres_rtol ||b||, gmres_atol);
+ * STWR_ERR_NOT_CONVERGED if gmres_maxit iterations do not get there. */
 int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* stats);
 
 /* Newton's method from the U given (zero = the standard start), in place:

@@ -25,7 +25,8 @@ EXPORTED = [
     "stwr_default_opts", "stwr_ctx_create", "stwr_ctx_destroy", "stwr_ctx_set_stream",
     "stwr_last_error", "stwr_ctx_bytes_in_use", "stwr_problem_bytes", "stwr_mesh_info",
     "stwr_problem_create", "stwr_problem_destroy", "stwr_problem_sizes", "stwr_set_opts",
-    "stwr_nonlinear_residual", "stwr_velocity_l2_error", "stwr_expand", "stwr_assemble",
+    "stwr_nonlinear_residual", "stwr_linear_rhs", "stwr_velocity_l2_error", "stwr_expand",
+    "stwr_assemble",
     "stwr_get_operator", "stwr_apply",
     "stwr_residual", "stwr_patch_factor", "stwr_patch_apply", "stwr_eig_estimate",
     "stwr_relax", "stwr_restrict", "stwr_prolong_add", "stwr_coarse_solve",
@@ -44,7 +45,8 @@ class ProblemDesc(ctypes.Structure):
                 ("psi_coef", ctypes.POINTER(ctypes.c_double)),
                 ("p_ab", ctypes.POINTER(ctypes.c_int32)),
                 ("p_coef", ctypes.POINTER(ctypes.c_double)), ("flow", ctypes.c_int32),
-                ("temporal_nodes", ctypes.c_int32)]
+                ("temporal_nodes", ctypes.c_int32), ("equation", ctypes.c_int32),
+                ("degree", ctypes.c_int32)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -54,7 +56,7 @@ class SolverOpts(ctypes.Structure):
                 ("gmres_restart", ctypes.c_int32), ("gmres_maxit", ctypes.c_int32),
                 ("gmres_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
                 ("newton_rtol", ctypes.c_double), ("vcycle_graph", ctypes.c_int32),
-                ("newton_ew", ctypes.c_int32)]
+                ("newton_ew", ctypes.c_int32), ("gmres_atol", ctypes.c_double)]
 
 
 MAX_NEWTON, MAX_LEVELS = 64, 16
@@ -179,7 +181,8 @@ def make_desc(prob):
                     psi_coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     p_ab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                     p_coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                    int(getattr(prob, "flow", 0)), int(getattr(prob, "nodes", 0)))
+                    int(getattr(prob, "flow", 0)), int(getattr(prob, "nodes", 0)),
+                    int(getattr(prob, "equation", 0)), int(getattr(prob, "degree", 0)))
     return d, (psi_ab, psi_coef, p_ab, p_coef)
 
 
@@ -298,6 +301,10 @@ class Problem:
 
     def nonlinear_residual(self, U, F):
         self.ctx.check(self.lib.stwr_nonlinear_residual(self.h, _ptr(U), _ptr(F)))
+
+    def linear_rhs(self, b):
+        """b = -F(0); the heat equation's right-hand side."""
+        self.ctx.check(self.lib.stwr_linear_rhs(self.h, _ptr(b)))
 
     def velocity_l2_error(self, U) -> float:
         err = ctypes.c_double()

@@ -115,7 +115,8 @@ struct Level {
   std::vector<int64_t> fac_off, y_off, mp_off;
   // device arrays
   int *row_ptr = nullptr, *col = nullptr, *cells = nullptr, *cell_p2 = nullptr,
-      *cell_dofs = nullptr, *cell_nz = nullptr, *node_free = nullptr;
+      *cell_dofs = nullptr, *cell_nz = nullptr, *node_free = nullptr, *node_cell_ptr = nullptr,
+      *node_cell = nullptr;
   int *patch_ptr = nullptr, *patch_dofs = nullptr, *patch_nbu = nullptr, *patch_nz = nullptr,
       *dof_ptr = nullptr, *dof_slot = nullptr, *slot_patch = nullptr;
   int64_t *patch_nz_off = nullptr, *d_fac_off = nullptr, *d_y_off = nullptr, *d_mp_off = nullptr;
@@ -145,6 +146,8 @@ struct stwr_problem {
   RefTables tab{};
   RefTables* d_tab = nullptr;
   MmsDev mms{};
+  double* b0 = nullptr;     // heat equation: right-hand side e0 (x) M U_0 of level 0
+  bool heat() const { return desc.equation == STWR_EQ_HEAT; }
   std::vector<DBuf> bufs;
   uint64_t bytes = 0;
   bool assembled = false;
@@ -223,8 +226,14 @@ int32_t guarded(stwr_ctx* ctx, F&& f) {
   }
 }
 
+bool is_heat(const stwr_problem_desc* d) { return d->equation == STWR_EQ_HEAT; }
+
 void check_desc(const stwr_problem_desc* d) {
   if (!d) throw StwrError(STWR_ERR_ARG, "null problem descriptor");
+  if (d->equation != STWR_EQ_NAVIER_STOKES && d->equation != STWR_EQ_HEAT)
+    throw StwrError(STWR_ERR_ARG, "bad equation");
+  if (is_heat(d) && (d->degree < 1 || d->degree > kMaxPk))
+    throw StwrError(STWR_ERR_ARG, "heat equation degree must be 1, 2 or 3");
   if (d->q < 0 || d->q > 1) throw StwrError(STWR_ERR_ARG, "q must be 0 or 1");
   if (d->n_levels < 1 || d->n_levels > STWR_MAX_LEVELS) throw StwrError(STWR_ERR_ARG, "bad n_levels");
   if (d->mesh_n < 2 || d->n_slabs < 1) throw StwrError(STWR_ERR_ARG, "bad mesh_n or n_slabs");
@@ -239,8 +248,9 @@ void check_desc(const stwr_problem_desc* d) {
   if ((d->n_psi_modes > 0 && (!d->psi_ab || !d->psi_coef)) || (d->n_p_modes > 0 && (!d->p_ab || !d->p_coef)))
     throw StwrError(STWR_ERR_ARG, "null mode arrays");
   const int mc = d->mesh_n >> (d->n_levels - 1);
-  const int nfc = 2 * (2 * mc - 1) * (2 * mc - 1) + (mc + 1) * (mc + 1);
-  if (nfc * (d->q + 1) + d->q + 1 > 2048)
+  const int nfc = is_heat(d) ? (d->degree * mc + 1) * (d->degree * mc + 1)
+                             : 2 * (2 * mc - 1) * (2 * mc - 1) + (mc + 1) * (mc + 1);
+  if (nfc * (d->q + 1) + (is_heat(d) ? 0 : d->q + 1) > 2048)
     throw StwrError(STWR_ERR_ARG, "coarsest level too large for the dense coarse solve (use more levels)");
 }
 
@@ -250,7 +260,7 @@ void check_opts(const stwr_solver_opts* o) {
       o->gmres_restart > 200 || o->gmres_maxit < 1 || o->newton_maxit < 0 || o->newton_maxit > STWR_MAX_NEWTON ||
       (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
       !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1) ||
-      (o->newton_ew != 0 && o->newton_ew != 1))
+      (o->newton_ew != 0 && o->newton_ew != 1) || !(o->gmres_atol >= 0.0))
     throw StwrError(STWR_ERR_ARG, "invalid solver options");
 }
 
@@ -287,7 +297,8 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
   uint64_t b = 0;
   b += (uint64_t)nnz * N * NQ * NQ * 8 + nnz * 8;                       // Jv, Mv
   b += (uint64_t)(H.nf + 1 + nnz) * 4;                                  // CSR
-  b += (uint64_t)H.nc * (3 + 6 + 15 + 225) * 4 + (uint64_t)H.nn * 4;    // cell maps
+  b += (uint64_t)(H.cells.size() + H.cell_p2.size() + H.cell_dofs.size() + H.cell_nz.size() +
+                 H.node_free.size() + H.node_cell_ptr.size() + H.node_cell.size()) * 4;   // cell maps
   b += (uint64_t)(H.nv + 1) * 4 * 2 + (uint64_t)H.patch_dofs.size() * 4 * 2 + H.patch_nz.size() * 4;
   b += (uint64_t)(H.nv + 1) * 8 * 4 + (uint64_t)(H.nf + 1 + H.patch_dofs.size()) * 4;
   b += (uint64_t)4 * n_st * 8;                                          // r, d, x, b
@@ -299,7 +310,7 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
     for (int v = 0; v < H.nv; ++v)                                      // Y
       b += (uint64_t)y_elems(H.patch_ptr[v + 1] - H.patch_ptr[v], N, NQ) * 8;
   } else {
-    const int64_t mm = (int64_t)H.nf * NQ + NQ;
+    const int64_t mm = (int64_t)H.nf * NQ + (H.po < H.nf ? NQ : 0);
     b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8 + (mm > kCoarseSmall ? (uint64_t)N * 32 * mm * 8 : 0);
   }
   if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
@@ -309,13 +320,17 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
 void build_levels(const stwr_problem_desc* d, std::vector<Level>& lv) {
   lv.resize(d->n_levels);
   for (int l = 0; l < d->n_levels; ++l) {
-    build_level(d->mesh_n >> l, lv[l].H);
+    if (is_heat(d)) build_level_heat(d->mesh_n >> l, d->degree, lv[l].H);
+    else build_level(d->mesh_n >> l, lv[l].H);
     lv[l].N = d->n_slabs;
     lv[l].NQ = d->q + 1;
     lv[l].dt = d->t_final / d->n_slabs;
     lv[l].n_st = (int64_t)lv[l].H.nf * d->n_slabs * (d->q + 1);
   }
-  for (int l = 0; l + 1 < d->n_levels; ++l) build_transfer(lv[l].H, lv[l + 1].H, lv[l].Tr);
+  for (int l = 0; l + 1 < d->n_levels; ++l) {
+    if (is_heat(d)) build_transfer_heat(lv[l].H, lv[l + 1].H, lv[l].Tr);
+    else build_transfer(lv[l].H, lv[l + 1].H, lv[l].Tr);
+  }
 }
 
 uint64_t plan_bytes(const stwr_problem_desc* d, const stwr_solver_opts* o, const std::vector<Level>& lv) {
@@ -326,6 +341,7 @@ uint64_t plan_bytes(const stwr_problem_desc* d, const stwr_solver_opts* o, const
   const int64_t n0 = lv[0].n_st;
   b += (uint64_t)(2 * o->gmres_restart + 1) * n0 * 8;
   if (o->vcycle_graph) b += (uint64_t)2 * n0 * 8;                       // graph input, output
+  if (is_heat(d)) b += (uint64_t)n0 * 8;                                // heat right-hand side
   b += (uint64_t)(256 + 4) * 256 * 8 + sizeof(RefTables) + 4096;
   return b;
 }
@@ -341,6 +357,10 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   L.cell_dofs = P->upload(H.cell_dofs);
   L.cell_nz = P->upload(H.cell_nz);
   L.node_free = P->upload(H.node_free);
+  if (H.kdeg > 0) {
+    L.node_cell_ptr = P->upload(H.node_cell_ptr);
+    L.node_cell = P->upload(H.node_cell);
+  }
   const int64_t nnz = H.row_ptr[H.nf];
   L.Jv = P->alloc<double>((size_t)nnz * L.N * L.NQ * L.NQ);
   L.Mv = P->alloc<double>((size_t)nnz);
@@ -354,6 +374,9 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   v.row_ptr = L.row_ptr; v.col = L.col; v.cells = L.cells; v.cell_p2 = L.cell_p2;
   v.cell_dofs = L.cell_dofs; v.cell_nz = L.cell_nz; v.node_free = L.node_free;
   v.n2 = H.n2; v.n1 = H.n1;
+  v.kdeg = H.kdeg; v.nloc = H.nloc;
+  v.node_cell_ptr = L.node_cell_ptr; v.node_cell = L.node_cell;
+  v.nbord = H.po < H.nf ? L.NQ : 0;
   // patches (the coarsest level is solved directly and needs none)
   PatchView& pv = L.pview;
   pv.n_patch = H.nv;
@@ -402,7 +425,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     L.R_col = P->upload(L.Tr.r_col);
     L.R_val = P->upload(L.Tr.r_val);
   } else {
-    L.coarse_mm = H.nf * L.NQ + L.NQ;
+    L.coarse_mm = H.nf * L.NQ + L.view.nbord;
     L.Binv = P->alloc<double>((size_t)L.N * L.coarse_mm * L.coarse_mm);
     L.gbuf = P->alloc<double>((size_t)L.coarse_mm);
     L.perm = P->alloc<int>((size_t)L.N * L.coarse_mm);
@@ -494,6 +517,7 @@ void spmv(stwr_problem* P, int l, const double* x, const double* b, double* y) {
 
 void project(stwr_problem* P, int l, double* x) {
   Level& L = P->lv[l];
+  if (L.H.po >= L.H.nf) return;   // no pressure (heat equation)
   HIPCHK(launch_pressure_project(L.H.nf, L.H.po, L.N * L.NQ, x, P->dscal + 256, P->s()));
 }
 
@@ -765,6 +789,13 @@ void assemble(stwr_problem* P, const double* U) {
   const int L = (int)P->lv.size();
   for (int l = 0; l < L; ++l) {
     Level& Lv = P->lv[l];
+    if (P->heat()) {
+      // linear and state-independent: every entry is written
+      HIPCHK(launch_heat_operator(Lv.view, P->d_tab, Lv.Jv, Lv.Mv, P->s()));
+      Lv.fac_prec = -1;
+      Lv.has_lambda = false;
+      continue;
+    }
     const double* Ul = U;
     if (l > 0) {
       Level& F = P->lv[l - 1];
@@ -786,6 +817,19 @@ void assemble(stwr_problem* P, const double* U) {
   P->assembled = true;
 }
 
+// F(U) on level 0: the nonlinear residual of eq. nsfem, or A U - b of the
+// heat equation
+void residual(stwr_problem* P, const double* U, double* F) {
+  Level& L = P->lv[0];
+  if (P->heat()) {
+    spmv(P, 0, U, P->b0, F);                                  // b - A U
+    HIPCHK(launch_axpby(L.n_st, -1.0, F, 0.0, F, P->s()));
+    return;
+  }
+  HIPCHK(launch_fill(L.n_st, 0.0, F, P->s()));
+  HIPCHK(launch_assemble_residual(L.view, P->d_tab, P->mms, U, F, P->s()));
+}
+
 void setup_smoothers(stwr_problem* P) {
   for (int l = 0; l + 1 < (int)P->lv.size(); ++l) {
     patch_factor(P, l, P->opts.smoother_prec);
@@ -796,7 +840,7 @@ void setup_smoothers(stwr_problem* P) {
 // Right-preconditioned restarted FGMRES with modified Gram-Schmidt.
 // Stops when ||r|| <= max(rtol ||b||, atol).
 void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* its_out, double* rel_out,
-            double atol = 0.0, double rtol = -1.0) {
+            double atol = 0.0, double rtol = -1.0, bool* conv_out = nullptr) {
   const stwr_solver_opts& o = P->opts;
   Level& L0 = P->lv[0];
   const int64_t n = L0.n_st;
@@ -805,8 +849,13 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
   const double bnorm = norm_host(P, n, b);
   int its = 0;
   double rel = 0.0;
-  if (bnorm == 0.0) { if (its_out) *its_out = 0; if (rel_out) *rel_out = 0.0; return; }
-  const double target = std::max((rtol >= 0.0 ? rtol : o.gmres_rtol) * bnorm, atol);
+  if (bnorm == 0.0) {
+    if (its_out) *its_out = 0;
+    if (rel_out) *rel_out = 0.0;
+    if (conv_out) *conv_out = true;
+    return;
+  }
+  const double target = std::max((rtol >= 0.0 ? rtol : o.gmres_rtol) * bnorm, std::max(atol, o.gmres_atol));
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
   auto V = [&](int j) { return P->V + j * n; };
   auto Z = [&](int j) { return P->Z + j * n; };
@@ -866,6 +915,7 @@ void fgmres(stwr_problem* P, const double* b, double* x, stwr_stats* st, int* it
   HIPCHK(hipStreamSynchronize(P->s()));
   if (its_out) *its_out = its;
   if (rel_out) *rel_out = rel;
+  if (conv_out) *conv_out = rel * bnorm <= target;
   (void)st;
 }
 
@@ -889,6 +939,7 @@ int32_t stwr_default_opts(stwr_solver_opts* o) {
   o->newton_rtol = 1e-10;
   o->vcycle_graph = 1;
   o->newton_ew = 0;
+  o->gmres_atol = 0.0;
   return STWR_OK;
 }
 
@@ -1040,6 +1091,7 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
     P->bytes = need;
     try {
       build_ref_tables(desc->q, desc->temporal_nodes, P->tab);
+      if (is_heat(desc)) build_pk_tables(desc->degree, P->tab);
       P->d_tab = P->alloc<RefTables>(1);
       HIPCHK(hipMemcpyAsync(P->d_tab, &P->tab, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1066,6 +1118,14 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
       P->dstatus = P->alloc<int>(4);
       HIPCHK(hipMemsetAsync(P->dstatus, 0, 4 * sizeof(int), ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (is_heat(desc)) {
+        // the heat operator does not depend on the state: assemble it and
+        // the right-hand side once
+        P->b0 = P->alloc<double>((size_t)n0);
+        assemble(P.get(), nullptr);
+        HIPCHK(launch_heat_rhs(P->lv[0].view, P->d_tab, P->lv[0].Mv, P->b0, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+      }
       // host copies no longer needed on the device side can be dropped
       for (auto& Lv : P->lv) {
         std::vector<int>().swap(Lv.H.cell_nz);
@@ -1125,9 +1185,24 @@ int32_t stwr_nonlinear_residual(stwr_problem* p, const double* U, double* F) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
     if (!U || !F) throw StwrError(STWR_ERR_ARG, "null vector");
+    residual(p, U, F);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_linear_rhs(stwr_problem* p, double* b) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    if (!b) throw StwrError(STWR_ERR_ARG, "null vector");
     Level& L = p->lv[0];
-    HIPCHK(launch_fill(L.n_st, 0.0, F, p->s()));
-    HIPCHK(launch_assemble_residual(L.view, p->d_tab, p->mms, U, F, p->s()));
+    if (p->heat()) {
+      HIPCHK(hipMemcpyAsync(b, p->b0, L.n_st * 8, hipMemcpyDeviceToDevice, p->s()));
+      return STWR_OK;
+    }
+    // -F(0): the residual at zero, negated (L.x is scratch outside solves)
+    HIPCHK(launch_fill(L.n_st, 0.0, L.x, p->s()));
+    residual(p, L.x, b);
+    HIPCHK(launch_axpby(L.n_st, -1.0, b, 0.0, b, p->s()));
     return STWR_OK;
   });
 }
@@ -1136,6 +1211,7 @@ int32_t stwr_velocity_l2_error(stwr_problem* p, const double* U, double* err) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
     if (!U || !err) throw StwrError(STWR_ERR_ARG, "null pointer");
+    if (p->heat()) throw StwrError(STWR_ERR_STATE, "no velocity in the heat equation");
     Level& L = p->lv[0];
     // per-(cell, slab) partial sums in the finest level's residual buffer
     // (nc N <= n_st), the total in the scalar buffer
@@ -1152,6 +1228,7 @@ int32_t stwr_expand(stwr_problem* p, const double* U, double* full) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
     if (!U || !full) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (p->heat()) throw StwrError(STWR_ERR_STATE, "the heat equation has no eliminated DoFs");
     HIPCHK(launch_expand(p->lv[0].view, p->d_tab, p->mms, U, full, p->s()));
     return STWR_OK;
   });
@@ -1160,7 +1237,7 @@ int32_t stwr_expand(stwr_problem* p, const double* U, double* full) {
 int32_t stwr_assemble(stwr_problem* p, const double* U) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
-    if (!U) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (!U && !p->heat()) throw StwrError(STWR_ERR_ARG, "null vector");
     assemble(p, U);
     return STWR_OK;
   });
@@ -1314,8 +1391,9 @@ int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* sta
     if (!p->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
     int its = 0;
     double rel = 0.0;
+    bool conv = false;
     const double t0 = now_s();
-    fgmres(p, b, x, stats, &its, &rel);
+    fgmres(p, b, x, stats, &its, &rel, 0.0, -1.0, &conv);
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
       stats->linear_its_total = its;
@@ -1324,7 +1402,7 @@ int32_t stwr_fgmres(stwr_problem* p, const double* b, double* x, stwr_stats* sta
       stats->solve_seconds = now_s() - t0;
       for (int l = 0; l < (int)p->lv.size() && l < STWR_MAX_LEVELS; ++l) stats->lambda[l] = p->lv[l].lambda;
     }
-    if (rel > p->opts.gmres_rtol) return fail(p->ctx, STWR_ERR_NOT_CONVERGED, "FGMRES reached its iteration limit");
+    if (!conv) return fail(p->ctx, STWR_ERR_NOT_CONVERGED, "FGMRES reached its iteration limit");
     return STWR_OK;
   });
 }
@@ -1361,8 +1439,7 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
     stwr_stats& st = stats ? *stats : local;
     std::memset(&st, 0, sizeof(st));
     auto resid = [&]() {
-      HIPCHK(launch_fill(n, 0.0, F, p->s()));
-      HIPCHK(launch_assemble_residual(L0.view, p->d_tab, p->mms, U, F, p->s()));
+      residual(p, U, F);
       return norm_host(p, n, F);
     };
     double f = resid();

@@ -1,5 +1,6 @@
 // Space-time assembly of Taylor-Hood P2-P1 x DG(q) Navier-Stokes on gfx950
-// (Sec. 2, eq. nsfem with forcing; upwind jump of eq. dgintime).
+// (Sec. 2, eq. nsfem with forcing; upwind jump of eq. dgintime), and of the
+// P_k x DG(q) heat equation (eq. heatfem) at the end of the file.
 //
 // One 64-lane workgroup per (cell, slab).  The workgroup stages the cell's
 // nodal values, its physical basis gradients and the fields at the
@@ -453,7 +454,91 @@ __global__ __launch_bounds__(256) void k_expand(LevelView L, const RefTables* __
   full[e] = v;
 }
 
+
+// ---- heat equation ------------------------------------------------------------
+// Slab blocks of the heat equation (Sec. 2, eq. heatfem): per spatial nonzero
+// (r, c), M_rc and K_rc are summed over the cells that hold both nodes, in
+// the fixed order of the node's cell slots (deterministic, no atomics), from
+// the P_k basis at the 25 quadrature points; then every slab's block
+// T (x) M + dt W (x) K is written, and Mv = M.  One thread per row.
+__global__ __launch_bounds__(256) void k_heat_operator(LevelView L, const RefTables* __restrict__ T,
+                                                       double* __restrict__ Jv, double* __restrict__ Mv) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= L.nf) return;
+  const int nloc = L.nloc, NQ = T->NQ, N = L.N;
+  for (int k = L.row_ptr[r]; k < L.row_ptr[r + 1]; ++k) {
+    const int c = L.col[k];
+    double m = 0.0, st = 0.0;
+    for (int e = L.node_cell_ptr[r]; e < L.node_cell_ptr[r + 1]; ++e) {
+      const int slot = L.node_cell[e], cell = slot / nloc, i = slot % nloc;
+      const int* cd = L.cell_dofs + (int64_t)cell * nloc;
+      int j = -1;
+      for (int t = 0; t < nloc; ++t)
+        if (cd[t] == c) j = t;
+      if (j < 0) continue;
+      const int* cv = L.cells + 3 * cell;
+      double px[3], py[3];
+      for (int t = 0; t < 3; ++t) {
+        px[t] = (cv[t] % L.n1) * L.h;
+        py[t] = (cv[t] / L.n1) * L.h;
+      }
+      const double j00 = px[1] - px[0], j01 = px[2] - px[0], j10 = py[1] - py[0], j11 = py[2] - py[0];
+      const double det = j00 * j11 - j01 * j10, ad = fabs(det), id = 1.0 / det;
+      double me = 0.0, ke = 0.0;
+      for (int q = 0; q < kQx; ++q) {
+        const double w = T->wq[q] * ad;
+        const double* gi = T->dNk[q][i];
+        const double* gj = T->dNk[q][j];
+        const double ix = (j11 * gi[0] - j10 * gi[1]) * id, iy = (-j01 * gi[0] + j00 * gi[1]) * id;
+        const double jx = (j11 * gj[0] - j10 * gj[1]) * id, jy = (-j01 * gj[0] + j00 * gj[1]) * id;
+        me += w * T->Nk[q][i] * T->Nk[q][j];
+        ke += w * (ix * jx + iy * jy);
+      }
+      m += me;
+      st += ke;
+    }
+    Mv[k] = m;
+    double* out = Jv + (int64_t)k * N * NQ * NQ;
+    for (int n = 0; n < N; ++n)
+      for (int a = 0; a < NQ; ++a)
+        for (int b = 0; b < NQ; ++b) out[(n * NQ + a) * NQ + b] = T->T[a][b] * m + L.dt * T->W[a][b] * st;
+  }
+}
+
+__device__ inline double heat_u0(double x, double y) { return sin(M_PI * x) + cos(2.0 * M_PI * y); }
+
+// b0 = e0 (x) (M U_0) on slab 0, zero elsewhere; one thread per (row, slab)
+__global__ __launch_bounds__(256) void k_heat_rhs(LevelView L, const RefTables* __restrict__ T,
+                                                  const double* __restrict__ Mv, double* __restrict__ b0) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)L.nf * L.N) return;
+  const int i = (int)(t / L.N), n = (int)(t % L.N);
+  const int NQ = T->NQ;
+  double s = 0.0;
+  if (n == 0) {
+    const double hs = L.h / L.kdeg;
+    for (int k = L.row_ptr[i]; k < L.row_ptr[i + 1]; ++k) {
+      const int c = L.col[k];
+      s += Mv[k] * heat_u0((c % L.n2) * hs, (c / L.n2) * hs);
+    }
+  }
+  for (int a = 0; a < NQ; ++a) b0[t * NQ + a] = n == 0 ? T->e0[a] * s : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_heat_operator(const LevelView& L, const RefTables* tab, double* Jv, double* Mv,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_heat_operator, dim3((unsigned)((L.nf + 255) / 256)), dim3(256), 0, s, L, tab, Jv, Mv);
+  return hipGetLastError();
+}
+
+hipError_t launch_heat_rhs(const LevelView& L, const RefTables* tab, const double* Mv, double* b0,
+                           hipStream_t s) {
+  const int64_t n = (int64_t)L.nf * L.N;
+  hipLaunchKernelGGL(k_heat_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L, tab, Mv, b0);
+  return hipGetLastError();
+}
 
 hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDev mms,
                                  const double* U, double* part, double* out, hipStream_t s) {

@@ -33,6 +33,13 @@ struct LevelView {
   const int* cell_nz;    // nc x 225
   const int* node_free;  // nn
   int n2, n1;
+  // heat equation (kdeg = k >= 1; 0 for Navier-Stokes): cells hold nloc
+  // lattice nodes, n2 is the lattice width, node_cell the (cell * nloc +
+  // local) slots of each node
+  int kdeg, nloc;
+  const int* node_cell_ptr;
+  const int* node_cell;
+  int nbord;             // constraint rows bordering a coarsest slab block: q+1 with pressure, else 0
 };
 
 struct PatchView {
@@ -108,6 +115,16 @@ hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDe
 hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, const double* U,
                          double* full, hipStream_t s);
 
+// Heat equation: slab blocks Jv = T (x) M + dt W (x) K and the jump mass
+// Mv = M of the P_k discretisation, every CSR entry summed over its cells in
+// a fixed order (no atomics)
+hipError_t launch_heat_operator(const LevelView& L, const RefTables* tab, double* Jv, double* Mv,
+                                hipStream_t s);
+// b0 = e0 (x) M U_0 on slab 0 (U_0 the nodal interpolant of sin(pi x) +
+// cos(2 pi y)), zero on the other slabs
+hipError_t launch_heat_rhs(const LevelView& L, const RefTables* tab, const double* Mv, double* b0,
+                           hipStream_t s);
+
 // ---- linear algebra ----------------------------------------------------------
 hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, const double* e0,
                        const double* e1, const double* x, const double* b, double* y,
@@ -138,8 +155,10 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
                                int prec, void* fac, int* status, hipStream_t s);
 hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const double* Mv,
                              double* Mp, hipStream_t s);
-// Y: patch outputs, FP64 at element offset y_off[p] (prec 0), or FP32 at
-// element offset 2 y_off[p] (prec 1); the buffer holds y_off[n_patch] doubles.
+// Y: patch outputs, FP64 at element offset y_off[p] (prec 0, and FP32
+// factors of the heat equation's scalar patches), or FP32 at element offset
+// 2 y_off[p] (FP32 factors of Navier-Stokes patches); the buffer holds
+// y_off[n_patch] doubles.
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, void* Y, hipStream_t s);
@@ -157,7 +176,7 @@ hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, 
 // workspace (used when m > kCoarseSmall; rbuf = NULL selects the unblocked form)
 hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
                                 double* colbuf, double* rbuf, hipStream_t s);
-// gbuf: nf (q+1) + q + 1 doubles of workspace (used for large coarsest levels)
+// gbuf: nf (q+1) + nbord doubles of workspace (used for large coarsest levels)
 hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const double* Mv,
                                const double* e0, const double* e1, const double* b, double* x,
                                double* gbuf, hipStream_t s);

@@ -124,9 +124,92 @@ void build_ref_tables(int q, int nodes, RefTables& t) {
     }
 }
 
+// CSR pattern of the DoF pairs that share a cell, and each cell's positions
+// in it (cell_dofs holds nloc DoFs per cell, -1 for eliminated ones).
+static int find_nz(const HostLevel& L, int r, int c) {
+  auto b = L.col.begin() + L.row_ptr[r], e = L.col.begin() + L.row_ptr[r + 1];
+  auto it = std::lower_bound(b, e, c);
+  return (it != e && *it == c) ? int(it - L.col.begin()) : -1;
+}
+
+static void csr_from_cells(HostLevel& L) {
+  const int nl = L.nloc;
+  std::vector<std::vector<int>> rows(L.nf);
+  for (int c = 0; c < L.nc; ++c) {
+    const int* d = &L.cell_dofs[(size_t)nl * c];
+    for (int I = 0; I < nl; ++I) {
+      if (d[I] < 0) continue;
+      for (int J = 0; J < nl; ++J)
+        if (d[J] >= 0) rows[d[I]].push_back(d[J]);
+    }
+  }
+  L.row_ptr.assign(L.nf + 1, 0);
+  for (int r = 0; r < L.nf; ++r) {
+    auto& v = rows[r];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    L.row_ptr[r + 1] = L.row_ptr[r] + (int)v.size();
+  }
+  L.col.resize(L.row_ptr[L.nf]);
+  for (int r = 0; r < L.nf; ++r) std::copy(rows[r].begin(), rows[r].end(), L.col.begin() + L.row_ptr[r]);
+  rows.clear();
+  rows.shrink_to_fit();
+  L.cell_nz.resize((size_t)nl * nl * L.nc);
+  for (int c = 0; c < L.nc; ++c) {
+    const int* d = &L.cell_dofs[(size_t)nl * c];
+    for (int I = 0; I < nl; ++I)
+      for (int J = 0; J < nl; ++J)
+        L.cell_nz[(size_t)nl * nl * c + nl * I + J] = (d[I] >= 0 && d[J] >= 0) ? find_nz(L, d[I], d[J]) : -1;
+  }
+}
+
+// Patch-block CSR positions and the DoF -> patch-slot transpose, from
+// patch_ptr / patch_dofs.
+static void patch_maps(HostLevel& L) {
+  L.patch_nz_off.assign(L.nv + 1, 0);
+  for (int v = 0; v < L.nv; ++v) {
+    int64_t nb = L.patch_ptr[v + 1] - L.patch_ptr[v];
+    L.patch_nz_off[v + 1] = L.patch_nz_off[v] + nb * nb;
+  }
+  L.patch_nz.resize(L.patch_nz_off[L.nv]);
+  for (int v = 0; v < L.nv; ++v) {
+    int s = L.patch_ptr[v], nb = L.patch_ptr[v + 1] - s;
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j)
+        L.patch_nz[L.patch_nz_off[v] + (int64_t)i * nb + j] = find_nz(L, L.patch_dofs[s + i], L.patch_dofs[s + j]);
+  }
+  const int ns = (int)L.patch_dofs.size();
+  L.slot_patch.resize(ns);
+  for (int v = 0; v < L.nv; ++v)
+    for (int s = L.patch_ptr[v]; s < L.patch_ptr[v + 1]; ++s) L.slot_patch[s] = v;
+  L.dof_ptr.assign(L.nf + 1, 0);
+  for (int s = 0; s < ns; ++s) L.dof_ptr[L.patch_dofs[s] + 1]++;
+  for (int r = 0; r < L.nf; ++r) L.dof_ptr[r + 1] += L.dof_ptr[r];
+  L.dof_slot.resize(ns);
+  std::vector<int> fill(L.dof_ptr.begin(), L.dof_ptr.end() - 1);
+  for (int s = 0; s < ns; ++s) L.dof_slot[fill[L.patch_dofs[s]]++] = s;
+}
+
+// structured mesh cells: square (i, j) gives (v_ij, v_i+1,j, v_i,j+1) and
+// (v_i+1,j+1, v_i,j+1, v_i+1,j)
+static void mesh_cells(HostLevel& L) {
+  const int M = L.M, n1 = L.n1;
+  L.cells.resize(3 * L.nc);
+  for (int j = 0; j < M; ++j)
+    for (int i = 0; i < M; ++i) {
+      int a = i + n1 * j, b = i + 1 + n1 * j, c = i + n1 * (j + 1), d = i + 1 + n1 * (j + 1);
+      int c0 = 2 * (i + M * j);
+      int tri[2][3] = {{a, b, c}, {d, c, b}};
+      for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < 3; ++k) L.cells[3 * (c0 + s) + k] = tri[s][k];
+    }
+}
+
 // ---------------------------------------------------------------------------
 void build_level(int M, HostLevel& L) {
   if (M < 1) throw std::invalid_argument("mesh size must be positive");
+  L.kdeg = 0;
+  L.nloc = 15;
   L.M = M;
   L.n1 = M + 1;
   L.n2 = 2 * M + 1;
@@ -137,16 +220,8 @@ void build_level(int M, HostLevel& L) {
   L.po = 2 * L.nfn;
   L.nf = L.po + L.nv;
   const int n1 = L.n1, n2 = L.n2;
-  L.cells.resize(3 * L.nc);
+  mesh_cells(L);
   L.cell_p2.resize(6 * L.nc);
-  for (int j = 0; j < M; ++j)
-    for (int i = 0; i < M; ++i) {
-      int a = i + n1 * j, b = i + 1 + n1 * j, c = i + n1 * (j + 1), d = i + 1 + n1 * (j + 1);
-      int c0 = 2 * (i + M * j);
-      int tri[2][3] = {{a, b, c}, {d, c, b}};
-      for (int s = 0; s < 2; ++s)
-        for (int k = 0; k < 3; ++k) L.cells[3 * (c0 + s) + k] = tri[s][k];
-    }
   auto vnode = [&](int v) { return 2 * (v % n1) + n2 * 2 * (v / n1); };
   for (int c = 0; c < L.nc; ++c) {
     int g[3];
@@ -171,39 +246,7 @@ void build_level(int M, HostLevel& L) {
     }
     for (int i = 0; i < 3; ++i) d[12 + i] = L.po + L.cells[3 * c + i];
   }
-  // CSR pattern: DoF pairs that share a cell
-  std::vector<std::vector<int>> rows(L.nf);
-  for (int c = 0; c < L.nc; ++c) {
-    const int* d = &L.cell_dofs[15 * c];
-    for (int I = 0; I < 15; ++I) {
-      if (d[I] < 0) continue;
-      for (int J = 0; J < 15; ++J)
-        if (d[J] >= 0) rows[d[I]].push_back(d[J]);
-    }
-  }
-  L.row_ptr.assign(L.nf + 1, 0);
-  for (int r = 0; r < L.nf; ++r) {
-    auto& v = rows[r];
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    L.row_ptr[r + 1] = L.row_ptr[r] + (int)v.size();
-  }
-  L.col.resize(L.row_ptr[L.nf]);
-  for (int r = 0; r < L.nf; ++r) std::copy(rows[r].begin(), rows[r].end(), L.col.begin() + L.row_ptr[r]);
-  rows.clear();
-  rows.shrink_to_fit();
-  auto find_nz = [&](int r, int c) -> int {
-    auto b = L.col.begin() + L.row_ptr[r], e = L.col.begin() + L.row_ptr[r + 1];
-    auto it = std::lower_bound(b, e, c);
-    return (it != e && *it == c) ? int(it - L.col.begin()) : -1;
-  };
-  L.cell_nz.resize((size_t)225 * L.nc);
-  for (int c = 0; c < L.nc; ++c) {
-    const int* d = &L.cell_dofs[15 * c];
-    for (int I = 0; I < 15; ++I)
-      for (int J = 0; J < 15; ++J)
-        L.cell_nz[(size_t)225 * c + 15 * I + J] = (d[I] >= 0 && d[J] >= 0) ? find_nz(d[I], d[J]) : -1;
-  }
+  csr_from_cells(L);
   // Vanka+star patches: every free velocity DoF on the closure of the vertex
   // star, plus the pressure DoF of the vertex.
   std::vector<std::vector<int>> inc(L.nv);
@@ -226,29 +269,7 @@ void build_level(int M, HostLevel& L) {
     L.patch_dofs.insert(L.patch_dofs.end(), d.begin(), d.end());
     L.patch_ptr[v + 1] = (int)L.patch_dofs.size();
   }
-  L.patch_nz_off.assign(L.nv + 1, 0);
-  for (int v = 0; v < L.nv; ++v) {
-    int64_t nb = L.patch_ptr[v + 1] - L.patch_ptr[v];
-    L.patch_nz_off[v + 1] = L.patch_nz_off[v] + nb * nb;
-  }
-  L.patch_nz.resize(L.patch_nz_off[L.nv]);
-  for (int v = 0; v < L.nv; ++v) {
-    int s = L.patch_ptr[v], nb = L.patch_ptr[v + 1] - s;
-    for (int i = 0; i < nb; ++i)
-      for (int j = 0; j < nb; ++j)
-        L.patch_nz[L.patch_nz_off[v] + (int64_t)i * nb + j] = find_nz(L.patch_dofs[s + i], L.patch_dofs[s + j]);
-  }
-  // transpose: DoF -> slots
-  const int ns = (int)L.patch_dofs.size();
-  L.slot_patch.resize(ns);
-  for (int v = 0; v < L.nv; ++v)
-    for (int s = L.patch_ptr[v]; s < L.patch_ptr[v + 1]; ++s) L.slot_patch[s] = v;
-  L.dof_ptr.assign(L.nf + 1, 0);
-  for (int s = 0; s < ns; ++s) L.dof_ptr[L.patch_dofs[s] + 1]++;
-  for (int r = 0; r < L.nf; ++r) L.dof_ptr[r + 1] += L.dof_ptr[r];
-  L.dof_slot.resize(ns);
-  std::vector<int> fill(L.dof_ptr.begin(), L.dof_ptr.end() - 1);
-  for (int s = 0; s < ns; ++s) L.dof_slot[fill[L.patch_dofs[s]]++] = s;
+  patch_maps(L);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,6 +288,33 @@ static void locate(const HostLevel& C, double x, double y, int& cell, double& xi
     cell = 2 * (i + M * j) + 1;
     xi = 1.0 - fx; eta = 1.0 - fy;
   }
+}
+
+// P by fine rows from per-row (coarse column, value) lists, and R = P^T.
+static void transfer_csr(const HostLevel& F, const HostLevel& C,
+                         std::vector<std::vector<std::pair<int, double>>>& rows, HostTransfer& T) {
+  T.p_ptr.assign(F.nf + 1, 0);
+  T.p_col.clear();
+  T.p_val.clear();
+  for (int r = 0; r < F.nf; ++r) {
+    auto& e = rows[r];
+    std::sort(e.begin(), e.end());
+    for (auto& pr : e) { T.p_col.push_back(pr.first); T.p_val.push_back(pr.second); }
+    T.p_ptr[r + 1] = (int)T.p_col.size();
+  }
+  T.r_ptr.assign(C.nf + 1, 0);
+  for (int c : T.p_col) T.r_ptr[c + 1]++;
+  for (int r = 0; r < C.nf; ++r) T.r_ptr[r + 1] += T.r_ptr[r];
+  T.r_col.resize(T.p_col.size());
+  T.r_val.resize(T.p_col.size());
+  std::vector<int> fill(T.r_ptr.begin(), T.r_ptr.end() - 1);
+  for (int r = 0; r < F.nf; ++r)
+    for (int k = T.p_ptr[r]; k < T.p_ptr[r + 1]; ++k) {
+      int c = T.p_col[k];
+      T.r_col[fill[c]] = r;
+      T.r_val[fill[c]] = T.p_val[k];
+      fill[c]++;
+    }
 }
 
 void build_transfer(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
@@ -301,29 +349,7 @@ void build_transfer(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
       rows[F.po + vf].push_back({C.po + C.cells[3 * cell + i], v[i]});
     }
   }
-  T.p_ptr.assign(F.nf + 1, 0);
-  T.p_col.clear();
-  T.p_val.clear();
-  for (int r = 0; r < F.nf; ++r) {
-    auto& e = rows[r];
-    std::sort(e.begin(), e.end());
-    for (auto& pr : e) { T.p_col.push_back(pr.first); T.p_val.push_back(pr.second); }
-    T.p_ptr[r + 1] = (int)T.p_col.size();
-  }
-  // transpose
-  T.r_ptr.assign(C.nf + 1, 0);
-  for (int c : T.p_col) T.r_ptr[c + 1]++;
-  for (int r = 0; r < C.nf; ++r) T.r_ptr[r + 1] += T.r_ptr[r];
-  T.r_col.resize(T.p_col.size());
-  T.r_val.resize(T.p_col.size());
-  std::vector<int> fill(T.r_ptr.begin(), T.r_ptr.end() - 1);
-  for (int r = 0; r < F.nf; ++r)
-    for (int k = T.p_ptr[r]; k < T.p_ptr[r + 1]; ++k) {
-      int c = T.p_col[k];
-      T.r_col[fill[c]] = r;
-      T.r_val[fill[c]] = T.p_val[k];
-      fill[c]++;
-    }
+  transfer_csr(F, C, rows, T);
   // injection: coarse node (a, b) on the coarse node grid is fine node (2a, 2b)
   T.inject.assign(C.nf, -1);
   for (int g = 0; g < C.nn; ++g) {
@@ -338,6 +364,139 @@ void build_transfer(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
     int vf = 2 * (v % C.n1) + F.n1 * 2 * (v / C.n1);
     T.inject[C.po + v] = F.po + vf;
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// Heat equation: scalar P_k (Sec. 2, Definition of the heat equation).
+//
+// Basis: for the node (a, b) / k with c = k - a - b, in barycentric
+// coordinates (l0, l1, l2) = (1 - xi - eta, xi, eta),
+//   phi = F_a(l1) F_b(l2) F_c(l0),  F_n(l) = prod_{i < n} (k l - i) / (i + 1),
+// which is one at its node and vanishes at every other lattice node of the
+// triangle (some factor k l_j - i is zero there).
+static void pk_factor(int k, int n, double l, double& f, double& df) {
+  f = 1.0;
+  df = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double t = (k * l - i) / (i + 1.0), dt = k / (i + 1.0);
+    df = df * t + f * dt;
+    f *= t;
+  }
+}
+
+void pk_eval(int k, double xi, double eta, double* v, double (*g)[2]) {
+  const double l0 = 1.0 - xi - eta, l1 = xi, l2 = eta;
+  int i = 0;
+  for (int b = 0; b <= k; ++b)
+    for (int a = 0; a + b <= k; ++a, ++i) {
+      const int c = k - a - b;
+      double f1, d1, f2, d2, f0, d0;
+      pk_factor(k, a, l1, f1, d1);
+      pk_factor(k, b, l2, f2, d2);
+      pk_factor(k, c, l0, f0, d0);
+      v[i] = f1 * f2 * f0;
+      if (g) {
+        // d/dxi: l1' = 1, l0' = -1; d/deta: l2' = 1, l0' = -1
+        g[i][0] = d1 * f2 * f0 - f1 * f2 * d0;
+        g[i][1] = f1 * d2 * f0 - f1 * f2 * d0;
+      }
+    }
+}
+
+void build_pk_tables(int k, RefTables& t) {
+  if (k < 1 || k > kMaxPk) throw std::invalid_argument("spatial degree must be 1, 2 or 3");
+  t.kdeg = k;
+  t.nloc = (k + 1) * (k + 2) / 2;
+  for (int x = 0; x < kQx; ++x) pk_eval(k, t.xq[x][0], t.xq[x][1], t.Nk[x], t.dNk[x]);
+}
+
+void build_level_heat(int M, int k, HostLevel& L) {
+  if (M < 1) throw std::invalid_argument("mesh size must be positive");
+  if (k < 1 || k > kMaxPk) throw std::invalid_argument("spatial degree must be 1, 2 or 3");
+  L.kdeg = k;
+  L.nloc = (k + 1) * (k + 2) / 2;
+  L.M = M;
+  L.n1 = M + 1;
+  L.n2 = k * M + 1;            // node lattice width
+  L.nv = L.n1 * L.n1;
+  L.nc = 2 * M * M;
+  L.nn = L.n2 * L.n2;
+  L.nfn = L.nn;
+  L.nf = L.nn;
+  L.po = L.nf;                 // no pressure
+  const int n1 = L.n1, nl = L.n2, nloc = L.nloc;
+  mesh_cells(L);
+  L.cell_p2.clear();
+  L.node_free.resize(L.nn);
+  for (int g = 0; g < L.nn; ++g) L.node_free[g] = g;
+  // local node (a, b) of a lower cell with corner vertex (i, j) is lattice
+  // node (k i + a, k j + b); of an upper cell with corner (i+1, j+1) it is
+  // (k (i+1) - a, k (j+1) - b) (its reference axes point left and down)
+  L.cell_dofs.resize((size_t)nloc * L.nc);
+  for (int c = 0; c < L.nc; ++c) {
+    const int v0 = L.cells[3 * c], vi = v0 % n1, vj = v0 / n1;
+    const bool lower = c % 2 == 0;
+    int i = 0;
+    for (int b = 0; b <= k; ++b)
+      for (int a = 0; a + b <= k; ++a, ++i) {
+        const int gi = lower ? k * vi + a : k * vi - a;
+        const int gj = lower ? k * vj + b : k * vj - b;
+        L.cell_dofs[(size_t)nloc * c + i] = gi + nl * gj;
+      }
+  }
+  csr_from_cells(L);
+  // vertex-star patches: the nodes of each incident cell whose barycentric
+  // coordinate for the vertex is positive (the vertex and the interiors of
+  // its incident edges and cells)
+  std::vector<std::vector<int>> pd(L.nv);
+  for (int c = 0; c < L.nc; ++c) {
+    int i = 0;
+    for (int b = 0; b <= k; ++b)
+      for (int a = 0; a + b <= k; ++a, ++i) {
+        const int lam[3] = {k - a - b, a, b};
+        for (int corner = 0; corner < 3; ++corner)
+          if (lam[corner] > 0) pd[L.cells[3 * c + corner]].push_back(L.cell_dofs[(size_t)nloc * c + i]);
+      }
+  }
+  L.patch_ptr.assign(L.nv + 1, 0);
+  L.patch_nbu.assign(L.nv, 0);
+  L.patch_dofs.clear();
+  for (int v = 0; v < L.nv; ++v) {
+    auto& d = pd[v];
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    L.patch_nbu[v] = (int)d.size();   // every DoF carries the jump coupling
+    L.patch_dofs.insert(L.patch_dofs.end(), d.begin(), d.end());
+    L.patch_ptr[v + 1] = (int)L.patch_dofs.size();
+  }
+  patch_maps(L);
+  // node -> (cell, local index) slots, cells in increasing order
+  L.node_cell_ptr.assign(L.nn + 1, 0);
+  for (int e = 0; e < nloc * L.nc; ++e) L.node_cell_ptr[L.cell_dofs[e] + 1]++;
+  for (int g = 0; g < L.nn; ++g) L.node_cell_ptr[g + 1] += L.node_cell_ptr[g];
+  L.node_cell.resize((size_t)nloc * L.nc);
+  std::vector<int> fill(L.node_cell_ptr.begin(), L.node_cell_ptr.end() - 1);
+  for (int e = 0; e < nloc * L.nc; ++e) L.node_cell[fill[L.cell_dofs[e]]++] = e;
+}
+
+void build_transfer_heat(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
+  if (F.M != 2 * C.M || F.kdeg != C.kdeg || F.kdeg < 1)
+    throw std::invalid_argument("heat transfer needs a factor-2 refinement of the same degree");
+  const int k = F.kdeg, nloc = C.nloc;
+  std::vector<std::vector<std::pair<int, double>>> rows(F.nf);
+  const double hs = 1.0 / (F.M * k);
+  for (int g = 0; g < F.nf; ++g) {
+    const double x = (g % F.n2) * hs, y = (g / F.n2) * hs;
+    int cell; double xi, eta;
+    locate(C, x, y, cell, xi, eta);
+    double v[kMaxLoc];
+    pk_eval(k, xi, eta, v, nullptr);
+    for (int i = 0; i < nloc; ++i)
+      if (std::fabs(v[i]) >= 1e-14) rows[g].push_back({C.cell_dofs[(size_t)nloc * cell + i], v[i]});
+  }
+  transfer_csr(F, C, rows, T);
+  T.inject.clear();
 }
 
 }  // namespace stwr

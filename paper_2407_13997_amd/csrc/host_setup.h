@@ -1,8 +1,9 @@
 // Host-side construction of one space-time level: structured triangle-split
-// mesh, Taylor-Hood P2-P1 free-DoF numbering, CSR sparsity pattern, cell and
-// patch index maps (Vanka+star patches, Sec. 3), nested-grid transfer
-// stencils (P = I (x) blockdiag(P_u, P_phi), Sec. 3) and the quadrature and
-// temporal reference tables.  Pure C++: no device calls.
+// mesh, Taylor-Hood P2-P1 free-DoF numbering (or the heat equation's P_k
+// node lattice), CSR sparsity pattern, cell and patch index maps (Vanka+star
+// or vertex-star patches, Sec. 3), nested-grid transfer stencils
+// (P = I (x) blockdiag(P_u, P_phi), or I (x) P_k, Sec. 3) and the quadrature
+// and temporal reference tables.  Pure C++: no device calls.
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -14,6 +15,9 @@ constexpr int kMaxG = 6;      // temporal Gauss points (q + 3)
 constexpr int kMaxNQ = 2;     // temporal nodes per slab (q <= 1)
 constexpr int kMaxNb = 39;    // spatial DoFs in a Vanka+star patch (interior)
 constexpr int kMaxNbu = 38;   // velocity DoFs in a patch
+
+constexpr int kMaxPk = 3;     // highest spatial degree of the heat equation's P_k
+constexpr int kMaxLoc = 10;   // nodes of a P_k cell, (k + 1)(k + 2) / 2
 
 // Reference tables consumed by the assembly kernels (plain doubles so the
 // struct can be copied to device memory as is).
@@ -31,13 +35,29 @@ struct RefTables {
   double e0[kMaxNQ], e1[kMaxNQ], tnode[kMaxNQ];
   double T[kMaxNQ][kMaxNQ];  // int phi_b' phi_a + phi_b(0) phi_a(0)
   double W[kMaxNQ][kMaxNQ];  // int phi_a phi_b
+  // heat equation: P_k basis (k = kdeg) at the spatial quadrature points
+  int kdeg, nloc;
+  double Nk[kQx][kMaxLoc];
+  double dNk[kQx][kMaxLoc][2];
 };
 
 // nodes: 0 right Gauss-Radau, 1 Gauss-Legendre (the slab's Lagrange nodes)
 void build_ref_tables(int q, int nodes, RefTables& t);
 void gauss_legendre01(int n, double* x, double* w);
+// P_k Lagrange basis of the heat equation (1 <= k <= 3) into t.Nk, t.dNk
+void build_pk_tables(int k, RefTables& t);
+// P_k basis on the reference triangle, equispaced nodes (a, b) / k with
+// a + b <= k ordered b outer, a inner: values v[nloc], gradients g[nloc][2]
+void pk_eval(int k, double xi, double eta, double* v, double (*g)[2]);
 
+// One level of either discretisation.  Navier-Stokes (kdeg = 0): Taylor-Hood
+// P2-P1, cell_dofs 15 per cell, Vanka+star patches.  Heat (kdeg = k): scalar
+// P_k on the (kM+1)^2 node lattice (n2 = kM+1, every node free, po = nf),
+// cell_dofs nloc per cell, cell_nz nloc^2 per cell, vertex-star patches, and
+// node_cell_ptr / node_cell = the (cell * nloc + local index) slots of each
+// node for the gather-form assembly.
 struct HostLevel {
+  int kdeg = 0, nloc = 15;
   int M = 0, n1 = 0, n2 = 0;
   int nv = 0, nc = 0, nn = 0;
   int nfn = 0, nf = 0, po = 0;   // free P2 nodes, free DoFs, pressure offset
@@ -55,9 +75,11 @@ struct HostLevel {
   std::vector<int> dof_ptr;      // nf + 1: transpose map, DoF -> patch slots
   std::vector<int> dof_slot;     // positions in patch_dofs that hold the DoF
   std::vector<int> slot_patch;   // sum nb: patch owning each slot
+  std::vector<int> node_cell_ptr, node_cell;   // heat only
 };
 
 void build_level(int M, HostLevel& L);
+void build_level_heat(int M, int k, HostLevel& L);
 
 // Prolongation from coarse (M/2) to fine (M) in free-DoF numbering, stored by
 // fine rows (P) and by coarse rows (R = P^T).  Injection map: coarse free DoF
@@ -71,5 +93,7 @@ struct HostTransfer {
 };
 
 void build_transfer(const HostLevel& fine, const HostLevel& coarse, HostTransfer& T);
+// P_k interpolation of the coarse heat space at the fine lattice nodes (no injection map)
+void build_transfer_heat(const HostLevel& fine, const HostLevel& coarse, HostTransfer& T);
 
 }  // namespace stwr

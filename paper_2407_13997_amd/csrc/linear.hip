@@ -174,9 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_gemv_cols(int64_t n, int k, const do
 }
 
 // Dense bordered slab blocks of the coarsest level: B_n = [J_nn C; C^T 0],
-// C = one indicator column of the pressure DoFs per temporal node.
+// C = one indicator column of the pressure DoFs per temporal node (nbord =
+// q + 1 columns); without a pressure (nbord = 0) B_n = J_nn.
 template <int NQ>
-__global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N,
+__global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N, int nbord,
                                                          const int* __restrict__ rp,
                                                          const int* __restrict__ col,
                                                          const double* __restrict__ Jv,
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N,
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= (int64_t)nf * N) return;
   const int i = (int)(t / N), n = (int)(t % N);
-  const int m = nf * NQ, mm = m + NQ;
+  const int m = nf * NQ, mm = m + nbord;
   double* Bn = B + (int64_t)n * mm * mm;
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
     const int j = col[k];
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_bgj_panel_reg(int m, int k0, 
 // Forward block substitution over the slabs of the coarsest level with the
 // inverted bordered slab blocks; one workgroup walks the slabs in order.
 template <int NQ>
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N, int nbord,
                                                          const int* __restrict__ rp,
                                                          const int* __restrict__ col,
                                                          const double* __restrict__ Mv, double e00,
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x) {
   __shared__ double g[kMaxCoarse];
-  const int m = nf * NQ, mm = m + NQ;
+  const int m = nf * NQ, mm = m + nbord;
   const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
   const int tid = threadIdx.x;
   for (int n = 0; n < N; ++n) {
@@ -680,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
       }
       g[r] = v;
     }
-    if (tid < NQ) g[m + tid] = 0.0;
+    if (tid < nbord) g[m + tid] = 0.0;
     __syncthreads();
     const double* Bn = Binv + (int64_t)n * mm * mm;
     for (int r = tid; r < m; r += kBlock) {
@@ -699,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N,
 // right-hand side takes 16 lanes per row, each summing every 16th nonzero of
 // the row's mass entries.
 template <int NQ>
-__global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, int n,
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, int n, int nbord,
                                                        const int* __restrict__ rp,
                                                        const int* __restrict__ col,
                                                        const double* __restrict__ Mv, double e00,
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, in
                                                        double* __restrict__ g) {
   const int r = blockIdx.x * (kBlock / 16) + threadIdx.x / 16, l = threadIdx.x % 16;
   const int m = nf * NQ;
-  if (r >= m + NQ) return;
+  if (r >= m + nbord) return;
   if (r >= m) {
     if (l == 0) g[r] = 0.0;
     return;
@@ -839,10 +840,10 @@ hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, 
   const int64_t n = (int64_t)L.nf * L.N;
   if (L.NQ == 1)
     hipLaunchKernelGGL(k_coarse_build<1>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
-                       L.row_ptr, L.col, Jv, B);
+                       L.nbord, L.row_ptr, L.col, Jv, B);
   else
     hipLaunchKernelGGL(k_coarse_build<2>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
-                       L.row_ptr, L.col, Jv, B);
+                       L.nbord, L.row_ptr, L.col, Jv, B);
   return hipGetLastError();
 }
 
@@ -883,7 +884,7 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
 hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const double* Mv,
                                const double* e0, const double* e1, const double* b, double* x,
                                double* gbuf, hipStream_t s) {
-  const int mm = L.nf * L.NQ + L.NQ;
+  const int mm = L.nf * L.NQ + L.nbord;
   if (mm > kMaxCoarse) return hipErrorInvalidValue;
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
   if (mm > kCoarseSmall) {
@@ -892,20 +893,20 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
     for (int n = 0; n < L.N; ++n) {
       const double* Bn = Binv + (int64_t)n * mm * mm;
       if (L.NQ == 1) {
-        hipLaunchKernelGGL(k_coarse_rhs<1>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
+        hipLaunchKernelGGL(k_coarse_rhs<1>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.nbord, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
         hipLaunchKernelGGL(k_coarse_gemv<1>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
       } else {
-        hipLaunchKernelGGL(k_coarse_rhs<2>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
+        hipLaunchKernelGGL(k_coarse_rhs<2>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.nbord, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
         hipLaunchKernelGGL(k_coarse_gemv<2>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
       }
     }
     return hipGetLastError();
   }
   if (L.NQ == 1)
-    hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.row_ptr,
+    hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.nbord, L.row_ptr,
                        L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);
   else
-    hipLaunchKernelGGL(k_coarse_solve<2>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.row_ptr,
+    hipLaunchKernelGGL(k_coarse_solve<2>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.nbord, L.row_ptr,
                        L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);
   return hipGetLastError();
 }

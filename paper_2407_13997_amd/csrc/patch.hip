@@ -722,7 +722,12 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
   dim3 grid(P.n_patch);
   // wavefronts per patch = panels of the largest block / kPanelsPerWave
-  if (prec == 1) {
+  if (prec == 1 && L.kdeg > 0) {
+    // scalar heat patches (at most 19 DoFs, 38 rows): one wavefront holds a
+    // whole FP32 block; outputs stay FP64
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, float, 1>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+    else hipLaunchKernelGGL((k_patch_sweep<2, float, 1>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+  } else if (prec == 1) {
     if (L.NQ == 1) {
       hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     } else {
@@ -740,7 +745,7 @@ hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec,
                                hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (prec == 1) {
+  if (prec == 1 && L.kdeg == 0) {
     const float* Yf = (const float*)Y;
     if (L.NQ == 1) hipLaunchKernelGGL((k_patch_gather<1, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
     else hipLaunchKernelGGL((k_patch_gather<2, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);

@@ -31,7 +31,8 @@ __all__ = ["Problem", "draw_modes", "named_problem", "batch_problems", "arrival_
 
 @dataclasses.dataclass
 class Problem:
-    """One space-time Navier-Stokes problem on the unit square."""
+    """One space-time problem on the unit square: Navier-Stokes (equation 0)
+    or the heat equation with P_degree elements (equation 1)."""
     mesh_n: int            # finest mesh: mesh_n x mesh_n squares, each cut into 2 triangles
     n_levels: int          # spatial multigrid levels (finest .. mesh_n / 2**(n_levels-1))
     q: int                 # DG degree in time
@@ -45,10 +46,14 @@ class Problem:
     seed: int = 0
     flow: int = 0          # 0: manufactured modes; 1: Chorin problem; 2: lid-driven cavity
     nodes: int = 0         # temporal nodes: 0 right Gauss-Radau, 1 Gauss-Legendre
+    equation: int = 0      # 0: Navier-Stokes; 1: heat equation
+    degree: int = 0        # heat equation: spatial degree k of P_k
 
     @property
     def n_free_spatial(self) -> int:
         m = self.mesh_n
+        if self.equation == 1:
+            return (self.degree * m + 1) ** 2
         return 2 * (2 * m - 1) ** 2 + (m + 1) ** 2
 
     @property
@@ -128,6 +133,18 @@ def cavity_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int, reynolds: f
     none_f = np.zeros((0, 3))
     return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, none_i, none_f, none_i, none_f,
                    seed=0, flow=2, nodes=nodes)
+
+
+def heat_problem(mesh_n: int, n_levels: int, degree: int, q: int, n_slabs: int = 20,
+                 t_final: float = 0.02, nodes: int = 1) -> Problem:
+    """The heat equation with P_degree x DG(q) and the paper's initial data
+    sin(pi x) + cos(2 pi y) (its runs: 80 x 80 and 160 x 160 meshes from a
+    10 x 10 base, k = 1..3, t in [0, 0.02], N = 20), Gauss-Legendre temporal
+    nodes by default.  Nothing is drawn: the problem has no random data."""
+    none_i = np.zeros((0, 2), dtype=np.int64)
+    none_f = np.zeros((0, 3))
+    return Problem(mesh_n, n_levels, q, n_slabs, t_final, 0.0, none_i, none_f, none_i, none_f,
+                   seed=0, nodes=nodes, equation=1, degree=degree)
 
 
 def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,

@@ -1,0 +1,139 @@
+"""The heat equation (Sec. 2 Definition of the heat equation, eq. heatfem) on
+the GPU through the C ABI, against the heat oracle.
+
+* Parity on small meshes (P1, P2, P3 x DG(0), DG(1), three slabs, two
+  levels): operator application on both levels, the right-hand side, one
+  vertex-star patch application (FP64 and FP32 factors), the transfers, the
+  coarsest solve, the eigen-estimate, a V-cycle, and FGMRES solutions.
+* The paper's FGMRES-WRMG runs (Sec. 4.1: 80 x 80 and 160 x 160 meshes from
+  a 10 x 10 base, k = 1..3, q = 0, 1, t in [0, 0.02], N = 20, stopping at a
+  residual reduction of 1e-6 or a residual below 1e-6): three iterations
+  each, with the FP64 and the FP32 smoother."""
+import numpy as np
+import pytest
+
+import stwr_workloads as w
+from gpu_common import gpu_problem, log, rel, seeded, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(k, q) for k in (1, 2, 3) for q in (0, 1)]
+
+
+def _oracle(M, L, k, q, N, **opt):
+    from oracle.heat import HeatHierarchy
+    from oracle.multigrid import Options
+    return HeatHierarchy(M, L, k, q, N, 0.02, Options(**opt), "gauss")
+
+
+@pytest.mark.parametrize("k,q", CASES)
+def test_heat_operator_rhs_transfers_coarse(k, q):
+    torch_cuda()
+    N = 3
+    p = w.heat_problem(8, 2, k, q, N)
+    G = gpu_problem(p)
+    H = _oracle(8, 2, k, q, N)
+    errs = {}
+    for l in (0, 1):
+        A = H.A[l]
+        x = seeded(A.shape[0], 10 + l)
+        y = G.vec(l)
+        G.apply(l, to_dev(x), y)
+        errs[f"apply{l}"] = rel(to_host(y), A @ x)
+    b = G.vec()
+    G.linear_rhs(b)
+    errs["rhs"] = rel(to_host(b), H.levels[0].rhs())
+    F = G.vec()
+    U = seeded(H.A[0].shape[0], 5)
+    G.nonlinear_residual(to_dev(U), F)
+    errs["residual"] = rel(to_host(F), H.A[0] @ U - H.levels[0].rhs())
+    rf = seeded(H.A[0].shape[0], 6)
+    rc = G.vec(1)
+    G.restrict(0, to_dev(rf), rc)
+    errs["restrict"] = rel(to_host(rc), H.P[0].T @ rf)
+    ec = seeded(H.A[1].shape[0], 7)
+    xf = to_dev(np.zeros(H.A[0].shape[0]))
+    G.prolong_add(0, to_dev(ec), xf)
+    errs["prolong"] = rel(to_host(xf), H.P[0] @ ec)
+    bc = seeded(H.A[1].shape[0], 8)
+    xc = G.vec(1)
+    G.coarse_solve(to_dev(bc), xc)
+    errs["coarse"] = rel(to_host(xc), H.coarse.solve(bc))
+    log(f"[heat 8x8 k={k} q={q}] " + " ".join(f"{a}={v:.1e}" for a, v in errs.items()))
+    for key, v in errs.items():
+        assert v < (1e-11 if key == "coarse" else 1e-13), (key, v)
+    G.close()
+
+
+@pytest.mark.parametrize("k,q", CASES)
+def test_heat_smoother_vcycle_fgmres(k, q):
+    torch_cuda()
+    from oracle.heat import heat_solve
+    from oracle.multigrid import Options
+    N = 3
+    p = w.heat_problem(8, 2, k, q, N)
+    H = _oracle(8, 2, k, q, N)
+    errs = {}
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        G = gpu_problem(p, smoother_prec=prec)
+        G.patch_factor(0, prec)
+        r = seeded(H.A[0].shape[0], 21)
+        z = G.vec()
+        G.patch_apply(0, to_dev(r), z)
+        errs[f"patch{prec}"] = rel(to_host(z), H.smoothers[0].apply(r))
+        assert errs[f"patch{prec}"] < tol
+        G.close()
+    G = gpu_problem(p)
+    G.setup_smoothers()
+    lam = G.eig_estimate(0)
+    errs["lambda"] = abs(lam / H.lams[0] - 1.0)
+    b = seeded(H.A[0].shape[0], 22)
+    x = G.vec()
+    G.vcycle(to_dev(b), x)
+    errs["vcycle"] = rel(to_host(x), H.vcycle(b))
+    G.close()
+    # FGMRES to 1e-10 on the paper's right-hand side
+    G = gpu_problem(p, gmres_rtol=1e-10)
+    G.setup_smoothers()
+    b = G.vec()
+    G.linear_rhs(b)
+    x = G.vec()
+    st = G.fgmres(b, x)
+    xo, its, _, _ = heat_solve(8, 2, k, q, N, rtol=1e-10, atol=0.0, opts=Options())
+    errs["fgmres"] = rel(to_host(x), xo)
+    log(f"[heat 8x8 k={k} q={q}] " + " ".join(f"{a}={v:.1e}" for a, v in errs.items())
+        + f" its gpu={st['linear_total']} oracle={its}")
+    assert errs["lambda"] < 1e-10
+    assert errs["vcycle"] < 1e-11
+    assert errs["fgmres"] < 1e-9
+    assert abs(st["linear_total"] - its) <= 1
+    G.close()
+
+
+PAPER_SIZES = [(80, 4), (160, 5)]
+
+
+@pytest.mark.parametrize("M,L", PAPER_SIZES)
+@pytest.mark.parametrize("k,q", CASES)
+def test_heat_paper_three_iterations(M, L, k, q):
+    """Sec. 4.1: every FGMRES-WRMG solve of the paper's heat runs takes three
+    iterations (four at k = 2, q = 3 on the 80 x 80 mesh, outside q <= 1)."""
+    torch = torch_cuda()
+    p = w.heat_problem(M, L, k, q)
+    its = {}
+    for prec in (0, 1):
+        G = gpu_problem(p, smoother_prec=prec, gmres_rtol=1e-6, gmres_atol=1e-6)
+        G.setup_smoothers()
+        b = G.vec()
+        G.linear_rhs(b)
+        x = G.vec()
+        torch.cuda.synchronize()
+        st = G.fgmres(b, x)
+        r = G.vec()
+        G.residual(0, b, x, r)
+        bn, rn = float(b.norm()), float(r.norm())
+        its[prec] = st["linear_total"]
+        assert rn <= max(1e-6 * bn, 1e-6) * (1 + 1e-8)
+        G.close()
+    log(f"[heat {M}x{M} k={k} q={q}] st-dofs={p.n_st} iterations fp64={its[0]} fp32={its[1]} (paper 3)")
+    assert its[0] == 3 and its[1] == 3
