@@ -226,6 +226,8 @@ def main():
     if not args.no_paper_context:
         out["paper_context"] = paper_context()
         log(f"[bench] paper context: {out['paper_context']}")
+        out["paper_context"]["heat"] = heat_context()
+        log(f"[bench] heat context: {out['paper_context']['heat']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
@@ -324,6 +326,97 @@ def paper_context() -> dict:
                        "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
     ctx.close()
     return {"chorin": chorin, "cavity": cavity}
+
+
+# The paper's FGMRES-WRMG heat runs (Sec. 4.1, times to solution at Mref = 3
+# and 4, i.e. 80 x 80 and 160 x 160 meshes from a 10 x 10 base; N = 20,
+# t in [0, 0.02]): (mesh, k, q) -> seconds on 8 Xeon cores
+PAPER_HEAT = {
+    (80, 1, 0): 7.0, (80, 2, 0): 17.9, (80, 3, 0): 48.9,
+    (80, 1, 1): 14.0, (80, 2, 1): 48.4, (80, 3, 1): 183.1,
+    (160, 1, 0): 21.4, (160, 2, 0): 148.7, (160, 3, 0): 373.4,
+    (160, 1, 1): 50.8, (160, 2, 1): 375.5, (160, 3, 1): 1090.0,
+}
+
+
+def heat_context(sweep_steps: int = 20) -> dict:
+    """The paper's heat runs on this GPU (FP32 smoother, FGMRES to a residual
+    reduction of 1e-6 or below 1e-6): iterations and time to solution (problem
+    set-up with the operator's assembly, smoother set-up, solve), beside the
+    paper's times; and the WR sweep of the largest run (160 x 160, P3 x DG(1),
+    9.25 M st-DoFs) against the HBM roofline: per (patch, slab) the FP32
+    inverse block, the FP64 residual gather and the FP64 output."""
+    import numpy as np
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    ctx = binding.Context(0)
+
+    def opts():
+        o = binding.default_opts()
+        o.smoother_prec = binding.FP32
+        o.gmres_rtol = 1e-6
+        o.gmres_atol = 1e-6
+        return o
+
+    runs = []
+    for (M, k, q), p_time in sorted(PAPER_HEAT.items()):
+        prob = w.heat_problem(M, 4 if M == 80 else 5, k, q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = binding.Problem(ctx, prob, opts())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P.setup_smoothers()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        b = P.vec()
+        P.linear_rhs(b)
+        x = P.vec()
+        st = P.fgmres(b, x)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        P.close()
+        runs.append({"mesh": M, "k": k, "q": q, "st_dofs": prob.n_st, "iterations": st["linear_total"],
+                     "paper_iterations": 3, "time_s": t3 - t0, "create_s": t1 - t0,
+                     "smoother_setup_s": t2 - t1, "solve_s": t3 - t2, "paper_time_s": p_time})
+    # sweep of the largest run
+    prob = w.heat_problem(160, 5, 3, 1)
+    P = binding.Problem(ctx, prob, opts())
+    P.setup_smoothers()
+    lam = P.eig_estimate(0)
+    n_st = P.sizes(0)[0]
+    g = torch.Generator(device="cpu").manual_seed(4100)
+    b = torch.randn(n_st, generator=g, dtype=torch.float64).to("cuda")
+    x = torch.zeros(n_st, dtype=torch.float64, device="cuda")
+    a, bnd = 0.25 * lam, 1.05 * lam
+    P.relax(0, b, x, 2, a, bnd)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.kernel_times()
+    t0 = time.perf_counter()
+    for _ in range(sweep_steps):
+        P.relax(0, b, x, 1, a, bnd)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    nq, N = prob.q + 1, prob.n_slabs
+    m = P.patch_sizes(0).astype(np.int64) * nq
+    algo = int(N * np.sum(m * m * 4 + 8 * m + 8 * m))
+    sweep_ms = kt["sweep"][0] / max(kt["sweep"][1], 1)
+    achieved = algo / (sweep_ms * 1e-3) / 1e9
+    P.close()
+    ctx.close()
+    return {"runs": runs,
+            "sweep": {"workload": "heat_p3_dg1_m160_n20 finest-level WR sweep", "st_dofs": n_st,
+                      "ms_per_step": wall / sweep_steps * 1e3,
+                      "st_dof_per_s": n_st / (wall / sweep_steps),
+                      "kernels_ms_per_sweep": {k2: v[0] / max(v[1], 1) for k2, v in kt.items()},
+                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                   "kernel": "k_patch_sweep (FP32 blocks, FP64 outputs)",
+                                   "avg_ms": sweep_ms, "algorithmic_bytes": algo}}}
 
 
 def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:

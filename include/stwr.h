@@ -216,6 +216,12 @@ int32_t stwr_problem_sizes(const stwr_problem* p, int32_t level, int64_t* n_st,
                            int64_t* n_spatial_free, int32_t* n_patches);
 int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts);
 
+/* Spatial DoFs of every patch of a level (the slab blocks are (q+1) nb
+ * square), patch v at nb[v]: host int32[n_patches] (Sec. 3 patches: the
+ * Vanka+star patch of each vertex, or its vertex star for the heat
+ * equation). */
+int32_t stwr_patch_sizes(const stwr_problem* p, int32_t level, int32_t* nb);
+
 /* Nonlinear space-time residual F(U) of eq. nsfem (level 0), U and F of
  * length n_st(0).  Boundary values are the exact velocity at the temporal
  * nodes; the initial value is the P2 interpolant of the velocity at t = 0.

@@ -24,7 +24,8 @@ FP64, FP32 = 0, 1
 EXPORTED = [
     "stwr_default_opts", "stwr_ctx_create", "stwr_ctx_destroy", "stwr_ctx_set_stream",
     "stwr_last_error", "stwr_ctx_bytes_in_use", "stwr_problem_bytes", "stwr_mesh_info",
-    "stwr_problem_create", "stwr_problem_destroy", "stwr_problem_sizes", "stwr_set_opts",
+    "stwr_problem_create", "stwr_problem_destroy", "stwr_problem_sizes", "stwr_patch_sizes",
+    "stwr_set_opts",
     "stwr_nonlinear_residual", "stwr_linear_rhs", "stwr_velocity_l2_error", "stwr_expand",
     "stwr_assemble",
     "stwr_get_operator", "stwr_apply",
@@ -290,6 +291,12 @@ class Problem:
         self.ctx.check(self.lib.stwr_problem_sizes(self.h, level, ctypes.byref(a), ctypes.byref(b),
                                                    ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def patch_sizes(self, level=0) -> np.ndarray:
+        """Spatial DoFs of every patch of a level."""
+        nb = np.zeros(self.sizes(level)[2], dtype=np.int32)
+        self.ctx.check(self.lib.stwr_patch_sizes(self.h, level, nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return nb
 
     def vec(self, level=0):
         import torch

@@ -1169,6 +1169,13 @@ int32_t stwr_problem_sizes(const stwr_problem* p, int32_t level, int64_t* n_st, 
   return STWR_OK;
 }
 
+int32_t stwr_patch_sizes(const stwr_problem* p, int32_t level, int32_t* nb) {
+  if (!p || !nb || level < 0 || level >= (int)p->lv.size()) return STWR_ERR_ARG;
+  const HostLevel& H = p->lv[level].H;
+  for (int v = 0; v < H.nv; ++v) nb[v] = H.patch_ptr[v + 1] - H.patch_ptr[v];
+  return STWR_OK;
+}
+
 int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {

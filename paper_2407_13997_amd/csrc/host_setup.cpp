@@ -466,6 +466,7 @@ void build_level_heat(int M, int k, HostLevel& L) {
     auto& d = pd[v];
     std::sort(d.begin(), d.end());
     d.erase(std::unique(d.begin(), d.end()), d.end());
+    if ((int)d.size() > kHeatMaxNb) throw std::logic_error("vertex-star patch larger than its bound");
     L.patch_nbu[v] = (int)d.size();   // every DoF carries the jump coupling
     L.patch_dofs.insert(L.patch_dofs.end(), d.begin(), d.end());
     L.patch_ptr[v + 1] = (int)L.patch_dofs.size();

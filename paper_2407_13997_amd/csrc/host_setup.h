@@ -18,6 +18,7 @@ constexpr int kMaxNbu = 38;   // velocity DoFs in a patch
 
 constexpr int kMaxPk = 3;     // highest spatial degree of the heat equation's P_k
 constexpr int kMaxLoc = 10;   // nodes of a P_k cell, (k + 1)(k + 2) / 2
+constexpr int kHeatMaxNb = 19;  // DoFs of a P_k vertex-star patch, 3k^2 - 3k + 1 at k = 3
 
 // Reference tables consumed by the assembly kernels (plain doubles so the
 // struct can be copied to device memory as is).

@@ -58,11 +58,11 @@ __device__ inline float4 load_stream(const float* p) {
 // writing the inverse out in the sweep's panel layout.  Per element the
 // arithmetic and the pivot choice (largest magnitude, ties to the smaller
 // row) are those of the textbook in-place Gauss-Jordan inverse.
-template <int NQ, typename T, int TPB, int RPL>
+template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb>
 __global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, int first,
                                                       const double* __restrict__ Jv,
                                                       T* __restrict__ fac, int* __restrict__ status) {
-  constexpr int MAXM = kMaxNb * NQ;
+  constexpr int MAXM = NBMAX * NQ;
   constexpr int NW = TPB / 64;
   constexpr int VW = Vec<T>::W;
   // row buffers padded to whole 16-byte vectors
@@ -522,26 +522,26 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
 // the residual values of slab n + 1 are loaded too.  The jump coupling
 // mj = M_v (e1 . y_{n-1}) is formed once per velocity DoF at the end of the
 // previous slab.
-template <int NQ, typename T, int WAVES>
+template <int NQ, typename T, int WAVES, int NBMAX = kMaxNb, int NBUMAX = kMaxNbu>
 __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchView P,
                                                             const T* __restrict__ fac,
                                                             const double* __restrict__ Mp,
                                                             double e00, double e01, double e10,
                                                             double e11, const double* __restrict__ r,
                                                             double* __restrict__ Y) {
-  constexpr int MAXM = kMaxNb * NQ;
+  constexpr int MAXM = NBMAX * NQ;
   constexpr int VW = Vec<T>::W;
   constexpr int MAXP = (MAXM + VW - 1) / VW;
   constexpr int PW = panels_per_wave(VW);
   constexpr int K2 = (PW + 3) / 4;
   constexpr bool kTwo = MAXM > 64;
   using V = typename Vec<T>::type;
-  __shared__ int dofs[kMaxNb];
-  __shared__ double Ms[kMaxNbu * kMaxNbu];
+  __shared__ int dofs[NBMAX];
+  __shared__ double Ms[NBUMAX * NBUMAX];
   __shared__ T g[WAVES * PW * VW];
   __shared__ double part[WAVES][MAXM];
   __shared__ double ys[MAXM];
-  __shared__ double mj[kMaxNbu];
+  __shared__ double mj[NBUMAX];
   const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
   const int p = blockIdx.x, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int s0 = P.patch_ptr[p];
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   for (int i = tid; i < nb; i += 64 * WAVES) dofs[i] = P.patch_dofs[s0 + i];
   const double* mp = Mp + P.mp_off[p];
   for (int e = tid; e < nbu * nbu; e += 64 * WAVES) Ms[e] = mp[e];
-  for (int i = tid; i < kMaxNbu; i += 64 * WAVES) mj[i] = 0.0;
+  for (int i = tid; i < NBUMAX; i += 64 * WAVES) mj[i] = 0.0;
   for (int i = tid; i < WAVES * PW * VW; i += 64 * WAVES) g[i] = (T)0;
   __syncthreads();
   const int64_t S = P.slab_stride;
@@ -689,6 +689,19 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
   // per lane (FP32) or two wavefronts (FP64); the others one row per lane
   const int big = L.NQ == 2 ? P.n_big : 0, small = P.n_patch - big;
   const dim3 gb((unsigned)big * L.N), gs((unsigned)small * L.N);
+  if (L.kdeg > 0) {
+    // scalar heat patches: at most kHeatMaxNb DoFs, (q+1) kHeatMaxNb <= 64 rows
+    if (prec == 1) {
+      float* f = (float*)fac;
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, float, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+      else hipLaunchKernelGGL((k_patch_factor<2, float, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+    } else {
+      double* f = (double*)fac;
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, double, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+      else hipLaunchKernelGGL((k_patch_factor<2, double, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+    }
+    return hipGetLastError();
+  }
   if (prec == 1) {
     float* f = (float*)fac;
     if (L.NQ == 1) {
@@ -722,11 +735,17 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
   const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
   dim3 grid(P.n_patch);
   // wavefronts per patch = panels of the largest block / kPanelsPerWave
-  if (prec == 1 && L.kdeg > 0) {
-    // scalar heat patches (at most 19 DoFs, 38 rows): one wavefront holds a
-    // whole FP32 block; outputs stay FP64
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, float, 1>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
-    else hipLaunchKernelGGL((k_patch_sweep<2, float, 1>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+  if (L.kdeg > 0) {
+    // scalar heat patches (at most kHeatMaxNb DoFs, 38 rows): one wavefront
+    // holds a whole FP32 block (two an FP64 one at q = 1); outputs stay FP64
+    constexpr int H = kHeatMaxNb;
+    if (prec == 1) {
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, float, 1, H, H>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+      else hipLaunchKernelGGL((k_patch_sweep<2, float, 1, H, H>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+    } else {
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 1, H, H>), grid, dim3(64), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+      else hipLaunchKernelGGL((k_patch_sweep<2, double, 2, H, H>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+    }
   } else if (prec == 1) {
     if (L.NQ == 1) {
       hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
