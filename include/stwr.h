@@ -86,7 +86,7 @@ typedef struct {
 /* equation = STWR_EQ_HEAT selects the heat equation u_t - Laplace u = 0 of
  * Sec. 2 (eq. heatfem) on the unit square with natural (homogeneous Neumann)
  * boundary conditions, scalar continuous P_k in space (k = degree, 1..3) and
- * DG(q) in time (q in {0, 1}), initial value the nodal interpolant of
+ * DG(q) in time (q in 0..3), initial value the nodal interpolant of
  * u_0 = sin(pi x) + cos(2 pi y) (the paper's runs, Sec. 4.1).  Reynolds
  * number, modes and flow are ignored.  Every node of the (k M + 1)^2 lattice
  * of spacing 1/(k M) is an unknown: node g = gi + (k M + 1) gj is DoF g, so
@@ -96,7 +96,7 @@ typedef struct {
  * assembled at creation; stwr_nonlinear_residual gives F(U) = A U - b with
  * b = e0 (x) M U_0 on slab 0 (stwr_linear_rhs returns b), so
  * stwr_fgmres(b) is the paper's solve and stwr_newton_solve converges in one
- * step.  The coarsest level must satisfy (k M_c + 1)^2 (q + 1) <= 2048. */
+ * step.  The coarsest level must satisfy (k M_c + 1)^2 (q + 1) <= 4096. */
 #define STWR_EQ_NAVIER_STOKES 0
 #define STWR_EQ_HEAT 1
 

@@ -234,7 +234,8 @@ void check_desc(const stwr_problem_desc* d) {
     throw StwrError(STWR_ERR_ARG, "bad equation");
   if (is_heat(d) && (d->degree < 1 || d->degree > kMaxPk))
     throw StwrError(STWR_ERR_ARG, "heat equation degree must be 1, 2 or 3");
-  if (d->q < 0 || d->q > 1) throw StwrError(STWR_ERR_ARG, "q must be 0 or 1");
+  if (d->q < 0 || d->q > (is_heat(d) ? kMaxNQ - 1 : 1))
+    throw StwrError(STWR_ERR_ARG, is_heat(d) ? "q must be 0..3 for the heat equation" : "q must be 0 or 1");
   if (d->n_levels < 1 || d->n_levels > STWR_MAX_LEVELS) throw StwrError(STWR_ERR_ARG, "bad n_levels");
   if (d->mesh_n < 2 || d->n_slabs < 1) throw StwrError(STWR_ERR_ARG, "bad mesh_n or n_slabs");
   if (d->mesh_n % (1 << (d->n_levels - 1)) != 0 || (d->mesh_n >> (d->n_levels - 1)) < 2)
@@ -250,7 +251,7 @@ void check_desc(const stwr_problem_desc* d) {
   const int mc = d->mesh_n >> (d->n_levels - 1);
   const int nfc = is_heat(d) ? (d->degree * mc + 1) * (d->degree * mc + 1)
                              : 2 * (2 * mc - 1) * (2 * mc - 1) + (mc + 1) * (mc + 1);
-  if (nfc * (d->q + 1) + (is_heat(d) ? 0 : d->q + 1) > 2048)
+  if (nfc * (d->q + 1) + (is_heat(d) ? 0 : d->q + 1) > 4096)
     throw StwrError(STWR_ERR_ARG, "coarsest level too large for the dense coarse solve (use more levels)");
 }
 

@@ -20,6 +20,20 @@ struct MmsDev {
   int flow;               // 0: the modes; 1: Chorin problem; 2: lid-driven cavity (modes unused)
 };
 
+// Slab-end values of the temporal Lagrange basis, e0[a] = phi_a(0) and
+// e1[a] = phi_a(1), passed to kernels by value (first NQ entries used).
+struct TimeEnds {
+  double e0[kMaxNQ], e1[kMaxNQ];
+};
+inline TimeEnds time_ends(int NQ, const double* e0, const double* e1) {
+  TimeEnds t{};
+  for (int a = 0; a < NQ && a < kMaxNQ; ++a) {
+    t.e0[a] = e0[a];
+    t.e1[a] = e1[a];
+  }
+  return t;
+}
+
 // Read-only structure of one level on the device.
 struct LevelView {
   int M, nf, po, nv, nc, N, NQ;

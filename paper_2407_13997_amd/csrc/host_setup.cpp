@@ -64,8 +64,46 @@ static void p1_eval(double xi, double eta, double* v) {
   v[2] = eta;
 }
 
+// Legendre P_n(z) by the three-term recurrence
+static double legendre(int n, double z) {
+  double p0 = 1.0, p1 = z;
+  if (n == 0) return p0;
+  for (int k = 2; k <= n; ++k) {
+    const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = pk;
+  }
+  return p1;
+}
+
+// Right Gauss-Radau points of [0, 1]: z = 1 and the q roots of
+// P_{q+1} - P_q in (-1, 1), mapped by (z + 1) / 2; roots bracketed on a fine
+// grid and bisected.
+static void radau_right01(int q, double* x) {
+  int found = 0;
+  const int G = 4000;
+  auto f = [&](double z) { return legendre(q + 1, z) - legendre(q, z); };
+  double za = -1.0, fa = f(za);
+  for (int i = 1; i <= G && found < q; ++i) {
+    const double zb = -1.0 + 2.0 * i / (G + 1.0), fb = f(zb);
+    if (fa == 0.0 || fa * fb < 0.0) {
+      double lo = za, hi = zb, flo = fa;
+      for (int it = 0; it < 200 && hi - lo > 1e-16; ++it) {
+        const double mid = 0.5 * (lo + hi), fm = f(mid);
+        if (flo * fm <= 0.0) hi = mid;
+        else { lo = mid; flo = fm; }
+      }
+      x[found++] = 0.5 * (0.5 * (lo + hi) + 1.0);
+    }
+    za = zb;
+    fa = fb;
+  }
+  if (found != q) throw std::logic_error("Radau node search failed");
+  x[q] = 1.0;
+}
+
 void build_ref_tables(int q, int nodes, RefTables& t) {
-  if (q < 0 || q > 1) throw std::invalid_argument("q must be 0 or 1");
+  if (q < 0 || q > kMaxNQ - 1) throw std::invalid_argument("q must be 0..3");
   if (nodes != 0 && nodes != 1) throw std::invalid_argument("temporal nodes must be 0 or 1");
   double u[5], wu[5];
   gauss_legendre01(5, u, wu);
@@ -87,9 +125,8 @@ void build_ref_tables(int q, int nodes, RefTables& t) {
   t.G = q + 3;
   gauss_legendre01(t.G, t.sg, t.wg);
   if (nodes == 0) {
-    // right Gauss-Radau nodes of the slab: {1} or {1/3, 1}
-    if (q == 0) t.tnode[0] = 1.0;
-    else { t.tnode[0] = 1.0 / 3.0; t.tnode[1] = 1.0; }
+    // right Gauss-Radau nodes of the slab: {1}, {1/3, 1}, ...
+    radau_right01(q, t.tnode);
   } else {
     // Gauss-Legendre nodes of the slab
     double w[kMaxNQ];

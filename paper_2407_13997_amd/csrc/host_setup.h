@@ -12,7 +12,7 @@ namespace stwr {
 
 constexpr int kQx = 25;       // spatial quadrature points (5x5 collapsed Gauss rule)
 constexpr int kMaxG = 6;      // temporal Gauss points (q + 3)
-constexpr int kMaxNQ = 2;     // temporal nodes per slab (q <= 1)
+constexpr int kMaxNQ = 4;     // temporal nodes per slab (q <= 3; Navier-Stokes q <= 1)
 constexpr int kMaxNb = 39;    // spatial DoFs in a Vanka+star patch (interior)
 constexpr int kMaxNbu = 38;   // velocity DoFs in a patch
 

@@ -19,15 +19,15 @@ template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int N, const int* __restrict__ rp,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ Jv,
-                                                 const double* __restrict__ Mv, double e00,
-                                                 double e01, double e10, double e11,
+                                                 const double* __restrict__ Mv, TimeEnds te,
                                                  const double* __restrict__ x,
                                                  const double* __restrict__ b,
                                                  double* __restrict__ y) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= (int64_t)nf * N) return;
   const int i = (int)(t / N), n = (int)(t % N);
-  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  const double* e0 = te.e0;
+  const double* e1 = te.e1;
   double acc[NQ];
   for (int a = 0; a < NQ; ++a) acc[a] = 0.0;
   double jump = 0.0;
@@ -201,15 +201,15 @@ __global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N, 
   }
 }
 
-constexpr int kMaxCoarse = 2048;
+constexpr int kMaxCoarse = 4096;
 
 // In-place Gauss-Jordan inversion with partial pivoting of B[blockIdx.x]
 // (m x m, row-major, global memory), one workgroup per matrix.
 __global__ __launch_bounds__(kBlock) void k_dense_inverse(int m, double* __restrict__ Ball,
                                                           int* __restrict__ status) {
   double* B = Ball + (int64_t)blockIdx.x * m * m;
-  __shared__ int perm[kMaxCoarse];
-  __shared__ double colk[kMaxCoarse];
+  __shared__ int perm[kCoarseSmall];
+  __shared__ double colk[kCoarseSmall];
   __shared__ double rv[kBlock / 64];
   __shared__ int ri[kBlock / 64];
   __shared__ int piv_s;
@@ -654,14 +654,14 @@ template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N, int nbord,
                                                          const int* __restrict__ rp,
                                                          const int* __restrict__ col,
-                                                         const double* __restrict__ Mv, double e00,
-                                                         double e01, double e10, double e11,
+                                                         const double* __restrict__ Mv, TimeEnds te,
                                                          const double* __restrict__ Binv,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x) {
-  __shared__ double g[kMaxCoarse];
+  __shared__ double g[kCoarseSmall];
   const int m = nf * NQ, mm = m + nbord;
-  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  const double* e0 = te.e0;
+  const double* e1 = te.e1;
   const int tid = threadIdx.x;
   for (int n = 0; n < N; ++n) {
     for (int r = tid; r < m; r += kBlock) {
@@ -703,8 +703,7 @@ template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, int n, int nbord,
                                                        const int* __restrict__ rp,
                                                        const int* __restrict__ col,
-                                                       const double* __restrict__ Mv, double e00,
-                                                       double e01, double e10, double e11,
+                                                       const double* __restrict__ Mv, TimeEnds te,
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ g) {
@@ -715,7 +714,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(int nf, int po, int N, in
     if (l == 0) g[r] = 0.0;
     return;
   }
-  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  const double* e0 = te.e0;
+  const double* e1 = te.e1;
   const int i = r / NQ, a = r % NQ;
   const bool jumps = n > 0 && i < po;
   double jump = 0.0;
@@ -761,17 +761,24 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 }  // namespace
 
+// one launch per temporal-node count: every NQ-templated launcher below
+// switches over 1..kMaxNQ
+#define STWR_NQ_SWITCH(NQ, CALL)                 \
+  switch (NQ) {                                  \
+    case 1: { constexpr int Q = 1; CALL; } break; \
+    case 2: { constexpr int Q = 2; CALL; } break; \
+    case 3: { constexpr int Q = 3; CALL; } break; \
+    case 4: { constexpr int Q = 4; CALL; } break; \
+    default: return hipErrorInvalidValue;        \
+  }
+
 hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, const double* e0,
                        const double* e1, const double* x, const double* b, double* y,
                        hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
-  const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
-  if (L.NQ == 1)
-    hipLaunchKernelGGL(k_spmv<1>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.N, L.row_ptr, L.col,
-                       Jv, Mv, e0[0], e01, e1[0], e11, x, b, y);
-  else
-    hipLaunchKernelGGL(k_spmv<2>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.N, L.row_ptr, L.col,
-                       Jv, Mv, e0[0], e01, e1[0], e11, x, b, y);
+  const TimeEnds te = time_ends(L.NQ, e0, e1);
+  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_spmv<Q>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.N,
+                                          L.row_ptr, L.col, Jv, Mv, te, x, b, y));
   return hipGetLastError();
 }
 
@@ -838,12 +845,8 @@ hipError_t launch_gemv_cols(int64_t n, int k, const double* Z, int64_t ldz, cons
 
 hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
-  if (L.NQ == 1)
-    hipLaunchKernelGGL(k_coarse_build<1>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
-                       L.nbord, L.row_ptr, L.col, Jv, B);
-  else
-    hipLaunchKernelGGL(k_coarse_build<2>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
-                       L.nbord, L.row_ptr, L.col, Jv, B);
+  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_coarse_build<Q>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf,
+                                          L.po, L.N, L.nbord, L.row_ptr, L.col, Jv, B));
   return hipGetLastError();
 }
 
@@ -886,28 +889,22 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
                                double* gbuf, hipStream_t s) {
   const int mm = L.nf * L.NQ + L.nbord;
   if (mm > kMaxCoarse) return hipErrorInvalidValue;
-  const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
+  const TimeEnds te = time_ends(L.NQ, e0, e1);
   if (mm > kCoarseSmall) {
     const unsigned gr = (unsigned)((mm + kBlock / 16 - 1) / (kBlock / 16));
     const unsigned gg = (unsigned)((L.nf * L.NQ + kBlock / 64 - 1) / (kBlock / 64));
     for (int n = 0; n < L.N; ++n) {
       const double* Bn = Binv + (int64_t)n * mm * mm;
-      if (L.NQ == 1) {
-        hipLaunchKernelGGL(k_coarse_rhs<1>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.nbord, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
-        hipLaunchKernelGGL(k_coarse_gemv<1>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
-      } else {
-        hipLaunchKernelGGL(k_coarse_rhs<2>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.nbord, L.row_ptr, L.col, Mv, e0[0], e01, e1[0], e11, b, x, gbuf);
-        hipLaunchKernelGGL(k_coarse_gemv<2>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
-      }
+      STWR_NQ_SWITCH(L.NQ, {
+        hipLaunchKernelGGL(k_coarse_rhs<Q>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.nbord,
+                           L.row_ptr, L.col, Mv, te, b, x, gbuf);
+        hipLaunchKernelGGL(k_coarse_gemv<Q>, dim3(gg), dim3(kBlock), 0, s, L.nf, L.N, n, mm, Bn, gbuf, x);
+      });
     }
     return hipGetLastError();
   }
-  if (L.NQ == 1)
-    hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.nbord, L.row_ptr,
-                       L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);
-  else
-    hipLaunchKernelGGL(k_coarse_solve<2>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po, L.N, L.nbord, L.row_ptr,
-                       L.col, Mv, e0[0], e01, e1[0], e11, Binv, b, x);
+  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_coarse_solve<Q>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po,
+                                          L.N, L.nbord, L.row_ptr, L.col, Mv, te, Binv, b, x));
   return hipGetLastError();
 }
 

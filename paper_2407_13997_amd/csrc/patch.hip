@@ -526,8 +526,7 @@ template <int NQ, typename T, int WAVES, int NBMAX = kMaxNb, int NBUMAX = kMaxNb
 __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchView P,
                                                             const T* __restrict__ fac,
                                                             const double* __restrict__ Mp,
-                                                            double e00, double e01, double e10,
-                                                            double e11, const double* __restrict__ r,
+                                                            TimeEnds te, const double* __restrict__ r,
                                                             double* __restrict__ Y) {
   constexpr int MAXM = NBMAX * NQ;
   constexpr int VW = Vec<T>::W;
@@ -542,7 +541,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   __shared__ double part[WAVES][MAXM];
   __shared__ double ys[MAXM];
   __shared__ double mj[NBUMAX];
-  const double e0[2] = {e00, e01}, e1[2] = {e10, e11};
+  const double* e0 = te.e0;
+  const double* e1 = te.e1;
   const int p = blockIdx.x, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0, nbu = P.patch_nbu[p];
@@ -690,15 +690,28 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
   const int big = L.NQ == 2 ? P.n_big : 0, small = P.n_patch - big;
   const dim3 gb((unsigned)big * L.N), gs((unsigned)small * L.N);
   if (L.kdeg > 0) {
-    // scalar heat patches: at most kHeatMaxNb DoFs, (q+1) kHeatMaxNb <= 64 rows
+    // scalar heat patches: at most kHeatMaxNb DoFs, so (q+1) kHeatMaxNb rows:
+    // one row per lane up to 64 rows, two (FP32) or two wavefronts (FP64) at q = 3
+    constexpr int H = kHeatMaxNb;
+    const dim3 ga((unsigned)P.n_patch * L.N);
     if (prec == 1) {
       float* f = (float*)fac;
-      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, float, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
-      else hipLaunchKernelGGL((k_patch_factor<2, float, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+      switch (L.NQ) {
+        case 1: hipLaunchKernelGGL((k_patch_factor<1, float, 64, 1, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        case 2: hipLaunchKernelGGL((k_patch_factor<2, float, 64, 1, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        case 3: hipLaunchKernelGGL((k_patch_factor<3, float, 64, 1, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        case 4: hipLaunchKernelGGL((k_patch_factor<4, float, 64, 2, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        default: return hipErrorInvalidValue;
+      }
     } else {
       double* f = (double*)fac;
-      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, double, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
-      else hipLaunchKernelGGL((k_patch_factor<2, double, 64, 1, kHeatMaxNb>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
+      switch (L.NQ) {
+        case 1: hipLaunchKernelGGL((k_patch_factor<1, double, 64, 1, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        case 2: hipLaunchKernelGGL((k_patch_factor<2, double, 64, 1, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        case 3: hipLaunchKernelGGL((k_patch_factor<3, double, 64, 1, H>), ga, dim3(64), 0, s, L, P, 0, Jv, f, status); break;
+        case 4: hipLaunchKernelGGL((k_patch_factor<4, double, 128, 1, H>), ga, dim3(128), 0, s, L, P, 0, Jv, f, status); break;
+        default: return hipErrorInvalidValue;
+      }
     }
     return hipGetLastError();
   }
@@ -736,15 +749,30 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
   dim3 grid(P.n_patch);
   // wavefronts per patch = panels of the largest block / kPanelsPerWave
   if (L.kdeg > 0) {
-    // scalar heat patches (at most kHeatMaxNb DoFs, 38 rows): one wavefront
-    // holds a whole FP32 block (two an FP64 one at q = 1); outputs stay FP64
+    // scalar heat patches (at most kHeatMaxNb DoFs, (q+1) kHeatMaxNb rows):
+    // a wavefront's threads form up to 64 rows and hold up to 20 FP32 or 10
+    // FP64 column panels; outputs stay FP64
     constexpr int H = kHeatMaxNb;
+    const TimeEnds te = time_ends(L.NQ, e0, e1);
+    const float* ff = (const float*)fac;
+    const double* fd = (const double*)fac;
+    double* Yd = (double*)Y;
     if (prec == 1) {
-      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, float, 1, H, H>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
-      else hipLaunchKernelGGL((k_patch_sweep<2, float, 1, H, H>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+      switch (L.NQ) {
+        case 1: hipLaunchKernelGGL((k_patch_sweep<1, float, 1, H, H>), grid, dim3(64), 0, s, L, P, ff, Mp, te, r, Yd); break;
+        case 2: hipLaunchKernelGGL((k_patch_sweep<2, float, 1, H, H>), grid, dim3(64), 0, s, L, P, ff, Mp, te, r, Yd); break;
+        case 3: hipLaunchKernelGGL((k_patch_sweep<3, float, 1, H, H>), grid, dim3(64), 0, s, L, P, ff, Mp, te, r, Yd); break;
+        case 4: hipLaunchKernelGGL((k_patch_sweep<4, float, 2, H, H>), grid, dim3(128), 0, s, L, P, ff, Mp, te, r, Yd); break;
+        default: return hipErrorInvalidValue;
+      }
     } else {
-      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 1, H, H>), grid, dim3(64), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
-      else hipLaunchKernelGGL((k_patch_sweep<2, double, 2, H, H>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+      switch (L.NQ) {
+        case 1: hipLaunchKernelGGL((k_patch_sweep<1, double, 1, H, H>), grid, dim3(64), 0, s, L, P, fd, Mp, te, r, Yd); break;
+        case 2: hipLaunchKernelGGL((k_patch_sweep<2, double, 2, H, H>), grid, dim3(128), 0, s, L, P, fd, Mp, te, r, Yd); break;
+        case 3: hipLaunchKernelGGL((k_patch_sweep<3, double, 3, H, H>), grid, dim3(192), 0, s, L, P, fd, Mp, te, r, Yd); break;
+        case 4: hipLaunchKernelGGL((k_patch_sweep<4, double, 4, H, H>), grid, dim3(256), 0, s, L, P, fd, Mp, te, r, Yd); break;
+        default: return hipErrorInvalidValue;
+      }
     }
   } else if (prec == 1) {
     if (L.NQ == 1) {
@@ -753,8 +781,9 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
       hipLaunchKernelGGL(k_patch_sweep_f32<2>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     }
   } else {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
-    else hipLaunchKernelGGL((k_patch_sweep<2, double, 4>), grid, dim3(256), 0, s, L, P, (const double*)fac, Mp, e0[0], e01, e1[0], e11, r, (double*)Y);
+    const TimeEnds te = time_ends(L.NQ, e0, e1);
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, te, r, (double*)Y);
+    else hipLaunchKernelGGL((k_patch_sweep<2, double, 4>), grid, dim3(256), 0, s, L, P, (const double*)fac, Mp, te, r, (double*)Y);
   }
   return hipGetLastError();
 }
@@ -770,8 +799,13 @@ hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec,
     else hipLaunchKernelGGL((k_patch_gather<2, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
   } else {
     const double* Yd = (const double*)Y;
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_gather<1, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x);
-    else hipLaunchKernelGGL((k_patch_gather<2, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x);
+    switch (L.NQ) {
+      case 1: hipLaunchKernelGGL((k_patch_gather<1, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      case 2: hipLaunchKernelGGL((k_patch_gather<2, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      case 3: hipLaunchKernelGGL((k_patch_gather<3, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      case 4: hipLaunchKernelGGL((k_patch_gather<4, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -1,14 +1,16 @@
 """The heat equation (Sec. 2 Definition of the heat equation, eq. heatfem) on
 the GPU through the C ABI, against the heat oracle.
 
-* Parity on small meshes (P1, P2, P3 x DG(0), DG(1), three slabs, two
+* Parity on small meshes (P1, P2, P3 x DG(0) .. DG(3), three slabs, two
   levels): operator application on both levels, the right-hand side, one
   vertex-star patch application (FP64 and FP32 factors), the transfers, the
   coarsest solve, the eigen-estimate, a V-cycle, and FGMRES solutions.
 * The paper's FGMRES-WRMG runs (Sec. 4.1: 80 x 80 and 160 x 160 meshes from
-  a 10 x 10 base, k = 1..3, q = 0, 1, t in [0, 0.02], N = 20, stopping at a
+  a 10 x 10 base, k = 1..3, q = 0..3, t in [0, 0.02], N = 20, stopping at a
   residual reduction of 1e-6 or a residual below 1e-6): three iterations
-  each, with the FP64 and the FP32 smoother."""
+  each, four at k = 2, q = 3 on the 80 x 80 mesh, with the FP64 and the FP32
+  smoother (the paper's P3 runs at q = 2, 3 on 160 x 160 ran out of memory
+  and have no count)."""
 import numpy as np
 import pytest
 
@@ -17,7 +19,7 @@ from gpu_common import gpu_problem, log, rel, seeded, to_dev, to_host, torch_cud
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(k, q) for k in (1, 2, 3) for q in (0, 1)]
+CASES = [(k, q) for k in (1, 2, 3) for q in (0, 1, 2, 3)]
 
 
 def _oracle(M, L, k, q, N, **opt):
@@ -110,14 +112,18 @@ def test_heat_smoother_vcycle_fgmres(k, q):
     G.close()
 
 
-PAPER_SIZES = [(80, 4), (160, 5)]
+PAPER_RUNS = [(M, L, k, q) for (M, L) in ((80, 4), (160, 5)) for (k, q) in CASES
+              if not (M == 160 and k == 3 and q >= 2)]
 
 
-@pytest.mark.parametrize("M,L", PAPER_SIZES)
-@pytest.mark.parametrize("k,q", CASES)
-def test_heat_paper_three_iterations(M, L, k, q):
+def paper_iterations(M, k, q):
+    return 4 if (M, k, q) == (80, 2, 3) else 3
+
+
+@pytest.mark.parametrize("M,L,k,q", PAPER_RUNS)
+def test_heat_paper_iteration_counts(M, L, k, q):
     """Sec. 4.1: every FGMRES-WRMG solve of the paper's heat runs takes three
-    iterations (four at k = 2, q = 3 on the 80 x 80 mesh, outside q <= 1)."""
+    iterations, except four at k = 2, q = 3 on the 80 x 80 mesh."""
     torch = torch_cuda()
     p = w.heat_problem(M, L, k, q)
     its = {}
@@ -135,5 +141,6 @@ def test_heat_paper_three_iterations(M, L, k, q):
         its[prec] = st["linear_total"]
         assert rn <= max(1e-6 * bn, 1e-6) * (1 + 1e-8)
         G.close()
-    log(f"[heat {M}x{M} k={k} q={q}] st-dofs={p.n_st} iterations fp64={its[0]} fp32={its[1]} (paper 3)")
-    assert its[0] == 3 and its[1] == 3
+    want = paper_iterations(M, k, q)
+    log(f"[heat {M}x{M} k={k} q={q}] st-dofs={p.n_st} iterations fp64={its[0]} fp32={its[1]} (paper {want})")
+    assert its[0] == want and its[1] == want
