@@ -145,7 +145,24 @@ typedef struct {
   int32_t newton_ew;           /* 1: Eisenstat-Walker linear tolerances in Newton (see below) */
   double gmres_atol;           /* stwr_fgmres also stops once ||r|| <= gmres_atol (default 0;
                                   the paper's heat runs: rtol 1e-6, atol 1e-6) */
+  int32_t time_chunks;         /* sweeps in time chunks (cyclic reduction in time, below):
+                                  0 = autotuned per level (default), 1 = plain, c = c chunks */
 } stwr_solver_opts;
+
+/* Time chunks (the cyclic reduction in time of Sec. 3.1, single-GPU form).
+ * A patch's sweep is a forward substitution over the N slabs.  With c chunks
+ * of L = ceil(N / c) slabs, every chunk is first swept from zero incoming
+ * slab-end values (all chunks at once), then a small recurrence per patch
+ * carries the true end values across the chunks with the chunk transfer
+ * matrices T = prod (E1 A_n^{-1} E0 M_v) (built with the factors), and the
+ * chunks after the first are swept again from them: 2N - L slab solves and
+ * c small steps instead of N sequential slab solves, in exchange for c times
+ * the parallelism.  The result equals the plain sweep up to rounding.  With
+ * time_chunks = 0, stwr_setup_smoothers times 1, 2, 4, ... chunks (at least
+ * two slabs each) on every level with at most 2048 patches and keeps the
+ * fastest; larger levels keep the plain sweep.  The transfer matrices and end
+ * values take (nv c (b^2 + 2 b)) doubles per level, b = 38 (19 for the heat
+ * equation). */
 
 /* newton_ew = 1 replaces gmres_rtol in Newton's linear solves by Eisenstat and
  * Walker's second forcing term (SIAM J. Sci. Comput. 17, 1996; the paper's
@@ -221,6 +238,10 @@ int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts);
  * Vanka+star patch of each vertex, or its vertex star for the heat
  * equation). */
 int32_t stwr_patch_sizes(const stwr_problem* p, int32_t level, int32_t* nb);
+
+/* Time chunks the sweeps of a level currently use (1 = the plain sweep); the
+ * autotuned count is known after stwr_setup_smoothers. */
+int32_t stwr_level_time_chunks(const stwr_problem* p, int32_t level, int32_t* chunks);
 
 /* Nonlinear space-time residual F(U) of eq. nsfem (level 0), U and F of
  * length n_st(0).  Boundary values are the exact velocity at the temporal

@@ -25,6 +25,7 @@ EXPORTED = [
     "stwr_default_opts", "stwr_ctx_create", "stwr_ctx_destroy", "stwr_ctx_set_stream",
     "stwr_last_error", "stwr_ctx_bytes_in_use", "stwr_problem_bytes", "stwr_mesh_info",
     "stwr_problem_create", "stwr_problem_destroy", "stwr_problem_sizes", "stwr_patch_sizes",
+    "stwr_level_time_chunks",
     "stwr_set_opts",
     "stwr_nonlinear_residual", "stwr_linear_rhs", "stwr_velocity_l2_error", "stwr_expand",
     "stwr_assemble",
@@ -57,7 +58,8 @@ class SolverOpts(ctypes.Structure):
                 ("gmres_restart", ctypes.c_int32), ("gmres_maxit", ctypes.c_int32),
                 ("gmres_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
                 ("newton_rtol", ctypes.c_double), ("vcycle_graph", ctypes.c_int32),
-                ("newton_ew", ctypes.c_int32), ("gmres_atol", ctypes.c_double)]
+                ("newton_ew", ctypes.c_int32), ("gmres_atol", ctypes.c_double),
+                ("time_chunks", ctypes.c_int32)]
 
 
 MAX_NEWTON, MAX_LEVELS = 64, 16
@@ -297,6 +299,11 @@ class Problem:
         nb = np.zeros(self.sizes(level)[2], dtype=np.int32)
         self.ctx.check(self.lib.stwr_patch_sizes(self.h, level, nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return nb
+
+    def time_chunks(self, level=0) -> int:
+        c = ctypes.c_int32()
+        self.ctx.check(self.lib.stwr_level_time_chunks(self.h, level, ctypes.byref(c)))
+        return c.value
 
     def vec(self, level=0):
         import torch

@@ -112,6 +112,12 @@ struct Level {
   size_t fac_budgeted = 0;  // factor bytes already charged to the context
   double lambda = 0.0;
   bool has_lambda = false;
+  // time chunks of the sweeps (cyclic reduction in time): buffers for up to
+  // chunk_cap chunks, and the autotuner's choice once made
+  double* chunk_buf = nullptr;
+  int chunk_cap = 0;
+  size_t chunk_bytes = 0;
+  int chunk_choice = 0;   // 0: not chosen yet
   std::vector<int64_t> fac_off, y_off, mp_off;
   // device arrays
   int *row_ptr = nullptr, *col = nullptr, *cells = nullptr, *cell_p2 = nullptr,
@@ -255,13 +261,20 @@ void check_desc(const stwr_problem_desc* d) {
     throw StwrError(STWR_ERR_ARG, "coarsest level too large for the dense coarse solve (use more levels)");
 }
 
+// time chunks per sweep: at most this many, and the autotuner only tries
+// them on levels with at most kTuneMaxPatches patches (larger levels fill
+// the chip with patches alone, and chunking doubles their block traffic)
+constexpr int kMaxTimeChunks = 64;
+constexpr int kTuneMaxPatches = 2048;
+
 void check_opts(const stwr_solver_opts* o) {
   if (!o) throw StwrError(STWR_ERR_ARG, "null options");
   if (o->nu_pre < 0 || o->nu_post < 0 || o->eig_steps < 1 || o->eig_steps > 64 || o->gmres_restart < 1 ||
       o->gmres_restart > 200 || o->gmres_maxit < 1 || o->newton_maxit < 0 || o->newton_maxit > STWR_MAX_NEWTON ||
       (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
       !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1) ||
-      (o->newton_ew != 0 && o->newton_ew != 1) || !(o->gmres_atol >= 0.0))
+      (o->newton_ew != 0 && o->newton_ew != 1) || !(o->gmres_atol >= 0.0) || o->time_chunks < 0 ||
+      o->time_chunks > kMaxTimeChunks)
     throw StwrError(STWR_ERR_ARG, "invalid solver options");
 }
 
@@ -537,7 +550,83 @@ void patch_factor(stwr_problem* P, int l, int prec) {
   HIPCHK(launch_patch_factor(L.view, L.pview, L.Jv, prec, L.fac, P->dstatus, P->s()));
   HIPCHK(launch_patch_mass(L.view, L.pview, L.Mv, L.Mp, P->s()));
   L.fac_prec = prec;
+  HIPCHK(launch_patch_chunk_transfer(L.view, L.pview, prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, P->s()));
   check_status_flag(P, "patch factorization");
+}
+
+// Split every sweep of level L into nc time chunks (1: the plain sweep; nc is
+// capped at N and rounded so that no chunk is empty).  The chunk buffers
+// (transfer matrices, end values) grow on demand against the budget; the
+// transfer matrices of the current factors are rebuilt.
+void set_time_chunks(stwr_problem* P, Level& L, int nc) {
+  nc = std::max(1, std::min(nc, L.N));
+  const int len = (L.N + nc - 1) / nc;
+  nc = (L.N + len - 1) / len;
+  if (nc > 1 && nc > L.chunk_cap) {
+    const size_t bound = L.H.kdeg > 0 ? kHeatMaxNb : kMaxNbu;
+    const size_t nT = (size_t)L.H.nv * nc * bound * bound, nW = (size_t)L.H.nv * nc * bound;
+    const size_t need = (nT + 2 * nW) * sizeof(double);
+    {
+      std::lock_guard<std::mutex> g(P->ctx->mu);
+      const uint64_t budget = P->ctx->budget;
+      const size_t extra = need - L.chunk_bytes;
+      if (budget && P->ctx->in_use + extra > budget)
+        throw StwrError(STWR_ERR_BUDGET, "time-chunk buffers exceed the HBM budget");
+      P->ctx->in_use += extra;
+      P->bytes += extra;
+    }
+    if (L.chunk_buf) P->release(L.chunk_buf);
+    L.chunk_buf = P->alloc<double>(nT + 2 * nW);
+    L.chunk_bytes = need;
+    L.chunk_cap = nc;
+    L.pview.chunk_T = L.chunk_buf;
+    L.pview.chunk_w_end = L.chunk_buf + nT;
+    L.pview.chunk_w_in = L.chunk_buf + nT + nW;
+  }
+  L.pview.time_chunks = nc;
+  L.pview.chunk_len = len;
+  if (nc > 1 && L.fac_prec >= 0)
+    HIPCHK(launch_patch_chunk_transfer(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, P->s()));
+}
+
+// Time chunks of level l: the options' fixed count, or (time_chunks = 0) the
+// fastest of 1, 2, 4, ... chunks (at least two slabs each) by timing three
+// sweeps of each with HIP events, chosen once per level; levels with more
+// than kTuneMaxPatches patches keep the plain sweep.
+void tune_time_chunks(stwr_problem* P, int l) {
+  Level& L = P->lv[l];
+  const int want = P->opts.time_chunks;
+  if (want >= 1) { set_time_chunks(P, L, want); return; }
+  if (L.chunk_choice > 0) { set_time_chunks(P, L, L.chunk_choice); return; }
+  if (L.H.nv > kTuneMaxPatches || L.N < 4) {
+    L.chunk_choice = 1;
+    set_time_chunks(P, L, 1);
+    return;
+  }
+  HIPCHK(launch_fill(L.n_st, 0.0, L.r, P->s()));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = 1;
+  float best_ms = 0.0f;
+  for (int c = 1; c <= L.N / 2 && c <= kMaxTimeChunks; c *= 2) {
+    set_time_chunks(P, L, c);
+    auto sweep = [&]() {
+      HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, L.r, L.Y, P->s()));
+    };
+    sweep();
+    HIPCHK(hipEventRecord(e0, P->s()));
+    for (int k = 0; k < 3; ++k) sweep();
+    HIPCHK(hipEventRecord(e1, P->s()));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (c == 1 || ms < 0.97f * best_ms) { best = c; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  L.chunk_choice = best;
+  set_time_chunks(P, L, best);
 }
 
 void patch_apply(stwr_problem* P, int l, const double* r, double* z) {
@@ -630,6 +719,9 @@ std::vector<double> vcycle_signature(stwr_problem* P) {
     s.push_back(L.lambda);
     s.push_back((double)L.fac_prec);
     s.push_back((double)(uintptr_t)L.fac);
+    s.push_back((double)L.pview.time_chunks);
+    s.push_back((double)L.pview.chunk_len);
+    s.push_back((double)(uintptr_t)L.chunk_buf);
   }
   return s;
 }
@@ -834,6 +926,7 @@ void residual(stwr_problem* P, const double* U, double* F) {
 void setup_smoothers(stwr_problem* P) {
   for (int l = 0; l + 1 < (int)P->lv.size(); ++l) {
     patch_factor(P, l, P->opts.smoother_prec);
+    tune_time_chunks(P, l);
     eig_estimate(P, l);
   }
 }
@@ -941,6 +1034,7 @@ int32_t stwr_default_opts(stwr_solver_opts* o) {
   o->vcycle_graph = 1;
   o->newton_ew = 0;
   o->gmres_atol = 0.0;
+  o->time_chunks = 0;
   return STWR_OK;
 }
 
@@ -1177,6 +1271,13 @@ int32_t stwr_patch_sizes(const stwr_problem* p, int32_t level, int32_t* nb) {
   return STWR_OK;
 }
 
+int32_t stwr_level_time_chunks(const stwr_problem* p, int32_t level, int32_t* chunks) {
+  if (!p || !chunks || level < 0 || level >= (int)p->lv.size()) return STWR_ERR_ARG;
+  const int c = p->lv[level].pview.time_chunks;
+  *chunks = c > 1 ? c : 1;
+  return STWR_OK;
+}
+
 int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts) {
   if (!p) return STWR_ERR_ARG;
   return guarded(p->ctx, [&]() -> int32_t {
@@ -1184,6 +1285,8 @@ int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts) {
     if (opts->gmres_restart != p->restart) throw StwrError(STWR_ERR_ARG, "gmres_restart is fixed at creation");
     if (opts->smoother_prec != p->opts.smoother_prec)
       for (auto& L : p->lv) { L.fac_prec = -1; L.has_lambda = false; }
+    if (opts->time_chunks != p->opts.time_chunks || opts->smoother_prec != p->opts.smoother_prec)
+      for (auto& L : p->lv) L.chunk_choice = 0;
     p->opts = *opts;
     return STWR_OK;
   });

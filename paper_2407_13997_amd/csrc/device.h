@@ -56,6 +56,16 @@ struct LevelView {
   int nbord;             // constraint rows bordering a coarsest slab block: q+1 with pressure, else 0
 };
 
+// Time chunks of one sweep (see k_patch_sweep): chunk c covers slabs
+// [c len, min(N, (c+1) len)); outputs are written for chunks <= y_max;
+// w_in / w_end: incoming and final slab-end values, [patch][chunk][bound]
+// (bound: kMaxNbu, or kHeatMaxNb for the heat equation), or null.
+struct ChunkArgs {
+  int len, first, y_max, n_chunks;
+  const double* w_in;
+  double* w_end;
+};
+
 struct PatchView {
   int n_patch;
   const int* patch_ptr;
@@ -73,6 +83,13 @@ struct PatchView {
   const int* order;         // n_patch, by decreasing size: interior (full-size) patches first
   int n_full;               // number of full-size patches at the front of order
   int n_big;                // number of patches with (q+1) nb > 64 at the front of order
+  // cyclic reduction in time: time_chunks > 1 splits every sweep into that
+  // many chunks of chunk_len slabs (buffers as in ChunkArgs; chunk_T holds
+  // the chunk transfer matrices, [patch][chunk][bound^2])
+  int time_chunks, chunk_len;
+  const double* chunk_T;
+  double* chunk_w_end;
+  double* chunk_w_in;
 };
 
 // Storage of one inverted m x m slab block for the patch sweep, in T-typed
@@ -176,6 +193,14 @@ hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const doubl
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, void* Y, hipStream_t s);
+// Chunk transfer matrices of the current factors (time_chunks > 1 only).
+hipError_t launch_patch_chunk_transfer(const LevelView& L, const PatchView& P, int prec, const void* fac,
+                                       const double* Mp, const double* e0, const double* e1,
+                                       hipStream_t s);
+// Whether the sweep leaves FP32 outputs (the gather reads them as such).
+inline bool sweep_outputs_f32(const LevelView& L, const PatchView& P, int prec) {
+  return prec == 1 && L.kdeg == 0 && P.time_chunks <= 1;
+}
 // mode 0: z = sum; mode 1: d = c1 d + c2 sum, x += d.
 hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,
                                int mode, double c1, double c2, double* z, double* d, double* x,

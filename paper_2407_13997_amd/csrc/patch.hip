@@ -16,6 +16,8 @@
 // * k_patch_gather: each DoF sums its contributions from the <= 7 patches that
 //   hold it in a fixed order (deterministic additive scatter), optionally
 //   fused with the Chebyshev update d = c1 d + c2 z, x += d.
+#include <climits>
+
 #include "device.h"
 
 namespace stwr {
@@ -522,12 +524,18 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
 // the residual values of slab n + 1 are loaded too.  The jump coupling
 // mj = M_v (e1 . y_{n-1}) is formed once per velocity DoF at the end of the
 // previous slab.
+//
+// Time chunks (cyclic reduction in time): blockIdx.y + ca.first is the chunk
+// c, covering slabs [c len, min(N, (c + 1) len)).  The chunk's sweep starts
+// from the incoming slab-end values w_in of the previous chunk (none: zero)
+// and may leave its own final slab-end values in w_end; outputs are written
+// for chunks c <= y_max.  One chunk of length N is the plain sweep.
 template <int NQ, typename T, int WAVES, int NBMAX = kMaxNb, int NBUMAX = kMaxNbu>
 __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchView P,
                                                             const T* __restrict__ fac,
                                                             const double* __restrict__ Mp,
                                                             TimeEnds te, const double* __restrict__ r,
-                                                            double* __restrict__ Y) {
+                                                            double* __restrict__ Y, ChunkArgs ca) {
   constexpr int MAXM = NBMAX * NQ;
   constexpr int VW = Vec<T>::W;
   constexpr int MAXP = (MAXM + VW - 1) / VW;
@@ -547,13 +555,26 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0, nbu = P.patch_nbu[p];
   const int m = nb * NQ, N = L.N;
+  const int chunk = ca.first + (int)blockIdx.y;
+  const int n0 = chunk * ca.len, n1 = n0 + ca.len < N ? n0 + ca.len : N;
+  if (n0 >= N) return;   // uniform over the workgroup
+  const bool write_y = chunk <= ca.y_max;
   const BlockLayout lay(m, VW);
   const int PH = lay.panels(w), r1 = lay.r1, r2 = lay.r2;
   for (int i = tid; i < nb; i += 64 * WAVES) dofs[i] = P.patch_dofs[s0 + i];
   const double* mp = Mp + P.mp_off[p];
   for (int e = tid; e < nbu * nbu; e += 64 * WAVES) Ms[e] = mp[e];
-  for (int i = tid; i < NBUMAX; i += 64 * WAVES) mj[i] = 0.0;
   for (int i = tid; i < WAVES * PW * VW; i += 64 * WAVES) g[i] = (T)0;
+  __syncthreads();
+  // coupling into the chunk's first slab: M_v times the incoming end values
+  for (int i = tid; i < NBUMAX; i += 64 * WAVES) {
+    double acc = 0.0;
+    if (ca.w_in && n0 > 0 && i < nbu) {
+      const double* wi = ca.w_in + ((int64_t)p * ca.n_chunks + chunk) * NBUMAX;
+      for (int j = 0; j < nbu; ++j) acc += Ms[i * nbu + j] * wi[j];
+    }
+    mj[i] = acc;
+  }
   __syncthreads();
   const int64_t S = P.slab_stride;
   const T* Ab = fac + P.fac_off[p];
@@ -573,23 +594,26 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   const int64_t rbase = hasRow ? (int64_t)dofs[tid / NQ] * N * NQ + tid % NQ : 0;
   const int ia = tid / NQ, aa = tid % NQ;
   V cur1[PW], nxt1[PW], cur2[K2], nxt2[K2];
+  {
+    const T* blk0 = Ab + (int64_t)n0 * S;
 #pragma unroll
-  for (int q = 0; q < PW; ++q) cur1[q] = *reinterpret_cast<const V*>(Ab + O1(q));
-  if constexpr (kTwo) {
+    for (int q = 0; q < PW; ++q) cur1[q] = *reinterpret_cast<const V*>(blk0 + O1(q));
+    if constexpr (kTwo) {
 #pragma unroll
-    for (int k = 0; k < K2; ++k) cur2[k] = *reinterpret_cast<const V*>(Ab + O2(k));
+      for (int k = 0; k < K2; ++k) cur2[k] = *reinterpret_cast<const V*>(blk0 + O2(k));
+    }
   }
-  double rcur = hasRow ? r[rbase] : 0.0;
+  double rcur = hasRow ? r[rbase + (int64_t)n0 * NQ] : 0.0;
   const int quarter = lane & 3;
-  for (int n = 0; n < N; ++n) {
-    const T* nblk = Ab + (int64_t)(n + 1 < N ? n + 1 : n) * S;
+  for (int n = n0; n < n1; ++n) {
+    const T* nblk = Ab + (int64_t)(n + 1 < n1 ? n + 1 : n) * S;
 #pragma unroll
     for (int q = 0; q < PW; ++q) nxt1[q] = *reinterpret_cast<const V*>(nblk + O1(q));
     if constexpr (kTwo) {
 #pragma unroll
       for (int k = 0; k < K2; ++k) nxt2[k] = *reinterpret_cast<const V*>(nblk + O2(k));
     }
-    const double rnext = (hasRow && n + 1 < N) ? r[rbase + (int64_t)(n + 1) * NQ] : 0.0;
+    const double rnext = (hasRow && n + 1 < n1) ? r[rbase + (int64_t)(n + 1) * NQ] : 0.0;
     if (hasRow) {
       double gv = rcur;
       if (n > 0 && ia < nbu) gv += e0[aa] * mj[ia];
@@ -623,7 +647,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
 #pragma unroll
       for (int v = 0; v < WAVES; ++v) y += v < lay.waves ? part[v][tid] : 0.0;
       ys[tid] = y;
-      yout[(int64_t)n * m + tid] = y;
+      if (write_y) yout[(int64_t)n * m + tid] = y;
     }
     __syncthreads();
     if (tid < nbu) {
@@ -646,8 +670,91 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
     }
     rcur = rnext;
   }
+  // the chunk's final slab-end values (ys holds its last slab)
+  if (ca.w_end && tid < nbu) {
+    double v = 0.0;
+    for (int b = 0; b < NQ; ++b) v += e1[b] * ys[tid * NQ + b];
+    ca.w_end[((int64_t)p * ca.n_chunks + chunk) * NBUMAX + tid] = v;
+  }
 #undef O1
 #undef O2
+}
+
+// Transfer of slab-end values across a time chunk: with
+// K_n = E1 A_n^{-1} E0 (K[i][k] = sum_ab e1[b] A_n^{-1}(i q1 + b, k q1 + a) e0[a])
+// the end values obey w_n = K_n (M_v w_{n-1}) + (E1 A_n^{-1} r_n), so a chunk
+// maps its incoming values by T_c = K_{n1-1} M_v ... K_{n0} M_v.  One
+// workgroup per (patch, chunk); T_c in FP64, nbu x nbu in a slot of NBUMAX^2.
+template <int NQ, typename T, int NBUMAX>
+__global__ __launch_bounds__(256) void k_patch_chunk_transfer(LevelView L, PatchView P,
+                                                              const T* __restrict__ fac,
+                                                              const double* __restrict__ Mp,
+                                                              TimeEnds te, ChunkArgs ca,
+                                                              double* __restrict__ Tc) {
+  __shared__ double Ms[NBUMAX * NBUMAX], Tm[NBUMAX * NBUMAX], Q[NBUMAX * NBUMAX], K[NBUMAX * NBUMAX];
+  constexpr int VW = Vec<T>::W;
+  const int p = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const int nb = P.patch_ptr[p + 1] - P.patch_ptr[p], nbu = P.patch_nbu[p];
+  const int m = nb * NQ, N = L.N;
+  const int n0 = c * ca.len, n1 = n0 + ca.len < N ? n0 + ca.len : N;
+  const BlockLayout lay(m, VW);
+  const double* mp = Mp + P.mp_off[p];
+  const int nn = nbu * nbu;
+  for (int e = tid; e < nn; e += 256) {
+    Ms[e] = mp[e];
+    Tm[e] = (e / nbu == e % nbu) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int n = n0; n < n1; ++n) {
+    const T* blk = fac + P.fac_off[p] + (int64_t)n * P.slab_stride;
+    for (int e = tid; e < nn; e += 256) {
+      const int i = e / nbu, j = e % nbu;
+      double q = 0.0, k = 0.0;
+      for (int t = 0; t < nbu; ++t) q += Ms[i * nbu + t] * Tm[t * nbu + j];
+      for (int b = 0; b < NQ; ++b)
+        for (int a = 0; a < NQ; ++a) k += te.e1[b] * (double)blk[lay.at(i * NQ + b, j * NQ + a)] * te.e0[a];
+      Q[e] = q;
+      K[e] = k;
+    }
+    __syncthreads();
+    for (int e = tid; e < nn; e += 256) {
+      const int i = e / nbu, j = e % nbu;
+      double v = 0.0;
+      for (int t = 0; t < nbu; ++t) v += K[i * nbu + t] * Q[t * nbu + j];
+      Tm[e] = v;
+    }
+    __syncthreads();
+  }
+  double* out = Tc + ((int64_t)p * ca.n_chunks + c) * NBUMAX * NBUMAX;
+  for (int e = tid; e < nn; e += 256) out[e] = Tm[e];
+}
+
+// Incoming end values of every chunk: w_in(0) = 0 and
+// w_in(c) = w_end0(c-1) + T_{c-1} w_in(c-1), with w_end0 the chunk ends of
+// the sweep from zero incoming values.  One wavefront per patch.
+template <int NBUMAX>
+__global__ __launch_bounds__(64) void k_patch_chunk_interface(PatchView P, ChunkArgs ca,
+                                                              const double* __restrict__ Tc,
+                                                              const double* __restrict__ w_end0,
+                                                              double* __restrict__ w_in) {
+  __shared__ double wv[NBUMAX];
+  const int p = blockIdx.x, tid = threadIdx.x, nbu = P.patch_nbu[p];
+  if (tid < NBUMAX) wv[tid] = 0.0;
+  __syncthreads();
+  for (int c = 1; c < ca.n_chunks; ++c) {
+    double v = 0.0;
+    if (tid < nbu) {
+      const double* t = Tc + ((int64_t)p * ca.n_chunks + c - 1) * NBUMAX * NBUMAX + tid * nbu;
+      v = w_end0[((int64_t)p * ca.n_chunks + c - 1) * NBUMAX + tid];
+      for (int j = 0; j < nbu; ++j) v += t[j] * wv[j];
+    }
+    __syncthreads();
+    if (tid < nbu) {
+      wv[tid] = v;
+      w_in[((int64_t)p * ca.n_chunks + c) * NBUMAX + tid] = v;
+    }
+    __syncthreads();
+  }
 }
 
 // Y: FP64 patch outputs at y_off, or FP32 ones at twice y_off (same bytes)
@@ -742,50 +849,113 @@ hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const doubl
   return hipGetLastError();
 }
 
+// The generic sweep over all patches, as one launch or, with time chunks,
+// as the chunked passes: every chunk from zero incoming values (outputs of
+// chunk 0, end values of every chunk), the interface recurrence, then the
+// chunks after the first from their true incoming values.
+template <int NQ, typename T, int WAVES, int NBMAX, int NBUMAX>
+hipError_t sweep_generic(const LevelView& L, const PatchView& P, const void* fac, const double* Mp,
+                         TimeEnds te, const double* r, double* Y, hipStream_t s) {
+  const T* f = (const T*)fac;
+  const dim3 block(64 * WAVES);
+  const int nc = P.time_chunks > 1 ? P.time_chunks : 1;
+  if (nc == 1) {
+    const ChunkArgs ca{L.N, 0, INT_MAX, 1, nullptr, nullptr};
+    hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, NBMAX, NBUMAX>), dim3(P.n_patch), block, 0, s, L, P, f, Mp, te, r, Y, ca);
+    return hipGetLastError();
+  }
+  const ChunkArgs a{P.chunk_len, 0, 0, nc, nullptr, P.chunk_w_end};
+  hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, NBMAX, NBUMAX>), dim3(P.n_patch, nc), block, 0, s, L, P, f, Mp, te, r, Y, a);
+  const ChunkArgs ci{P.chunk_len, 0, 0, nc, nullptr, nullptr};
+  hipLaunchKernelGGL((k_patch_chunk_interface<NBUMAX>), dim3(P.n_patch), dim3(64), 0, s, P, ci, P.chunk_T, P.chunk_w_end, P.chunk_w_in);
+  const ChunkArgs c{P.chunk_len, 1, INT_MAX, nc, P.chunk_w_in, nullptr};
+  hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, NBMAX, NBUMAX>), dim3(P.n_patch, nc - 1), block, 0, s, L, P, f, Mp, te, r, Y, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, void* Y, hipStream_t s) {
-  const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
-  dim3 grid(P.n_patch);
-  // wavefronts per patch = panels of the largest block / kPanelsPerWave
+  const TimeEnds te = time_ends(L.NQ, e0, e1);
+  double* Yd = (double*)Y;
   if (L.kdeg > 0) {
     // scalar heat patches (at most kHeatMaxNb DoFs, (q+1) kHeatMaxNb rows):
     // a wavefront's threads form up to 64 rows and hold up to 20 FP32 or 10
     // FP64 column panels; outputs stay FP64
     constexpr int H = kHeatMaxNb;
-    const TimeEnds te = time_ends(L.NQ, e0, e1);
-    const float* ff = (const float*)fac;
-    const double* fd = (const double*)fac;
-    double* Yd = (double*)Y;
     if (prec == 1) {
       switch (L.NQ) {
-        case 1: hipLaunchKernelGGL((k_patch_sweep<1, float, 1, H, H>), grid, dim3(64), 0, s, L, P, ff, Mp, te, r, Yd); break;
-        case 2: hipLaunchKernelGGL((k_patch_sweep<2, float, 1, H, H>), grid, dim3(64), 0, s, L, P, ff, Mp, te, r, Yd); break;
-        case 3: hipLaunchKernelGGL((k_patch_sweep<3, float, 1, H, H>), grid, dim3(64), 0, s, L, P, ff, Mp, te, r, Yd); break;
-        case 4: hipLaunchKernelGGL((k_patch_sweep<4, float, 2, H, H>), grid, dim3(128), 0, s, L, P, ff, Mp, te, r, Yd); break;
-        default: return hipErrorInvalidValue;
-      }
-    } else {
-      switch (L.NQ) {
-        case 1: hipLaunchKernelGGL((k_patch_sweep<1, double, 1, H, H>), grid, dim3(64), 0, s, L, P, fd, Mp, te, r, Yd); break;
-        case 2: hipLaunchKernelGGL((k_patch_sweep<2, double, 2, H, H>), grid, dim3(128), 0, s, L, P, fd, Mp, te, r, Yd); break;
-        case 3: hipLaunchKernelGGL((k_patch_sweep<3, double, 3, H, H>), grid, dim3(192), 0, s, L, P, fd, Mp, te, r, Yd); break;
-        case 4: hipLaunchKernelGGL((k_patch_sweep<4, double, 4, H, H>), grid, dim3(256), 0, s, L, P, fd, Mp, te, r, Yd); break;
+        case 1: return sweep_generic<1, float, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 2: return sweep_generic<2, float, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 3: return sweep_generic<3, float, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 4: return sweep_generic<4, float, 2, H, H>(L, P, fac, Mp, te, r, Yd, s);
         default: return hipErrorInvalidValue;
       }
     }
-  } else if (prec == 1) {
+    switch (L.NQ) {
+      case 1: return sweep_generic<1, double, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 2: return sweep_generic<2, double, 2, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 3: return sweep_generic<3, double, 3, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 4: return sweep_generic<4, double, 4, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (prec == 1 && P.time_chunks > 1) {
+    // chunked FP32 Navier-Stokes sweeps take the generic kernel (FP64 outputs)
+    if (L.NQ == 1) return sweep_generic<1, float, 1, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+    return sweep_generic<2, float, 2, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+  }
+  if (prec == 1) {
+    const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
+    dim3 grid(P.n_patch);
     if (L.NQ == 1) {
       hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     } else {
       hipLaunchKernelGGL(k_patch_sweep_f32<2>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     }
-  } else {
-    const TimeEnds te = time_ends(L.NQ, e0, e1);
-    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep<1, double, 2>), grid, dim3(128), 0, s, L, P, (const double*)fac, Mp, te, r, (double*)Y);
-    else hipLaunchKernelGGL((k_patch_sweep<2, double, 4>), grid, dim3(256), 0, s, L, P, (const double*)fac, Mp, te, r, (double*)Y);
+    return hipGetLastError();
   }
+  if (L.NQ == 1) return sweep_generic<1, double, 2, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+  return sweep_generic<2, double, 4, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+}
+
+template <int NQ, typename T, int NBUMAX>
+hipError_t chunk_transfer(const LevelView& L, const PatchView& P, const void* fac, const double* Mp,
+                          TimeEnds te, hipStream_t s) {
+  const ChunkArgs ca{P.chunk_len, 0, 0, P.time_chunks, nullptr, nullptr};
+  hipLaunchKernelGGL((k_patch_chunk_transfer<NQ, T, NBUMAX>), dim3(P.n_patch, P.time_chunks), dim3(256), 0, s, L, P,
+                     (const T*)fac, Mp, te, ca, (double*)P.chunk_T);
   return hipGetLastError();
+}
+
+hipError_t launch_patch_chunk_transfer(const LevelView& L, const PatchView& P, int prec, const void* fac,
+                                       const double* Mp, const double* e0, const double* e1,
+                                       hipStream_t s) {
+  if (P.time_chunks <= 1) return hipSuccess;
+  const TimeEnds te = time_ends(L.NQ, e0, e1);
+  constexpr int H = kHeatMaxNb;
+  if (L.kdeg > 0) {
+    if (prec == 1) {
+      switch (L.NQ) {
+        case 1: return chunk_transfer<1, float, H>(L, P, fac, Mp, te, s);
+        case 2: return chunk_transfer<2, float, H>(L, P, fac, Mp, te, s);
+        case 3: return chunk_transfer<3, float, H>(L, P, fac, Mp, te, s);
+        case 4: return chunk_transfer<4, float, H>(L, P, fac, Mp, te, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
+    switch (L.NQ) {
+      case 1: return chunk_transfer<1, double, H>(L, P, fac, Mp, te, s);
+      case 2: return chunk_transfer<2, double, H>(L, P, fac, Mp, te, s);
+      case 3: return chunk_transfer<3, double, H>(L, P, fac, Mp, te, s);
+      case 4: return chunk_transfer<4, double, H>(L, P, fac, Mp, te, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (prec == 1) return L.NQ == 1 ? chunk_transfer<1, float, kMaxNbu>(L, P, fac, Mp, te, s)
+                                  : chunk_transfer<2, float, kMaxNbu>(L, P, fac, Mp, te, s);
+  return L.NQ == 1 ? chunk_transfer<1, double, kMaxNbu>(L, P, fac, Mp, te, s)
+                   : chunk_transfer<2, double, kMaxNbu>(L, P, fac, Mp, te, s);
 }
 
 hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,
@@ -793,7 +963,7 @@ hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec,
                                hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (prec == 1 && L.kdeg == 0) {
+  if (sweep_outputs_f32(L, P, prec)) {
     const float* Yf = (const float*)Y;
     if (L.NQ == 1) hipLaunchKernelGGL((k_patch_gather<1, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
     else hipLaunchKernelGGL((k_patch_gather<2, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
