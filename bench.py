@@ -228,6 +228,8 @@ def main():
         log(f"[bench] paper context: {out['paper_context']}")
         out["paper_context"]["heat"] = heat_context()
         log(f"[bench] heat context: {out['paper_context']['heat']}")
+        out["time_chunks"] = time_chunk_context()
+        log(f"[bench] time chunks: {out['time_chunks']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
@@ -422,6 +424,49 @@ def heat_context(sweep_steps: int = 20, runs_too: bool = True) -> dict:
                                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                                    "kernel": "k_patch_sweep (FP32 blocks, FP64 outputs)",
                                    "avg_ms": sweep_ms, "algorithmic_bytes": algo}}}
+
+
+def time_chunk_context(steps: int = 10) -> list:
+    """Cyclic reduction in time on small meshes with long time axes (the
+    uneven-batch distribution's small end: P2-P1 x DG(1), 128 slabs, Re 10):
+    finest-level sweep time of the plain sweep and of the autotuned chunking,
+    FP64 and FP32 factors."""
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    ctx = binding.Context(0)
+    rows = []
+    for M in (4, 8, 16):
+        prob = w.small_problem(M, 2, 1, 128, 10.0, 103)
+        for prec in (binding.FP64, binding.FP32):
+            t = {}
+            for chunks in (1, 0):
+                o = binding.default_opts()
+                o.smoother_prec = prec
+                o.time_chunks = chunks
+                P = binding.Problem(ctx, prob, o)
+                U = P.vec()
+                P.assemble(U)
+                P.setup_smoothers()
+                lam = P.eig_estimate(0)
+                g = torch.Generator(device="cpu").manual_seed(4200)
+                b = torch.randn(P.sizes(0)[0], generator=g, dtype=torch.float64).to("cuda")
+                x = P.vec()
+                P.relax(0, b, x, 2, 0.25 * lam, 1.05 * lam)
+                ctx.set_timing(True)
+                ctx.kernel_times()
+                for _ in range(steps):
+                    P.relax(0, b, x, 1, 0.25 * lam, 1.05 * lam)
+                kt = ctx.kernel_times()
+                ctx.set_timing(False)
+                t[chunks] = (kt["sweep"][0] / steps, P.time_chunks(0))
+                P.close()
+            rows.append({"mesh": M, "slabs": 128, "patches": (M + 1) ** 2,
+                         "smoother_prec": "fp32" if prec == binding.FP32 else "fp64",
+                         "plain_sweep_ms": t[1][0], "tuned_sweep_ms": t[0][0], "tuned_chunks": t[0][1],
+                         "speedup": t[1][0] / t[0][0]})
+    ctx.close()
+    return rows
 
 
 def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:
