@@ -127,6 +127,7 @@ struct Level {
       *dof_ptr = nullptr, *dof_slot = nullptr, *slot_patch = nullptr;
   int64_t *patch_nz_off = nullptr, *d_fac_off = nullptr, *d_y_off = nullptr, *d_mp_off = nullptr;
   double *Jv = nullptr, *Mv = nullptr, *Mp = nullptr, *Y = nullptr;
+  double* Kv = nullptr;   // heat equation: spatial stiffness values
   void* fac = nullptr;
   size_t fac_bytes = 0;
   int *P_ptr = nullptr, *P_col = nullptr, *R_ptr = nullptr, *R_col = nullptr, *inject = nullptr;
@@ -286,8 +287,14 @@ int round_up(int m, int w) { return (m + w - 1) / w * w; }
 // every 1 KiB wavefront load inside it, starts on a cache-line boundary.
 int64_t block_elems(int m, int VW) { return round_up(BlockLayout(m, VW).size(), 16 * VW); }
 
+// Slabs with their own patch blocks: the heat operator is the same on every
+// slab (uniform slabs, time-independent coefficients), so its blocks are
+// factored once and read for every slab.
+int fac_slabs_of(const HostLevel& H, int N) { return H.kdeg > 0 ? 1 : N; }
+
 // Element count of the factor storage of one level at a precision.
 int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
+  N = fac_slabs_of(H, N);
   int64_t tot = 0;
   for (int v = 0; v < H.nv; ++v) {
     const int m = (H.patch_ptr[v + 1] - H.patch_ptr[v]) * NQ;
@@ -310,6 +317,7 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
   const int64_t n_st = (int64_t)H.nf * N * NQ;
   uint64_t b = 0;
   b += (uint64_t)nnz * N * NQ * NQ * 8 + nnz * 8;                       // Jv, Mv
+  if (H.kdeg > 0) b += (uint64_t)nnz * 8;                               // Kv
   b += (uint64_t)(H.nf + 1 + nnz) * 4;                                  // CSR
   b += (uint64_t)(H.cells.size() + H.cell_p2.size() + H.cell_dofs.size() + H.cell_nz.size() +
                  H.node_free.size() + H.node_cell_ptr.size() + H.node_cell.size()) * 4;   // cell maps
@@ -378,6 +386,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   const int64_t nnz = H.row_ptr[H.nf];
   L.Jv = P->alloc<double>((size_t)nnz * L.N * L.NQ * L.NQ);
   L.Mv = P->alloc<double>((size_t)nnz);
+  if (H.kdeg > 0) L.Kv = P->alloc<double>((size_t)nnz);
   L.r = P->alloc<double>(L.n_st);
   L.d = P->alloc<double>(L.n_st);
   L.x = P->alloc<double>(L.n_st);
@@ -394,6 +403,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   // patches (the coarsest level is solved directly and needs none)
   PatchView& pv = L.pview;
   pv.n_patch = H.nv;
+  pv.fac_slabs = fac_slabs_of(H, L.N);
   if (!coarsest) {
     L.patch_ptr = P->upload(H.patch_ptr);
     L.patch_dofs = P->upload(H.patch_dofs);
@@ -486,7 +496,7 @@ void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
     const int m = (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ;
     L.fac_off[v + 1] = L.fac_off[v] + block_elems(m, vw_of(prec));
   }
-  L.pview.slab_stride = L.fac_off[L.H.nv];
+  L.pview.slab_stride = L.pview.fac_slabs == 1 ? 0 : L.fac_off[L.H.nv];
   HIPCHK(hipMemcpyAsync(L.d_fac_off, L.fac_off.data(), L.fac_off.size() * 8, hipMemcpyHostToDevice, P->s()));
 }
 
@@ -526,6 +536,10 @@ double norm_host(stwr_problem* P, int64_t n, const double* x) {
 void spmv(stwr_problem* P, int l, const double* x, const double* b, double* y) {
   Level& L = P->lv[l];
   KernelMark mark(P->ctx, 1);
+  if (P->heat()) {
+    HIPCHK(launch_heat_spmv(L.view, P->d_tab, L.Mv, L.Kv, x, b, y, P->s()));
+    return;
+  }
   HIPCHK(launch_spmv(L.view, L.Jv, L.Mv, P->tab.e0, P->tab.e1, x, b, y, P->s()));
 }
 
@@ -884,7 +898,7 @@ void assemble(stwr_problem* P, const double* U) {
     Level& Lv = P->lv[l];
     if (P->heat()) {
       // linear and state-independent: every entry is written
-      HIPCHK(launch_heat_operator(Lv.view, P->d_tab, Lv.Jv, Lv.Mv, P->s()));
+      HIPCHK(launch_heat_operator(Lv.view, P->d_tab, Lv.Jv, Lv.Mv, Lv.Kv, P->s()));
       Lv.fac_prec = -1;
       Lv.has_lambda = false;
       continue;

@@ -462,7 +462,8 @@ __global__ __launch_bounds__(256) void k_expand(LevelView L, const RefTables* __
 // the P_k basis at the 25 quadrature points; then every slab's block
 // T (x) M + dt W (x) K is written, and Mv = M.  One thread per row.
 __global__ __launch_bounds__(256) void k_heat_operator(LevelView L, const RefTables* __restrict__ T,
-                                                       double* __restrict__ Jv, double* __restrict__ Mv) {
+                                                       double* __restrict__ Jv, double* __restrict__ Mv,
+                                                       double* __restrict__ Kv) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= L.nf) return;
   const int nloc = L.nloc, NQ = T->NQ, N = L.N;
@@ -498,10 +499,51 @@ __global__ __launch_bounds__(256) void k_heat_operator(LevelView L, const RefTab
       st += ke;
     }
     Mv[k] = m;
+    Kv[k] = st;
     double* out = Jv + (int64_t)k * N * NQ * NQ;
     for (int n = 0; n < N; ++n)
       for (int a = 0; a < NQ; ++a)
         for (int b = 0; b < NQ; ++b) out[(n * NQ + a) * NQ + b] = T->T[a][b] * m + L.dt * T->W[a][b] * st;
+  }
+}
+
+// y = A x (or b - A x) of the heat equation, one thread per (row, slab):
+// the spatial products M x_n and K x_n per temporal node, then the slab's
+// temporal matrices, minus the jump coupling to slab n-1
+template <int NQ>
+__global__ __launch_bounds__(256) void k_heat_spmv(LevelView L, const RefTables* __restrict__ T,
+                                                   const double* __restrict__ Mv,
+                                                   const double* __restrict__ Kv,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ b,
+                                                   double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int N = L.N;
+  if (t >= (int64_t)L.nf * N) return;
+  const int i = (int)(t / N), n = (int)(t % N);
+  double mx[NQ], kx[NQ];
+  for (int a = 0; a < NQ; ++a) mx[a] = kx[a] = 0.0;
+  double jump = 0.0;
+  for (int k = L.row_ptr[i]; k < L.row_ptr[i + 1]; ++k) {
+    const double* xv = x + ((int64_t)L.col[k] * N + n) * NQ;
+    const double m = Mv[k], st = Kv[k];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+      mx[a] += m * xv[a];
+      kx[a] += st * xv[a];
+    }
+    if (n > 0) {
+      double xl = 0.0;
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) xl += T->e1[a] * xv[a - NQ];
+      jump += m * xl;
+    }
+  }
+  for (int a = 0; a < NQ; ++a) {
+    double out = -T->e0[a] * jump;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) out += T->T[a][c] * mx[c] + L.dt * T->W[a][c] * kx[c];
+    y[t * NQ + a] = b ? b[t * NQ + a] - out : out;
   }
 }
 
@@ -528,8 +570,22 @@ __global__ __launch_bounds__(256) void k_heat_rhs(LevelView L, const RefTables* 
 }  // namespace
 
 hipError_t launch_heat_operator(const LevelView& L, const RefTables* tab, double* Jv, double* Mv,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_heat_operator, dim3((unsigned)((L.nf + 255) / 256)), dim3(256), 0, s, L, tab, Jv, Mv);
+                                double* Kv, hipStream_t s) {
+  hipLaunchKernelGGL(k_heat_operator, dim3((unsigned)((L.nf + 255) / 256)), dim3(256), 0, s, L, tab, Jv, Mv, Kv);
+  return hipGetLastError();
+}
+
+hipError_t launch_heat_spmv(const LevelView& L, const RefTables* tab, const double* Mv,
+                            const double* Kv, const double* x, const double* b, double* y,
+                            hipStream_t s) {
+  const dim3 grid((unsigned)(((int64_t)L.nf * L.N + 255) / 256));
+  switch (L.NQ) {
+    case 1: hipLaunchKernelGGL(k_heat_spmv<1>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+    case 2: hipLaunchKernelGGL(k_heat_spmv<2>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+    case 3: hipLaunchKernelGGL(k_heat_spmv<3>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+    case 4: hipLaunchKernelGGL(k_heat_spmv<4>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

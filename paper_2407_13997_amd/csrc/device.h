@@ -75,6 +75,8 @@ struct PatchView {
   const int* patch_nz;
   const int64_t* fac_off;   // n_patch + 1, element offset of each patch's block inside a slab
   int64_t slab_stride;      // elements of one slab's blocks (all patches): blocks are [slab][patch]
+  int fac_slabs;            // slabs with their own blocks: N, or 1 when every slab's blocks are
+                            // the same (the heat equation; slab_stride is then 0)
   const int64_t* y_off;     // n_patch + 1, offsets into the patch output buffer
   const int64_t* mp_off;    // n_patch + 1, offsets of the patch mass blocks
   const int* dof_ptr;
@@ -146,11 +148,16 @@ hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDe
 hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, const double* U,
                          double* full, hipStream_t s);
 
-// Heat equation: slab blocks Jv = T (x) M + dt W (x) K and the jump mass
-// Mv = M of the P_k discretisation, every CSR entry summed over its cells in
-// a fixed order (no atomics)
+// Heat equation: slab blocks Jv = T (x) M + dt W (x) K, the jump mass Mv = M
+// and the stiffness Kv = K of the P_k discretisation, every CSR entry summed
+// over its cells in a fixed order (no atomics)
 hipError_t launch_heat_operator(const LevelView& L, const RefTables* tab, double* Jv, double* Mv,
-                                hipStream_t s);
+                                double* Kv, hipStream_t s);
+// y = A x or y = b - A x for the heat equation from the spatial M and K
+// alone: per slab (T (x) M + dt W (x) K) x_n - e0 (x) M (e1 . x_{n-1})
+hipError_t launch_heat_spmv(const LevelView& L, const RefTables* tab, const double* Mv,
+                            const double* Kv, const double* x, const double* b, double* y,
+                            hipStream_t s);
 // b0 = e0 (x) M U_0 on slab 0 (U_0 the nodal interpolant of sin(pi x) +
 // cos(2 pi y)), zero on the other slabs
 hipError_t launch_heat_rhs(const LevelView& L, const RefTables* tab, const double* Mv, double* b0,

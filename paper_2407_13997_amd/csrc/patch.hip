@@ -76,7 +76,7 @@ __global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, 
   __shared__ int ri[NW];
   __shared__ int perm[MAXM];
   __shared__ int ofs1[MAXM], ofs2[MAXM];
-  const int p = P.order[first + blockIdx.x / L.N], n = blockIdx.x % L.N;
+  const int p = P.order[first + blockIdx.x / P.fac_slabs], n = blockIdx.x % P.fac_slabs;
   const int tid = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0;
@@ -540,7 +540,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   constexpr int VW = Vec<T>::W;
   constexpr int MAXP = (MAXM + VW - 1) / VW;
   constexpr int PW = panels_per_wave(VW);
-  constexpr int K2 = (PW + 3) / 4;
+  // panels a wavefront can hold for blocks up to MAXM (the loops and block
+  // registers need no more than the block has)
+  constexpr int PWU = MAXP < PW ? MAXP : PW;
+  constexpr int K2 = (PWU + 3) / 4;
   constexpr bool kTwo = MAXM > 64;
   using V = typename Vec<T>::type;
   __shared__ int dofs[NBMAX];
@@ -593,11 +596,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   const bool hasRow = tid < m;
   const int64_t rbase = hasRow ? (int64_t)dofs[tid / NQ] * N * NQ + tid % NQ : 0;
   const int ia = tid / NQ, aa = tid % NQ;
-  V cur1[PW], nxt1[PW], cur2[K2], nxt2[K2];
+  V cur1[PWU], nxt1[PWU], cur2[K2], nxt2[K2];
   {
     const T* blk0 = Ab + (int64_t)n0 * S;
 #pragma unroll
-    for (int q = 0; q < PW; ++q) cur1[q] = *reinterpret_cast<const V*>(blk0 + O1(q));
+    for (int q = 0; q < PWU; ++q) cur1[q] = *reinterpret_cast<const V*>(blk0 + O1(q));
     if constexpr (kTwo) {
 #pragma unroll
       for (int k = 0; k < K2; ++k) cur2[k] = *reinterpret_cast<const V*>(blk0 + O2(k));
@@ -605,13 +608,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   }
   double rcur = hasRow ? r[rbase + (int64_t)n0 * NQ] : 0.0;
   const int quarter = lane & 3;
+  // every slab shares one block (slab_stride 0): it stays in registers
+  const bool invariant = S == 0;
   for (int n = n0; n < n1; ++n) {
-    const T* nblk = Ab + (int64_t)(n + 1 < n1 ? n + 1 : n) * S;
+    if (!invariant) {
+      const T* nblk = Ab + (int64_t)(n + 1 < n1 ? n + 1 : n) * S;
 #pragma unroll
-    for (int q = 0; q < PW; ++q) nxt1[q] = *reinterpret_cast<const V*>(nblk + O1(q));
-    if constexpr (kTwo) {
+      for (int q = 0; q < PWU; ++q) nxt1[q] = *reinterpret_cast<const V*>(nblk + O1(q));
+      if constexpr (kTwo) {
 #pragma unroll
-      for (int k = 0; k < K2; ++k) nxt2[k] = *reinterpret_cast<const V*>(nblk + O2(k));
+        for (int k = 0; k < K2; ++k) nxt2[k] = *reinterpret_cast<const V*>(nblk + O2(k));
+      }
     }
     const double rnext = (hasRow && n + 1 < n1) ? r[rbase + (int64_t)(n + 1) * NQ] : 0.0;
     if (hasRow) {
@@ -624,7 +631,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
     const T* gw = g + w * PW * VW;
     T acc1 = (T)0;
 #pragma unroll
-    for (int q = 0; q < PW; ++q) {
+    for (int q = 0; q < PWU; ++q) {
       const T d = dotv<V, T>(cur1[q], gw + q * VW);
       acc1 += q < PH ? d : (T)0;
     }
@@ -634,7 +641,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
 #pragma unroll
       for (int k = 0; k < K2; ++k) {
         const int ql = quarter + 4 * k;
-        const T d = dotv<V, T>(cur2[k], gw + (ql < PW ? ql : 0) * VW);
+        const T d = dotv<V, T>(cur2[k], gw + (ql < PWU ? ql : 0) * VW);
         acc2 += ql < PH ? d : (T)0;
       }
       acc2 += __shfl_xor(acc2, 1);
@@ -662,11 +669,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
       mj[tid] = acc;
     }
     __syncthreads();
+    if (!invariant) {
 #pragma unroll
-    for (int q = 0; q < PW; ++q) cur1[q] = nxt1[q];
-    if constexpr (kTwo) {
+      for (int q = 0; q < PWU; ++q) cur1[q] = nxt1[q];
+      if constexpr (kTwo) {
 #pragma unroll
-      for (int k = 0; k < K2; ++k) cur2[k] = nxt2[k];
+        for (int k = 0; k < K2; ++k) cur2[k] = nxt2[k];
+      }
     }
     rcur = rnext;
   }
@@ -795,12 +804,12 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
   // blocks larger than 64 rows (the front of the patch order) take two rows
   // per lane (FP32) or two wavefronts (FP64); the others one row per lane
   const int big = L.NQ == 2 ? P.n_big : 0, small = P.n_patch - big;
-  const dim3 gb((unsigned)big * L.N), gs((unsigned)small * L.N);
+  const dim3 gb((unsigned)big * P.fac_slabs), gs((unsigned)small * P.fac_slabs);
   if (L.kdeg > 0) {
     // scalar heat patches: at most kHeatMaxNb DoFs, so (q+1) kHeatMaxNb rows:
     // one row per lane up to 64 rows, two (FP32) or two wavefronts (FP64) at q = 3
     constexpr int H = kHeatMaxNb;
-    const dim3 ga((unsigned)P.n_patch * L.N);
+    const dim3 ga((unsigned)P.n_patch * P.fac_slabs);
     if (prec == 1) {
       float* f = (float*)fac;
       switch (L.NQ) {
