@@ -689,12 +689,16 @@ void coarse_solve(stwr_problem* P, const double* b, double* x) {
   HIPCHK(launch_coarse_solve(C.view, C.Binv, C.Mv, P->tab.e0, P->tab.e1, b, x, C.gbuf, P->s()));
 }
 
+void require_smoothers(stwr_problem* P) {
+  for (int l = 0; l + 1 < (int)P->lv.size(); ++l)
+    if (!P->lv[l].has_lambda || P->lv[l].fac_prec < 0)
+      throw StwrError(STWR_ERR_STATE, "smoothers not set up (call stwr_setup_smoothers)");
+}
+
 void vcycle(stwr_problem* P, const double* b0, double* x0) {
   const int L = (int)P->lv.size();
   const stwr_solver_opts& o = P->opts;
-  for (int l = 0; l + 1 < L; ++l)
-    if (!P->lv[l].has_lambda || P->lv[l].fac_prec < 0)
-      throw StwrError(STWR_ERR_STATE, "smoothers not set up (call stwr_setup_smoothers)");
+  require_smoothers(P);
   std::vector<const double*> bs(L);
   std::vector<double*> xs(L);
   for (int l = 0; l < L; ++l) {
@@ -752,6 +756,7 @@ void drop_vcycle_graph(stwr_problem* P) {
 // so other threads' streams are not affected), with the context's stream
 // pointed at it while the launches are recorded.
 void vcycle_apply(stwr_problem* P, const double* b, double* x) {
+  require_smoothers(P);   // before any capture begins
   if (!P->opts.vcycle_graph || P->ctx->timing) {
     vcycle(P, b, x);
     return;
