@@ -33,7 +33,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds_budget: float = 10.0) -> dict:
+def cpu_baseline(seconds_budget: float = 5.0) -> dict:
     """Time the oracle's sweep (residual + patch solves + Chebyshev update) on a
     bounded sample with the same per-patch work as the benchmark workload:
     16x16 mesh (289 patches, interior blocks of 78x78 per slab), q = 1,
