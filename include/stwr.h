@@ -147,6 +147,9 @@ typedef struct {
                                   the paper's heat runs: rtol 1e-6, atol 1e-6) */
   int32_t time_chunks;         /* sweeps in time chunks (cyclic reduction in time, below):
                                   0 = autotuned per level (default), 1 = plain, c = c chunks */
+  int32_t factor_mfma;         /* 1 (default): FP32 patch blocks of more than 64 rows are inverted
+                                  by blocked Gauss-Jordan with MFMA trailing updates; 0: by the
+                                  column-at-a-time register Gauss-Jordan (same pivoting rule) */
 } stwr_solver_opts;
 
 /* Time chunks (the cyclic reduction in time of Sec. 3.1, single-GPU form).

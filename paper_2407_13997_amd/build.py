@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libstwr.so")
 
-SOURCES = ["host_setup.cpp", "assembly.hip", "linear.hip", "patch.hip", "api.hip", "server.cpp"]
+SOURCES = ["host_setup.cpp", "assembly.hip", "linear.hip", "patch.hip", "factor_mfma.hip", "api.hip",
+           "server.cpp"]
 ARCH = "gfx950"
 
 

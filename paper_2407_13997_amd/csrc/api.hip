@@ -275,7 +275,7 @@ void check_opts(const stwr_solver_opts* o) {
       (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
       !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1) ||
       (o->newton_ew != 0 && o->newton_ew != 1) || !(o->gmres_atol >= 0.0) || o->time_chunks < 0 ||
-      o->time_chunks > kMaxTimeChunks)
+      o->time_chunks > kMaxTimeChunks || (o->factor_mfma != 0 && o->factor_mfma != 1))
     throw StwrError(STWR_ERR_ARG, "invalid solver options");
 }
 
@@ -561,6 +561,7 @@ void patch_factor(stwr_problem* P, int l, int prec) {
   if (prec != STWR_FP32 && prec != STWR_FP64) throw StwrError(STWR_ERR_ARG, "bad precision");
   Level& L = P->lv[l];
   ensure_factor_storage(P, L, prec);
+  L.pview.factor_mfma = P->opts.factor_mfma;
   HIPCHK(launch_patch_factor(L.view, L.pview, L.Jv, prec, L.fac, P->dstatus, P->s()));
   HIPCHK(launch_patch_mass(L.view, L.pview, L.Mv, L.Mp, P->s()));
   L.fac_prec = prec;
@@ -1054,6 +1055,7 @@ int32_t stwr_default_opts(stwr_solver_opts* o) {
   o->newton_ew = 0;
   o->gmres_atol = 0.0;
   o->time_chunks = 0;
+  o->factor_mfma = 1;
   return STWR_OK;
 }
 

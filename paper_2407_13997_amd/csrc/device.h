@@ -77,6 +77,7 @@ struct PatchView {
   int64_t slab_stride;      // elements of one slab's blocks (all patches): blocks are [slab][patch]
   int fac_slabs;            // slabs with their own blocks: N, or 1 when every slab's blocks are
                             // the same (the heat equation; slab_stride is then 0)
+  int factor_mfma;          // 1: FP32 blocks over 64 rows by the MFMA blocked Gauss-Jordan
   const int64_t* y_off;     // n_patch + 1, offsets into the patch output buffer
   const int64_t* mp_off;    // n_patch + 1, offsets of the patch mass blocks
   const int* dof_ptr;
@@ -191,6 +192,10 @@ hipError_t launch_gemv_cols(int64_t n, int k, const double* Z, int64_t ldz, cons
 // ---- patches -------------------------------------------------------------------
 hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const double* Jv,
                                int prec, void* fac, int* status, hipStream_t s);
+// FP32 blocks of more than 64 (at most 80) rows, patches order[first ..
+// first + count): blocked Gauss-Jordan with MFMA trailing updates
+hipError_t launch_patch_factor_mfma(const LevelView& L, const PatchView& P, const double* Jv, float* fac,
+                                    int* status, int first, int count, hipStream_t s);
 hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const double* Mv,
                              double* Mp, hipStream_t s);
 // Y: patch outputs, FP64 at element offset y_off[p] (prec 0, and FP32

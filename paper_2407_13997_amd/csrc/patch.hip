@@ -833,6 +833,12 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
   }
   if (prec == 1) {
     float* f = (float*)fac;
+    if (L.NQ == 2 && big && P.factor_mfma) {
+      hipError_t e = launch_patch_factor_mfma(L, P, Jv, f, status, 0, big, s);
+      if (e != hipSuccess) return e;
+      if (small) hipLaunchKernelGGL((k_patch_factor<2, float, 64, 1>), gs, dim3(64), 0, s, L, P, big, Jv, f, status);
+      return hipGetLastError();
+    }
     if (L.NQ == 1) {
       hipLaunchKernelGGL((k_patch_factor<1, float, 64, 1>), gs, dim3(64), 0, s, L, P, 0, Jv, f, status);
     } else {
