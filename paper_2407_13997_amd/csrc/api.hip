@@ -333,7 +333,8 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
       b += (uint64_t)y_elems(H.patch_ptr[v + 1] - H.patch_ptr[v], N, NQ) * 8;
   } else {
     const int64_t mm = (int64_t)H.nf * NQ + (H.po < H.nf ? NQ : 0);
-    b += (uint64_t)N * mm * mm * 8 + (uint64_t)N * mm * 12 + mm * 8 + (mm > kCoarseSmall ? (uint64_t)N * 32 * mm * 8 : 0);
+    const int64_t cs = fac_slabs_of(H, N);
+    b += (uint64_t)cs * mm * mm * 8 + (uint64_t)cs * mm * 12 + mm * 8 + (mm > kCoarseSmall ? (uint64_t)cs * 32 * mm * 8 : 0);
   }
   if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
   return b;
@@ -400,6 +401,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   v.kdeg = H.kdeg; v.nloc = H.nloc;
   v.node_cell_ptr = L.node_cell_ptr; v.node_cell = L.node_cell;
   v.nbord = H.po < H.nf ? L.NQ : 0;
+  v.coarse_slabs = fac_slabs_of(H, L.N);
   // patches (the coarsest level is solved directly and needs none)
   PatchView& pv = L.pview;
   pv.n_patch = H.nv;
@@ -450,11 +452,12 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     L.R_val = P->upload(L.Tr.r_val);
   } else {
     L.coarse_mm = H.nf * L.NQ + L.view.nbord;
-    L.Binv = P->alloc<double>((size_t)L.N * L.coarse_mm * L.coarse_mm);
+    const size_t cs = L.view.coarse_slabs;
+    L.Binv = P->alloc<double>(cs * L.coarse_mm * L.coarse_mm);
     L.gbuf = P->alloc<double>((size_t)L.coarse_mm);
-    L.perm = P->alloc<int>((size_t)L.N * L.coarse_mm);
-    L.colbuf = P->alloc<double>((size_t)L.N * L.coarse_mm);
-    if (L.coarse_mm > kCoarseSmall) L.rbuf = P->alloc<double>((size_t)L.N * 32 * L.coarse_mm);
+    L.perm = P->alloc<int>(cs * L.coarse_mm);
+    L.colbuf = P->alloc<double>(cs * L.coarse_mm);
+    if (L.coarse_mm > kCoarseSmall) L.rbuf = P->alloc<double>(cs * 32 * L.coarse_mm);
   }
 }
 
@@ -923,9 +926,10 @@ void assemble(stwr_problem* P, const double* U) {
     Lv.has_lambda = false;
   }
   Level& C = P->lv.back();
-  HIPCHK(launch_fill((int64_t)C.N * C.coarse_mm * C.coarse_mm, 0.0, C.Binv, P->s()));
+  HIPCHK(launch_fill((int64_t)C.view.coarse_slabs * C.coarse_mm * C.coarse_mm, 0.0, C.Binv, P->s()));
   HIPCHK(launch_coarse_build(C.view, C.Jv, C.Binv, P->s()));
-  HIPCHK(launch_dense_inverse(C.N, C.coarse_mm, C.Binv, P->dstatus, C.perm, C.colbuf, C.rbuf, P->s()));
+  HIPCHK(launch_dense_inverse(C.view.coarse_slabs, C.coarse_mm, C.Binv, P->dstatus, C.perm, C.colbuf, C.rbuf,
+                              P->s()));
   check_status_flag(P, "coarse factorization");
   P->assembled = true;
 }

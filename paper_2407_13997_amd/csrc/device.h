@@ -54,6 +54,7 @@ struct LevelView {
   const int* node_cell_ptr;
   const int* node_cell;
   int nbord;             // constraint rows bordering a coarsest slab block: q+1 with pressure, else 0
+  int coarse_slabs;      // coarsest slab blocks stored: N, or 1 when every slab's block is the same
 };
 
 // Time chunks of one sweep (see k_patch_sweep): chunk c covers slabs

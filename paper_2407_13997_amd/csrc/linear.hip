@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_cols(int64_t n, int k, const do
 // C = one indicator column of the pressure DoFs per temporal node (nbord =
 // q + 1 columns); without a pressure (nbord = 0) B_n = J_nn.
 template <int NQ>
-__global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N, int nbord,
+__global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N, int nbord, int nbuild,
                                                          const int* __restrict__ rp,
                                                          const int* __restrict__ col,
                                                          const double* __restrict__ Jv,
@@ -185,6 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_build(int nf, int po, int N, 
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= (int64_t)nf * N) return;
   const int i = (int)(t / N), n = (int)(t % N);
+  if (n >= nbuild) return;   // slabs sharing the first slab's block
   const int m = nf * NQ, mm = m + nbord;
   double* Bn = B + (int64_t)n * mm * mm;
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_bgj_panel_reg(int m, int k0, 
 // Forward block substitution over the slabs of the coarsest level with the
 // inverted bordered slab blocks; one workgroup walks the slabs in order.
 template <int NQ>
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N, int nbord,
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N, int nbord, int cs,
                                                          const int* __restrict__ rp,
                                                          const int* __restrict__ col,
                                                          const double* __restrict__ Mv, TimeEnds te,
@@ -683,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int nf, int po, int N, 
     }
     if (tid < nbord) g[m + tid] = 0.0;
     __syncthreads();
-    const double* Bn = Binv + (int64_t)n * mm * mm;
+    const double* Bn = Binv + (int64_t)(n % cs) * mm * mm;
     for (int r = tid; r < m; r += kBlock) {
       double acc = 0.0;
       for (int c = 0; c < mm; ++c) acc += Bn[(int64_t)r * mm + c] * g[c];
@@ -846,7 +847,7 @@ hipError_t launch_gemv_cols(int64_t n, int k, const double* Z, int64_t ldz, cons
 hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_coarse_build<Q>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf,
-                                          L.po, L.N, L.nbord, L.row_ptr, L.col, Jv, B));
+                                          L.po, L.N, L.nbord, L.coarse_slabs, L.row_ptr, L.col, Jv, B));
   return hipGetLastError();
 }
 
@@ -894,7 +895,7 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
     const unsigned gr = (unsigned)((mm + kBlock / 16 - 1) / (kBlock / 16));
     const unsigned gg = (unsigned)((L.nf * L.NQ + kBlock / 64 - 1) / (kBlock / 64));
     for (int n = 0; n < L.N; ++n) {
-      const double* Bn = Binv + (int64_t)n * mm * mm;
+      const double* Bn = Binv + (int64_t)(n % L.coarse_slabs) * mm * mm;
       STWR_NQ_SWITCH(L.NQ, {
         hipLaunchKernelGGL(k_coarse_rhs<Q>, dim3(gr), dim3(kBlock), 0, s, L.nf, L.po, L.N, n, L.nbord,
                            L.row_ptr, L.col, Mv, te, b, x, gbuf);
@@ -904,7 +905,7 @@ hipError_t launch_coarse_solve(const LevelView& L, const double* Binv, const dou
     return hipGetLastError();
   }
   STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_coarse_solve<Q>, dim3(1), dim3(kBlock), 0, s, L.nf, L.po,
-                                          L.N, L.nbord, L.row_ptr, L.col, Mv, te, Binv, b, x));
+                                          L.N, L.nbord, L.coarse_slabs, L.row_ptr, L.col, Mv, te, Binv, b, x));
   return hipGetLastError();
 }
 
