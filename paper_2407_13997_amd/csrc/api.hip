@@ -9,10 +9,12 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "device.h"
@@ -340,20 +342,37 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
   return b;
 }
 
+// Host construction of every level, then of every transfer, each on a
+// thread of its own (the builders split their larger loops further).
 void build_levels(const stwr_problem_desc* d, std::vector<Level>& lv) {
   lv.resize(d->n_levels);
-  for (int l = 0; l < d->n_levels; ++l) {
+  std::vector<std::exception_ptr> err(d->n_levels);
+  auto run_all = [&](int count, auto&& job) {
+    std::vector<std::thread> th;
+    for (int l = 0; l < count; ++l)
+      th.emplace_back([&, l]() {
+        try {
+          job(l);
+        } catch (...) {
+          err[l] = std::current_exception();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (auto& e : err)
+      if (e) std::rethrow_exception(e);
+  };
+  run_all(d->n_levels, [&](int l) {
     if (is_heat(d)) build_level_heat(d->mesh_n >> l, d->degree, lv[l].H);
     else build_level(d->mesh_n >> l, lv[l].H);
     lv[l].N = d->n_slabs;
     lv[l].NQ = d->q + 1;
     lv[l].dt = d->t_final / d->n_slabs;
     lv[l].n_st = (int64_t)lv[l].H.nf * d->n_slabs * (d->q + 1);
-  }
-  for (int l = 0; l + 1 < d->n_levels; ++l) {
+  });
+  run_all(d->n_levels - 1, [&](int l) {
     if (is_heat(d)) build_transfer_heat(lv[l].H, lv[l + 1].H, lv[l].Tr);
     else build_transfer(lv[l].H, lv[l + 1].H, lv[l].Tr);
-  }
+  });
 }
 
 uint64_t plan_bytes(const stwr_problem_desc* d, const stwr_solver_opts* o, const std::vector<Level>& lv) {

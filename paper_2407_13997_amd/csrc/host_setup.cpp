@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <stdexcept>
+#include <thread>
 
 namespace stwr {
 
@@ -161,6 +162,26 @@ void build_ref_tables(int q, int nodes, RefTables& t) {
     }
 }
 
+// f(i) for i in [0, n): independent items split over up to 16 host threads
+// (serially below a few thousand items)
+template <class F>
+static void parallel_for(int n, F&& f) {
+  const int hw = (int)std::thread::hardware_concurrency();
+  const int T = std::min(std::max(hw, 1), 16);
+  if (n < 4096 || T == 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  const int chunk = (n + T - 1) / T;
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&, t]() {
+      const int a = t * chunk, b = std::min(n, a + chunk);
+      for (int i = a; i < b; ++i) f(i);
+    });
+  for (auto& x : th) x.join();
+}
+
 // CSR pattern of the DoF pairs that share a cell, and each cell's positions
 // in it (cell_dofs holds nloc DoFs per cell, -1 for eliminated ones).
 static int find_nz(const HostLevel& L, int r, int c) {
@@ -180,24 +201,24 @@ static void csr_from_cells(HostLevel& L) {
         if (d[J] >= 0) rows[d[I]].push_back(d[J]);
     }
   }
-  L.row_ptr.assign(L.nf + 1, 0);
-  for (int r = 0; r < L.nf; ++r) {
+  parallel_for(L.nf, [&](int r) {
     auto& v = rows[r];
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
-    L.row_ptr[r + 1] = L.row_ptr[r] + (int)v.size();
-  }
+  });
+  L.row_ptr.assign(L.nf + 1, 0);
+  for (int r = 0; r < L.nf; ++r) L.row_ptr[r + 1] = L.row_ptr[r] + (int)rows[r].size();
   L.col.resize(L.row_ptr[L.nf]);
-  for (int r = 0; r < L.nf; ++r) std::copy(rows[r].begin(), rows[r].end(), L.col.begin() + L.row_ptr[r]);
+  parallel_for(L.nf, [&](int r) { std::copy(rows[r].begin(), rows[r].end(), L.col.begin() + L.row_ptr[r]); });
   rows.clear();
   rows.shrink_to_fit();
   L.cell_nz.resize((size_t)nl * nl * L.nc);
-  for (int c = 0; c < L.nc; ++c) {
+  parallel_for(L.nc, [&](int c) {
     const int* d = &L.cell_dofs[(size_t)nl * c];
     for (int I = 0; I < nl; ++I)
       for (int J = 0; J < nl; ++J)
         L.cell_nz[(size_t)nl * nl * c + nl * I + J] = (d[I] >= 0 && d[J] >= 0) ? find_nz(L, d[I], d[J]) : -1;
-  }
+  });
 }
 
 // Patch-block CSR positions and the DoF -> patch-slot transpose, from
@@ -209,12 +230,12 @@ static void patch_maps(HostLevel& L) {
     L.patch_nz_off[v + 1] = L.patch_nz_off[v] + nb * nb;
   }
   L.patch_nz.resize(L.patch_nz_off[L.nv]);
-  for (int v = 0; v < L.nv; ++v) {
+  parallel_for(L.nv, [&](int v) {
     int s = L.patch_ptr[v], nb = L.patch_ptr[v + 1] - s;
     for (int i = 0; i < nb; ++i)
       for (int j = 0; j < nb; ++j)
         L.patch_nz[L.patch_nz_off[v] + (int64_t)i * nb + j] = find_nz(L, L.patch_dofs[s + i], L.patch_dofs[s + j]);
-  }
+  });
   const int ns = (int)L.patch_dofs.size();
   L.slot_patch.resize(ns);
   for (int v = 0; v < L.nv; ++v)
@@ -330,15 +351,15 @@ static void locate(const HostLevel& C, double x, double y, int& cell, double& xi
 // P by fine rows from per-row (coarse column, value) lists, and R = P^T.
 static void transfer_csr(const HostLevel& F, const HostLevel& C,
                          std::vector<std::vector<std::pair<int, double>>>& rows, HostTransfer& T) {
+  parallel_for(F.nf, [&](int r) { std::sort(rows[r].begin(), rows[r].end()); });
   T.p_ptr.assign(F.nf + 1, 0);
-  T.p_col.clear();
-  T.p_val.clear();
-  for (int r = 0; r < F.nf; ++r) {
-    auto& e = rows[r];
-    std::sort(e.begin(), e.end());
-    for (auto& pr : e) { T.p_col.push_back(pr.first); T.p_val.push_back(pr.second); }
-    T.p_ptr[r + 1] = (int)T.p_col.size();
-  }
+  for (int r = 0; r < F.nf; ++r) T.p_ptr[r + 1] = T.p_ptr[r] + (int)rows[r].size();
+  T.p_col.resize(T.p_ptr[F.nf]);
+  T.p_val.resize(T.p_ptr[F.nf]);
+  parallel_for(F.nf, [&](int r) {
+    int o = T.p_ptr[r];
+    for (auto& pr : rows[r]) { T.p_col[o] = pr.first; T.p_val[o] = pr.second; ++o; }
+  });
   T.r_ptr.assign(C.nf + 1, 0);
   for (int c : T.p_col) T.r_ptr[c + 1]++;
   for (int r = 0; r < C.nf; ++r) T.r_ptr[r + 1] += T.r_ptr[r];
@@ -483,39 +504,53 @@ void build_level_heat(int M, int k, HostLevel& L) {
       }
   }
   csr_from_cells(L);
+  // node -> (cell, local index) slots, cells in increasing order
+  L.node_cell_ptr.assign(L.nn + 1, 0);
+  for (int e = 0; e < nloc * L.nc; ++e) L.node_cell_ptr[L.cell_dofs[e] + 1]++;
+  for (int g = 0; g < L.nn; ++g) L.node_cell_ptr[g + 1] += L.node_cell_ptr[g];
+  L.node_cell.resize((size_t)nloc * L.nc);
+  {
+    std::vector<int> fill(L.node_cell_ptr.begin(), L.node_cell_ptr.end() - 1);
+    for (int e = 0; e < nloc * L.nc; ++e) L.node_cell[fill[L.cell_dofs[e]]++] = e;
+  }
   // vertex-star patches: the nodes of each incident cell whose barycentric
   // coordinate for the vertex is positive (the vertex and the interiors of
-  // its incident edges and cells)
-  std::vector<std::vector<int>> pd(L.nv);
-  for (int c = 0; c < L.nc; ++c) {
+  // its incident edges and cells); the incident cells are those holding the
+  // vertex's lattice node, with the vertex at one of their corners
+  std::vector<int> lam_a(nloc), lam_b(nloc);
+  {
     int i = 0;
     for (int b = 0; b <= k; ++b)
-      for (int a = 0; a + b <= k; ++a, ++i) {
-        const int lam[3] = {k - a - b, a, b};
-        for (int corner = 0; corner < 3; ++corner)
-          if (lam[corner] > 0) pd[L.cells[3 * c + corner]].push_back(L.cell_dofs[(size_t)nloc * c + i]);
-      }
+      for (int a = 0; a + b <= k; ++a, ++i) { lam_a[i] = a; lam_b[i] = b; }
   }
+  std::vector<std::vector<int>> pd(L.nv);
+  parallel_for(L.nv, [&](int v) {
+    const int g = k * (v % n1) + nl * k * (v / n1);
+    auto& d = pd[v];
+    for (int e = L.node_cell_ptr[g]; e < L.node_cell_ptr[g + 1]; ++e) {
+      const int c = L.node_cell[e] / nloc;
+      int corner = 0;
+      for (int t = 0; t < 3; ++t)
+        if (L.cells[3 * c + t] == v) corner = t;
+      for (int i = 0; i < nloc; ++i) {
+        const int lam[3] = {k - lam_a[i] - lam_b[i], lam_a[i], lam_b[i]};
+        if (lam[corner] > 0) d.push_back(L.cell_dofs[(size_t)nloc * c + i]);
+      }
+    }
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+  });
   L.patch_ptr.assign(L.nv + 1, 0);
   L.patch_nbu.assign(L.nv, 0);
   L.patch_dofs.clear();
   for (int v = 0; v < L.nv; ++v) {
-    auto& d = pd[v];
-    std::sort(d.begin(), d.end());
-    d.erase(std::unique(d.begin(), d.end()), d.end());
+    const auto& d = pd[v];
     if ((int)d.size() > kHeatMaxNb) throw std::logic_error("vertex-star patch larger than its bound");
     L.patch_nbu[v] = (int)d.size();   // every DoF carries the jump coupling
     L.patch_dofs.insert(L.patch_dofs.end(), d.begin(), d.end());
     L.patch_ptr[v + 1] = (int)L.patch_dofs.size();
   }
   patch_maps(L);
-  // node -> (cell, local index) slots, cells in increasing order
-  L.node_cell_ptr.assign(L.nn + 1, 0);
-  for (int e = 0; e < nloc * L.nc; ++e) L.node_cell_ptr[L.cell_dofs[e] + 1]++;
-  for (int g = 0; g < L.nn; ++g) L.node_cell_ptr[g + 1] += L.node_cell_ptr[g];
-  L.node_cell.resize((size_t)nloc * L.nc);
-  std::vector<int> fill(L.node_cell_ptr.begin(), L.node_cell_ptr.end() - 1);
-  for (int e = 0; e < nloc * L.nc; ++e) L.node_cell[fill[L.cell_dofs[e]]++] = e;
 }
 
 void build_transfer_heat(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
@@ -524,7 +559,7 @@ void build_transfer_heat(const HostLevel& F, const HostLevel& C, HostTransfer& T
   const int k = F.kdeg, nloc = C.nloc;
   std::vector<std::vector<std::pair<int, double>>> rows(F.nf);
   const double hs = 1.0 / (F.M * k);
-  for (int g = 0; g < F.nf; ++g) {
+  parallel_for(F.nf, [&](int g) {
     const double x = (g % F.n2) * hs, y = (g / F.n2) * hs;
     int cell; double xi, eta;
     locate(C, x, y, cell, xi, eta);
@@ -532,7 +567,7 @@ void build_transfer_heat(const HostLevel& F, const HostLevel& C, HostTransfer& T
     pk_eval(k, xi, eta, v, nullptr);
     for (int i = 0; i < nloc; ++i)
       if (std::fabs(v[i]) >= 1e-14) rows[g].push_back({C.cell_dofs[(size_t)nloc * cell + i], v[i]});
-  }
+  });
   transfer_csr(F, C, rows, T);
   T.inject.clear();
 }
