@@ -221,6 +221,8 @@ def main():
     }
     P.close()
     if not args.no_serving:
+        out["single_solve"] = single_solve()
+        log(f"[bench] single solve: {out['single_solve']}")
         out["serving"] = serving_benchmark()
         log(f"[bench] serving: {out['serving']}")
     if not args.no_paper_context:
@@ -427,6 +429,43 @@ def heat_context(sweep_steps: int = 20, runs_too: bool = True) -> dict:
                                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                                    "kernel": "k_patch_sweep (FP32 block per patch, FP64 outputs)",
                                    "avg_ms": sweep_ms, "algorithmic_bytes": algo}}}
+
+
+def single_solve() -> dict:
+    """The 32 x 32, P2-P1 x DG(1), 32-slab, Re 100 Newton solve to 1e-10 with
+    the FP64 smoother (the plain form) and with FP32 patch factors and
+    relaxation (FP64 FGMRES, Newton, residual and coarse solve): time,
+    iterations, and the relative difference of the two solutions.  Three
+    levels (coarsest 8 x 8): with four, the rediscretised 4 x 4 operator is
+    too convection-dominated for the V-cycle at Re 100."""
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    base = w.named_problem(w.MEDIUM)
+    prob = w.Problem(base.mesh_n, 3, base.q, base.n_slabs, base.t_final, base.reynolds, base.psi_ab,
+                     base.psi_coef, base.p_ab, base.p_coef, seed=base.seed)
+    ctx = binding.Context(0)
+    out, sol = {}, {}
+    for name, prec in (("fp64", binding.FP64), ("fp32", binding.FP32)):
+        o = binding.default_opts()
+        o.smoother_prec = prec
+        o.newton_rtol = 1e-10
+        P = binding.Problem(ctx, prob, o)
+        U = P.vec()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = P.newton_solve(U)
+        torch.cuda.synchronize()
+        out[name] = {"time_s": time.perf_counter() - t0, "newton": st["newton"],
+                     "linear_total": sum(st["linear"])}
+        sol[name] = U.clone()
+        P.close()
+    ctx.close()
+    out["workload"] = f"{w.MEDIUM} (3 levels), Newton to 1e-10"
+    out["st_dofs"] = prob.n_st
+    out["rel_diff_fp32_vs_fp64"] = float((sol["fp32"] - sol["fp64"]).norm() / sol["fp64"].norm())
+    out["speedup"] = out["fp64"]["time_s"] / out["fp32"]["time_s"]
+    return out
 
 
 def time_chunk_context(steps: int = 10) -> list:
