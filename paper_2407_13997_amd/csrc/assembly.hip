@@ -509,7 +509,8 @@ __global__ __launch_bounds__(256) void k_heat_operator(LevelView L, const RefTab
 
 // y = A x (or b - A x) of the heat equation, one thread per (row, slab):
 // the spatial products M x_n and K x_n per temporal node, then the slab's
-// temporal matrices, minus the jump coupling to slab n-1
+// temporal matrices, minus the jump coupling to slab n-1 (the path for more
+// than 256 slabs; k_heat_spmv_rows below takes the others)
 template <int NQ>
 __global__ __launch_bounds__(256) void k_heat_spmv(LevelView L, const RefTables* __restrict__ T,
                                                    const double* __restrict__ Mv,
@@ -539,6 +540,76 @@ __global__ __launch_bounds__(256) void k_heat_spmv(LevelView L, const RefTables*
       jump += m * xl;
     }
   }
+  for (int a = 0; a < NQ; ++a) {
+    double out = -T->e0[a] * jump;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) out += T->T[a][c] * mx[c] + L.dt * T->W[a][c] * kx[c];
+    y[t * NQ + a] = b ? b[t * NQ + a] - out : out;
+  }
+}
+
+// The same operator over whole rows: a workgroup takes R = 256 / N rows and
+// every slab of each (thread r N + n), stages the rows' CSR entries in LDS
+// (when they fit), and forms per (row, slab) the mass and stiffness products
+// of the slab's nodal values.  The jump coupling of slab n needs
+// sum_k M_ik (e1 . x_{n-1}(col k)) = e1 . (M x)_{n-1}, the previous slab's
+// mass product, which the neighbouring thread of the same row holds: x is
+// read once per CSR entry, and the entries once per workgroup.
+constexpr int kHeatStage = 768;   // staged CSR entries per workgroup (15 KB)
+
+template <int NQ>
+__global__ __launch_bounds__(256) void k_heat_spmv_rows(LevelView L, const RefTables* __restrict__ T,
+                                                        const double* __restrict__ Mv,
+                                                        const double* __restrict__ Kv,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ y) {
+  __shared__ int s_col[kHeatStage];
+  __shared__ double s_m[kHeatStage], s_k[kHeatStage];
+  __shared__ double s_end[256];
+  const int N = L.N, R = 256 / N, tid = threadIdx.x;
+  const int i0 = blockIdx.x * R, i1 = i0 + R < L.nf ? i0 + R : L.nf;
+  const int k0 = L.row_ptr[i0], nk = L.row_ptr[i1] - k0;
+  const bool staged = nk <= kHeatStage;   // uniform over the workgroup
+  if (staged) {
+    for (int e = tid; e < nk; e += 256) {
+      s_col[e] = L.col[k0 + e];
+      s_m[e] = Mv[k0 + e];
+      s_k[e] = Kv[k0 + e];
+    }
+  }
+  __syncthreads();
+  const int r = tid / N, n = tid % N, i = i0 + r;
+  const bool active = r < R && i < L.nf;
+  double mx[NQ], kx[NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) mx[a] = kx[a] = 0.0;
+  auto entry = [&](int c, double m, double st) {
+    const double* xv = x + ((int64_t)c * N + n) * NQ;
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+      mx[a] += m * xv[a];
+      kx[a] += st * xv[a];
+    }
+  };
+  if (active) {
+    const int ka = L.row_ptr[i], kb = L.row_ptr[i + 1];
+    if (staged) {
+#pragma unroll 4
+      for (int k = ka - k0; k < kb - k0; ++k) entry(s_col[k], s_m[k], s_k[k]);
+    } else {
+      for (int k = ka; k < kb; ++k) entry(L.col[k], Mv[k], Kv[k]);
+    }
+  }
+  double e = 0.0;
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) e += T->e1[a] * mx[a];
+  s_end[tid] = e;
+  __syncthreads();
+  if (!active) return;
+  const double jump = n > 0 ? s_end[tid - 1] : 0.0;
+  const int64_t t = (int64_t)i * N + n;
+#pragma unroll
   for (int a = 0; a < NQ; ++a) {
     double out = -T->e0[a] * jump;
 #pragma unroll
@@ -578,6 +649,18 @@ hipError_t launch_heat_operator(const LevelView& L, const RefTables* tab, double
 hipError_t launch_heat_spmv(const LevelView& L, const RefTables* tab, const double* Mv,
                             const double* Kv, const double* x, const double* b, double* y,
                             hipStream_t s) {
+  if (L.N <= 256) {
+    const int R = 256 / L.N;
+    const dim3 grid((unsigned)((L.nf + R - 1) / R));
+    switch (L.NQ) {
+      case 1: hipLaunchKernelGGL(k_heat_spmv_rows<1>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+      case 2: hipLaunchKernelGGL(k_heat_spmv_rows<2>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+      case 3: hipLaunchKernelGGL(k_heat_spmv_rows<3>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+      case 4: hipLaunchKernelGGL(k_heat_spmv_rows<4>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)(((int64_t)L.nf * L.N + 255) / 256));
   switch (L.NQ) {
     case 1: hipLaunchKernelGGL(k_heat_spmv<1>, grid, dim3(256), 0, s, L, tab, Mv, Kv, x, b, y); break;

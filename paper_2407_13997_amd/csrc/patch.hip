@@ -260,6 +260,11 @@ __global__ __launch_bounds__(256) void k_patch_mass(PatchView P, const double* _
   }
 }
 
+// An empty asm that reads and rewrites the lanes of a loaded vector: the
+// load is complete here, and later uses of the registers wait for nothing.
+__device__ inline void pin_loaded(float4& v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
+__device__ inline void pin_loaded(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+
 template <typename V, typename T>
 __device__ inline T dotv(const V& w, const T* g) {
   if constexpr (sizeof(V) / sizeof(T) == 4) return w.x * g[0] + w.y * g[1] + w.z * g[2] + w.w * g[3];
@@ -520,17 +525,23 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
 // slabs are walked in order (forward block substitution).  Software pipeline:
 // while slab n is formed and multiplied, the block of slab n + 1 is already in
 // flight into a second register set (every load is unconditional, with
-// clamped addresses, so the wait counts leave the prefetch outstanding), and
-// the residual values of slab n + 1 are loaded too.  The jump coupling
-// mj = M_v (e1 . y_{n-1}) is formed once per velocity DoF at the end of the
-// previous slab.
+// clamped addresses, so the wait counts leave the prefetch outstanding).  INV
+// (one block shared by every slab, slab_stride 0) keeps the block in
+// registers for the whole sweep and drops the second set.  The residual of
+// kRGroup slabs at a time is loaded a whole group ahead into registers and
+// parked in LDS (each thread reads back only its own row), so the slab loop
+// waits on memory once per group, not once per slab.  The jump coupling
+// mj = M_v (e1 . y_{n-1}) is formed at the end of the previous slab: first the
+// slab-end value of each DoF, then one row of M_v per thread.
 //
 // Time chunks (cyclic reduction in time): blockIdx.y + ca.first is the chunk
 // c, covering slabs [c len, min(N, (c + 1) len)).  The chunk's sweep starts
 // from the incoming slab-end values w_in of the previous chunk (none: zero)
 // and may leave its own final slab-end values in w_end; outputs are written
 // for chunks c <= y_max.  One chunk of length N is the plain sweep.
-template <int NQ, typename T, int WAVES, int NBMAX = kMaxNb, int NBUMAX = kMaxNbu>
+constexpr int kRGroup = 4;
+
+template <int NQ, typename T, int WAVES, bool INV, int NBMAX = kMaxNb, int NBUMAX = kMaxNbu>
 __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchView P,
                                                             const T* __restrict__ fac,
                                                             const double* __restrict__ Mp,
@@ -545,14 +556,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   constexpr int PWU = MAXP < PW ? MAXP : PW;
   constexpr int K2 = (PWU + 3) / 4;
   constexpr bool kTwo = MAXM > 64;
+  // one wavefront and at most 64 rows: row i's product ends on lane i
+  constexpr bool kLane = WAVES == 1 && !kTwo;
+  constexpr int G = kRGroup;
+  static_assert(MAXM <= 64 * WAVES && NBUMAX <= 64, "a thread per row and per velocity DoF");
+  static_assert(!kLane || MAXP <= PW, "one wavefront holds every panel");
   using V = typename Vec<T>::type;
   __shared__ int dofs[NBMAX];
-  __shared__ double Ms[NBUMAX * NBUMAX];
+  __shared__ double MsT[NBUMAX * NBUMAX];   // MsT[j nbu + i] = M_v(i, j)
   __shared__ T g[WAVES * PW * VW];
-  __shared__ double part[WAVES][MAXM];
+  __shared__ double part[kLane ? 1 : WAVES][kLane ? 1 : MAXM];
   __shared__ double ys[MAXM];
+  __shared__ double yend[NBUMAX];
   __shared__ double mj[NBUMAX];
-  const double* e0 = te.e0;
+  __shared__ double rs[G][64 * WAVES];
   const double* e1 = te.e1;
   const int p = blockIdx.x, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int s0 = P.patch_ptr[p];
@@ -566,7 +583,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   const int PH = lay.panels(w), r1 = lay.r1, r2 = lay.r2;
   for (int i = tid; i < nb; i += 64 * WAVES) dofs[i] = P.patch_dofs[s0 + i];
   const double* mp = Mp + P.mp_off[p];
-  for (int e = tid; e < nbu * nbu; e += 64 * WAVES) Ms[e] = mp[e];
+  for (int e = tid; e < nbu * nbu; e += 64 * WAVES) MsT[(e % nbu) * nbu + e / nbu] = mp[e];
   for (int i = tid; i < WAVES * PW * VW; i += 64 * WAVES) g[i] = (T)0;
   __syncthreads();
   // coupling into the chunk's first slab: M_v times the incoming end values
@@ -574,11 +591,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
     double acc = 0.0;
     if (ca.w_in && n0 > 0 && i < nbu) {
       const double* wi = ca.w_in + ((int64_t)p * ca.n_chunks + chunk) * NBUMAX;
-      for (int j = 0; j < nbu; ++j) acc += Ms[i * nbu + j] * wi[j];
+      for (int j = 0; j < nbu; ++j) acc += MsT[j * nbu + i] * wi[j];
     }
     mj[i] = acc;
   }
-  __syncthreads();
   const int64_t S = P.slab_stride;
   const T* Ab = fac + P.fac_off[p];
   double* yout = Y + P.y_off[p];
@@ -592,11 +608,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   const int base2 = off2 + lane2 * VW, step2 = 4 * r2 * VW, nk2 = lay.k2(w);
 #define O1(q) ((q) < PH ? base1 + (q) * step1 : 0)
 #define O2(k) ((kTwo && (k) < nk2) ? base2 + (k) * step2 : 0)
-  // the row whose right-hand side this thread forms
+  // the row whose right-hand side this thread forms (threads past the block
+  // read row 0's residual and discard it)
   const bool hasRow = tid < m;
   const int64_t rbase = hasRow ? (int64_t)dofs[tid / NQ] * N * NQ + tid % NQ : 0;
   const int ia = tid / NQ, aa = tid % NQ;
-  V cur1[PWU], nxt1[PWU], cur2[K2], nxt2[K2];
+  double e0a = te.e0[aa];
+  V cur1[PWU], cur2[K2];
+  V nxt1[INV ? 1 : PWU], nxt2[INV ? 1 : K2];
   {
     const T* blk0 = Ab + (int64_t)n0 * S;
 #pragma unroll
@@ -606,12 +625,40 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
       for (int k = 0; k < K2; ++k) cur2[k] = *reinterpret_cast<const V*>(blk0 + O2(k));
     }
   }
-  double rcur = hasRow ? r[rbase + (int64_t)n0 * NQ] : 0.0;
+  // residual of slabs [na, na + G), clamped to the chunk's last slab
+  double rn[G];
+  auto issue_r = [&](int na) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int n = na + j < n1 ? na + j : n1 - 1;
+      rn[j] = r[rbase + (int64_t)n * NQ];
+    }
+  };
+  // every thread parks its registers (rows past the block too): the waits
+  // for these loads then also cover the block loads issued before them
+  auto park_r = [&]() {
+#pragma unroll
+    for (int j = 0; j < G; ++j) rs[j][tid] = rn[j];
+  };
+  issue_r(n0);
+  park_r();
+  // the block registers and e0a count as written here (an empty asm takes
+  // them in and out), so the slab loop waits on memory only for the residual
+  // groups and, without INV, for the next block
+  asm volatile("" : "+v"(e0a));
+#pragma unroll
+  for (int q = 0; q < PWU; ++q) pin_loaded(cur1[q]);
+  if constexpr (kTwo) {
+#pragma unroll
+    for (int k = 0; k < K2; ++k) pin_loaded(cur2[k]);
+  }
   const int quarter = lane & 3;
-  // every slab shares one block (slab_stride 0): it stays in registers
-  const bool invariant = S == 0;
+  __syncthreads();
   for (int n = n0; n < n1; ++n) {
-    if (!invariant) {
+    const int jr = (n - n0) % G;
+    // a group's first slab starts the loads of the next group (uniform)
+    if (jr == 0 && n + G < n1) issue_r(n + G);
+    if constexpr (!INV) {
       const T* nblk = Ab + (int64_t)(n + 1 < n1 ? n + 1 : n) * S;
 #pragma unroll
       for (int q = 0; q < PWU; ++q) nxt1[q] = *reinterpret_cast<const V*>(nblk + O1(q));
@@ -620,10 +667,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
         for (int k = 0; k < K2; ++k) nxt2[k] = *reinterpret_cast<const V*>(nblk + O2(k));
       }
     }
-    const double rnext = (hasRow && n + 1 < n1) ? r[rbase + (int64_t)(n + 1) * NQ] : 0.0;
     if (hasRow) {
-      double gv = rcur;
-      if (n > 0 && ia < nbu) gv += e0[aa] * mj[ia];
+      double gv = rs[jr][tid];
+      if (n > 0 && ia < nbu) gv += e0a * mj[ia];
       g[tid] = (T)gv;
     }
     __syncthreads();
@@ -635,41 +681,57 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
       const T d = dotv<V, T>(cur1[q], gw + q * VW);
       acc1 += q < PH ? d : (T)0;
     }
-    if (lane < r1) part[w][lane] = (double)acc1;
-    if constexpr (kTwo) {
-      T acc2 = (T)0;
+    double y = 0.0;
+    if constexpr (kLane) {
+      y = (double)acc1;
+    } else {
+      if (lane < r1) part[w][lane] = (double)acc1;
+      if constexpr (kTwo) {
+        T acc2 = (T)0;
 #pragma unroll
-      for (int k = 0; k < K2; ++k) {
-        const int ql = quarter + 4 * k;
-        const T d = dotv<V, T>(cur2[k], gw + (ql < PWU ? ql : 0) * VW);
-        acc2 += ql < PH ? d : (T)0;
+        for (int k = 0; k < K2; ++k) {
+          const int ql = quarter + 4 * k;
+          const T d = dotv<V, T>(cur2[k], gw + (ql < PWU ? ql : 0) * VW);
+          acc2 += ql < PH ? d : (T)0;
+        }
+        acc2 += __shfl_xor(acc2, 1);
+        acc2 += __shfl_xor(acc2, 2);
+        if (lane < 4 * r2 && quarter == 0) part[w][64 + lane / 4] = (double)acc2;
       }
-      acc2 += __shfl_xor(acc2, 1);
-      acc2 += __shfl_xor(acc2, 2);
-      if (lane < 4 * r2 && quarter == 0) part[w][64 + lane / 4] = (double)acc2;
-    }
-    __syncthreads();
-    if (hasRow) {
-      double y = 0.0;
+      __syncthreads();
+      if (hasRow) {
 #pragma unroll
-      for (int v = 0; v < WAVES; ++v) y += v < lay.waves ? part[v][tid] : 0.0;
+        for (int v = 0; v < WAVES; ++v) y += v < lay.waves ? part[v][tid] : 0.0;
+      }
+    }
+    if (hasRow) {
       ys[tid] = y;
       if (write_y) yout[(int64_t)n * m + tid] = y;
     }
     __syncthreads();
     if (tid < nbu) {
-      const double* mrow = Ms + tid * nbu;
-      double acc = 0.0;
-#pragma unroll 2
-      for (int j = 0; j < nbu; ++j) {
-        double yl = 0.0;
-        for (int b = 0; b < NQ; ++b) yl += e1[b] * ys[j * NQ + b];
-        acc += mrow[j] * yl;
+      double v = 0.0;
+#pragma unroll
+      for (int b = 0; b < NQ; ++b) v += e1[b] * ys[tid * NQ + b];
+      yend[tid] = v;
+    }
+    // the next group's residual, loaded since this group's first slab (uniform)
+    if (jr == G - 1 && n + 1 < n1) park_r();
+    __syncthreads();
+    if (tid < nbu) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int k = 0;
+      for (; k + 4 <= nbu; k += 4) {
+        a0 += MsT[k * nbu + tid] * yend[k];
+        a1 += MsT[(k + 1) * nbu + tid] * yend[k + 1];
+        a2 += MsT[(k + 2) * nbu + tid] * yend[k + 2];
+        a3 += MsT[(k + 3) * nbu + tid] * yend[k + 3];
       }
-      mj[tid] = acc;
+      for (; k < nbu; ++k) a0 += MsT[k * nbu + tid] * yend[k];
+      mj[tid] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
-    if (!invariant) {
+    if constexpr (!INV) {
 #pragma unroll
       for (int q = 0; q < PWU; ++q) cur1[q] = nxt1[q];
       if constexpr (kTwo) {
@@ -677,14 +739,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
         for (int k = 0; k < K2; ++k) cur2[k] = nxt2[k];
       }
     }
-    rcur = rnext;
   }
-  // the chunk's final slab-end values (ys holds its last slab)
-  if (ca.w_end && tid < nbu) {
-    double v = 0.0;
-    for (int b = 0; b < NQ; ++b) v += e1[b] * ys[tid * NQ + b];
-    ca.w_end[((int64_t)p * ca.n_chunks + chunk) * NBUMAX + tid] = v;
-  }
+  // the chunk's final slab-end values (yend holds its last slab's)
+  if (ca.w_end && tid < nbu) ca.w_end[((int64_t)p * ca.n_chunks + chunk) * NBUMAX + tid] = yend[tid];
 #undef O1
 #undef O2
 }
@@ -797,6 +854,72 @@ __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P
   }
 }
 
+// The same gather over whole DoFs: a workgroup takes R = 256 / N DoFs and
+// every slab of each (thread r N + n).  The slot -> patch -> output offset
+// chain of the workgroup's patch slots is resolved once per slot into LDS
+// (when the slots fit), so each (DoF, slab) thread only reads the outputs.
+constexpr int kGatherStage = 1024;
+
+template <int NQ, typename TY>
+__global__ __launch_bounds__(256) void k_patch_gather_rows(int nf, int N, PatchView P,
+                                                           const TY* __restrict__ Y, int mode,
+                                                           double c1, double c2, double* __restrict__ z,
+                                                           double* __restrict__ d, double* __restrict__ x) {
+  __shared__ int64_t s_base[kGatherStage];
+  __shared__ int s_m[kGatherStage];
+  constexpr int YS = sizeof(TY) == 4 ? 2 : 1;
+  const int R = 256 / N, tid = threadIdx.x;
+  const int i0 = blockIdx.x * R, i1 = i0 + R < nf ? i0 + R : nf;
+  const int k0 = P.dof_ptr[i0], nk = P.dof_ptr[i1] - k0;
+  const bool staged = nk <= kGatherStage;   // uniform over the workgroup
+  // output offset of slot k (row of the DoF in slab 0) and the patch's rows
+  auto slot = [&](int k, int64_t& base, int& m) {
+    const int sl = P.dof_slot[k];
+    const int p = P.slot_patch[sl];
+    const int s0 = P.patch_ptr[p];
+    m = (P.patch_ptr[p + 1] - s0) * NQ;
+    base = YS * P.y_off[p] + (int64_t)(sl - s0) * NQ;
+  };
+  if (staged) {
+    for (int e = tid; e < nk; e += 256) slot(k0 + e, s_base[e], s_m[e]);
+  }
+  __syncthreads();
+  const int r = tid / N, n = tid % N, dof = i0 + r;
+  if (r >= R || dof >= nf) return;
+  double acc[NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) acc[a] = 0.0;
+  const int ka = P.dof_ptr[dof], kb = P.dof_ptr[dof + 1];
+  if (staged) {
+    for (int k = ka - k0; k < kb - k0; ++k) {
+      const TY* yp = Y + s_base[k] + (int64_t)n * s_m[k];
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) acc[a] += (double)yp[a];
+    }
+  } else {
+    for (int k = ka; k < kb; ++k) {
+      int64_t base;
+      int m;
+      slot(k, base, m);
+      const TY* yp = Y + base + (int64_t)n * m;
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) acc[a] += (double)yp[a];
+    }
+  }
+  const int64_t o = ((int64_t)dof * N + n) * NQ;
+  if (mode == 0) {
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) z[o + a] = acc[a];
+  } else {
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+      const double dd = (c1 == 0.0 ? 0.0 : c1 * d[o + a]) + c2 * acc[a];
+      d[o + a] = dd;
+      x[o + a] += dd;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const double* Jv, int prec,
@@ -868,23 +991,24 @@ hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const doubl
 // as the chunked passes: every chunk from zero incoming values (outputs of
 // chunk 0, end values of every chunk), the interface recurrence, then the
 // chunks after the first from their true incoming values.
-template <int NQ, typename T, int WAVES, int NBMAX, int NBUMAX>
+template <int NQ, typename T, int WAVES, bool INV, int NBMAX, int NBUMAX>
 hipError_t sweep_generic(const LevelView& L, const PatchView& P, const void* fac, const double* Mp,
                          TimeEnds te, const double* r, double* Y, hipStream_t s) {
+  if (INV && P.slab_stride != 0) return hipErrorInvalidValue;   // INV: one block for every slab
   const T* f = (const T*)fac;
   const dim3 block(64 * WAVES);
   const int nc = P.time_chunks > 1 ? P.time_chunks : 1;
   if (nc == 1) {
     const ChunkArgs ca{L.N, 0, INT_MAX, 1, nullptr, nullptr};
-    hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, NBMAX, NBUMAX>), dim3(P.n_patch), block, 0, s, L, P, f, Mp, te, r, Y, ca);
+    hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, INV, NBMAX, NBUMAX>), dim3(P.n_patch), block, 0, s, L, P, f, Mp, te, r, Y, ca);
     return hipGetLastError();
   }
   const ChunkArgs a{P.chunk_len, 0, 0, nc, nullptr, P.chunk_w_end};
-  hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, NBMAX, NBUMAX>), dim3(P.n_patch, nc), block, 0, s, L, P, f, Mp, te, r, Y, a);
+  hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, INV, NBMAX, NBUMAX>), dim3(P.n_patch, nc), block, 0, s, L, P, f, Mp, te, r, Y, a);
   const ChunkArgs ci{P.chunk_len, 0, 0, nc, nullptr, nullptr};
   hipLaunchKernelGGL((k_patch_chunk_interface<NBUMAX>), dim3(P.n_patch), dim3(64), 0, s, P, ci, P.chunk_T, P.chunk_w_end, P.chunk_w_in);
   const ChunkArgs c{P.chunk_len, 1, INT_MAX, nc, P.chunk_w_in, nullptr};
-  hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, NBMAX, NBUMAX>), dim3(P.n_patch, nc - 1), block, 0, s, L, P, f, Mp, te, r, Y, c);
+  hipLaunchKernelGGL((k_patch_sweep<NQ, T, WAVES, INV, NBMAX, NBUMAX>), dim3(P.n_patch, nc - 1), block, 0, s, L, P, f, Mp, te, r, Y, c);
   return hipGetLastError();
 }
 
@@ -900,25 +1024,25 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
     constexpr int H = kHeatMaxNb;
     if (prec == 1) {
       switch (L.NQ) {
-        case 1: return sweep_generic<1, float, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
-        case 2: return sweep_generic<2, float, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
-        case 3: return sweep_generic<3, float, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
-        case 4: return sweep_generic<4, float, 2, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 1: return sweep_generic<1, float, 1, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 2: return sweep_generic<2, float, 1, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 3: return sweep_generic<3, float, 1, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
+        case 4: return sweep_generic<4, float, 2, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
         default: return hipErrorInvalidValue;
       }
     }
     switch (L.NQ) {
-      case 1: return sweep_generic<1, double, 1, H, H>(L, P, fac, Mp, te, r, Yd, s);
-      case 2: return sweep_generic<2, double, 2, H, H>(L, P, fac, Mp, te, r, Yd, s);
-      case 3: return sweep_generic<3, double, 3, H, H>(L, P, fac, Mp, te, r, Yd, s);
-      case 4: return sweep_generic<4, double, 4, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 1: return sweep_generic<1, double, 1, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 2: return sweep_generic<2, double, 2, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 3: return sweep_generic<3, double, 3, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
+      case 4: return sweep_generic<4, double, 4, true, H, H>(L, P, fac, Mp, te, r, Yd, s);
       default: return hipErrorInvalidValue;
     }
   }
   if (prec == 1 && P.time_chunks > 1) {
     // chunked FP32 Navier-Stokes sweeps take the generic kernel (FP64 outputs)
-    if (L.NQ == 1) return sweep_generic<1, float, 1, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
-    return sweep_generic<2, float, 2, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+    if (L.NQ == 1) return sweep_generic<1, float, 1, false, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+    return sweep_generic<2, float, 2, false, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
   }
   if (prec == 1) {
     const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
@@ -930,8 +1054,8 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
     }
     return hipGetLastError();
   }
-  if (L.NQ == 1) return sweep_generic<1, double, 2, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
-  return sweep_generic<2, double, 4, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+  if (L.NQ == 1) return sweep_generic<1, double, 2, false, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+  return sweep_generic<2, double, 4, false, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
 }
 
 template <int NQ, typename T, int NBUMAX>
@@ -976,6 +1100,26 @@ hipError_t launch_patch_chunk_transfer(const LevelView& L, const PatchView& P, i
 hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,
                                int mode, double c1, double c2, double* z, double* d, double* x,
                                hipStream_t s) {
+  if (L.N <= 256) {
+    const int R = 256 / L.N;
+    const dim3 grid((unsigned)((L.nf + R - 1) / R)), block(256);
+    if (sweep_outputs_f32(L, P, prec)) {
+      const float* Yf = (const float*)Y;
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_gather_rows<1, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
+      else hipLaunchKernelGGL((k_patch_gather_rows<2, float>), grid, block, 0, s, L.nf, L.N, P, Yf, mode, c1, c2, z, d, x);
+      return hipGetLastError();
+    }
+    const double* Yd = (const double*)Y;
+    switch (L.NQ) {
+      case 1: hipLaunchKernelGGL((k_patch_gather_rows<1, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      case 2: hipLaunchKernelGGL((k_patch_gather_rows<2, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      case 3: hipLaunchKernelGGL((k_patch_gather_rows<3, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      case 4: hipLaunchKernelGGL((k_patch_gather_rows<4, double>), grid, block, 0, s, L.nf, L.N, P, Yd, mode, c1, c2, z, d, x); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  // more than 256 slabs: one thread per (DoF, slab) with its own index chain
   const int64_t n = (int64_t)L.nf * L.N;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (sweep_outputs_f32(L, P, prec)) {
