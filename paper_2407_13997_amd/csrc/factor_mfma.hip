@@ -8,9 +8,10 @@
 // columns (a panel) at a time:
 //   panel steps, with the panel's 80 x 16 values in registers (rows lane and
 //     lane + 64): pivot search in column k (largest magnitude, ties to the
-//     smaller row), a full-row swap (registers and LDS), then the pivot row's
-//     scaling, its broadcast through LDS and the elimination applied to the
-//     panel's columns only;
+//     smaller row: a DPP wave maximum and a ballot), a full-row swap
+//     (registers and LDS), then the pivot row read from its lane, scaled by
+//     the pivot's reciprocal, and the elimination applied to the panel's
+//     columns only;
 //   trailing update: every other column receives the panel's combined
 //     transform at once, A += W R, with W = the panel columns minus the
 //     selector of the panel rows (80 x 16) and R = the panel rows of those
@@ -31,6 +32,27 @@ constexpr int kFM = 80;        // padded block order: five 16-wide tiles
 constexpr int kFS = kFM + 1;   // LDS row stride (column reads fall in distinct banks)
 constexpr int kFP = 16;        // panel width
 constexpr int kFT = kFM / 16;  // tiles per side
+
+__device__ inline float read_lane(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Maximum over the 64 lanes of a wavefront (all active; NaN entries are
+// ignored unless every entry is NaN): DPP exchanges inside each row of 16
+// lanes (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror), then the four row maxima through scalar registers.
+__device__ inline float wave_max(float v) {
+  v = fmaxf(v, dpp_f<0xB1>(v));
+  v = fmaxf(v, dpp_f<0x4E>(v));
+  v = fmaxf(v, dpp_f<0x141>(v));
+  v = fmaxf(v, dpp_f<0x140>(v));
+  return fmaxf(fmaxf(read_lane(v, 0), read_lane(v, 16)), fmaxf(read_lane(v, 32), read_lane(v, 48)));
+}
 
 __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView P, int first,
                                                           const double* __restrict__ Jv,
@@ -62,7 +84,6 @@ __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView
   __syncthreads();
   bool bad = false;
   const int lr = lane % 16, lk = lane / 16;
-  __shared__ float prow[kFP];
   __shared__ float swp[2][kFP];
   // lane l holds rows l and l + 64 (the latter for l < 16) of the panel
   const int row0 = lane, row1 = lane + 64;
@@ -75,25 +96,19 @@ __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView
       pr[0][jj] = A[row0 * kFS + k0 + jj];
       pr[1][jj] = has1 ? A[row1 * kFS + k0 + jj] : 0.0f;
     }
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int kk = 0; kk < kFP; ++kk) {
       if (kk < b) {   // uniform
         const int k = k0 + kk;
-        // pivot: largest |entry| of column k among rows k .. m-1, ties to the smaller row
-        float best = -1.0f;
-        int bi = m;
-        {
-          const float v0 = (row0 >= k && row0 < m) ? fabsf(pr[0][kk]) : -1.0f;
-          if (v0 > best) { best = v0; bi = row0; }
-          const float v1 = (has1 && row1 >= k && row1 < m) ? fabsf(pr[1][kk]) : -1.0f;
-          if (v1 > best || (v1 == best && row1 < bi)) { best = v1; bi = row1; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const float ov = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-        }
-        int pi = bi;
+        // pivot: largest |entry| of column k among rows k .. m-1, ties to the
+        // smaller row: the wave's maximum, then the first lane (rows < 64
+        // before rows >= 64) that holds it
+        const float v0 = (row0 >= k && row0 < m) ? fabsf(pr[0][kk]) : -1.0f;
+        const float v1 = (has1 && row1 >= k && row1 < m) ? fabsf(pr[1][kk]) : -1.0f;
+        const float best = wave_max(fmaxf(v0, v1));
+        const uint64_t hit0 = __ballot(v0 == best), hit1 = __ballot(v1 == best);
+        int pi = hit0 ? __ffsll((unsigned long long)hit0) - 1
+                      : (hit1 ? 64 + __ffsll((unsigned long long)hit1) - 1 : m);
         if (!(best > 0.0f) || !isfinite(best) || pi >= m) {
           bad = true;
           pi = k;
@@ -122,37 +137,34 @@ __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView
             if (has1 && row1 == pi) pr[1][jj] = swp[1][jj];
           }
         }
-        // the pivot row: scaled (its pivot entry becomes 1 / pivot) and published
-        if (row0 == k || (has1 && row1 == k)) {
-          const int sl = row0 == k ? 0 : 1;
-          float rowv[kFP];
-#pragma unroll
-          for (int jj = 0; jj < kFP; ++jj) rowv[jj] = sl == 0 ? pr[0][jj] : pr[1][jj];
-          const float pv = rowv[kk];
-#pragma unroll
-          for (int jj = 0; jj < kFP; ++jj) {
-            rowv[jj] = (jj == kk ? 1.0f : rowv[jj]) / pv;
-            prow[jj] = rowv[jj];
-            if (sl == 0) pr[0][jj] = rowv[jj];
-            else pr[1][jj] = rowv[jj];
-          }
-        }
-        __syncthreads();
+        // the pivot row, read from its lane (k < 64: lane k, first register
+        // set; else lane k - 64, second set) and scaled so that its pivot
+        // entry becomes 1 / pivot
         float pw[kFP];
+        if (k < 64) {   // uniform
 #pragma unroll
-        for (int jj = 0; jj < kFP; ++jj) pw[jj] = prow[jj];
-        // eliminate column k from the other rows (panel columns)
-        if (row0 != k) {
+          for (int jj = 0; jj < kFP; ++jj) pw[jj] = read_lane(pr[0][jj], k);
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < kFP; ++jj) pw[jj] = read_lane(pr[1][jj], k - 64);
+        }
+        const float rpv = 1.0f / pw[kk];
+#pragma unroll
+        for (int jj = 0; jj < kFP; ++jj) pw[jj] = (jj == kk ? 1.0f : pw[jj]) * rpv;
+        // the pivot row takes the scaled values, the others eliminate column k
+        // (panel columns)
+        {
           const float f = pr[0][kk];
 #pragma unroll
-          for (int jj = 0; jj < kFP; ++jj) pr[0][jj] = (jj == kk ? 0.0f : pr[0][jj]) - f * pw[jj];
+          for (int jj = 0; jj < kFP; ++jj)
+            pr[0][jj] = row0 == k ? pw[jj] : (jj == kk ? 0.0f : pr[0][jj]) - f * pw[jj];
         }
-        if (has1 && row1 != k) {
+        if (has1) {
           const float f = pr[1][kk];
 #pragma unroll
-          for (int jj = 0; jj < kFP; ++jj) pr[1][jj] = (jj == kk ? 0.0f : pr[1][jj]) - f * pw[jj];
+          for (int jj = 0; jj < kFP; ++jj)
+            pr[1][jj] = row1 == k ? pw[jj] : (jj == kk ? 0.0f : pr[1][jj]) - f * pw[jj];
         }
-        __syncthreads();
       }
     }
 #pragma unroll
