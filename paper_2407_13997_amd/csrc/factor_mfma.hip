@@ -33,27 +33,6 @@ constexpr int kFS = kFM + 1;   // LDS row stride (column reads fall in distinct 
 constexpr int kFP = 16;        // panel width
 constexpr int kFT = kFM / 16;  // tiles per side
 
-__device__ inline float read_lane(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-template <int CTRL>
-__device__ inline float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Maximum over the 64 lanes of a wavefront (all active; NaN entries are
-// ignored unless every entry is NaN): DPP exchanges inside each row of 16
-// lanes (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
-// row_mirror), then the four row maxima through scalar registers.
-__device__ inline float wave_max(float v) {
-  v = fmaxf(v, dpp_f<0xB1>(v));
-  v = fmaxf(v, dpp_f<0x4E>(v));
-  v = fmaxf(v, dpp_f<0x141>(v));
-  v = fmaxf(v, dpp_f<0x140>(v));
-  return fmaxf(fmaxf(read_lane(v, 0), read_lane(v, 16)), fmaxf(read_lane(v, 32), read_lane(v, 48)));
-}
-
 __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView P, int first,
                                                           const double* __restrict__ Jv,
                                                           float* __restrict__ fac,

@@ -54,9 +54,9 @@ __device__ inline float4 load_stream(const float* p) {
 // one column, so the active column is always register 0 and every register
 // index is static; after m steps position j holds column (j + m) mod MAXM
 // (columns past m are zero padding and stay zero).  A step is a pivot search
-// (wavefront reduction, plus LDS across wavefronts when TPB > 64), a row swap
-// and the broadcast of the scaled pivot row through LDS, and the elimination
-// in registers.  The column permutation of the pivoting is applied while
+// (DPP wavefront maximum and ballots, plus LDS across wavefronts when
+// TPB > 64), a row swap, the pivot row scaled by the pivot's reciprocal and
+// broadcast through LDS, and the elimination in registers.  The column permutation of the pivoting is applied while
 // writing the inverse out in the sweep's panel layout.  Per element the
 // arithmetic and the pivot choice (largest magnitude, ties to the smaller
 // row) are those of the textbook in-place Gauss-Jordan inverse.
@@ -120,19 +120,24 @@ __global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, 
     }
   }
   for (int k = 0; k < m; ++k) {
-    // pivot: largest |entry| of column k among rows >= k
-    T best = (T)-1;
-    int bi = m;
+    // pivot: largest |entry| of column k among rows >= k, ties to the smaller
+    // row: each wavefront's maximum (DPP), the first of its rows holding it
+    // (ballots; register r = 0 holds the wavefront's smaller rows), then the
+    // best over the wavefronts through LDS
+    T vr[RPL];
+    T vmax = (T)-1;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = tid + TPB * r;
-      const T v = (i >= k && i < m) ? fabs(a[r][0]) : (T)-1;
-      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+      vr[r] = (i >= k && i < m) ? fabs(a[r][0]) : (T)-1;
+      vmax = fmax(vmax, vr[r]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const T ov = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    T best = wave_max(vmax);
+    int bi = m;
+#pragma unroll
+    for (int r = RPL - 1; r >= 0; --r) {
+      const uint64_t hit = __ballot(vr[r] == best);
+      if (hit) bi = TPB * r + (tid / 64) * 64 + __ffsll((unsigned long long)hit) - 1;
     }
     if constexpr (NW > 1) {
       if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
@@ -163,33 +168,36 @@ __global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, 
         if (i == pi) get(swp[1], r);
       }
     }
-    // scale the pivot row (its pivot entry becomes 1 / pivot) and publish it
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      if (tid + TPB * r == k) {
-        const T pv = a[r][0];
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j) a[r][j] = (j == 0 ? (T)1 : a[r][j]) / pv;
-        put(prow, r);
-      }
-    }
-    __syncthreads();
-    // eliminate column k from the other rows, one column at a time so that
-    // each pivot-row value is read just before its use; then rotate
+    // the pivot row scaled by the pivot's reciprocal (its pivot entry becomes
+    // 1 / pivot); the other rows eliminate column k; then every row rotates
     T f[RPL];
-    bool live[RPL];
+    bool live[RPL], own[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = tid + TPB * r;
       live[r] = i < m && i != k;
+      own[r] = i == k;
       f[r] = a[r][0];
     }
+    // the owner scales its row and publishes it in LDS
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      if (own[r]) {
+        const T rp = (T)1 / a[r][0];
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) a[r][j] = (j == 0 ? (T)1 : a[r][j]) * rp;
+        put(prow, r);
+      }
+    }
+    __syncthreads();
     {
       const T p0 = prow[0];
 #pragma unroll
       for (int r = 0; r < RPL; ++r)
         if (live[r]) a[r][0] = -f[r] * p0;
     }
+    // one column at a time, so that each pivot-row value is read just
+    // before its use
 #pragma unroll
     for (int j0 = 0; j0 < MP; j0 += RV) {
       const V16 v = *reinterpret_cast<const V16*>(prow + j0);
