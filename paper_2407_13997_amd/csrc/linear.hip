@@ -372,71 +372,9 @@ __global__ __launch_bounds__(kBlock) void k_gj_unpermute(int m, double* __restri
 // panel rows of those columns: one pass over each matrix per panel instead of
 // one per column.
 constexpr int kGjPanel = 32;
-
-__global__ __launch_bounds__(kBlock) void k_bgj_panel(int m, int k0, int k1, double* __restrict__ Ball,
-                                                      int* __restrict__ perm,
-                                                      double* __restrict__ colbuf,
-                                                      int* __restrict__ status) {
-  double* B = Ball + (int64_t)blockIdx.x * m * m;
-  double* col = colbuf + (int64_t)blockIdx.x * m;
-  __shared__ double rv[kBlock / 64];
-  __shared__ int ri[kBlock / 64];
-  __shared__ int piv_s;
-  const int tid = threadIdx.x, b = k1 - k0;
-  for (int k = k0; k < k1; ++k) {
-    double best = -1.0;
-    int bi = m;
-    for (int i = k + tid; i < m; i += kBlock) {
-      const double v = fabs(B[(int64_t)i * m + k]);
-      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double bb = rv[0];
-      int p = ri[0];
-      for (int w = 1; w < kBlock / 64; ++w)
-        if (rv[w] > bb || (rv[w] == bb && ri[w] < p)) { bb = rv[w]; p = ri[w]; }
-      if (!(bb > 0.0) || !isfinite(bb) || p >= m) {
-        status[0] = 1;
-        p = k;
-      }
-      piv_s = p;
-      perm[(int64_t)blockIdx.x * m + k] = p;
-    }
-    __syncthreads();
-    const int p = piv_s;
-    if (p != k && tid < b) {
-      const int j = k0 + tid;
-      const double a = B[(int64_t)k * m + j];
-      B[(int64_t)k * m + j] = B[(int64_t)p * m + j];
-      B[(int64_t)p * m + j] = a;
-    }
-    __syncthreads();
-    const double pv = B[(int64_t)k * m + k];
-    __syncthreads();
-    if (tid < b) {
-      const int j = k0 + tid;
-      B[(int64_t)k * m + j] = (j == k ? 1.0 : B[(int64_t)k * m + j]) / pv;
-    }
-    __syncthreads();
-    for (int i = tid; i < m; i += kBlock) col[i] = B[(int64_t)i * m + k];
-    __syncthreads();
-    for (int e = tid; e < m * b; e += kBlock) {
-      const int i = e / b, j = k0 + e % b;
-      if (i == k) continue;
-      const double f = col[i];
-      if (j == k) B[(int64_t)i * m + j] = -f * B[(int64_t)k * m + k];
-      else B[(int64_t)i * m + j] -= f * B[(int64_t)k * m + j];
-    }
-    __syncthreads();
-  }
-}
+// narrower panels where a thread keeps 6 or 8 rows' segments in registers
+constexpr int kGjPanel6 = 12;   // 1536 < m <= 3072
+constexpr int kGjPanel8 = 10;   // 3072 < m <= kMaxCoarse
 
 // Row swaps of the panel applied to every non-panel column, then the panel
 // rows of those columns copied to R (kGjPanel x m per matrix).
@@ -493,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, do
   for (int a = 0; a < 4; ++a)
     for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
 #pragma unroll 4
-  for (int t = 0; t < kGjPanel; ++t) {
+  for (int t = 0; t < b; ++t) {
     double wv[4], rv4[4];
     for (int a = 0; a < 4; ++a) wv[a] = Ws[tr + 16 * a][t];
     for (int c = 0; c < 4; ++c) rv4[c] = Rs[t][tc + 16 * c];
@@ -512,21 +450,22 @@ __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, do
 }
 
 // Register-resident panel of the blocked Gauss-Jordan inverse, for m <= 512 RP:
-// thread t keeps the panel segments (kGjPanel columns) of rows t + 512 r,
-// r < RP, in registers for the whole panel, so a column step costs a few LDS
+// thread t keeps the panel segments (PB columns) of rows t + 512 r, r < RP,
+// in registers for the whole panel, so a column step costs a few LDS
 // exchanges instead of a pass over the panel in memory.  After each step the
 // segments rotate left by one column, so the active column is always
 // register 0 and every register index is static; after b steps position j
-// holds panel column (j + b) mod kGjPanel.  Per element the arithmetic and
-// the pivot choice (largest magnitude, ties to the smaller row) are those of
-// k_bgj_panel.
+// holds panel column (j + b) mod PB.  Per element the arithmetic is that of
+// the column-at-a-time Gauss-Jordan inverse restricted to the panel columns
+// (the pivot row scaled by the pivot's reciprocal), and the pivot is the
+// largest magnitude, ties to the smaller row.
 constexpr int kPanelThreads = 512;
-template <int RP>
+template <int RP, int PB>
 __global__ __launch_bounds__(kPanelThreads) void k_bgj_panel_reg(int m, int k0, int k1,
                                                                  double* __restrict__ Ball,
                                                                  int* __restrict__ perm,
                                                                  int* __restrict__ status) {
-  constexpr int T = kPanelThreads, NW = T / 64, PB = kGjPanel;
+  constexpr int T = kPanelThreads, NW = T / 64;
   double* B = Ball + (int64_t)blockIdx.x * m * m;
   int* pm = perm + (int64_t)blockIdx.x * m;
   __shared__ double rv[NW];
@@ -543,19 +482,24 @@ __global__ __launch_bounds__(kPanelThreads) void k_bgj_panel_reg(int m, int k0, 
   }
   for (int kk = 0; kk < b; ++kk) {
     const int k = k0 + kk;
-    // pivot: largest |a| in column k among rows >= k
-    double best = -1.0;
-    int bi = m;
+    // pivot: largest |a| in column k among rows >= k, ties to the smaller
+    // row: each wavefront's maximum (DPP) and the first of its rows holding
+    // it (ballots; register r = 0 holds its smaller rows), then the best over
+    // the wavefronts through LDS
+    double vr[RP];
+    double vmax = -1.0;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       const int i = tid + T * r;
-      const double v = (i >= k && i < m) ? fabs(a[r][0]) : -1.0;
-      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+      vr[r] = (i >= k && i < m) ? fabs(a[r][0]) : -1.0;
+      vmax = fmax(vmax, vr[r]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    const double best = wave_max(vmax);
+    int bi = m;
+#pragma unroll
+    for (int r = RP - 1; r >= 0; --r) {
+      const uint64_t hit = __ballot(vr[r] == best);
+      if (hit) bi = T * r + (tid / 64) * 64 + __ffsll((unsigned long long)hit) - 1;
     }
     if (tid % 64 == 0) { rv[tid / 64] = best; ri[tid / 64] = bi; }
     __syncthreads();
@@ -592,14 +536,15 @@ __global__ __launch_bounds__(kPanelThreads) void k_bgj_panel_reg(int m, int k0, 
           for (int j = 0; j < PB; ++j) a[r][j] = swp[1][j];
       }
     }
-    // scale the pivot row: the pivot entry becomes 1 / pivot
+    // scale the pivot row by the pivot's reciprocal: the pivot entry becomes
+    // 1 / pivot
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       if (tid + T * r == k) {
-        const double pv = a[r][0];
+        const double rp = 1.0 / a[r][0];
 #pragma unroll
         for (int j = 0; j < PB; ++j) {
-          a[r][j] = (j == 0 ? 1.0 : a[r][j]) / pv;
+          a[r][j] = (j == 0 ? 1.0 : a[r][j]) * rp;
           prow[j] = a[r][j];
         }
       }
@@ -868,16 +813,21 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
     return hipGetLastError();
   }
   const dim3 gs(nblk(m), nmat), gt((m + 63) / 64, (m + 63) / 64, nmat), gp(nblk(m), nmat);
-  for (int k0 = 0; k0 < m; k0 += kGjPanel) {
-    const int k1 = k0 + kGjPanel < m ? k0 + kGjPanel : m;
+  // panels of kGjPanel columns up to 3 rows per thread, narrower ones (6 or
+  // 8 rows per thread, up to kMaxCoarse) so that the panel stays in registers
+  const int pw = m <= kPanelThreads * 3 ? kGjPanel : (m <= kPanelThreads * 6 ? kGjPanel6 : kGjPanel8);
+  for (int k0 = 0; k0 < m; k0 += pw) {
+    const int k1 = k0 + pw < m ? k0 + pw : m;
     if (m <= kPanelThreads)
-      hipLaunchKernelGGL(k_bgj_panel_reg<1>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+      hipLaunchKernelGGL((k_bgj_panel_reg<1, kGjPanel>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else if (m <= kPanelThreads * 2)
-      hipLaunchKernelGGL(k_bgj_panel_reg<2>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+      hipLaunchKernelGGL((k_bgj_panel_reg<2, kGjPanel>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else if (m <= kPanelThreads * 3)
-      hipLaunchKernelGGL(k_bgj_panel_reg<3>, dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+      hipLaunchKernelGGL((k_bgj_panel_reg<3, kGjPanel>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+    else if (m <= kPanelThreads * 6)
+      hipLaunchKernelGGL((k_bgj_panel_reg<6, kGjPanel6>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else
-      hipLaunchKernelGGL(k_bgj_panel, dim3(nmat), dim3(kBlock), 0, s, m, k0, k1, B, perm, colbuf, status);
+      hipLaunchKernelGGL((k_bgj_panel_reg<8, kGjPanel8>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf);
     hipLaunchKernelGGL(k_bgj_update, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
   }

@@ -144,3 +144,23 @@ def test_heat_paper_iteration_counts(M, L, k, q):
     want = paper_iterations(M, k, q)
     log(f"[heat {M}x{M} k={k} q={q}] st-dofs={p.n_st} iterations fp64={its[0]} fp32={its[1]} (paper {want})")
     assert its[0] == want and its[1] == want
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_heat_large_coarsest_inverse(q):
+    """The coarsest blocks of the paper's P3 runs at q = 2, 3 (the 10 x 10 P3
+    lattice, 961 nodes: orders 2,883 and 3,844, inverted by the register-panel
+    blocked Gauss-Jordan with 6 and 8 rows per thread): the coarse solve
+    against the oracle's dense solve, here under a 20 x 20 finest level."""
+    torch_cuda()
+    N = 3
+    p = w.heat_problem(20, 2, 3, q, N)
+    G = gpu_problem(p)
+    H = _oracle(20, 2, 3, q, N)
+    bc = seeded(H.A[1].shape[0], 8)
+    xc = G.vec(1)
+    G.coarse_solve(to_dev(bc), xc)
+    e = rel(to_host(xc), H.coarse.solve(bc))
+    log(f"[heat coarse 10x10 P3 q={q}] order {H.A[1].shape[0] // N} rel={e:.1e}")
+    assert e < 1e-11
+    G.close()
