@@ -202,21 +202,26 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
   const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ CellStage<NQ> S;
   stage_cell<NQ>(L, T, mms, U, c, n, S);
-  const int G = T->G;
+  // temporal Gauss points (q + 3 = NQ + 2, as the reference tables are built):
+  // a compile-time count keeps the per-thread accumulators in registers
+  constexpr int G = NQ + 2;
   const double dt = L.dt, R = mms.reynolds;
   const int* nzc = L.cell_nz + (int64_t)225 * c;
   if (tid < 36) {
     const int i = tid / 6, j = tid % 6;
     double Mij = 0.0, Kij = 0.0;
-    double c1[kMaxG], c2[kMaxG][2][2];
+    double c1[G], c2[G][2][2];
+#pragma unroll
     for (int g = 0; g < G; ++g) {
       c1[g] = 0.0;
       c2[g][0][0] = c2[g][0][1] = c2[g][1][0] = c2[g][1][1] = 0.0;
     }
+#pragma unroll 1
     for (int x = 0; x < kQx; ++x) {
       const double w = S.wdet[x], Ni = T->N2[x][i], Nj = T->N2[x][j];
       Mij += w * Ni * Nj;
       Kij += w * (S.gN[x][i][0] * S.gN[x][j][0] + S.gN[x][i][1] * S.gN[x][j][1]);
+#pragma unroll
       for (int g = 0; g < G; ++g) {
         c1[g] += w * Ni * (S.uq[g][x][0] * S.gN[x][j][0] + S.uq[g][x][1] * S.gN[x][j][1]);
         const double wnn = w * Ni * Nj;
@@ -227,6 +232,7 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
     for (int a = 0; a < NQ; ++a)
       for (int b = 0; b < NQ; ++b) {
         double C1 = 0.0, C2[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
         for (int g = 0; g < G; ++g) {
           const double cw = T->wg[g] * T->Phi[g][a] * T->Phi[g][b];
           C1 += cw * c1[g];
