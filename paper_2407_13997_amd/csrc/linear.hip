@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_unpermute(int m, double* __restri
 // one per column.
 constexpr int kGjPanel = 32;
 // narrower panels where a thread keeps 6 or 8 rows' segments in registers
-constexpr int kGjPanel6 = 12;   // 1536 < m <= 3072
+constexpr int kGjPanel6 = 16;   // 1536 < m <= 3072
 constexpr int kGjPanel8 = 10;   // 3072 < m <= kMaxCoarse
 
 // Row swaps of the panel applied to every non-panel column, then the panel
