@@ -175,6 +175,34 @@ def test_coarse_solve(case):
     assert e_o < tol and e_t < tol
 
 
+def test_coarse_solve_order_1688():
+    """A 10 x 10 coarsest level, as under the paper's 80 x 80 Chorin and cavity
+    hierarchies: bordered slab blocks of order 1,688 (q = 1), three of them
+    inverted together by the register-panel blocked Gauss-Jordan at 6 rows per
+    thread and 16-column panels, against the oracle's dense solve."""
+    torch_cuda()
+    from oracle.multigrid import CoarseSolver, project_pressure
+    prob = w.small_problem(20, 2, 1, 3, 10.0, 16)
+    G = gpu_problem(prob)
+    H = oracle_hierarchy(prob)
+    U = seeded(H.levels[0].n_st, 1016, 0.3)
+    G.assemble(to_dev(U))
+    H.assemble(U, with_smoothers=False)
+    lev = H.levels[-1]
+    xt = project_pressure(lev, seeded(lev.n_st, 32))
+    b = H.A[-1] @ xt
+    x = G.vec(len(H.levels) - 1)
+    G.coarse_solve(to_dev(b), x)
+    xo = CoarseSolver(lev, H.A[-1]).solve(b)
+    kappa = coarse_condition(lev, H.A[-1])
+    tol = max(1e-12, 50.0 * kappa * np.finfo(float).eps)
+    e_o, e_t = rel(to_host(x), xo), rel(to_host(x), xt)
+    log(f"[coarse 10x10 q=1] order {lev.n_free * lev.nq + lev.nq} kappa={kappa:.2e} tol={tol:.1e} "
+        f"vs oracle {e_o:.2e} vs truth {e_t:.2e}")
+    assert e_o < tol and e_t < tol
+    G.close()
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_patch_apply_fp64(case):
     prob, G, H, U, Ud = setup_case(case)
