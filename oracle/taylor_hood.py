@@ -1,0 +1,133 @@
+"""Taylor-Hood P_{k+1}-P_k structure on the structured mesh, for any k >= 1
+(oracle; test infrastructure only): Lagrange node lattices, the nodes of each
+cell, Vanka+star patches and the structural nonzeros of their matrices
+(Sec. 2 eq. nsfem with velocity of degree k+1 and pressure of degree k;
+Sec. 3 and Sec. 3.1 for the patches and their counts).
+
+The mesh is the one of oracle/mesh.py: M x M squares, square (i, j) split into
+the cells (v_ij, v_i+1,j, v_i,j+1) and (v_i+1,j+1, v_i,j+1, v_i+1,j).  A
+degree-K Lagrange space has the (KM+1)^2 lattice nodes of spacing h/K; node
+(gi, gj) is gi + (KM+1) gj.  A cell with vertex grid coordinates A, B, C
+holds the lattice nodes K A + s (B - A) + t (C - A), s, t >= 0, s + t <= K.
+
+Vanka+star patch of vertex v: every velocity node in the closure of the star
+of v (all nodes of the cells around v), both components, and the pressure
+nodes in the interior of the star (v and the nodes inside the edges and cells
+incident to v).  Two DoFs are structurally coupled when their nodes share a
+cell; the patch matrix holds the 2 x 2 component block of every coupled
+velocity node pair, both off-diagonal velocity-pressure blocks of every
+coupled (velocity node, pressure node) pair, and no pressure-pressure block.
+
+Every count here is a plain enumeration: no formula of the paper is used to
+produce it, so that the paper's closed forms can pin it.
+"""
+import numpy as np
+
+
+def _cells(M):
+    """(2 M^2, 3) vertex grid coordinates (i, j) of each cell's vertices."""
+    out = []
+    for j in range(M):
+        for i in range(M):
+            out.append([(i, j), (i + 1, j), (i, j + 1)])
+            out.append([(i + 1, j + 1), (i, j + 1), (i + 1, j)])
+    return np.array(out, dtype=np.int64)
+
+
+def cell_lattice_nodes(M, K):
+    """(2 M^2, (K+1)(K+2)/2) lattice node ids of the degree-K nodes of each cell."""
+    C = _cells(M)
+    n = K * M + 1
+    nodes = []
+    for A, B, Cv in C:
+        A, B, Cv = np.array(A), np.array(B), np.array(Cv)
+        row = []
+        for t in range(K + 1):
+            for s in range(K + 1 - t):
+                g = K * A + s * (B - A) + t * (Cv - A)
+                row.append(g[0] + n * g[1])
+        nodes.append(row)
+    return np.array(nodes, dtype=np.int64)
+
+
+class TaylorHood:
+    """P_{k+1} velocity / P_k pressure on the M x M mesh."""
+
+    def __init__(self, M, k):
+        if k < 1:
+            raise ValueError("pressure degree k must be at least 1")
+        self.M, self.k = M, k
+        self.Kv, self.Kp = k + 1, k
+        self.nv_side = (k + 1) * M + 1
+        self.np_side = k * M + 1
+        self.vel_cells = cell_lattice_nodes(M, self.Kv)
+        self.p_cells = cell_lattice_nodes(M, self.Kp)
+        self.cells = _cells(M)
+        self.nc = len(self.cells)
+
+    # --- counts over the whole mesh -----------------------------------------
+    def n_dofs_total(self):
+        """Every DoF, Dirichlet ones included: two velocity components on the
+        velocity lattice and one pressure per pressure-lattice node."""
+        return 2 * self.nv_side ** 2 + self.np_side ** 2
+
+    def n_dofs_free(self):
+        """Velocity DoFs at interior lattice nodes (Dirichlet boundary) plus all pressures."""
+        return 2 * (self.nv_side - 2) ** 2 + self.np_side ** 2
+
+    def _vel_interior(self, g):
+        gi, gj = g % self.nv_side, g // self.nv_side
+        return (gi > 0) & (gi < self.nv_side - 1) & (gj > 0) & (gj < self.nv_side - 1)
+
+    # --- patches --------------------------------------------------------------
+    def star_cells(self, v):
+        """Cells having grid vertex v = (i, j) as a vertex."""
+        i, j = v
+        hit = np.all(self.cells == np.array([i, j]), axis=2).any(axis=1)
+        return np.nonzero(hit)[0]
+
+    def patch(self, v, free_only=True):
+        """(velocity lattice nodes, pressure lattice nodes) of the Vanka+star
+        patch of grid vertex v.  With free_only, velocity nodes on the
+        Dirichlet boundary are left out."""
+        cs = self.star_cells(v)
+        vel = np.unique(self.vel_cells[cs].ravel())
+        if free_only:
+            vel = vel[self._vel_interior(vel)]
+        # pressure nodes inside the star: those of the star's cells that lie
+        # on no edge opposite v (the star's outer boundary)
+        Kp, n = self.Kp, self.np_side
+        pres = set()
+        for c in cs:
+            verts = [tuple(x) for x in self.cells[c]]
+            a = verts.index(tuple(v))
+            A = np.array(verts[a])
+            B, Cv = np.array(verts[(a + 1) % 3]), np.array(verts[(a + 2) % 3])
+            for t in range(Kp + 1):
+                for s in range(Kp + 1 - t):
+                    if s + t == Kp and Kp > 0:   # on the edge opposite v
+                        continue
+                    g = Kp * A + s * (B - A) + t * (Cv - A)
+                    pres.add(int(g[0] + n * g[1]))
+        return vel, np.array(sorted(pres), dtype=np.int64)
+
+    def patch_dofs(self, v, free_only=True):
+        vel, pres = self.patch(v, free_only)
+        return 2 * len(vel) + len(pres)
+
+    def patch_nnz(self, v, free_only=True):
+        """Structural nonzeros of the patch matrix: 4 per coupled (ordered)
+        velocity node pair, 2 x 2 per coupled (velocity node, pressure node)
+        pair (the (1,2) and (2,1) blocks), none between pressures."""
+        vel, pres = self.patch(v, free_only)
+        vset, pset = set(vel.tolist()), set(pres.tolist())
+        vv, vp = set(), set()
+        for c in range(self.nc):
+            cv = [g for g in self.vel_cells[c] if g in vset]
+            cp = [g for g in self.p_cells[c] if g in pset]
+            for a in cv:
+                for b in cv:
+                    vv.add((a, b))
+                for r in cp:
+                    vp.add((a, r))
+        return 4 * len(vv) + 4 * len(vp)
