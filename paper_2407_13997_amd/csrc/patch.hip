@@ -566,6 +566,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   constexpr bool kTwo = MAXM > 64;
   // one wavefront and at most 64 rows: row i's product ends on lane i
   constexpr bool kLane = WAVES == 1 && !kTwo;
+  // one wavefront and at most two temporal nodes: the slab-end values and the
+  // jump coupling stay in registers (DPP pair sums and v_readlane broadcasts)
+  constexpr bool kFast = kLane && NQ <= 2;
   constexpr int G = kRGroup;
   static_assert(MAXM <= 64 * WAVES && NBUMAX <= 64, "a thread per row and per velocity DoF");
   static_assert(!kLane || MAXP <= PW, "one wavefront holds every panel");
@@ -621,7 +624,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   const bool hasRow = tid < m;
   const int64_t rbase = hasRow ? (int64_t)dofs[tid / NQ] * N * NQ + tid % NQ : 0;
   const int ia = tid / NQ, aa = tid % NQ;
-  double e0a = te.e0[aa];
+  double e0a = te.e0[aa], e1a = te.e1[aa];
   V cur1[PWU], cur2[K2];
   V nxt1[INV ? 1 : PWU], nxt2[INV ? 1 : K2];
   {
@@ -653,7 +656,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   // the block registers and e0a count as written here (an empty asm takes
   // them in and out), so the slab loop waits on memory only for the residual
   // groups and, without INV, for the next block
-  asm volatile("" : "+v"(e0a));
+  asm volatile("" : "+v"(e0a), "+v"(e1a));
 #pragma unroll
   for (int q = 0; q < PWU; ++q) pin_loaded(cur1[q]);
   if constexpr (kTwo) {
@@ -662,6 +665,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   }
   const int quarter = lane & 3;
   __syncthreads();
+  // kFast: this lane's DoF's coupling (mjr) and slab-end value (yendr)
+  double mjr = (kFast && ia < nbu) ? mj[ia] : 0.0, yendr = 0.0;
+  const int iac = ia < nbu ? ia : 0;
   for (int n = n0; n < n1; ++n) {
     const int jr = (n - n0) % G;
     // a group's first slab starts the loads of the next group (uniform)
@@ -677,7 +683,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
     }
     if (hasRow) {
       double gv = rs[jr][tid];
-      if (n > 0 && ia < nbu) gv += e0a * mj[ia];
+      if (n > 0 && ia < nbu) gv += e0a * (kFast ? mjr : mj[ia]);
       g[tid] = (T)gv;
     }
     __syncthreads();
@@ -711,6 +717,34 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
 #pragma unroll
         for (int v = 0; v < WAVES; ++v) y += v < lay.waves ? part[v][tid] : 0.0;
       }
+    }
+    if constexpr (kFast) {
+      if (hasRow && write_y) yout[(int64_t)n * m + tid] = y;
+      // slab-end value of the lane's DoF: its NQ rows sit in adjacent lanes
+      double ve = e1a * y;
+      if constexpr (NQ == 2) ve += dpp_move<0xB1>(ve);   // quad_perm [1,0,3,2]
+      yendr = ve;
+      // the next group's residual, loaded since this group's first slab (uniform)
+      if (jr == G - 1 && n + 1 < n1) park_r();
+      // coupling of the next slab, mj(ia) = sum_k M_v(ia, k) (slab-end value
+      // of DoF k, from lane k NQ), formed by every lane of the DoF
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NBUMAX; ++k) {
+        if (k < nbu) {   // uniform
+          const double t = MsT[k * nbu + iac] * read_lane(ve, k * NQ);
+          if (k % 4 == 0) a0 += t;
+          else if (k % 4 == 1) a1 += t;
+          else if (k % 4 == 2) a2 += t;
+          else a3 += t;
+        }
+      }
+      mjr = (a0 + a1) + (a2 + a3);
+      if constexpr (!INV) {
+#pragma unroll
+        for (int q = 0; q < PWU; ++q) cur1[q] = nxt1[q];
+      }
+      continue;
     }
     if (hasRow) {
       ys[tid] = y;
@@ -748,8 +782,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
       }
     }
   }
-  // the chunk's final slab-end values (yend holds its last slab's)
-  if (ca.w_end && tid < nbu) ca.w_end[((int64_t)p * ca.n_chunks + chunk) * NBUMAX + tid] = yend[tid];
+  // the chunk's final slab-end values (yend, or with kFast yendr in lane
+  // d NQ, holds its last slab's)
+  if constexpr (kFast) {
+    if (ca.w_end && aa == 0 && ia < nbu) ca.w_end[((int64_t)p * ca.n_chunks + chunk) * NBUMAX + ia] = yendr;
+  } else {
+    if (ca.w_end && tid < nbu) ca.w_end[((int64_t)p * ca.n_chunks + chunk) * NBUMAX + tid] = yend[tid];
+  }
 #undef O1
 #undef O2
 }
