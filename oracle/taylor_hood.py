@@ -19,9 +19,17 @@ velocity node pair, both off-diagonal velocity-pressure blocks of every
 coupled (velocity node, pressure node) pair, and no pressure-pressure block.
 
 Every count here is a plain enumeration: no formula of the paper is used to
-produce it, so that the paper's closed forms can pin it.
+produce it, so that the paper's closed forms can pin it.  The spatial
+operators of eq. nsfem's linear terms (velocity mass and stiffness of one
+component, the two divergence blocks) are assembled cell by cell with the
+degree-8 triangle rule, which integrates every one of them exactly for
+k <= 2.
 """
 import numpy as np
+import scipy.sparse as sp
+
+from .heat import HeatSpace, lagrange_pk
+from .quadrature import duffy_triangle
 
 
 def _cells(M):
@@ -131,3 +139,36 @@ class TaylorHood:
                 for r in cp:
                     vp.add((a, r))
         return 4 * len(vv) + 4 * len(vp)
+
+
+def spatial_operators(M, k):
+    """Velocity mass Mu and stiffness Ku of one component (degree k+1) and the
+    divergence blocks Bx[r, u] = int psi_r d(phi_u)/dx, By likewise (pressure
+    degree k rows, velocity degree k+1 columns), over every lattice node
+    (Dirichlet nodes included), as CSR matrices.  Velocity and pressure nodes
+    are numbered on their own lattices, as in TaylorHood."""
+    V, P = HeatSpace(M, k + 1), HeatSpace(M, k)
+    Mu, Ku = V.matrices()
+    pts, w = duffy_triangle(5)
+    _, vgrad = lagrange_pk(k + 1, pts)
+    pval, _ = lagrange_pk(k, pts)
+    mesh = V.mesh
+    rows, cols, bx, by = [], [], [], []
+    for c in range(mesh.nc):
+        v = mesh.vxy[mesh.cells[c]]
+        J = np.stack([v[1] - v[0], v[2] - v[0]], axis=1)
+        det = abs(np.linalg.det(J))
+        G = vgrad @ np.linalg.inv(J)           # physical velocity gradients (nq, nloc_v, 2)
+        Bxe = np.einsum("q,qr,qu->ru", w * det, pval, G[:, :, 0])
+        Bye = np.einsum("q,qr,qu->ru", w * det, pval, G[:, :, 1])
+        pn, vn = P.cell_nodes[c], V.cell_nodes[c]
+        rows.append(np.repeat(pn, len(vn)))
+        cols.append(np.tile(vn, len(pn)))
+        bx.append(Bxe.ravel())
+        by.append(Bye.ravel())
+    r, cc = np.concatenate(rows), np.concatenate(cols)
+    Bx = sp.csr_matrix((np.concatenate(bx), (r, cc)), shape=(P.n, V.n))
+    By = sp.csr_matrix((np.concatenate(by), (r, cc)), shape=(P.n, V.n))
+    Bx.sum_duplicates()
+    By.sum_duplicates()
+    return Mu, Ku, Bx, By, V, P

@@ -70,3 +70,56 @@ def test_boundary_patches_are_smaller():
     interior = th.patch_dofs((3, 3))
     assert th.patch_dofs((0, 0)) < th.patch_dofs((0, 3)) < interior
     assert th.n_dofs_free() == 2 * (3 * 6 - 1) ** 2 + (2 * 6 + 1) ** 2
+
+
+def _mono_integral(p, r):
+    """int over the unit square of x^p y^r."""
+    return 1.0 / ((p + 1) * (r + 1))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("M", [2, 4])
+def test_spatial_operators_integrate_polynomials_exactly(M, k):
+    """The degree-(k+1) velocity and degree-k pressure spaces reproduce
+    monomials of their degree, and the degree-8 rule integrates the mass,
+    stiffness and divergence integrands exactly: u^T M u, u^T K u and
+    q^T B u equal the closed-form integrals over the unit square."""
+    from oracle.taylor_hood import spatial_operators
+    Mu, Ku, Bx, By, V, P = spatial_operators(M, k)
+    K = k + 1
+    assert Mu.sum() == pytest.approx(1.0, abs=1e-13)
+    assert np.abs(Ku @ np.ones(V.n)).max() < 1e-12
+    x, y = V.xy[:, 0], V.xy[:, 1]
+    px, py = P.xy[:, 0], P.xy[:, 1]
+    for a in range(K + 1):
+        b = K - a
+        u = x ** a * y ** b
+        assert u @ (Mu @ u) == pytest.approx(_mono_integral(2 * a, 2 * b), rel=1e-12)
+        grad2 = (a * a * _mono_integral(2 * a - 2, 2 * b) if a else 0.0) + \
+                (b * b * _mono_integral(2 * a, 2 * b - 2) if b else 0.0)
+        assert u @ (Ku @ u) == pytest.approx(grad2, rel=1e-12, abs=1e-13)
+        for c in range(k + 1):
+            d = k - c
+            q = px ** c * py ** d
+            ex = a * _mono_integral(c + a - 1, d + b) if a else 0.0
+            ey = b * _mono_integral(c + a, d + b - 1) if b else 0.0
+            assert q @ (Bx @ u) == pytest.approx(ex, rel=1e-12, abs=1e-13)
+            assert q @ (By @ u) == pytest.approx(ey, rel=1e-12, abs=1e-13)
+
+
+@pytest.mark.parametrize("k,nnz", [(1, 728), (2, 2552)])
+def test_assembled_patterns_give_the_patch_nonzeros(k, nnz):
+    """The sparsity of the assembled operators, restricted to an interior
+    Vanka+star patch, has the structural nonzeros the enumeration and Sec. 3.1
+    give: 4 per coupled velocity node pair (the velocity blocks), 2 x 2 per
+    coupled (velocity, pressure) node pair."""
+    from oracle.taylor_hood import spatial_operators
+    Mu, Ku, Bx, By, V, P = spatial_operators(6, k)
+    th = TaylorHood(6, k)
+    vel, pres = th.patch((3, 3))
+    # stored entries (the assembly stores every pair of nodes of a cell, zeros
+    # included); Bx and By share one pattern
+    vv = Mu[vel][:, vel].nnz
+    pv = Bx[pres][:, vel].nnz
+    assert By[pres][:, vel].nnz == pv
+    assert 4 * vv + 4 * pv == nnz == th.patch_nnz((3, 3))
