@@ -375,6 +375,7 @@ constexpr int kGjPanel = 32;
 // narrower panels where a thread keeps 6 or 8 rows' segments in registers
 constexpr int kGjPanel6 = 16;   // 1536 < m <= 3072
 constexpr int kGjPanel8 = 10;   // 3072 < m <= kMaxCoarse
+static_assert(kGjPanel8 <= kGjPanel6 && kGjPanel6 <= kGjPanel, "the update's staging bounds the narrow panels");
 
 // Row swaps of the panel applied to every non-panel column, then the panel
 // rows of those columns copied to R (kGjPanel x m per matrix).
@@ -397,13 +398,15 @@ __global__ __launch_bounds__(kBlock) void k_bgj_swap(int m, int k0, int k1, doub
   for (int k = k0; k < k1; ++k) R[(int64_t)(k - k0) * m + j] = B[(int64_t)k * m + j];
 }
 
-// A[i][j] += sum_t W[i][t] R[t][j] over non-panel columns j, in 64 x 64 tiles.
+// A[i][j] += sum_t W[i][t] R[t][j] over non-panel columns j, in 64 x 64 tiles
+// (panels of at most PBM columns: the staging takes no more LDS than that).
+template <int PBM>
 __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, double* __restrict__ Ball,
                                                        const double* __restrict__ Rall) {
   double* B = Ball + (int64_t)blockIdx.z * m * m;
   const double* R = Rall + (int64_t)blockIdx.z * kGjPanel * m;
-  __shared__ double Ws[64][kGjPanel + 1];
-  __shared__ double Rs[kGjPanel][64 + 1];
+  __shared__ double Ws[64][PBM + 1];
+  __shared__ double Rs[PBM][64 + 1];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64, tid = threadIdx.x, b = k1 - k0;
   if (j0 + 64 > k0 && j0 < k1 && j0 >= k0 && j0 + 64 <= k1) return;   // tile inside the panel
   const int tr = tid / 16, tc = tid % 16;   // 4 x 4 outputs per thread
@@ -416,13 +419,13 @@ __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, do
 #pragma unroll
     for (int c = 0; c < 4; ++c) bo[a][c] = B[(int64_t)i * m + min(j0 + tc + 16 * c, m - 1)];
   }
-  for (int e = tid; e < 64 * kGjPanel; e += kBlock) {
-    const int r = e / kGjPanel, t = e % kGjPanel, i = i0 + r;
+  for (int e = tid; e < 64 * PBM; e += kBlock) {
+    const int r = e / PBM, t = e % PBM, i = i0 + r;
     double w = 0.0;
     if (i < m && t < b) w = B[(int64_t)i * m + k0 + t] - (i == k0 + t ? 1.0 : 0.0);
     Ws[r][t] = w;
   }
-  for (int e = tid; e < kGjPanel * 64; e += kBlock) {
+  for (int e = tid; e < PBM * 64; e += kBlock) {
     const int t = e / 64, c = e % 64, j = j0 + c;
     Rs[t][c] = (t < b && j < m) ? R[(int64_t)t * m + j] : 0.0;
   }
@@ -829,7 +832,8 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
     else
       hipLaunchKernelGGL((k_bgj_panel_reg<8, kGjPanel8>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf);
-    hipLaunchKernelGGL(k_bgj_update, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
+    if (pw == kGjPanel) hipLaunchKernelGGL(k_bgj_update<kGjPanel>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
+    else hipLaunchKernelGGL(k_bgj_update<kGjPanel6>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
   }
   hipLaunchKernelGGL(k_gj_unpermute, gp, dim3(kBlock), 0, s, m, B, perm);
   return hipGetLastError();
