@@ -372,10 +372,11 @@ __global__ __launch_bounds__(kBlock) void k_gj_unpermute(int m, double* __restri
 // panel rows of those columns: one pass over each matrix per panel instead of
 // one per column.
 constexpr int kGjPanel = 32;
-// narrower panels where a thread keeps 6 or 8 rows' segments in registers
-constexpr int kGjPanel6 = 16;   // 1536 < m <= 3072
+// narrower panels where a thread keeps 4, 6 or 8 rows' segments in registers
+constexpr int kGjPanel4 = 24;   // 1536 < m <= 2048
+constexpr int kGjPanel6 = 16;   // 2048 < m <= 3072
 constexpr int kGjPanel8 = 10;   // 3072 < m <= kMaxCoarse
-static_assert(kGjPanel8 <= kGjPanel6 && kGjPanel6 <= kGjPanel, "the update's staging bounds the narrow panels");
+static_assert(kGjPanel8 <= kGjPanel6 && kGjPanel4 <= kGjPanel, "the update's staging bounds the narrow panels");
 
 // Row swaps of the panel applied to every non-panel column, then the panel
 // rows of those columns copied to R (kGjPanel x m per matrix).
@@ -816,9 +817,11 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
     return hipGetLastError();
   }
   const dim3 gs(nblk(m), nmat), gt((m + 63) / 64, (m + 63) / 64, nmat), gp(nblk(m), nmat);
-  // panels of kGjPanel columns up to 3 rows per thread, narrower ones (6 or
-  // 8 rows per thread, up to kMaxCoarse) so that the panel stays in registers
-  const int pw = m <= kPanelThreads * 3 ? kGjPanel : (m <= kPanelThreads * 6 ? kGjPanel6 : kGjPanel8);
+  // panels of kGjPanel columns up to 3 rows per thread, narrower ones (4, 6
+  // or 8 rows per thread, up to kMaxCoarse) so that the panel stays in registers
+  const int pw = m <= kPanelThreads * 3 ? kGjPanel
+               : m <= kPanelThreads * 4 ? kGjPanel4
+               : m <= kPanelThreads * 6 ? kGjPanel6 : kGjPanel8;
   for (int k0 = 0; k0 < m; k0 += pw) {
     const int k1 = k0 + pw < m ? k0 + pw : m;
     if (m <= kPanelThreads)
@@ -827,12 +830,14 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
       hipLaunchKernelGGL((k_bgj_panel_reg<2, kGjPanel>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else if (m <= kPanelThreads * 3)
       hipLaunchKernelGGL((k_bgj_panel_reg<3, kGjPanel>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
+    else if (m <= kPanelThreads * 4)
+      hipLaunchKernelGGL((k_bgj_panel_reg<4, kGjPanel4>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else if (m <= kPanelThreads * 6)
       hipLaunchKernelGGL((k_bgj_panel_reg<6, kGjPanel6>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else
       hipLaunchKernelGGL((k_bgj_panel_reg<8, kGjPanel8>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf);
-    if (pw == kGjPanel) hipLaunchKernelGGL(k_bgj_update<kGjPanel>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
+    if (pw > kGjPanel6) hipLaunchKernelGGL(k_bgj_update<kGjPanel>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
     else hipLaunchKernelGGL(k_bgj_update<kGjPanel6>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
   }
   hipLaunchKernelGGL(k_gj_unpermute, gp, dim3(kBlock), 0, s, m, B, perm);

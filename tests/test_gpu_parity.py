@@ -178,8 +178,8 @@ def test_coarse_solve(case):
 def test_coarse_solve_order_1688():
     """A 10 x 10 coarsest level, as under the paper's 80 x 80 Chorin and cavity
     hierarchies: bordered slab blocks of order 1,688 (q = 1), three of them
-    inverted together by the register-panel blocked Gauss-Jordan at 6 rows per
-    thread and 16-column panels, against the oracle's dense solve."""
+    inverted together by the register-panel blocked Gauss-Jordan at 4 rows per
+    thread and 24-column panels, against the oracle's dense solve."""
     torch_cuda()
     from oracle.multigrid import CoarseSolver, project_pressure
     prob = w.small_problem(20, 2, 1, 3, 10.0, 16)
