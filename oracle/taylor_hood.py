@@ -172,3 +172,16 @@ def spatial_operators(M, k):
     Bx.sum_duplicates()
     By.sum_duplicates()
     return Mu, Ku, Bx, By, V, P
+
+
+def prolongation(M_fine, k):
+    """Prolongation of the Taylor-Hood space from the M_fine / 2 mesh to the
+    M_fine mesh (Sec. 3: the spaces are nested, P = blockdiag(P_u, P_u,
+    P_phi)): nodal interpolation of each coarse field at the fine lattice
+    nodes, velocity (degree k+1) and pressure (degree k) on their own
+    lattices.  Returns (P_u, P_p), CSR, every lattice node included."""
+    if M_fine % 2:
+        raise ValueError("the fine mesh must have an even number of squares per side")
+    Vf, Vc = HeatSpace(M_fine, k + 1), HeatSpace(M_fine // 2, k + 1)
+    Pf, Pc = HeatSpace(M_fine, k), HeatSpace(M_fine // 2, k)
+    return Vf.prolongation(Vc), Pf.prolongation(Pc)

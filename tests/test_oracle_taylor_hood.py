@@ -123,3 +123,22 @@ def test_assembled_patterns_give_the_patch_nonzeros(k, nnz):
     pv = Bx[pres][:, vel].nnz
     assert By[pres][:, vel].nnz == pv
     assert 4 * vv + 4 * pv == nnz == th.patch_nnz((3, 3))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_prolongation_reproduces_the_coarse_fields(k):
+    """Nested spaces: prolonging the coarse interpolant of any polynomial of
+    the space's degree gives the fine interpolant exactly, and constants are
+    kept (rows sum to one), for velocity (degree k+1) and pressure (degree k)."""
+    from oracle.heat import HeatSpace
+    from oracle.taylor_hood import prolongation
+    M = 4
+    Pu, Pp = prolongation(M, k)
+    for P, K in ((Pu, k + 1), (Pp, k)):
+        fine, coarse = HeatSpace(M, K), HeatSpace(M // 2, K)
+        assert np.allclose(P @ np.ones(coarse.n), 1.0, atol=1e-13)
+        for a in range(K + 1):
+            for b in range(K + 1 - a):
+                fc = coarse.xy[:, 0] ** a * coarse.xy[:, 1] ** b
+                ff = fine.xy[:, 0] ** a * fine.xy[:, 1] ** b
+                assert np.abs(P @ fc - ff).max() < 1e-12, (K, a, b)
