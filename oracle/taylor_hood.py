@@ -185,3 +185,43 @@ def prolongation(M_fine, k):
     Vf, Vc = HeatSpace(M_fine, k + 1), HeatSpace(M_fine // 2, k + 1)
     Pf, Pc = HeatSpace(M_fine, k), HeatSpace(M_fine // 2, k)
     return Vf.prolongation(Vc), Pf.prolongation(Pc)
+
+
+def convection_operators(M, k, ux, uy):
+    """The two parts of the Newton linearization of the convection term of
+    eq. nsfem about a velocity field (ux, uy) of degree k+1, given by its
+    values at the velocity lattice nodes, on one component's lattice:
+    C[i, j] = int phi_i (u . grad phi_j)   (the same block for both components),
+    D[a][b][i, j] = int phi_i phi_j d u_a / d x_b   (a, b in {x, y}),
+    CSR.  The integrands have degree 3(k+1) - 1, at most 8 for k <= 2."""
+    V = HeatSpace(M, k + 1)
+    pts, w = duffy_triangle(5)
+    val, grad = lagrange_pk(k + 1, pts)
+    mesh = V.mesh
+    nloc = V.cell_nodes.shape[1]
+    rows, cols = [], []
+    cv = []
+    dv = [[[], []], [[], []]]
+    for c in range(mesh.nc):
+        v = mesh.vxy[mesh.cells[c]]
+        J = np.stack([v[1] - v[0], v[2] - v[0]], axis=1)
+        wd = w * abs(np.linalg.det(J))
+        G = grad @ np.linalg.inv(J)
+        nodes = V.cell_nodes[c]
+        u = [val @ ux[nodes], val @ uy[nodes]]                       # (nq,)
+        gu = [G.transpose(0, 2, 1) @ ux[nodes], G.transpose(0, 2, 1) @ uy[nodes]]   # (nq, 2)
+        adv = u[0][:, None] * G[:, :, 0] + u[1][:, None] * G[:, :, 1]               # (nq, nloc)
+        cv.append(np.einsum("q,qi,qj->ij", wd, val, adv).ravel())
+        for a in range(2):
+            for b in range(2):
+                dv[a][b].append(np.einsum("q,qi,qj->ij", wd * gu[a][:, b], val, val).ravel())
+        rows.append(np.repeat(nodes, nloc))
+        cols.append(np.tile(nodes, nloc))
+    r, cc = np.concatenate(rows), np.concatenate(cols)
+
+    def mat(parts):
+        A = sp.csr_matrix((np.concatenate(parts), (r, cc)), shape=(V.n, V.n))
+        A.sum_duplicates()
+        return A
+
+    return mat(cv), [[mat(dv[a][b]) for b in range(2)] for a in range(2)], V

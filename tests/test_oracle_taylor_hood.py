@@ -142,3 +142,38 @@ def test_prolongation_reproduces_the_coarse_fields(k):
                 fc = coarse.xy[:, 0] ** a * coarse.xy[:, 1] ** b
                 ff = fine.xy[:, 0] ** a * fine.xy[:, 1] ** b
                 assert np.abs(P @ fc - ff).max() < 1e-12, (K, a, b)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_convection_operators_integrate_polynomials_exactly(k):
+    """For a velocity field and test/trial fields of the velocity degree
+    (monomials), v^T C(u) w = int v (u . grad w) and v^T D_ab(u) w =
+    int v w du_a/dx_b, the closed forms over the unit square."""
+    from oracle.taylor_hood import convection_operators
+    K = k + 1
+    mono = [(a, K - a) for a in range(K + 1)] + [(1, 0), (0, 1)]
+    from oracle.heat import HeatSpace
+    sp_ = HeatSpace(3, K)
+    x, y = sp_.xy[:, 0], sp_.xy[:, 1]
+    f = lambda e: x ** e[0] * y ** e[1]
+    for ue_x, ue_y in (((K, 0), (0, K)), ((1, K - 1), (K - 1, 1))):
+        C, D, _ = convection_operators(3, k, f(ue_x), f(ue_y))
+        for ve in mono:
+            for we in mono:
+                vv, ww = f(ve), f(we)
+                # u . grad w = ux dw/dx + uy dw/dy, all monomial products
+                ex = 0.0
+                if we[0]:
+                    ex += we[0] * _mono_integral(ve[0] + ue_x[0] + we[0] - 1, ve[1] + ue_x[1] + we[1])
+                if we[1]:
+                    ex += we[1] * _mono_integral(ve[0] + ue_y[0] + we[0], ve[1] + ue_y[1] + we[1] - 1)
+                assert vv @ (C @ ww) == pytest.approx(ex, rel=1e-11, abs=1e-13)
+                for a, ue in enumerate((ue_x, ue_y)):
+                    for b in range(2):
+                        if ue[b] == 0:
+                            exd = 0.0
+                        else:
+                            de = [ue[0], ue[1]]
+                            de[b] -= 1
+                            exd = ue[b] * _mono_integral(ve[0] + we[0] + de[0], ve[1] + we[1] + de[1])
+                        assert vv @ (D[a][b] @ ww) == pytest.approx(exd, rel=1e-11, abs=1e-13)
