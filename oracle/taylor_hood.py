@@ -23,7 +23,8 @@ produce it, so that the paper's closed forms can pin it.  The spatial
 operators of eq. nsfem's linear terms (velocity mass and stiffness of one
 component, the two divergence blocks) are assembled cell by cell with the
 degree-8 triangle rule, which integrates every one of them exactly for
-k <= 2.
+k <= 2.  TaylorHoodLevel assembles the full space-time Jacobian (DG(q) in
+time, full Newton, as oracle/assembly.py does at k = 1) for any k <= 2.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -225,3 +226,119 @@ def convection_operators(M, k, ux, uy):
         return A
 
     return mat(cv), [[mat(dv[a][b]) for b in range(2)] for a in range(2)], V
+
+
+class TaylorHoodLevel:
+    """One space-time level of Taylor-Hood P_{k+1}-P_k x DG(q) Navier-Stokes
+    (oracle): the space-time Jacobian of eq. nsfem (full Newton, as the P2-P1
+    level of oracle/assembly.py defines it, with the element degrees as
+    parameters).  Free numbering: interior velocity lattice node
+    (gi, gj) -> k = (gi-1) + (n-2)(gj-1) with DoFs 2k (x), 2k+1 (y); pressure
+    lattice node r -> 2 (n-2)^2 + r (n the velocity lattice side); Dirichlet
+    velocity values are the flow's velocity at the boundary lattice nodes."""
+
+    def __init__(self, M, k, q, n_slabs, t_final, mms, nodes="radau"):
+        from .temporal import SlabBasis
+        self.V, self.P = HeatSpace(M, k + 1), HeatSpace(M, k)
+        self.k, self.q, self.N, self.nq = k, q, n_slabs, q + 1
+        self.dt = t_final / n_slabs
+        self.tb = SlabBasis(q, nodes)
+        self.mms, self.R = mms, mms.R
+        nl = self.V.nl
+        g = np.arange(self.V.n)
+        gi, gj = g % nl, g // nl
+        interior = (gi > 0) & (gi < nl - 1) & (gj > 0) & (gj < nl - 1)
+        self.node_free = np.full(self.V.n, -1, dtype=np.int64)
+        self.node_free[interior] = (gi[interior] - 1) + (nl - 2) * (gj[interior] - 1)
+        self.p_offset = 2 * (nl - 2) ** 2
+        self.n_free = self.p_offset + self.P.n
+        self.n_st = self.n_free * n_slabs * self.nq
+        xq, wq = duffy_triangle(5)
+        self.Nv, dNv = lagrange_pk(k + 1, xq)
+        self.Np, _ = lagrange_pk(k, xq)
+        mesh = self.V.mesh
+        v = mesh.vxy[mesh.cells]
+        Jc = np.stack([v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]], axis=2)
+        det = Jc[:, 0, 0] * Jc[:, 1, 1] - Jc[:, 0, 1] * Jc[:, 1, 0]
+        inv = np.linalg.inv(Jc)
+        self.wdet = wq[None, :] * np.abs(det)[:, None]
+        self.gNv = np.einsum("qim,cmk->cqik", dNv, inv)
+        cv, cp = self.V.cell_nodes, self.P.cell_nodes
+        fv = self.node_free[cv]
+        self.cdofs = np.concatenate([np.where(fv >= 0, 2 * fv, -1), np.where(fv >= 0, 2 * fv + 1, -1),
+                                     self.p_offset + cp], axis=1)
+        self.nlv, self.nlp = cv.shape[1], cp.shape[1]
+
+    def full_state(self, x_free):
+        """Nodal (ux, uy) of shape (velocity nodes, N, nq) from a free space-time vector."""
+        t = ((np.arange(self.N)[:, None] + self.tb.nodes[None, :]) * self.dt)[None, :, :]
+        bx, by = self.mms.velocity(t, self.V.xy[:, 0][:, None, None], self.V.xy[:, 1][:, None, None])
+        ux, uy = np.array(bx, dtype=float), np.array(by, dtype=float)
+        fr = self.node_free >= 0
+        kf = self.node_free[fr]
+        ux[fr] = x_free[2 * kf]
+        uy[fr] = x_free[2 * kf + 1]
+        return ux, uy
+
+    def jacobian(self, x_free):
+        """Space-time Jacobian dF/dU at U (free DoFs), CSR of size n_st."""
+        ux, uy = self.full_state(np.asarray(x_free).reshape(self.n_free, self.N, self.nq))
+        tb, dt, R, nq, N = self.tb, self.dt, self.R, self.nq, self.N
+        nlv, nlp = self.nlv, self.nlp
+        ndl = 2 * nlv + nlp
+        cv = self.V.cell_nodes
+        Mloc = np.einsum("cq,qi,qj->cij", self.wdet, self.Nv, self.Nv)
+        Kloc = np.einsum("cq,cqik,cqjk->cij", self.wdet, self.gNv, self.gNv)
+        Bq = np.einsum("cq,qj,cqik->cjik", self.wdet, self.Np, self.gNv)   # int chi_j d_k phi_i
+        Tq = np.einsum("g,ga,gb->ab", tb.wg, tb.Phi, tb.dPhi) + np.outer(tb.e0, tb.e0)
+        Wq = np.einsum("g,ga,gb->gab", tb.wg, tb.Phi, tb.Phi)
+        st = N * nq
+        rows, cols, vals = [], [], []
+        for n in range(N):
+            f = {}
+            for name, u in (("x", ux), ("y", uy)):
+                uc = u[cv, n, :]
+                f["u" + name] = np.einsum("gb,cib,qi->cgq", tb.Phi, uc, self.Nv)
+                f["g" + name] = np.einsum("gb,cib,cqik->cgqk", tb.Phi, uc, self.gNv)
+            conv1 = (np.einsum("cq,qi,cgq,cqj->cgij", self.wdet, self.Nv, f["ux"], self.gNv[..., 0])
+                     + np.einsum("cq,qi,cgq,cqj->cgij", self.wdet, self.Nv, f["uy"], self.gNv[..., 1]))
+            gu = np.stack([f["gx"], f["gy"]], axis=2)
+            conv2 = np.einsum("cq,qi,qj,cgaqb->cgabij", self.wdet, self.Nv, self.Nv, gu)
+            J = np.zeros((len(cv), nq, nq, ndl, ndl))
+            pv = slice(2 * nlv, ndl)
+            for ci in range(2):
+                sl = slice(nlv * ci, nlv * ci + nlv)
+                J[:, :, :, sl, sl] += (Tq[None, :, :, None, None] * Mloc[:, None, None]
+                                       + dt * np.einsum("gab,cij->cabij", Wq, Kloc)
+                                       + dt * R * np.einsum("gab,cgij->cabij", Wq, conv1))
+                for cj in range(2):
+                    slj = slice(nlv * cj, nlv * cj + nlv)
+                    J[:, :, :, sl, slj] += dt * R * np.einsum("gab,cgij->cabij", Wq, conv2[:, :, ci, cj])
+                J[:, :, :, sl, pv] += -dt * np.einsum("gab,cji->cabij", Wq, Bq[..., ci])
+                J[:, :, :, pv, sl] += -dt * np.einsum("gab,cji->cabji", Wq, Bq[..., ci])
+            d = self.cdofs
+            ok = (d[:, :, None] >= 0) & (d[:, None, :] >= 0)
+            for a in range(nq):
+                for b in range(nq):
+                    r = np.broadcast_to((d * st + n * nq + a)[:, :, None], ok.shape)
+                    c = np.broadcast_to((d * st + n * nq + b)[:, None, :], ok.shape)
+                    rows.append(r[ok]); cols.append(c[ok]); vals.append(J[:, a, b][ok])
+        # jump blocks -phi_a(0) phi_b(1) M between slab n and slab n - 1 (velocity rows)
+        dv = self.cdofs[:, :2 * nlv]
+        Mblk = np.zeros((len(cv), 2 * nlv, 2 * nlv))
+        Mblk[:, :nlv, :nlv] = Mloc
+        Mblk[:, nlv:, nlv:] = Mloc
+        okm = (dv[:, :, None] >= 0) & (dv[:, None, :] >= 0)
+        for n in range(1, N):
+            for a in range(nq):
+                for b in range(nq):
+                    coef = -tb.e0[a] * tb.e1[b]
+                    if coef == 0.0:
+                        continue
+                    r = np.broadcast_to((dv * st + n * nq + a)[:, :, None], okm.shape)
+                    c = np.broadcast_to((dv * st + (n - 1) * nq + b)[:, None, :], okm.shape)
+                    rows.append(r[okm]); cols.append(c[okm]); vals.append(coef * Mblk[okm])
+        Jst = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                            shape=(self.n_st, self.n_st))
+        Jst.sum_duplicates()
+        return Jst

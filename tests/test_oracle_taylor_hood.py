@@ -177,3 +177,53 @@ def test_convection_operators_integrate_polynomials_exactly(k):
                             de[b] -= 1
                             exd = ue[b] * _mono_integral(ve[0] + we[0] + de[0], ve[1] + we[1] + de[1])
                         assert vv @ (D[a][b] @ ww) == pytest.approx(exd, rel=1e-11, abs=1e-13)
+
+
+def _mms(R, seed=5):
+    import stwr_workloads as w
+    from oracle.mms import MMS
+    psi_ab, psi_coef, p_ab, p_coef = w.draw_modes(seed, 4, 3, 4, np.pi)
+    return MMS(psi_ab, psi_coef, p_ab, p_coef, R)
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_space_time_jacobian_k1_equals_the_p2p1_oracle(q):
+    """At k = 1 the degree-generic space-time Jacobian is the P2-P1 one of
+    oracle/assembly.py (independent code: its own bases, cell maps and
+    numbering), entry by entry at a seeded state."""
+    from oracle.assembly import Level
+    from oracle.taylor_hood import TaylorHoodLevel
+    mms = _mms(7.0)
+    L = Level(4, q, 3, 1.0, mms)
+    T = TaylorHoodLevel(4, 1, q, 3, 1.0, mms)
+    assert T.n_free == L.n_free and T.n_st == L.n_st
+    x = 0.3 * np.random.default_rng(3).standard_normal((L.n_free, 3, q + 1))
+    A, B = L.jacobian(x), T.jacobian(x)
+    assert abs(A - B).max() <= 1e-14 * abs(A).max()
+
+
+def test_space_time_jacobian_k2_stokes_blocks():
+    """P3-P2 at R = 0 (Stokes): the diagonal slab block of the x velocity is
+    T (x) M_u + dt W (x) K_u on the free nodes, and the velocity-pressure
+    blocks are -dt W (x) B, with M_u, K_u, B the pinned spatial operators and
+    T, W the DG(q) temporal matrices."""
+    from oracle.taylor_hood import TaylorHoodLevel, spatial_operators
+    M, k, q, N = 4, 2, 1, 2
+    T = TaylorHoodLevel(M, k, q, N, 1.0, _mms(0.0))
+    J = T.jacobian(np.zeros(T.n_st)).tocsr()
+    Mu, Ku, Bx, By, V, P = spatial_operators(M, k)
+    tb, nq, st = T.tb, T.nq, T.N * T.nq
+    Tq = np.einsum("g,ga,gb->ab", tb.wg, tb.Phi, tb.dPhi) + np.outer(tb.e0, tb.e0)
+    Wt = np.einsum("g,ga,gb->ab", tb.wg, tb.Phi, tb.Phi)
+    free = np.nonzero(T.node_free >= 0)[0]
+    fx = 2 * T.node_free[free]
+    pd = T.p_offset + np.arange(P.n)
+    Muf, Kuf = Mu[free][:, free].toarray(), Ku[free][:, free].toarray()
+    Bxf = Bx[:, free].toarray()
+    for n in range(N):
+        for a in range(nq):
+            for b in range(nq):
+                blk = J[fx * st + n * nq + a][:, fx * st + n * nq + b].toarray()
+                assert np.abs(blk - (Tq[a, b] * Muf + T.dt * Wt[a, b] * Kuf)).max() < 1e-13
+                pu = J[pd * st + n * nq + a][:, fx * st + n * nq + b].toarray()
+                assert np.abs(pu + T.dt * Wt[a, b] * Bxf).max() < 1e-13
