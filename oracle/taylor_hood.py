@@ -240,7 +240,7 @@ class TaylorHoodLevel:
     def __init__(self, M, k, q, n_slabs, t_final, mms, nodes="radau"):
         from .temporal import SlabBasis
         self.V, self.P = HeatSpace(M, k + 1), HeatSpace(M, k)
-        self.k, self.q, self.N, self.nq = k, q, n_slabs, q + 1
+        self.M, self.k, self.q, self.N, self.nq = M, k, q, n_slabs, q + 1
         self.dt = t_final / n_slabs
         self.tb = SlabBasis(q, nodes)
         self.mms, self.R = mms, mms.R
@@ -268,6 +268,18 @@ class TaylorHoodLevel:
         self.cdofs = np.concatenate([np.where(fv >= 0, 2 * fv, -1), np.where(fv >= 0, 2 * fv + 1, -1),
                                      self.p_offset + cp], axis=1)
         self.nlv, self.nlp = cv.shape[1], cp.shape[1]
+
+    def patches(self):
+        """Vanka+star patches (one per vertex, boundary vertices included) as
+        sorted free DoF lists, for oracle/smoother.py's PatchSmoother."""
+        th = TaylorHood(self.M, self.k)
+        n1 = self.M + 1
+        out = []
+        for vid in range(n1 * n1):
+            vel, pres = th.patch((vid % n1, vid // n1))
+            f = self.node_free[vel]
+            out.append(np.sort(np.concatenate([2 * f, 2 * f + 1, self.p_offset + pres])))
+        return out
 
     def full_state(self, x_free):
         """Nodal (ux, uy) of shape (velocity nodes, N, nq) from a free space-time vector."""

@@ -227,3 +227,41 @@ def test_space_time_jacobian_k2_stokes_blocks():
                 assert np.abs(blk - (Tq[a, b] * Muf + T.dt * Wt[a, b] * Kuf)).max() < 1e-13
                 pu = J[pd * st + n * nq + a][:, fx * st + n * nq + b].toarray()
                 assert np.abs(pu + T.dt * Wt[a, b] * Bxf).max() < 1e-13
+
+
+def test_patch_smoother_k1_equals_the_p2p1_oracle():
+    """The WR Vanka+star smoother (oracle/smoother.py) on the degree-generic
+    level at k = 1 is the P2-P1 oracle's: same patches, same Jacobian."""
+    from oracle.assembly import Level
+    from oracle.smoother import PatchSmoother
+    from oracle.taylor_hood import TaylorHoodLevel
+    mms = _mms(7.0)
+    L = Level(4, 1, 3, 1.0, mms)
+    T = TaylorHoodLevel(4, 1, 1, 3, 1.0, mms)
+    x = 0.3 * np.random.default_rng(6).standard_normal((L.n_free, 3, 2))
+    r = np.random.default_rng(7).standard_normal(L.n_st)
+    za = PatchSmoother(L, L.jacobian(x)).apply(r)
+    zb = PatchSmoother(T, T.jacobian(x), T.patches()).apply(r)
+    assert np.linalg.norm(za - zb) <= 1e-12 * np.linalg.norm(za)
+
+
+def test_p3p2_patch_blocks_and_solves():
+    """P3-P2 x DG(1): interior slab blocks of 81 x 2 = 162 rows (Sec. 3.1's
+    81 patch DoFs, two temporal nodes), and every patch solve satisfies its
+    space-time patch system A_v y = r_v (forward block substitution)."""
+    from oracle.smoother import PatchSmoother
+    from oracle.taylor_hood import TaylorHoodLevel
+    T = TaylorHoodLevel(4, 2, 1, 2, 1.0, _mms(5.0))
+    A = T.jacobian(0.2 * np.random.default_rng(8).standard_normal(T.n_st)).tocsr()
+    S = PatchSmoother(T, A, T.patches())
+    sizes = [k for (_, _, _, _, k) in S.blocks]
+    # full patches: vertices at least two squares from the boundary (whose
+    # star closure holds no Dirichlet node), (M - 3)^2 of them
+    assert max(sizes) == 162 and sizes.count(162) == (4 - 3) ** 2
+    rng = np.random.default_rng(9)
+    for i in (0, 12, 24):
+        idx, perm, lus, subs, k = S.blocks[i]
+        Ap = A[idx][:, idx].toarray()[np.ix_(perm, perm)]
+        rp = rng.standard_normal(len(idx))
+        y = S.patch_solve(i, rp)
+        assert np.linalg.norm(Ap @ y - rp) <= 1e-10 * np.linalg.norm(rp)
