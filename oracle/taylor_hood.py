@@ -292,6 +292,74 @@ class TaylorHoodLevel:
         uy[fr] = x_free[2 * kf + 1]
         return ux, uy
 
+    def initial_full(self):
+        """Interpolant of the initial velocity at every velocity lattice node
+        (the flow's own initial value where it states one, else u(0))."""
+        x, y = self.V.xy[:, 0], self.V.xy[:, 1]
+        if hasattr(self.mms, "initial_velocity"):
+            return self.mms.initial_velocity(x, y)
+        return self.mms.velocity(0.0, x, y)
+
+    def residual(self, x_free):
+        """F(U) at the free DoFs, shape (n_free, N, nq): the weak form of eq.
+        nsfem per slab, as oracle/assembly.py writes it at k = 1 (upwind jump
+        against the previous slab's end value, pressure as -(P, div psi) and
+        -(div U, chi), the flow's forcing)."""
+        xf = np.asarray(x_free).reshape(self.n_free, self.N, self.nq)
+        ux, uy = self.full_state(xf)
+        p = xf[self.p_offset:]
+        tb, dt, R, nq = self.tb, self.dt, self.R, self.nq
+        mesh = self.V.mesh
+        cv, cp = self.V.cell_nodes, self.P.cell_nodes
+        v = mesh.vxy[mesh.cells]
+        Jc = np.stack([v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]], axis=2)
+        xq, _ = duffy_triangle(5)
+        xphys = v[:, 0, None, :] + np.einsum("ckm,qm->cqk", Jc, xq)
+        i0x, i0y = self.initial_full()
+        Fx = np.zeros((self.V.n, self.N, nq))
+        Fy = np.zeros((self.V.n, self.N, nq))
+        Fp = np.zeros((self.P.n, self.N, nq))
+        for n in range(self.N):
+            f = {}
+            for name, u in (("x", ux), ("y", uy)):
+                uc = u[cv, n, :]
+                f["u" + name] = np.einsum("gb,cib,qi->cgq", tb.Phi, uc, self.Nv)
+                f["g" + name] = np.einsum("gb,cib,cqik->cgqk", tb.Phi, uc, self.gNv)
+                f["d" + name] = np.einsum("gb,cib,qi->cgq", tb.dPhi, uc, self.Nv)
+                f["s0" + name] = np.einsum("b,cib,qi->cq", tb.e0, uc, self.Nv)
+            f["p"] = np.einsum("gb,cjb,qj->cgq", tb.Phi, p[cp, n, :], self.Np)
+            tg = (n + tb.sg) * dt
+            fx, fy = self.mms.forcing(tg[None, :, None], xphys[:, None, :, 0], xphys[:, None, :, 1])
+            if n == 0:
+                px_, py_ = i0x, i0y
+            else:
+                px_, py_ = ux[:, n - 1, :] @ tb.e1, uy[:, n - 1, :] @ tb.e1
+            prevx = np.einsum("ci,qi->cq", px_[cv], self.Nv)
+            prevy = np.einsum("ci,qi->cq", py_[cv], self.Nv)
+            div = f["gx"][..., 0] + f["gy"][..., 1]
+            for comp, (g_, d_, s0, prev, ff) in enumerate(
+                    [(f["gx"], f["dx"], f["s0x"], prevx, fx), (f["gy"], f["dy"], f["s0y"], prevy, fy)]):
+                conv = f["ux"] * g_[..., 0] + f["uy"] * g_[..., 1]
+                val = d_ + dt * (R * conv - ff)
+                grd = dt * g_.copy()
+                grd[..., comp] -= dt * f["p"]
+                loc = (np.einsum("g,ga,cgq,cq,qi->cai", tb.wg, tb.Phi, val, self.wdet, self.Nv)
+                       + np.einsum("g,ga,cgqk,cq,cqik->cai", tb.wg, tb.Phi, grd, self.wdet, self.gNv)
+                       + np.einsum("a,cq,cq,qi->cai", tb.e0, s0 - prev, self.wdet, self.Nv))
+                target = Fx if comp == 0 else Fy
+                for a in range(nq):
+                    np.add.at(target[:, n, a], cv, loc[:, a, :])
+            locp = -dt * np.einsum("g,ga,cgq,cq,qj->caj", tb.wg, tb.Phi, div, self.wdet, self.Np)
+            for a in range(nq):
+                np.add.at(Fp[:, n, a], cp, locp[:, a, :])
+        out = np.zeros((self.n_free, self.N, nq))
+        fr = self.node_free >= 0
+        kf = self.node_free[fr]
+        out[2 * kf] = Fx[fr]
+        out[2 * kf + 1] = Fy[fr]
+        out[self.p_offset:] = Fp
+        return out
+
     def jacobian(self, x_free):
         """Space-time Jacobian dF/dU at U (free DoFs), CSR of size n_st."""
         ux, uy = self.full_state(np.asarray(x_free).reshape(self.n_free, self.N, self.nq))

@@ -265,3 +265,31 @@ def test_p3p2_patch_blocks_and_solves():
         rp = rng.standard_normal(len(idx))
         y = S.patch_solve(i, rp)
         assert np.linalg.norm(Ap @ y - rp) <= 1e-10 * np.linalg.norm(rp)
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_residual_k1_equals_the_p2p1_oracle(q):
+    """At k = 1 the degree-generic space-time residual is oracle/assembly.py's."""
+    from oracle.assembly import Level
+    from oracle.taylor_hood import TaylorHoodLevel
+    mms = _mms(7.0)
+    L = Level(4, q, 3, 1.0, mms)
+    T = TaylorHoodLevel(4, 1, q, 3, 1.0, mms)
+    x = 0.3 * np.random.default_rng(3).standard_normal((L.n_free, 3, q + 1))
+    a, b = L.residual(x), T.residual(x)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_p3p2_jacobian_is_the_derivative_of_the_residual(q):
+    """P3-P2: the Jacobian is the exact derivative of the residual (full
+    Newton): a central difference of F along a seeded direction matches J d
+    to the difference's own error."""
+    from oracle.taylor_hood import TaylorHoodLevel
+    T = TaylorHoodLevel(4, 2, q, 2, 1.0, _mms(5.0))
+    x = 0.3 * np.random.default_rng(4).standard_normal(T.n_st)
+    d = np.random.default_rng(5).standard_normal(T.n_st)
+    Jd = T.jacobian(x) @ d
+    eps = 1e-6
+    fd = (T.residual(x + eps * d).ravel() - T.residual(x - eps * d).ravel()) / (2 * eps)
+    assert np.linalg.norm(fd - Jd) <= 1e-8 * np.linalg.norm(Jd)
