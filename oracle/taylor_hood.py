@@ -228,6 +228,18 @@ def convection_operators(M, k, ux, uy):
     return mat(cv), [[mat(dv[a][b]) for b in range(2)] for a in range(2)], V
 
 
+class _LevelMesh:
+    """The part of a level's mesh that oracle/multigrid.py and
+    oracle/smoother.py read: the pressure offset and the patches."""
+
+    def __init__(self, level):
+        self._level = level
+        self.p_offset = level.p_offset
+
+    def patches(self):
+        return self._level.patches()
+
+
 class TaylorHoodLevel:
     """One space-time level of Taylor-Hood P_{k+1}-P_k x DG(q) Navier-Stokes
     (oracle): the space-time Jacobian of eq. nsfem (full Newton, as the P2-P1
@@ -268,6 +280,8 @@ class TaylorHoodLevel:
         self.cdofs = np.concatenate([np.where(fv >= 0, 2 * fv, -1), np.where(fv >= 0, 2 * fv + 1, -1),
                                      self.p_offset + cp], axis=1)
         self.nlv, self.nlp = cv.shape[1], cp.shape[1]
+        # what the shared multigrid code reads from a level's mesh
+        self.mesh = _LevelMesh(self)
 
     def patches(self):
         """Vanka+star patches (one per vertex, boundary vertices included) as
@@ -422,3 +436,65 @@ class TaylorHoodLevel:
                             shape=(self.n_st, self.n_st))
         Jst.sum_duplicates()
         return Jst
+
+
+def free_prolongation(fine, coarse):
+    """Prolongation between two TaylorHoodLevels in the free numbering: the
+    nested-space interpolation of each velocity component restricted to free
+    nodes (Dirichlet coarse nodes carry no correction) and the pressure one,
+    then the identity over the [slab][temporal node] positions."""
+    Pu, Pp = prolongation(fine.M, fine.k)
+    ff = np.nonzero(fine.node_free >= 0)[0]
+    cf = np.nonzero(coarse.node_free >= 0)[0]
+    Puf = Pu[ff][:, cf].tocoo()
+    rf, rc = fine.node_free[ff][Puf.row], coarse.node_free[cf][Puf.col]
+    Ppc = Pp.tocoo()
+    rows = np.concatenate([2 * rf, 2 * rf + 1, fine.p_offset + Ppc.row])
+    cols = np.concatenate([2 * rc, 2 * rc + 1, coarse.p_offset + Ppc.col])
+    vals = np.concatenate([Puf.data, Puf.data, Ppc.data])
+    P = sp.csr_matrix((vals, (rows, cols)), shape=(fine.n_free, coarse.n_free))
+    return sp.kron(P, sp.identity(fine.N * fine.nq), format="csr")
+
+
+def _hierarchy_base():
+    from .multigrid import Hierarchy
+    return Hierarchy
+
+
+class TaylorHoodHierarchy(_hierarchy_base()):
+    """The multigrid hierarchy of oracle/multigrid.py (V-cycle of Alg. 1,
+    WR Vanka+star smoothing, bordered coarsest solve) over TaylorHoodLevels:
+    meshes M, M/2, ..., nested-space transfers, the Newton iterate injected at
+    the coarse lattice nodes (every coarse node is a fine node)."""
+
+    def __init__(self, M, n_levels, k, q, n_slabs, t_final, mms, opts=None, nodes="radau"):
+        from .multigrid import Options
+        self.opts = opts or Options()
+        self.mms = mms
+        self.levels = [TaylorHoodLevel(M >> l, k, q, n_slabs, t_final, mms, nodes)
+                       for l in range(n_levels)]
+        self.P = [free_prolongation(self.levels[l], self.levels[l + 1]) for l in range(n_levels - 1)]
+        self.A = None
+
+    def level_states(self, x_fine):
+        out = [x_fine]
+        L0 = self.levels[0]
+        ux, uy = L0.full_state(x_fine.reshape(L0.n_free, L0.N, L0.nq))
+        p = x_fine.reshape(L0.n_free, L0.N, L0.nq)[L0.p_offset:]
+        for l in range(1, len(self.levels)):
+            F, C = self.levels[l - 1], self.levels[l]
+
+            def inject(n_f, n_c):
+                g = np.arange(n_c * n_c)
+                return 2 * (g % n_c) + n_f * 2 * (g // n_c)
+
+            iv, ip = inject(F.V.nl, C.V.nl), inject(F.P.nl, C.P.nl)
+            ux, uy, p = ux[iv], uy[iv], p[ip]
+            fr = C.node_free >= 0
+            kf = C.node_free[fr]
+            x = np.zeros((C.n_free, C.N, C.nq))
+            x[2 * kf] = ux[fr]
+            x[2 * kf + 1] = uy[fr]
+            x[C.p_offset:] = p
+            out.append(x)
+        return out

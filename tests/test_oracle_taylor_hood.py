@@ -293,3 +293,43 @@ def test_p3p2_jacobian_is_the_derivative_of_the_residual(q):
     eps = 1e-6
     fd = (T.residual(x + eps * d).ravel() - T.residual(x - eps * d).ravel()) / (2 * eps)
     assert np.linalg.norm(fd - Jd) <= 1e-8 * np.linalg.norm(Jd)
+
+
+def test_hierarchy_k1_vcycle_equals_the_p2p1_oracle():
+    """At k = 1 the Taylor-Hood hierarchy (its levels, transfers and state
+    injection) gives the P2-P1 oracle hierarchy's V-cycle (Alg. 1)."""
+    import stwr_workloads as w
+    from oracle.multigrid import Hierarchy
+    from oracle.taylor_hood import TaylorHoodHierarchy
+    prob = w.small_problem(8, 2, 1, 3, 10.0, 11)
+    H = Hierarchy(prob)
+    T = TaylorHoodHierarchy(8, 2, 1, 1, 3, prob.t_final, H.mms)
+    x = 0.3 * np.random.default_rng(2).standard_normal(H.levels[0].n_st)
+    H.assemble(x)
+    T.assemble(x)
+    b = np.random.default_rng(3).standard_normal(H.levels[0].n_st)
+    a1, a2 = H.vcycle(b), T.vcycle(b)
+    assert np.linalg.norm(a1 - a2) <= 1e-12 * np.linalg.norm(a1)
+
+
+def test_p3p2_fgmres_wrmg_solves():
+    """P3-P2 x DG(1) on an 8 x 8 mesh with two levels: FGMRES(30)
+    right-preconditioned by one V-cycle with the WR Vanka+star smoother
+    (Alg. 1, Sec. 3) reduces the residual of a consistent system by 1e-10
+    in a handful of iterations and recovers its solution (pressure up to its
+    constant)."""
+    import stwr_workloads as w
+    from oracle.mms import MMS
+    from oracle.multigrid import fgmres, project_pressure
+    from oracle.taylor_hood import TaylorHoodHierarchy
+    psi_ab, psi_coef, p_ab, p_coef = w.draw_modes(11, 4, 3, 4, np.pi)
+    T = TaylorHoodHierarchy(8, 2, 2, 1, 2, 0.1, MMS(psi_ab, psi_coef, p_ab, p_coef, 10.0))
+    L0 = T.levels[0]
+    T.assemble(0.1 * np.random.default_rng(2).standard_normal(L0.n_st))
+    A = T.A[0]
+    xt = project_pressure(L0, np.random.default_rng(3).standard_normal(L0.n_st))
+    b = A @ xt
+    x, its, _ = fgmres(A, T.vcycle, b, 1e-10, 30, 200, project=lambda v: project_pressure(L0, v))
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-8)
+    assert its <= 20
+    assert np.linalg.norm(project_pressure(L0, x) - xt) <= 1e-5 * np.linalg.norm(xt)
