@@ -333,3 +333,52 @@ def test_p3p2_fgmres_wrmg_solves():
     assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-8)
     assert its <= 20
     assert np.linalg.norm(project_pressure(L0, x) - xt) <= 1e-5 * np.linalg.norm(xt)
+
+
+class _CubicFlow:
+    """u = (1 + t) (2 x^2 y, -2 x y^2) (stream function (1 + t) x^2 y^2,
+    divergence-free), p = x^2 - y^2, and the forcing that makes them solve
+    eq. nsfem's strong form u_t + R (u . grad) u - lap u + grad p = f:
+    (u . grad) u = (1 + t)^2 (4 x^3 y^2, 4 x^2 y^3), lap u = (1 + t) (4 y, -4 x)."""
+
+    def __init__(self, R):
+        self.R = R
+
+    def velocity(self, t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float), np.asarray(y, float))
+        return (1 + t) * 2 * x ** 2 * y, -(1 + t) * 2 * x * y ** 2
+
+    def forcing(self, t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float), np.asarray(y, float))
+        s = 1 + t
+        fx = 2 * x ** 2 * y + self.R * s ** 2 * 4 * x ** 3 * y ** 2 - s * 4 * y + 2 * x
+        fy = -2 * x * y ** 2 + self.R * s ** 2 * 4 * x ** 2 * y ** 3 + s * 4 * x - 2 * y
+        return fx, fy
+
+
+def _exact_free(T, flow):
+    t = (np.arange(T.N)[:, None] + T.tb.nodes[None, :]) * T.dt
+    ux, uy = flow.velocity(t[None], T.V.xy[:, 0][:, None, None], T.V.xy[:, 1][:, None, None])
+    x = np.zeros((T.n_free, T.N, T.nq))
+    fr = T.node_free >= 0
+    kf = T.node_free[fr]
+    x[2 * kf], x[2 * kf + 1] = ux[fr], uy[fr]
+    p = T.P.xy[:, 0] ** 2 - T.P.xy[:, 1] ** 2
+    x[T.p_offset:] = p[:, None, None]
+    return x
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_p3p2_residual_vanishes_at_a_solution_in_the_space(q):
+    """Galerkin consistency: when the exact solution lies in P3-P2 x DG(q)
+    (cubic velocity, quadratic pressure, polynomial in time) and every
+    integrand is integrated exactly, the space-time residual at its
+    interpolant is zero to rounding.  P2-P1 cannot represent the cubic, so
+    there the residual is far from zero."""
+    from oracle.taylor_hood import TaylorHoodLevel
+    flow = _CubicFlow(3.0)
+    T = TaylorHoodLevel(4, 2, q, 2, 0.5, flow)
+    F = T.residual(_exact_free(T, flow))
+    assert np.abs(F).max() < 1e-13
+    T1 = TaylorHoodLevel(4, 1, q, 2, 0.5, flow)
+    assert np.abs(T1.residual(_exact_free(T1, flow))).max() > 1e-5
