@@ -242,3 +242,46 @@ def test_cavity_newton_steps_with_direct_solves_match_paper():
     _, fn = newton_exact_linear(lev, rtol=1e-8)
     assert len(fn) - 1 == 2
     assert 1e-4 < fn[1] / fn[0] < 2e-3
+
+
+class _QuadraticFlow:
+    """u = (1 + t) (x^2, -2 x y) (stream function (1 + t) x^2 y), p = x - y,
+    and the forcing of eq. nsfem's strong form u_t + R (u . grad) u - lap u +
+    grad p = f: (u . grad) u = (1 + t)^2 (2 x^3, 2 x^2 y), lap u = (1 + t) (2, 0)."""
+
+    def __init__(self, R):
+        self.R = R
+
+    def velocity(self, t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float), np.asarray(y, float))
+        return (1 + t) * x ** 2, -(1 + t) * 2 * x * y
+
+    def forcing(self, t, x, y):
+        t, x, y = np.broadcast_arrays(np.asarray(t, float), np.asarray(x, float), np.asarray(y, float))
+        s = 1 + t
+        return (x ** 2 + self.R * s ** 2 * 2 * x ** 3 - 2 * s + 1,
+                -2 * x * y + self.R * s ** 2 * 2 * x ** 2 * y - 1)
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_residual_vanishes_at_a_solution_in_the_space(q):
+    """Galerkin consistency of the P2-P1 x DG(q) residual (eq. nsfem): at the
+    interpolant of an exact solution inside the discrete space (quadratic
+    divergence-free velocity, linear pressure, linear in time for q = 1) every
+    integrand is integrated exactly and the residual is zero to rounding.  At
+    q = 0 the linear-in-time velocity is not in the space: far from zero."""
+    flow = _QuadraticFlow(3.0)
+    L = Level(4, q, 2, 0.5, flow)
+    m = L.mesh
+    t = L.node_times()
+    ux, uy = flow.velocity(t[None], m.nxy[:, 0][:, None, None], m.nxy[:, 1][:, None, None])
+    x = np.zeros((L.n_free, L.N, L.nq))
+    fr = m.node_free >= 0
+    k = m.node_free[fr]
+    x[2 * k], x[2 * k + 1] = ux[fr], uy[fr]
+    x[m.p_offset:] = (m.vxy[:, 0] - m.vxy[:, 1])[:, None, None]
+    F = np.abs(L.residual(x)).max()
+    if q == 1:
+        assert F < 1e-13
+    else:
+        assert F > 1e-5
