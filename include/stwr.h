@@ -26,7 +26,8 @@
  *   is DoF 2(2M-1)^2 + v.
  * Space-time vectors: float64, length n_st = n_free * n_slabs * (q+1), index
  *   (dof * n_slabs + n) * (q+1) + a, i.e. [free DoF][slab][temporal node];
- *   temporal nodes are the right Gauss-Radau points of each slab.
+ *   the temporal nodes of each slab are the family the problem descriptor's
+ *   temporal_nodes names (right Gauss-Radau by default, or Gauss-Legendre).
  * Memory: every vector argument is a DEVICE pointer on the context's device,
  *   owned by the caller, non-overlapping unless stated.  Work is enqueued on
  *   the context's stream; calls that return host scalars synchronise it.
@@ -219,6 +220,13 @@ int32_t stwr_ctx_set_alloc_mode(stwr_ctx* ctx, int32_t stream_ordered);
  * precision, operators, maps, Krylov and smoother workspaces). */
 int32_t stwr_problem_bytes(const stwr_problem_desc* desc, const stwr_solver_opts* opts,
                            uint64_t* bytes);
+/* Length n_st of the problem's level-0 space-time vectors (the solution,
+ * F(U), right-hand sides): free spatial DoFs x n_slabs x (q+1), where the
+ * free DoFs are 2 (2M-1)^2 + (M+1)^2 for Navier-Stokes (Taylor-Hood P2-P1,
+ * boundary velocity eliminated) and (kM+1)^2 for the heat equation's P_k
+ * lattice (k = degree).  Host only; STWR_ERR_ARG for an invalid descriptor. */
+int32_t stwr_problem_n_st(const stwr_problem_desc* desc, int64_t* n_st);
+
 /* Host-built structure of one mesh with M squares a side, for checking the
  * setup against closed-form counts.  out[0..11] = n_free, n_nodes_p2,
  * n_vertices, n_cells, csr_nnz, n_patches, sum_patch_dofs, max_patch_dofs,
@@ -347,7 +355,8 @@ int32_t stwr_project_pressure(stwr_problem* p, int32_t level, double* x);
  * (0 = no bound); a request larger than the whole budget completes at once
  * with STWR_ERR_BUDGET.  An admitted request is created, solved by
  * stwr_newton_solve from the zero start, its solution copied to `host_out`
- * (n_st doubles, or NULL to discard), and its memory released, so solves of
+ * (n_st doubles as stwr_problem_n_st gives them, for either equation, or
+ * NULL to discard), and its memory released, so solves of
  * different sizes overlap on the device.  Times are seconds on the server's
  * steady clock (stwr_server_now). */
 typedef struct stwr_server stwr_server;

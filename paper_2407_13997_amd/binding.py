@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 
 EXPORTED = [
     "stwr_default_opts", "stwr_ctx_create", "stwr_ctx_destroy", "stwr_ctx_set_stream",
-    "stwr_last_error", "stwr_ctx_bytes_in_use", "stwr_problem_bytes", "stwr_mesh_info",
+    "stwr_last_error", "stwr_ctx_bytes_in_use", "stwr_problem_bytes", "stwr_problem_n_st", "stwr_mesh_info",
     "stwr_problem_create", "stwr_problem_destroy", "stwr_problem_sizes", "stwr_patch_sizes",
     "stwr_level_time_chunks",
     "stwr_set_opts",
@@ -121,6 +121,7 @@ def load(path: str | None = None):
         "stwr_ctx_set_stream": [P, V],
         "stwr_ctx_bytes_in_use": [P, ctypes.POINTER(u64)],
         "stwr_problem_bytes": [ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolverOpts), ctypes.POINTER(u64)],
+        "stwr_problem_n_st": [ctypes.POINTER(ProblemDesc), ctypes.POINTER(i64)],
         "stwr_mesh_info": [i32, ctypes.POINTER(i64)],
         "stwr_problem_create": [P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolverOpts), ctypes.POINTER(P)],
         "stwr_problem_destroy": [P],
@@ -195,6 +196,17 @@ def problem_bytes(prob, opts=None) -> int:
     opts = opts or default_opts()
     out = ctypes.c_uint64()
     rc = lib.stwr_problem_bytes(ctypes.byref(d), ctypes.byref(opts), ctypes.byref(out))
+    if rc != STWR_OK:
+        raise StwrError(rc, lib.stwr_last_error(None).decode())
+    return int(out.value)
+
+
+def problem_n_st(prob) -> int:
+    """Length of the problem's level-0 space-time vectors (stwr_problem_n_st)."""
+    lib = load()
+    d, keep = make_desc(prob)
+    out = ctypes.c_int64()
+    rc = lib.stwr_problem_n_st(ctypes.byref(d), ctypes.byref(out))
     if rc != STWR_OK:
         raise StwrError(rc, lib.stwr_last_error(None).decode())
     return int(out.value)
@@ -423,7 +435,7 @@ class Server:
     def submit(self, prob, opts: SolverOpts | None = None, want_solution: bool = True) -> int:
         d, keep = make_desc(prob)
         opts = opts or default_opts()
-        out = np.zeros(prob.n_st) if want_solution else None
+        out = np.zeros(problem_n_st(prob)) if want_solution else None
         rid = ctypes.c_int64()
         rc = self.lib.stwr_server_submit(self.h, ctypes.byref(d), ctypes.byref(opts),
                                          None if out is None else out.ctypes.data_as(ctypes.c_void_p),

@@ -237,6 +237,15 @@ int32_t guarded(stwr_ctx* ctx, F&& f) {
 
 bool is_heat(const stwr_problem_desc* d) { return d->equation == STWR_EQ_HEAT; }
 
+// Free spatial DoFs of a level with M squares a side: Taylor-Hood P2-P1 with
+// the boundary velocity eliminated, 2 (2M-1)^2 + (M+1)^2; the heat equation's
+// P_k lattice, (kM+1)^2 (every node free).  The level builders give the same
+// counts.
+int64_t free_dofs(const stwr_problem_desc* d, int M) {
+  if (is_heat(d)) return (int64_t)(d->degree * M + 1) * (d->degree * M + 1);
+  return 2LL * (2 * M - 1) * (2 * M - 1) + (int64_t)(M + 1) * (M + 1);
+}
+
 void check_desc(const stwr_problem_desc* d) {
   if (!d) throw StwrError(STWR_ERR_ARG, "null problem descriptor");
   if (d->equation != STWR_EQ_NAVIER_STOKES && d->equation != STWR_EQ_HEAT)
@@ -257,9 +266,7 @@ void check_desc(const stwr_problem_desc* d) {
     throw StwrError(STWR_ERR_ARG, "bad temporal nodes");
   if ((d->n_psi_modes > 0 && (!d->psi_ab || !d->psi_coef)) || (d->n_p_modes > 0 && (!d->p_ab || !d->p_coef)))
     throw StwrError(STWR_ERR_ARG, "null mode arrays");
-  const int mc = d->mesh_n >> (d->n_levels - 1);
-  const int nfc = is_heat(d) ? (d->degree * mc + 1) * (d->degree * mc + 1)
-                             : 2 * (2 * mc - 1) * (2 * mc - 1) + (mc + 1) * (mc + 1);
+  const int64_t nfc = free_dofs(d, d->mesh_n >> (d->n_levels - 1));
   if (nfc * (d->q + 1) + (is_heat(d) ? 0 : d->q + 1) > 4096)
     throw StwrError(STWR_ERR_ARG, "coarsest level too large for the dense coarse solve (use more levels)");
 }
@@ -1160,6 +1167,15 @@ int32_t stwr_problem_bytes(const stwr_problem_desc* desc, const stwr_solver_opts
     std::vector<Level> lv;
     build_levels(desc, lv);
     *bytes = plan_bytes(desc, opts, lv);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_problem_n_st(const stwr_problem_desc* desc, int64_t* n_st) {
+  return guarded(nullptr, [&]() -> int32_t {
+    check_desc(desc);
+    if (!n_st) throw StwrError(STWR_ERR_ARG, "null output");
+    *n_st = free_dofs(desc, desc->mesh_n) * desc->n_slabs * (desc->q + 1);
     return STWR_OK;
   });
 }

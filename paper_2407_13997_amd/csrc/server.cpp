@@ -111,6 +111,12 @@ void stwr_server::worker(int slot) {
       status = stwr_problem_create(ctx, &r.desc, &r.opts, &p);
     }
     if (status == STWR_OK) {
+      // the solution length the request was sized and budgeted for must be
+      // the created problem's (host_out holds that many doubles)
+      int64_t n_st = -1;
+      if (stwr_problem_sizes(p, 0, &n_st, nullptr, nullptr) != STWR_OK || n_st != r.n_st) status = STWR_ERR_STATE;
+    }
+    if (status == STWR_OK) {
       if (hipMallocAsync((void**)&U, r.n_st * sizeof(double), stream) != hipSuccess ||
           hipMemsetAsync(U, 0, r.n_st * sizeof(double), stream) != hipSuccess)
         status = STWR_ERR_OOM;
@@ -173,8 +179,8 @@ int32_t stwr_server_submit(stwr_server* S, const stwr_problem_desc* desc, const 
   uint64_t bytes = 0;
   const int32_t rc = stwr_problem_bytes(&r.desc, &r.opts, &bytes);
   if (rc != STWR_OK) return rc;
-  const int m = desc->mesh_n;
-  r.n_st = (int64_t)(2 * (2 * m - 1) * (2 * m - 1) + (m + 1) * (m + 1)) * desc->n_slabs * (desc->q + 1);
+  const int32_t rn = stwr_problem_n_st(&r.desc, &r.n_st);
+  if (rn != STWR_OK) return rn;
   r.bytes = bytes + (uint64_t)r.n_st * 8;
   r.host_out = host_out;
   std::unique_lock<std::mutex> lk(S->mu);

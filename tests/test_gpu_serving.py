@@ -41,7 +41,11 @@ def test_mix_equals_alone_and_oracle():
     assert sorted(res) == sorted(ids)
     starts = sorted((r["start_time"], r["end_time"]) for r in res.values())
     overlap = any(starts[i + 1][0] < starts[i][1] for i in range(len(starts) - 1))
-    log(f"[serve] overlap in flight: {overlap}; slots used {sorted({r['slot'] for r in res.values()})}")
+    slots = sorted({r['slot'] for r in res.values()})
+    log(f"[serve] overlap in flight: {overlap}; slots used {slots}")
+    # continuous batching, not a queue: solves were in flight together on
+    # more than one slot
+    assert overlap and len(slots) > 1
     for rid, p in zip(ids, probs):
         r = res[rid]
         assert r["status"] == 0, r
@@ -82,3 +86,34 @@ def test_budget_admission():
     for i in range(len(done) - 1):
         assert done[i + 1][0] >= done[i][1] - 1e-6, done   # never two in flight
     log(f"[serve] budget {budget} serialised {len(done)} solves; oversize request rejected")
+
+
+def test_heat_and_navier_stokes_requests_in_one_mix():
+    """Heat requests (P1 and P3 lattices, whose solution lengths are smaller
+    and larger than the Navier-Stokes count of the same mesh) served together
+    with Navier-Stokes ones: every solution has its problem's length and
+    equals the same solve run alone."""
+    torch_cuda()
+    from paper_2407_13997_amd import binding
+    probs = [w.heat_problem(8, 2, 1, 1, 5), w.small_problem(8, 2, 1, 4, 10.0, seed=31),
+             w.heat_problem(8, 2, 3, 1, 5), w.small_problem(8, 2, 0, 3, 1.0, seed=33),
+             w.heat_problem(8, 2, 2, 0, 4)]
+    srv = binding.Server(0, n_slots=3)
+    ids = [srv.submit(p, opts()) for p in probs]
+    assert srv.wait(300.0)
+    res = {r["id"]: r for r in srv.poll()}
+    srv.close()
+    assert sorted(res) == sorted(ids)
+    for rid, p in zip(ids, probs):
+        r = res[rid]
+        assert r["status"] == 0, r
+        assert r["solution"].size == binding.problem_n_st(p) == p.n_st
+        G = gpu_problem(p, smoother_prec=1)
+        U = G.vec()
+        assert U.numel() == p.n_st
+        G.newton_solve(U)
+        e_alone = rel(r["solution"], to_host(U))
+        log(f"[serve mix] id={rid} equation={p.equation} k={p.degree} M={p.mesh_n} q={p.q} "
+            f"N={p.n_slabs} n_st={p.n_st} vs alone {e_alone:.1e}")
+        assert e_alone <= 1e-12
+        G.close()

@@ -89,3 +89,28 @@ def test_null_handles_are_rejected():
     assert L.stwr_apply(None, 0, None, None) == -1
     assert L.stwr_ctx_set_timing(None, 1) == -1
     assert L.stwr_problem_destroy(None) == 0
+
+
+@pytest.mark.parametrize("kind", ["ns", "heat1", "heat2", "heat3"])
+def test_solution_length_both_equations(kind):
+    """stwr_problem_n_st (the length the server sizes, budgets and copies a
+    request's solution with) against independent counts: the host mesh
+    builder's free DoFs for Navier-Stokes, the oracle's P_k lattice for the
+    heat equation (Sec. 3.1 counts), times N (q+1)."""
+    b = lib()
+    import stwr_workloads as w
+    from oracle.heat import HeatSpace
+    for M, q, N in ((4, 0, 3), (8, 1, 5)):
+        if kind == "ns":
+            p = w.small_problem(M, 2, q, N, 1.0, 3)
+            nf = int(b.mesh_info(M)[0])
+        else:
+            k = int(kind[-1])
+            p = w.heat_problem(M, 2, k, q, N)
+            nf = HeatSpace(M, k).n
+        assert b.problem_n_st(p) == nf * N * (q + 1)
+    # P3 heat lattices are larger than the Navier-Stokes count, P1 and P2 smaller,
+    # so a solution sized by the wrong formula would overrun one way or the other
+    ns = w.small_problem(8, 2, 1, 5, 1.0, 3)
+    h1, h3 = w.heat_problem(8, 2, 1, 1, 5), w.heat_problem(8, 2, 3, 1, 5)
+    assert b.problem_n_st(h1) < b.problem_n_st(ns) < b.problem_n_st(h3)
