@@ -87,3 +87,19 @@ def spacetime_from_bsr(rp, col, val, mass, nf, N, NQ, e0, e1):
                       shape=(nf * st, nf * st))
     A.sum_duplicates()
     return A
+
+
+def entrywise(got, want, n_free, N, nq, floor=1e-2):
+    """Element-wise errors of a space-time vector [DoF][slab][node]:
+    (worst over slabs of max|got - want| / max|want| on that slab,
+     worst |got - want| / |want| over the entries with |want| >= floor times
+     their slab's largest |want|)."""
+    g = np.asarray(got, dtype=float).reshape(n_free, N, nq)
+    r = np.asarray(want, dtype=float).reshape(n_free, N, nq)
+    d = np.abs(g - r)
+    ref = np.abs(r)
+    smax = ref.max(axis=(0, 2))
+    slab = (d.max(axis=(0, 2)) / np.maximum(smax, 1e-300)).max()
+    big = ref >= floor * smax[None, :, None]
+    entry = (d[big] / ref[big]).max() if big.any() else 0.0
+    return float(slab), float(entry)
