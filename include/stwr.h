@@ -309,6 +309,19 @@ int32_t stwr_patch_factor(stwr_problem* p, int32_t level, int32_t prec);
  * per patch, forward block substitution over the slabs (eq. waveform_patch_solve). */
 int32_t stwr_patch_apply(stwr_problem* p, int32_t level, const double* r, double* z);
 
+/* stwr_patch_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, with the per-patch outputs kept in a
+ * fixed 64 MiB device area of the library (one per device, resolved when the
+ * first context on the device is created and held until the process ends)
+ * instead of the level's own buffer.  The call allocates nothing.  The area
+ * must hold the level's patch outputs, sum over patches of nb N (q+1) doubles
+ * (each patch rounded up to 16 doubles); a larger level gives STWR_ERR_ARG
+ * with the sizes in the message.  Every call on a device shares that
+ * device's area, so calls that overlap on one device (other streams or host
+ * threads) race; calls on one stream do not. */
+int32_t stwr_patch_apply_noalloc(stwr_problem* p, int32_t level, const double* r, double* z);
+
 /* lam = max real Ritz value of M^{-1} A_l after opts.eig_steps Arnoldi steps
  * from v0[i] = frac(0.6180339887498949 i) - 0.5 (normalised). */
 int32_t stwr_eig_estimate(stwr_problem* p, int32_t level, double* lambda);

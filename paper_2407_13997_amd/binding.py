@@ -30,7 +30,8 @@ EXPORTED = [
     "stwr_nonlinear_residual", "stwr_linear_rhs", "stwr_velocity_l2_error", "stwr_expand",
     "stwr_assemble",
     "stwr_get_operator", "stwr_apply",
-    "stwr_residual", "stwr_patch_factor", "stwr_patch_apply", "stwr_eig_estimate",
+    "stwr_residual", "stwr_patch_factor", "stwr_patch_apply", "stwr_patch_apply_noalloc",
+    "stwr_eig_estimate",
     "stwr_relax", "stwr_restrict", "stwr_prolong_add", "stwr_coarse_solve",
     "stwr_setup_smoothers", "stwr_vcycle", "stwr_fgmres", "stwr_newton_solve",
     "stwr_project_pressure", "stwr_ctx_set_timing", "stwr_ctx_kernel_times",
@@ -136,6 +137,7 @@ def load(path: str | None = None):
         "stwr_residual": [P, i32, V, V, V],
         "stwr_patch_factor": [P, i32, i32],
         "stwr_patch_apply": [P, i32, V, V],
+        "stwr_patch_apply_noalloc": [P, i32, V, V],
         "stwr_eig_estimate": [P, i32, ctypes.POINTER(f64)],
         "stwr_relax": [P, i32, V, V, i32, f64, f64],
         "stwr_restrict": [P, i32, V, V],
@@ -377,6 +379,9 @@ class Problem:
 
     def patch_apply(self, level, r, z):
         self.ctx.check(self.lib.stwr_patch_apply(self.h, level, _ptr(r), _ptr(z)))
+
+    def patch_apply_noalloc(self, level, r, z):
+        self.ctx.check(self.lib.stwr_patch_apply_noalloc(self.h, level, _ptr(r), _ptr(z)))
 
     def eig_estimate(self, level):
         lam = ctypes.c_double()

@@ -43,6 +43,36 @@ double now_s() {
 
 }  // namespace
 
+// Patch-output area of stwr_patch_apply_noalloc: one per device, held until
+// the process ends.  Host code never passes the array's name to a kernel or a
+// copy: it uses the device address from hipGetSymbolAddress, taken once per
+// device when the first context on that device is created.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device; null until resolved
+
+// Resolves (once per device, the device current) the device address of the
+// scratch array; throws on failure.
+void resolve_scratch(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (g_scratch_ptr[device]) return;
+  double* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw StwrError(STWR_ERR_DEVICE, std::string("scratch symbol address: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+}
+
+double* scratch_of(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
+
 struct stwr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -1096,6 +1126,7 @@ int32_t stwr_ctx_create(int32_t device, void* hip_stream, uint64_t hbm_budget, s
     HIPCHK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) throw StwrError(STWR_ERR_ARG, "bad device index");
     HIPCHK(hipSetDevice(device));
+    resolve_scratch(device);
     auto* c = new stwr_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -1470,6 +1501,27 @@ int32_t stwr_patch_apply(stwr_problem* p, int32_t level, const double* r, double
     level_at(p, level);
     if (!r || !z) throw StwrError(STWR_ERR_ARG, "null vector");
     patch_apply(p, level, r, z);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_patch_apply_noalloc(stwr_problem* p, int32_t level, const double* r, double* z) {
+  if (!p) return STWR_ERR_ARG;
+  return guarded(p->ctx, [&]() -> int32_t {
+    Level& L = level_at(p, level);
+    if (!r || !z) throw StwrError(STWR_ERR_ARG, "null vector");
+    if (level >= (int)p->lv.size() - 1 || L.y_off.empty())
+      throw StwrError(STWR_ERR_ARG, "the coarsest level has no smoother");
+    const uint64_t need = (uint64_t)L.y_off.back() * sizeof(double);
+    if (need > kScratchBytes)
+      throw StwrError(STWR_ERR_ARG, "patch outputs of level " + std::to_string(level) + " need " +
+                                        std::to_string(need) + " bytes, more than the " +
+                                        std::to_string(kScratchBytes) + "-byte scratch area");
+    double* ybuf = scratch_of(p->ctx->device);
+    if (!ybuf) throw StwrError(STWR_ERR_STATE, "scratch area not resolved on this device");
+    require_factor(p, level);
+    HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, p->tab.e0, p->tab.e1, r, ybuf, p->s()));
+    HIPCHK(launch_patch_gather(L.view, L.pview, L.fac_prec, ybuf, 0, 0.0, 0.0, z, nullptr, nullptr, p->s()));
     return STWR_OK;
   });
 }
