@@ -33,50 +33,93 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seconds_budget: float = 5.0) -> dict:
     """Time the oracle's sweep (residual + patch solves + Chebyshev update) on a
     bounded sample with the same per-patch work as the benchmark workload:
     16x16 mesh (289 patches, interior blocks of 78x78 per slab), q = 1,
-    64 slabs, Re = 1000; single-threaded BLAS/LAPACK."""
+    64 slabs, Re = 1000; single-threaded BLAS/LAPACK.  First on one core, then
+    on every core of the process's affinity set with the patches split over a
+    pool of worker processes (each holding the factors of its share of the
+    patches), the residual and the update in the parent."""
     code = r"""
 import os, sys, time, json
 sys.path.insert(0, %r)
+import multiprocessing as mp
 import numpy as np
 import stwr_workloads as w
 from oracle.multigrid import Hierarchy, Options
-from oracle.smoother import chebyshev
+from oracle.smoother import chebyshev, PatchSmoother
 prob = w.Problem(16, 2, 1, 64, 1.0, 1000.0, *w.draw_modes(4000, 16, 3, 8), seed=4000)
 H = Hierarchy(prob, Options())
 L0 = H.levels[0]
 H.assemble(L0.initial_guess().ravel(), with_smoothers=False)
-from oracle.smoother import PatchSmoother
 sm = PatchSmoother(L0, H.A[0])
 b = np.random.default_rng(1).standard_normal(L0.n_st)
 x0 = np.random.default_rng(2).standard_normal(L0.n_st)
+budget = %f
 t0 = time.perf_counter(); n = 0
 while True:
     x = chebyshev(H.A[0], sm.apply, b, x0, 1, 5.0, 22.0)
     n += 1
-    if time.perf_counter() - t0 > %f: break
-dt = (time.perf_counter() - t0) / n
-print(json.dumps({"n_st": L0.n_st, "sweep_s": dt, "sweeps": n}))
+    if time.perf_counter() - t0 > budget: break
+dt1 = (time.perf_counter() - t0) / n
+cores = len(os.sched_getaffinity(0))
+import copy
+SHARE = []
+for k in range(cores):
+    part = copy.copy(sm)
+    part.blocks = sm.blocks[k::cores]
+    SHARE.append(part)
+def work(args):
+    k, r = args
+    return SHARE[k].apply(r)
+ctx = mp.get_context("fork")
+with ctx.Pool(cores) as pool:
+    def par_apply(r):
+        return np.sum(pool.map(work, [(k, r) for k in range(cores)]), axis=0)
+    xp = chebyshev(H.A[0], par_apply, b, x0, 1, 5.0, 22.0)
+    err = float(np.max(np.abs(xp - x)) / np.max(np.abs(x)))
+    t0 = time.perf_counter(); m = 0
+    while True:
+        chebyshev(H.A[0], par_apply, b, x0, 1, 5.0, 22.0)
+        m += 1
+        if time.perf_counter() - t0 > budget: break
+    dtp = (time.perf_counter() - t0) / m
+print(json.dumps({"n_st": L0.n_st, "sweep_s": dt1, "sweeps": n, "cores": cores,
+                  "sweep_s_all": dtp, "sweeps_all": m, "all_vs_one_maxrel": err}))
 """ % (ROOT, seconds_budget)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     t0 = time.perf_counter()
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=600)
+                         timeout=900)
     if res.returncode != 0:
         log(res.stderr[-2000:])
         return {"value": None, "unit": "st-DoF/s", "cores": 1, "kind": "oracle",
                 "sample": "failed"}
     out = json.loads(res.stdout.strip().splitlines()[-1])
     return {"value": out["n_st"] / out["sweep_s"], "unit": "st-DoF/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": (f"oracle WR sweep (residual + 289 vertex-patch solves x 64 slabs + "
                        f"Chebyshev update) on a 16x16 mesh, q=1, N=64, Re=1000 "
                        f"({out['n_st']} st-DoFs, same per-patch work as the 128x128 workload), "
-                       f"{out['sweeps']} sweeps, wall {time.perf_counter() - t0:.1f}s incl. setup"),
-            "sweep_s": out["sweep_s"]}
+                       f"{out['sweeps']} sweeps on one core, {out['sweeps_all']} on {out['cores']}, "
+                       f"wall {time.perf_counter() - t0:.1f}s incl. setup"),
+            "sweep_s": out["sweep_s"],
+            "all_cores": {"value": out["n_st"] / out["sweep_s_all"], "unit": "st-DoF/s",
+                          "cores": out["cores"], "sweep_s": out["sweep_s_all"],
+                          "max_rel_diff_vs_one_core": out["all_vs_one_maxrel"],
+                          "how": "patches dealt round-robin to a fork pool of one process per core"},
+            "note": "reported baseline, not the target"}
 
 
 def main():
@@ -92,6 +135,9 @@ def main():
     ap.add_argument("--no-paper-context", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--vcycles", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--largest-solve", type=int, default=0,
+                    help="also run the 128x128 Newton solve with this many levels (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
     args = ap.parse_args()
 
@@ -163,9 +209,42 @@ def main():
     # outputs once
     s_f = 4 if prec == binding.FP32 else 8
     sweep_ms, sweep_n = kt["sweep"]
-    info_bytes = patch_sweep_bytes(prob, s_f)
+    io_bytes = patch_sweep_bytes(prob, s_f)
+    algo_bytes = patch_sweep_bytes_algorithmic(prob, s_f, n_st)
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
-    achieved = info_bytes / (sweep_avg_ms * 1e-3) / 1e9
+    achieved = algo_bytes / (sweep_avg_ms * 1e-3) / 1e9
+    achieved_io = io_bytes / (sweep_avg_ms * 1e-3) / 1e9
+
+    # the plain form on the same workload: FP64 factors and sweep (outside
+    # the timed region; the FP32 factors are replaced)
+    fp64_leg = None
+    if prec == binding.FP32 and args.fp64_steps > 0:
+        P.patch_factor(0, binding.FP64)
+        x64 = torch.zeros(n_st, dtype=torch.float64, device="cuda")
+        P.relax(0, b, x64, 2, a, bnd)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ctx.kernel_times()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.fp64_steps):
+            P.relax(0, b, x64, 1, a, bnd)
+        e1.record()
+        torch.cuda.synchronize()
+        kt64 = ctx.kernel_times()
+        ctx.set_timing(False)
+        ms64 = e0.elapsed_time(e1) / args.fp64_steps
+        sw64 = kt64["sweep"][0] / max(kt64["sweep"][1], 1)
+        algo64 = patch_sweep_bytes_algorithmic(prob, 8, n_st)
+        fp64_leg = {"smoother_prec": "fp64", "ms_per_step": ms64, "value": n_st / (ms64 * 1e-3),
+                    "unit": "st-DoF/s", "steps": args.fp64_steps,
+                    "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt64.items()},
+                    "roofline": {"bound": "hbm", "kernel": "k_patch_sweep (FP64)", "avg_ms": sw64,
+                                 "algorithmic_bytes": algo64,
+                                 "achieved": algo64 / (sw64 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": algo64 / (sw64 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+        log(f"[bench] fp64 sweep: {fp64_leg}")
+        P.patch_factor(0, prec)
 
     # one full V(2,2) cycle on all levels (outside the timed region)
     vc_ms = None
@@ -212,11 +291,17 @@ def main():
                                  else None),
                      "kernel": ("k_patch_sweep_f32 (interior + boundary launches)" if prec == binding.FP32
                                 else "k_patch_sweep"), "avg_ms": sweep_avg_ms,
-                     "algorithmic_bytes": info_bytes},
+                     "algorithmic_bytes": algo_bytes,
+                     "algorithmic_bytes_def": "sum over (patch, slab) of m^2 s_f + 24 n_st (r read, z read-modify-write)",
+                     "with_patch_io": {"bytes": io_bytes, "achieved": achieved_io,
+                                       "frac": achieved_io / HBM_PEAK_GBS,
+                                       "def": "sum over (patch, slab) of m^2 s_f + 8 m + s_f m "
+                                              "(each patch's residual gather and its own outputs)"}},
         "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "setup_s": {"assemble_all_levels": t_asm, "factor_finest": t_fac, "eig_estimate": t_eig},
         "vcycle_ms": vc_ms,
+        "fp64_sweep": fp64_leg,
         "lambda_finest": lam,
     }
     P.close()
@@ -225,6 +310,9 @@ def main():
         log(f"[bench] single solve: {out['single_solve']}")
         out["serving"] = serving_benchmark()
         log(f"[bench] serving: {out['serving']}")
+    if args.largest_solve > 0:
+        out["largest_solve"] = largest_solve(args.largest_solve)
+        log(f"[bench] largest solve: {out['largest_solve']}")
     if not args.no_paper_context:
         out["paper_context"] = paper_context()
         log(f"[bench] paper context: {out['paper_context']}")
@@ -468,6 +556,63 @@ def single_solve() -> dict:
     return out
 
 
+NEWTON_REF = os.path.join(ROOT, "tests", "golden", "ns_p2p1_dg1_m128_n64_re1000_newton_reference.json")
+
+
+def largest_solve(levels: int, newton_maxit: int = 8, gmres_maxit: int = 120) -> dict:
+    """The largest single solve: 128 x 128, P2-P1 x DG(1), 64 slabs, Re 1000,
+    16 stream-function modes; Newton to 1e-10 from zero with FGMRES(30)
+    preconditioned by V(2,2) cycles over `levels` levels, FP32 patch factors
+    and relaxation, FP64 Krylov, Newton, residual and coarsest solve.  Records
+    Newton and linear iterations, the residual history, time, device bytes
+    and (when the oracle's sampled slab 0-1 solution is present) the error of
+    slabs 0 and 1 against it."""
+    import numpy as np
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    base = w.named_problem(w.LARGE)
+    prob = w.Problem(base.mesh_n, levels, base.q, base.n_slabs, base.t_final, base.reynolds, base.psi_ab,
+                     base.psi_coef, base.p_ab, base.p_coef, seed=base.seed)
+    ctx = binding.Context(0)
+    o = binding.default_opts()
+    o.smoother_prec = binding.FP32
+    o.newton_rtol = 1e-10
+    o.newton_maxit = newton_maxit
+    o.gmres_maxit = gmres_maxit
+    t0 = time.perf_counter()
+    P = binding.Problem(ctx, prob, o)
+    t_create = time.perf_counter() - t0
+    U = P.vec()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = "converged"
+    try:
+        st = P.newton_solve(U, allow_unconverged=True)
+        if st["fnorm"][-1] > 1e-10 * st["fnorm"][0]:
+            status = "not converged"
+    except binding.StwrError as e:
+        st, status = None, str(e)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": f"{w.LARGE} Newton solve, {levels} levels (coarsest {128 >> (levels - 1)}x"
+                       f"{128 >> (levels - 1)}), FP32 smoother, newton_maxit {newton_maxit}, "
+                       f"FGMRES(30) maxit {gmres_maxit} per step",
+           "st_dofs": prob.n_st, "status": status, "create_s": t_create, "solve_s": dt,
+           "device_bytes": ctx.bytes_in_use(), "stats": st}
+    if st is not None and os.path.exists(NEWTON_REF):
+        ref = json.load(open(NEWTON_REF))
+        idx = np.array(ref["index"])
+        got = U.cpu().numpy()[idx]
+        want = np.array(ref["value"])
+        out["slab01_vs_oracle"] = {"samples": int(idx.size),
+                                   "max_abs_err_over_max_abs": float(np.max(np.abs(got - want))
+                                                                    / np.max(np.abs(want)))}
+    P.close()
+    ctx.close()
+    return out
+
+
 def time_chunk_context(steps: int = 10) -> list:
     """Cyclic reduction in time on small meshes with long time axes (the
     uneven-batch distribution's small end: P2-P1 x DG(1), 128 slabs, Re 10):
@@ -573,6 +718,17 @@ def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:
                     "p50_latency_s": float(np.percentile(lat, 50)) if lat else None,
                     "p99_latency_s": float(np.percentile(lat, 99)) if lat else None},
     }
+
+
+def patch_sweep_bytes_algorithmic(prob, s_f: int, n_st: int) -> int:
+    """Algorithmic bytes of one WR sweep's patch kernel: every (patch, slab)
+    inverse block once, m^2 s_f bytes (m = (q+1) nb), plus the FP64 residual
+    read once (8 n_st) and the correction read and written once (16 n_st)."""
+    from paper_2407_13997_amd import binding
+    hist = binding.mesh_info(prob.mesh_n)[12:52]
+    nq = prob.q + 1
+    blocks = sum(int(cnt) * prob.n_slabs * (nb * nq) ** 2 * s_f for nb, cnt in enumerate(hist))
+    return blocks + 24 * int(n_st)
 
 
 def patch_sweep_bytes(prob, s_f: int) -> int:

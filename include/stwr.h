@@ -186,6 +186,7 @@ typedef struct {
   double lambda[STWR_MAX_LEVELS];         /* last eigen-estimate per smoothed level */
   double final_rel_residual;              /* FGMRES: last relative residual */
   double setup_seconds, solve_seconds;    /* host wall clock of setup and Krylov phases */
+  double linear_rel[STWR_MAX_NEWTON];     /* Newton: ||b - A dU|| / ||b|| reached by each linear solve */
 } stwr_stats;
 
 /* ---- context ---------------------------------------------------------- */

@@ -39,7 +39,8 @@ class PatchSmoother:
             lus, subs = [], []
             for n in range(N):
                 lus.append(la.lu_factor(Ap[n * k:(n + 1) * k, n * k:(n + 1) * k]))
-                subs.append(Ap[n * k:(n + 1) * k, (n - 1) * k:n * k] if n > 0 else None)
+                # a copy: a view would keep the whole dense patch matrix alive
+                subs.append(Ap[n * k:(n + 1) * k, (n - 1) * k:n * k].copy() if n > 0 else None)
             self.blocks.append((idx, perm, lus, subs, k))
 
     def patch_solve(self, i, rp_slab_major):

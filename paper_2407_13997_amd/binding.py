@@ -72,7 +72,8 @@ class Stats(ctypes.Structure):
                 ("fnorm", ctypes.c_double * (MAX_NEWTON + 1)),
                 ("lambda_", ctypes.c_double * MAX_LEVELS),
                 ("final_rel_residual", ctypes.c_double),
-                ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
+                ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double),
+                ("linear_rel", ctypes.c_double * MAX_NEWTON)]
 
     def as_dict(self):
         k = self.newton_its
@@ -80,7 +81,8 @@ class Stats(ctypes.Structure):
                 "linear_total": self.linear_its_total,
                 "fnorm": list(self.fnorm[:k + 1]), "lambda": list(self.lambda_),
                 "final_rel_residual": self.final_rel_residual,
-                "setup_seconds": self.setup_seconds, "solve_seconds": self.solve_seconds}
+                "setup_seconds": self.setup_seconds, "solve_seconds": self.solve_seconds,
+                "linear_rel": list(self.linear_rel[:max(k, 1)])}
 
 
 class Result(ctypes.Structure):

@@ -1689,6 +1689,7 @@ int32_t stwr_newton_solve(stwr_problem* p, double* U, stwr_stats* stats) {
       st.solve_seconds += now_s() - tk;
       HIPCHK(launch_axpby(n, 1.0, dU, 1.0, U, p->s()));
       st.linear_its[k] = its;
+      st.linear_rel[k] = rel;
       st.linear_its_total += its;
       f = resid();
       st.fnorm[k + 1] = f;

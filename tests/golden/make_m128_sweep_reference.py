@@ -9,8 +9,10 @@ blocks of those slabs; at U = 0 those blocks are the ones of the same problem
 truncated to S slabs of the same length (t_final = S / 64).  The oracle
 assembles that truncated space-time Jacobian and applies its patch smoother
 on every vertex patch that contains a sampled DoF, so each sampled output is
-the complete additive sum.  Calls only the oracle and the seeded generators.
-Run: python tests/golden/make_m128_sweep_reference.py   (about a minute)
+the complete additive sum.  Samples are taken on slabs 0-2 and 8-9, so the
+check crosses the FP32 sweep's first 8-slab residual line.  Calls only the
+oracle and the seeded generators.
+Run: python tests/golden/make_m128_sweep_reference.py   (a few minutes)
 """
 import json
 import os
@@ -27,9 +29,11 @@ from oracle.assembly import Level  # noqa: E402
 from oracle.mms import MMS  # noqa: E402
 from oracle.smoother import PatchSmoother  # noqa: E402
 
-S = 3                 # slabs checked
+S = 10                # slabs of the truncated problem
+CHECKED = (0, 1, 2, 8, 9)   # slabs sampled: the first ones and two past the
+                            # first 8-slab residual line of the FP32 sweep
 R_SEED = 4100         # residual of the full problem: seeded_vector(n_st, R_SEED)
-N_SAMPLES = 240
+N_SAMPLES = 400
 
 
 def main():
@@ -45,8 +49,8 @@ def main():
     A = lev.jacobian(lev.initial_guess())
     rng = np.random.default_rng(4101)
     # sampled (DoF, slab, node): DoFs spread over velocity and pressure
-    dofs = np.sort(rng.choice(nf, N_SAMPLES // S, replace=False))
-    samples = [(int(d), n, int(rng.integers(nq))) for d in dofs for n in range(S)]
+    dofs = np.sort(rng.choice(nf, N_SAMPLES // len(CHECKED), replace=False))
+    samples = [(int(d), n, int(rng.integers(nq))) for d in dofs for n in CHECKED]
     patches = [P for P in lev.mesh.patches() if np.isin(P, dofs).any()]
     z = PatchSmoother(lev, A, patches=patches).apply(r).reshape(nf, S, nq)
     idx = [(d * p.n_slabs + n) * nq + a for d, n, a in samples]
@@ -54,7 +58,7 @@ def main():
     out = {"workload": "128x128, P2-P1 x DG(1), 64 slabs, Re 1000, seed 4000, U = 0",
            "operation": "one additive WR Vanka+star patch application z = M^{-1} r",
            "residual": f"seeded_vector(n_st, {R_SEED}) of the full problem",
-           "slabs_checked": S, "n_st": int(n_st_full), "patches_used": len(patches),
+           "slabs_checked": list(CHECKED), "n_st": int(n_st_full), "patches_used": len(patches),
            "index": idx, "value": val, "seconds": time.time() - t}
     with open(os.path.join(HERE, "ns_p2p1_dg1_m128_n64_re1000_sweep_reference.json"), "w") as f:
         json.dump(out, f)
