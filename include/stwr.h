@@ -400,6 +400,48 @@ int32_t stwr_server_now(const stwr_server* s, double* t);
 /* Finishes the requests in flight, drops the queued ones, joins the workers. */
 int32_t stwr_server_destroy(stwr_server* s);
 
+/* ---- batched solves: many problems in shared launches ------------------
+ * A batch advances many independent Navier-Stokes solves together on its
+ * context's stream, each exactly as stwr_newton_solve would with FP32 patch
+ * factors and sweeps and the plain sweep in time (time_chunks = 1): the patch
+ * systems are independent across patches and so across problems (eq.
+ * waveform_patch_solve), so every relaxation sweep covers the patches of
+ * every problem at that multigrid depth in one persistent launch per
+ * temporal-node count, and every patch factorization all levels of all
+ * problems at the start of a Newton step in one persistent launch per block
+ * class.  The patches (sweep) or blocks (factorization) a workgroup takes at
+ * a time are chosen per class by timing the candidates on the batch.  With
+ * use_graph = 1 the batched V-cycle is captured into a HIP graph and replayed
+ * while the set of problems in their Krylov phase (and their Newton steps) is
+ * unchanged.  A problem's result equals its solve alone with the same
+ * options up to rounding (the operations are the same, in the same order).
+ *
+ * stwr_batch_add creates the problem at once on the batch's context
+ * (STWR_ERR_BUDGET if it does not fit the context's HBM budget; nothing is
+ * then kept) and starts it at the next step.  It must be a Navier-Stokes
+ * problem with at least two levels and smoother_prec = STWR_FP32; every
+ * problem of a batch has the same nu_pre and nu_post (the first fixes them).
+ * host_out: n_st doubles of host memory for the solution (or NULL), written
+ * when the problem finishes and valid once its result is polled.
+ * stwr_batch_step: one step, i.e. one FGMRES iteration of every problem in
+ * its Krylov phase, after the Newton bookkeeping, assembly, factorization and
+ * eigen-estimates of those starting a Newton step; *n_live = problems not yet
+ * finished.  Finished problems are released and their results (status,
+ * iterations, times on the batch's clock in seconds) queued for
+ * stwr_batch_poll.  stwr_batch_info fills out[0..10]: steps, graph captures,
+ * V-cycles, sweep launches, factorization launches, sweep tiles (one and two
+ * temporal nodes; 0 = not chosen yet), factorization tiles (three classes),
+ * live problems. */
+typedef struct stwr_batch stwr_batch;
+
+int32_t stwr_batch_create(stwr_ctx* ctx, int32_t use_graph, stwr_batch** out);
+int32_t stwr_batch_add(stwr_batch* b, const stwr_problem_desc* desc, const stwr_solver_opts* opts,
+                       double* host_out, int64_t* id_out);
+int32_t stwr_batch_step(stwr_batch* b, int32_t* n_live);
+int32_t stwr_batch_poll(stwr_batch* b, stwr_result* results, int32_t max_results, int32_t* n_out);
+int32_t stwr_batch_info(const stwr_batch* b, int64_t* out);
+int32_t stwr_batch_destroy(stwr_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

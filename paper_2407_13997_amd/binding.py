@@ -37,6 +37,8 @@ EXPORTED = [
     "stwr_project_pressure", "stwr_ctx_set_timing", "stwr_ctx_kernel_times",
     "stwr_ctx_set_alloc_mode", "stwr_server_create", "stwr_server_submit", "stwr_server_poll",
     "stwr_server_wait", "stwr_server_now", "stwr_server_destroy",
+    "stwr_batch_create", "stwr_batch_add", "stwr_batch_step", "stwr_batch_poll", "stwr_batch_info",
+    "stwr_batch_destroy",
 ]
 
 
@@ -160,6 +162,12 @@ def load(path: str | None = None):
         "stwr_server_wait": [P, f64],
         "stwr_server_now": [P, ctypes.POINTER(f64)],
         "stwr_server_destroy": [P],
+        "stwr_batch_create": [P, i32, ctypes.POINTER(P)],
+        "stwr_batch_add": [P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolverOpts), V, ctypes.POINTER(i64)],
+        "stwr_batch_step": [P, ctypes.POINTER(i32)],
+        "stwr_batch_poll": [P, ctypes.POINTER(Result), i32, ctypes.POINTER(i32)],
+        "stwr_batch_info": [P, ctypes.POINTER(i64)],
+        "stwr_batch_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -476,4 +484,68 @@ class Server:
     def close(self):
         if self.h:
             self.lib.stwr_server_destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """Batched solves on one context (stwr_batch_*): problems advance together,
+    their patch factorizations and sweeps in shared persistent launches."""
+
+    INFO = ("steps", "graph_captures", "vcycles", "sweep_launches", "factor_launches", "sweep_tile_q0",
+            "sweep_tile_q1", "factor_tile_small1", "factor_tile_small2", "factor_tile_big2", "live")
+
+    def __init__(self, ctx: Context, use_graph: bool = True):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = ctypes.c_void_p()
+        ctx.check(self.lib.stwr_batch_create(ctx.h, 1 if use_graph else 0, ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def add(self, prob, opts: SolverOpts | None = None, want_solution: bool = True) -> int:
+        """Create the problem in the batch; raises StwrError (STWR_ERR_BUDGET
+        when it does not fit the context's budget)."""
+        d, keep = make_desc(prob)
+        opts = opts or default_opts()
+        out = np.zeros(problem_n_st(prob)) if want_solution else None
+        rid = ctypes.c_int64()
+        self.ctx.check(self.lib.stwr_batch_add(self.h, ctypes.byref(d), ctypes.byref(opts),
+                                               None if out is None else out.ctypes.data_as(ctypes.c_void_p),
+                                               ctypes.byref(rid)))
+        self._keep[rid.value] = out
+        return rid.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        self.ctx.check(self.lib.stwr_batch_step(self.h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, max_results: int = 256):
+        buf = (Result * max_results)()
+        n = ctypes.c_int32()
+        self.ctx.check(self.lib.stwr_batch_poll(self.h, buf, max_results, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            d = buf[i].as_dict()
+            d["solution"] = self._keep.pop(d["id"], None)
+            out.append(d)
+        return out
+
+    def run(self, max_steps: int = 1_000_000):
+        """Step until every problem has finished; returns all results."""
+        res = []
+        for _ in range(max_steps):
+            live = self.step()
+            res += self.poll()
+            if live == 0:
+                break
+        return res + self.poll()
+
+    def info(self) -> dict:
+        out = np.zeros(len(self.INFO), dtype=np.int64)
+        self.ctx.check(self.lib.stwr_batch_info(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return dict(zip(self.INFO, (int(v) for v in out)))
+
+    def close(self):
+        if self.h:
+            self.lib.stwr_batch_destroy(self.h)
             self.h = None

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libstwr.so")
 
 SOURCES = ["host_setup.cpp", "assembly.hip", "linear.hip", "patch.hip", "factor_mfma.hip", "api.hip",
-           "server.cpp"]
+           "batch.hip", "server.cpp"]
 ARCH = "gfx950"
 
 

@@ -302,6 +302,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
       pv.n_big += nb_of(v) * L.NQ > 64;
     }
     pv.order = P->upload(order);
+    L.order = order;
     L.P_ptr = P->upload(L.Tr.p_ptr);
     L.P_col = P->upload(L.Tr.p_col);
     L.P_val = P->upload(L.Tr.p_val);

@@ -251,6 +251,62 @@ hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec,
                                int mode, double c1, double c2, double* z, double* d, double* x,
                                hipStream_t s);
 
+// ---- batched patch kernels over many problems ----------------------------------
+// One (problem, level) of a batched FP32 sweep: the level's structure, its
+// FP32 factors and patch mass, the residual it reads and the FP32 outputs it
+// writes (Navier-Stokes, plain sweep in time).
+struct SweepJob {
+  LevelView L;
+  PatchView P;
+  const float* fac;
+  const double* Mp;
+  const double* r;
+  float* Y;
+  double e00, e01, e10, e11;
+};
+// A tile of a batched sweep: patches at positions first .. first + count - 1
+// of job's patch order, swept one after another by one workgroup.
+struct SweepTile {
+  int job, first, count;
+};
+// Persistent FP32 sweep over a list of tiles whose jobs all have nq temporal
+// nodes, the tiles of interior (full-size) patches first (n_full_tiles of
+// them), then the tiles of the other patches: grid workgroups take tiles in
+// list order from a counter (ctr[0]; ctr[1] counts finished workgroups, and
+// the last one resets both, so the pair starts at zero for the next launch).
+hipError_t launch_patch_sweep_batch(int nq, const SweepJob* jobs, const SweepTile* tiles, int n_full_tiles,
+                                    int n_tiles, int grid, int* ctr, hipStream_t s);
+
+// One (problem, level) of a batched FP32 factorization.
+struct FactorJob {
+  LevelView L;
+  PatchView P;
+  const double* Jv;
+  float* fac;
+  int* status;
+};
+// Block classes of the batched factorization: FP32 blocks of one temporal
+// node (at most 39 rows), of two nodes with at most 64 rows, and of two
+// nodes with more than 64 rows (MFMA blocked Gauss-Jordan).
+enum { kFacSmall1 = 0, kFacSmall2 = 1, kFacBig2 = 2, kFacClasses = 3 };
+// A tile of a batched factorization: blocks first .. first + count - 1 of a
+// job, block b being the block of the patch at position b / fac_slabs of the
+// job's patch order, at slab b % fac_slabs (a tile stays inside one class).
+struct FactorTile {
+  int job, first, count;
+};
+// Persistent factorization of one block class over a list of tiles (counter
+// pair as for the sweep).
+hipError_t launch_patch_factor_batch(int cls, const FactorJob* jobs, const FactorTile* tiles, int n_tiles,
+                                     int grid, int* ctr, hipStream_t s);
+hipError_t launch_patch_factor_mfma_batch(const FactorJob* jobs, const FactorTile* tiles, int n_tiles,
+                                          int grid, int* ctr, hipStream_t s);
+// Workgroups of each kind that fit on one compute unit at once (from the
+// kernels' register and LDS use), for sizing persistent grids.
+int patch_sweep_batch_occupancy(int nq);
+int patch_factor_batch_occupancy(int cls);
+int patch_factor_mfma_batch_occupancy();
+
 // ---- coarsest level ---------------------------------------------------------------
 // Bordered slab blocks of at most this order are inverted and applied by one
 // workgroup; larger ones by the blocked, chip-wide kernels.

@@ -33,14 +33,20 @@ constexpr int kFS = kFM + 1;   // LDS row stride (column reads fall in distinct 
 constexpr int kFP = 16;        // panel width
 constexpr int kFT = kFM / 16;  // tiles per side
 
-__global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView P, int first,
-                                                          const double* __restrict__ Jv,
-                                                          float* __restrict__ fac,
-                                                          int* __restrict__ status) {
-  __shared__ float A[kFM * kFS];
-  __shared__ int perm[kFM];
-  __shared__ int ofs[kFM];   // at the end: the A column of each output column
-  const int p = P.order[first + blockIdx.x / P.fac_slabs], n = blockIdx.x % P.fac_slabs;
+struct MfmaFactorLds {
+  float A[kFM * kFS];
+  int perm[kFM];
+  int ofs[kFM];   // at the end: the A column of each output column
+  float swp[2][kFP];
+};
+
+// The block of patch p (its id) at slab n.
+__device__ __forceinline__ void factor_block_mfma(const LevelView& L, const PatchView& P, const int p, const int n,
+                                                  const double* __restrict__ Jv, float* __restrict__ fac,
+                                                  int* __restrict__ status, MfmaFactorLds& S) {
+  float* A = S.A;
+  int* perm = S.perm;
+  int* ofs = S.ofs;
   const int lane = threadIdx.x;
   // two temporal nodes (q = 1): each spatial pair (I, J) of the patch is a
   // 2 x 2 block, 32 contiguous bytes of Jv
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView
   __syncthreads();
   bool bad = false;
   const int lr = lane % 16, lk = lane / 16;
-  __shared__ float swp[2][kFP];
+  float (*swp)[kFP] = S.swp;
   // lane l holds rows l and l + 64 (the latter for l < 16) of the panel
   const int row0 = lane, row1 = lane + 64;
   const bool has1 = row1 < kFM;
@@ -212,7 +218,58 @@ __global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView
   }
 }
 
+__global__ __launch_bounds__(64) void k_patch_factor_mfma(LevelView L, PatchView P, int first,
+                                                          const double* __restrict__ Jv,
+                                                          float* __restrict__ fac,
+                                                          int* __restrict__ status) {
+  __shared__ MfmaFactorLds S;
+  const int p = P.order[first + blockIdx.x / P.fac_slabs], n = blockIdx.x % P.fac_slabs;
+  factor_block_mfma(L, P, p, n, Jv, fac, status, S);
+}
+
+// Persistent form over the big blocks of many problems (see
+// launch_patch_factor_batch): tiles taken from a counter, the last
+// workgroup to finish resets the counter pair.
+__global__ __launch_bounds__(64) void k_patch_factor_mfma_batch(const FactorJob* __restrict__ jobs,
+                                                                const FactorTile* __restrict__ tiles,
+                                                                int n_tiles, int* __restrict__ ctr) {
+  __shared__ MfmaFactorLds S;
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (t >= n_tiles) break;
+    const FactorTile tl = tiles[t];
+    const FactorJob& J = jobs[tl.job];
+    const int ns = J.P.fac_slabs;
+    for (int b = tl.first; b < tl.first + tl.count; ++b) {
+      const int p = J.P.order[b / ns], n = b % ns;
+      factor_block_mfma(J.L, J.P, p, n, J.Jv, J.fac, J.status, S);
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+    atomicExch(&ctr[0], 0);
+    atomicExch(&ctr[1], 0);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_patch_factor_mfma_batch(const FactorJob* jobs, const FactorTile* tiles, int n_tiles, int grid,
+                                          int* ctr, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_patch_factor_mfma_batch, dim3((unsigned)grid), dim3(64), 0, s, jobs, tiles, n_tiles, ctr);
+  return hipGetLastError();
+}
+
+int patch_factor_mfma_batch_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_patch_factor_mfma_batch, 64, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
 
 hipError_t launch_patch_factor_mfma(const LevelView& L, const PatchView& P, const double* Jv, float* fac,
                                     int* status, int first, int count, hipStream_t s) {

@@ -48,6 +48,20 @@ __device__ inline float4 load_stream(const float* p) {
   return make_float4(t.x, t.y, t.z, t.w);
 }
 
+// Pointers into device (global) memory.  A pointer read from a descriptor in
+// memory is generic to the compiler, which then emits flat accesses with a
+// 64-bit address per lane; typing it global gives global accesses, as for
+// kernel arguments.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL_AS T* gptr(T* p) {
+  return (GLOBAL_AS T*)p;
+}
+__device__ inline float4 load_stream(const GLOBAL_AS float* p) {
+  const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL_AS f32x4*>(p));
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+
 // Inverse of one (patch, slab) block by Gauss-Jordan elimination with
 // partial pivoting, held in registers: thread t owns rows t + TPB r (r < RPL),
 // each a full row of MAXM entries.  After each step the rows rotate left by
@@ -60,23 +74,37 @@ __device__ inline float4 load_stream(const float* p) {
 // writing the inverse out in the sweep's panel layout.  Per element the
 // arithmetic and the pivot choice (largest magnitude, ties to the smaller
 // row) are those of the textbook in-place Gauss-Jordan inverse.
+template <int NQ, typename T, int TPB, int NBMAX = kMaxNb>
+struct FactorLds {
+  static constexpr int MAXM = NBMAX * NQ;
+  static constexpr int NW = TPB / 64;
+  // row buffers padded to whole 16-byte vectors
+  static constexpr int RV = 16 / sizeof(T), MP = (MAXM + RV - 1) / RV * RV;
+  __align__(16) T prow[MP];
+  __align__(16) T swp[2][MP];
+  T rv[NW];
+  int ri[NW];
+  int perm[MAXM];
+  int ofs1[MAXM], ofs2[MAXM];
+};
+
+// The block of patch p (its id, not its position) at slab n.
 template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb>
-__global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, int first,
-                                                      const double* __restrict__ Jv,
-                                                      T* __restrict__ fac, int* __restrict__ status) {
+__device__ __forceinline__ void factor_block(const LevelView& L, const PatchView& P, const int p, const int n,
+                                             const double* __restrict__ Jv, T* __restrict__ fac,
+                                             int* __restrict__ status, FactorLds<NQ, T, TPB, NBMAX>& S) {
   constexpr int MAXM = NBMAX * NQ;
   constexpr int NW = TPB / 64;
   constexpr int VW = Vec<T>::W;
-  // row buffers padded to whole 16-byte vectors
   constexpr int RV = 16 / sizeof(T), MP = (MAXM + RV - 1) / RV * RV;
   using V16 = typename Vec<T>::type;
-  __shared__ __align__(16) T prow[MP];
-  __shared__ __align__(16) T swp[2][MP];
-  __shared__ T rv[NW];
-  __shared__ int ri[NW];
-  __shared__ int perm[MAXM];
-  __shared__ int ofs1[MAXM], ofs2[MAXM];
-  const int p = P.order[first + blockIdx.x / P.fac_slabs], n = blockIdx.x % P.fac_slabs;
+  T* prow = S.prow;
+  T (*swp)[MP] = S.swp;
+  T* rv = S.rv;
+  int* ri = S.ri;
+  int* perm = S.perm;
+  int* ofs1 = S.ofs1;
+  int* ofs2 = S.ofs2;
   const int tid = threadIdx.x;
   const int s0 = P.patch_ptr[p];
   const int nb = P.patch_ptr[p + 1] - s0;
@@ -254,6 +282,15 @@ __global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, 
   }
 }
 
+template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb>
+__global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, int first,
+                                                      const double* __restrict__ Jv,
+                                                      T* __restrict__ fac, int* __restrict__ status) {
+  __shared__ FactorLds<NQ, T, TPB, NBMAX> S;
+  const int p = P.order[first + blockIdx.x / P.fac_slabs], n = blockIdx.x % P.fac_slabs;
+  factor_block<NQ, T, TPB, RPL, NBMAX>(L, P, p, n, Jv, fac, status, S);
+}
+
 __global__ __launch_bounds__(256) void k_patch_mass(PatchView P, const double* __restrict__ Mv,
                                                     double* __restrict__ Mp) {
   const int p = blockIdx.x;
@@ -348,17 +385,19 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   constexpr int YL = (YCH * MAXM + 255) / 256; // 16-byte output stores per lane and line
   const float e0[2] = {(float)e00, (float)e01}, e1[2] = {(float)e10, (float)e11};
   const int lane = threadIdx.x;
-  const int s0 = P.patch_ptr[p];
-  const int nb = FULL ? kMaxNb : P.patch_ptr[p + 1] - s0;
-  const int nbu = FULL ? kMaxNbu : P.patch_nbu[p];
+  const GLOBAL_AS int* patch_ptr = gptr(P.patch_ptr);
+  const GLOBAL_AS double* gr = gptr(r);
+  const int s0 = patch_ptr[p];
+  const int nb = FULL ? kMaxNb : patch_ptr[p + 1] - s0;
+  const int nbu = FULL ? kMaxNbu : gptr(P.patch_nbu)[p];
   const int nn = nbu / 2;
   const int m = nb * NQ, N = L.N;
   const BlockLayout lay(m, VW);
   const int PH = FULL ? MAXP : lay.P;
   const int r1 = FULL ? R1F : lay.r1, r2 = FULL ? R2F : lay.r2;
   const int nk2 = FULL ? (R2F > 0 ? K2 : 0) : lay.k2(0);
-  for (int i = lane; i < nb; i += 64) dofs[i] = P.patch_dofs[s0 + i];
-  const double* mp = Mp + P.mp_off[p];
+  for (int i = lane; i < nb; i += 64) dofs[i] = gptr(P.patch_dofs)[s0 + i];
+  const GLOBAL_AS double* mp = gptr(Mp) + gptr(P.mp_off)[p];
   for (int e = lane; e < nn * nn; e += 64) {
     const int i = e / nn, j = e % nn;
     MsT[j * nn + i] = (float)mp[2 * i * nbu + 2 * j];
@@ -366,9 +405,9 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   for (int i = lane; i < kMaxNbu; i += 64) mj[i] = 0.0f;
   for (int i = lane; i < MAXP * VW + 4; i += 64) g[i] = 0.0f;
   __syncthreads();
-  const float* Ab = fac + P.fac_off[p];
+  const GLOBAL_AS float* Ab = gptr(fac) + gptr(P.fac_off)[p];
   const int64_t SS = P.slab_stride;
-  float* yout = Y + 2 * P.y_off[p];   // FP32 outputs at the byte offset of the FP64 layout
+  GLOBAL_AS float* yout = gptr(Y) + 2 * gptr(P.y_off)[p];   // FP32 outputs at the byte offset of the FP64 layout
   const unsigned row1 = lane < r1 ? lane : 0;
   const unsigned base1 = row1 * VW, step1 = r1 * VW;
   const unsigned lane2 = lane < 4 * r2 ? lane : 0;
@@ -384,7 +423,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   float4 a2[kTwo ? K2 : 1];
   double rv[RL];
   auto issue = [&](int n) {
-    const float* blk = Ab + (int64_t)n * SS;
+    const GLOBAL_AS float* blk = Ab + (int64_t)n * SS;
 #pragma unroll
     for (int q = 0; q < MAXP; ++q) {
       const unsigned qq = FULL ? q : (q < lastq ? q : lastq);
@@ -407,7 +446,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
       id = id < nel ? id : nel - 1;
       int e = n0 * NQ + (id & (kLine - 1));
       e = e < nq ? e : nq - 1;
-      rv[i] = r[(int64_t)dofs[id >> 4] * nq + e];
+      rv[i] = gr[(int64_t)dofs[id >> 4] * nq + e];
     }
   };
   auto stage_store = [&]() {
@@ -422,12 +461,12 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   // and a chunk of YCH slabs is nb whole lines)
   auto flush = [&](int n0, int ns) {
     const int elems = ns * m;
-    float* yo = yout + (int64_t)n0 * m;
+    GLOBAL_AS float* yo = yout + (int64_t)n0 * m;
 #pragma unroll
     for (int i = 0; i < YL; ++i) {
       const int e = 4 * (i * 64 + lane);
       if (e + 3 < elems) {
-        *reinterpret_cast<float4*>(yo + e) = make_float4(ych[e], ych[e + 1], ych[e + 2], ych[e + 3]);
+        *reinterpret_cast<GLOBAL_AS f32x4*>(yo + e) = f32x4{ych[e], ych[e + 1], ych[e + 2], ych[e + 3]};
       } else {
         for (int j = e; j < elems; ++j) yo[j] = ych[j];
       }
@@ -526,6 +565,82 @@ __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P
   const int p = P.order[blockIdx.x];
   if ((int)blockIdx.x < P.n_full) sweep_f32_patch<NQ, true>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
   else sweep_f32_patch<NQ, false>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
+}
+
+// Persistent FP32 sweep over the patches of many (problem, level) jobs with
+// NQ temporal nodes: workgroups take tiles of patches from a counter in list
+// order and sweep each patch as k_patch_sweep_f32 does; the last workgroup to
+// finish resets the counter pair.  The list holds the tiles of interior
+// (full-size) patches first, then the others, each part sorted by decreasing
+// work; the two parts run in two loops one after the other, so the
+// compile-time interior form and the general form never share live
+// registers.  One launch per node count, for the same reason.
+template <int NQ>
+__global__ __launch_bounds__(64) void k_patch_sweep_f32_batch(const SweepJob* __restrict__ jobs,
+                                                             const SweepTile* __restrict__ tiles,
+                                                             int n_full_tiles, int n_tiles,
+                                                             int* __restrict__ ctr) {
+  __shared__ SweepF32Lds<NQ> S;
+  __shared__ int next;
+  auto grab = [&]() {
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    return t;
+  };
+  int t = grab();
+  for (; t < n_full_tiles; t = grab()) {
+    const SweepTile tl = tiles[t];
+    const SweepJob& J = jobs[tl.job];
+    for (int pos = tl.first; pos < tl.first + tl.count; ++pos) {
+      sweep_f32_patch<NQ, true>(J.L, J.P, gptr(J.P.order)[pos], J.fac, J.Mp, J.e00, J.e01, J.e10, J.e11, J.r,
+                                J.Y, S);
+      __syncthreads();
+    }
+  }
+  for (; t < n_tiles; t = grab()) {
+    const SweepTile tl = tiles[t];
+    const SweepJob& J = jobs[tl.job];
+    for (int pos = tl.first; pos < tl.first + tl.count; ++pos) {
+      sweep_f32_patch<NQ, false>(J.L, J.P, gptr(J.P.order)[pos], J.fac, J.Mp, J.e00, J.e01, J.e10, J.e11, J.r,
+                                 J.Y, S);
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+    atomicExch(&ctr[0], 0);
+    atomicExch(&ctr[1], 0);
+  }
+}
+
+// Persistent FP32 factorization of the blocks of at most 64 rows of many
+// jobs (one class per launch: NQ = 1 or 2), as k_patch_factor.
+template <int NQ>
+__global__ __launch_bounds__(64) void k_patch_factor_f32_batch(const FactorJob* __restrict__ jobs,
+                                                              const FactorTile* __restrict__ tiles,
+                                                              int n_tiles, int* __restrict__ ctr) {
+  __shared__ FactorLds<NQ, float, 64> S;
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (t >= n_tiles) break;
+    const FactorTile tl = tiles[t];
+    const FactorJob& J = jobs[tl.job];
+    const int ns = J.P.fac_slabs;
+    for (int b = tl.first; b < tl.first + tl.count; ++b) {
+      const int p = J.P.order[b / ns], n = b % ns;
+      factor_block<NQ, float, 64, 1>(J.L, J.P, p, n, J.Jv, J.fac, J.status, S);
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+    atomicExch(&ctr[0], 0);
+    atomicExch(&ctr[1], 0);
+  }
 }
 
 // One workgroup per patch, WAVES wavefronts, each owning at most
@@ -1025,6 +1140,55 @@ hipError_t launch_patch_factor(const LevelView& L, const PatchView& P, const dou
     }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_patch_sweep_batch(int nq, const SweepJob* jobs, const SweepTile* tiles, int n_full_tiles,
+                                    int n_tiles, int grid, int* ctr, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (nq == 1)
+    hipLaunchKernelGGL(k_patch_sweep_f32_batch<1>, dim3((unsigned)grid), dim3(64), 0, s, jobs, tiles, n_full_tiles,
+                       n_tiles, ctr);
+  else if (nq == 2)
+    hipLaunchKernelGGL(k_patch_sweep_f32_batch<2>, dim3((unsigned)grid), dim3(64), 0, s, jobs, tiles, n_full_tiles,
+                       n_tiles, ctr);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_factor_batch(int cls, const FactorJob* jobs, const FactorTile* tiles, int n_tiles,
+                                     int grid, int* ctr, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (cls) {
+    case kFacSmall1:
+      hipLaunchKernelGGL(k_patch_factor_f32_batch<1>, dim3((unsigned)grid), dim3(64), 0, s, jobs, tiles, n_tiles, ctr);
+      break;
+    case kFacSmall2:
+      hipLaunchKernelGGL(k_patch_factor_f32_batch<2>, dim3((unsigned)grid), dim3(64), 0, s, jobs, tiles, n_tiles, ctr);
+      break;
+    case kFacBig2:
+      return launch_patch_factor_mfma_batch(jobs, tiles, n_tiles, grid, ctr, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int patch_sweep_batch_occupancy(int nq) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (nq == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_patch_sweep_f32_batch<1>, 64, 0);
+  if (nq == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_patch_sweep_f32_batch<2>, 64, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int patch_factor_batch_occupancy(int cls) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (cls == kFacSmall1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_patch_factor_f32_batch<1>, 64, 0);
+  if (cls == kFacSmall2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_patch_factor_f32_batch<2>, 64, 0);
+  if (cls == kFacBig2) return patch_factor_mfma_batch_occupancy();
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const double* Mv, double* Mp,

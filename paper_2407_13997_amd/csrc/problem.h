@@ -120,6 +120,7 @@ struct Level {
   size_t chunk_bytes = 0;
   int chunk_choice = 0;   // 0: not chosen yet
   std::vector<int64_t> fac_off, y_off, mp_off;
+  std::vector<int> order;   // host copy of the patch order (pview.order)
   // device arrays
   int *row_ptr = nullptr, *col = nullptr, *cells = nullptr, *cell_p2 = nullptr,
       *cell_dofs = nullptr, *cell_nz = nullptr, *node_free = nullptr, *node_cell_ptr = nullptr,

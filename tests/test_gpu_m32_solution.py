@@ -50,10 +50,12 @@ def test_m32_solution(prec, tol):
 
 def test_m32_four_levels_stalls():
     """The workload's own 4-level hierarchy (coarsest 4x4), FP64 smoother:
-    the first Newton step's FGMRES(30) does not reach its 1e-10 bar in 90
-    iterations (it stays above 1e-4), Newton stops with STWR_ERR_NOT_CONVERGED
-    after its 2-step limit and the statistics are filled.  The 3-level
-    hierarchy above converges on the same problem."""
+    the first Newton step (at the zero start, where the convection is that of
+    the boundary data alone) converges in FGMRES(30), but the second step's
+    FGMRES stalls: after 90 iterations its residual is still above 1e-2 of the
+    right-hand side.  Newton stops with STWR_ERR_NOT_CONVERGED after its
+    2-step limit and the statistics are filled.  The 3-level hierarchy above
+    converges on the same problem."""
     torch_cuda()
     from paper_2407_13997_amd import binding
     p = w.named_problem(w.MEDIUM)
@@ -66,6 +68,6 @@ def test_m32_four_levels_stalls():
     log(f"[m32 4 levels] rc={rc} newton={d['newton']} linear={d['linear']} "
         f"linear_rel={d['linear_rel']} fnorm={d['fnorm']} lambda={d['lambda'][:3]}")
     assert rc == -7
-    assert d["newton"] == 2 and d["linear"] == [90, 90]
-    assert min(d["linear_rel"]) > 1e-4
+    assert d["newton"] == 2 and d["linear"][0] < 90 and d["linear"][1] == 90
+    assert d["linear_rel"][0] <= 1e-10 and d["linear_rel"][1] > 1e-2
     assert np.all(np.isfinite(to_host(U)))
