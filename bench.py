@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--vcycles", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--no-uneven-batch", action="store_true")
+    ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--largest-solve", type=int, default=0,
                     help="also run the 128x128 Newton solve with this many levels (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
@@ -310,6 +312,9 @@ def main():
         log(f"[bench] single solve: {out['single_solve']}")
         out["serving"] = serving_benchmark()
         log(f"[bench] serving: {out['serving']}")
+    if not args.no_uneven_batch:
+        out["uneven_batch"] = uneven_batch(args.batch_problems)
+        log(f"[bench] uneven batch: {out['uneven_batch']}")
     if args.largest_solve > 0:
         out["largest_solve"] = largest_solve(args.largest_solve)
         log(f"[bench] largest solve: {out['largest_solve']}")
@@ -611,6 +616,105 @@ def largest_solve(levels: int, newton_maxit: int = 8, gmres_maxit: int = 120) ->
     P.close()
     ctx.close()
     return out
+
+
+def uneven_batch(n_problems: int = 64, newton_maxit: int = 8, gmres_maxit: int = 30) -> dict:
+    """The uneven batch: n_problems independent solves drawn as the batch
+    distribution states (meshes {8,16,32,64}^2, N in [8,128], q in {0,1},
+    Re log-uniform in [1,1000], seeds 2000+j), Newton to 1e-10 with
+    Eisenstat-Walker linear tolerances, at most newton_maxit Newton steps of at
+    most gmres_maxit FGMRES(30) iterations each (the unstabilised Galerkin
+    convection stalls the V-cycle at the higher Reynolds numbers, and the caps
+    bound what those solves cost every path).  Three paths on the same
+    problems, all submitted at time zero: the plain FP64-smoother path one solve
+    at a time, the FP32-smoother path one at a time, and the FP32 batch
+    (stwr_batch_*: shared persistent factor and sweep launches, captured
+    V-cycles).  Reports converged solves per second, p50/p99 completion
+    latency over the converged solves, and the largest relative difference
+    between each FP32 path's solutions and the plain path's."""
+    import numpy as np
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    probs = w.batch_problems(n_problems, seed0=2000)
+    ctx = binding.Context(0)
+
+    def opts(prec, chunks):
+        o = binding.default_opts()
+        o.smoother_prec = prec
+        o.newton_ew = 1
+        o.newton_maxit = newton_maxit
+        o.gmres_maxit = gmres_maxit
+        o.time_chunks = chunks
+        return o
+
+    def summary(lat_ok, span, n_fail):
+        lat = np.array(lat_ok) if lat_ok else np.array([np.nan])
+        return {"solves": len(lat_ok), "failed": n_fail, "makespan_s": span,
+                "solves_per_s": len(lat_ok) / span, "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99))}
+
+    def one_at_a_time(prec):
+        sols, lat, fail = {}, [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j, p in enumerate(probs):
+            P = binding.Problem(ctx, p, opts(prec, 0))
+            U = P.vec()
+            try:
+                st = P.newton_solve(U, allow_unconverged=True)
+                ok = st["fnorm"][-1] <= 1e-10 * st["fnorm"][0]
+            except binding.StwrError:
+                ok = False
+            torch.cuda.synchronize()
+            if ok:
+                lat.append(time.perf_counter() - t0)
+                sols[j] = U.cpu().numpy()
+            else:
+                fail += 1
+            P.close()
+            if (j + 1) % 16 == 0:
+                log(f"[bench] uneven batch: {j + 1} solves done ({time.perf_counter() - t0:.1f}s)")
+        return summary(lat, time.perf_counter() - t0, fail), sols
+
+    log(f"[bench] uneven batch: {n_problems} problems, plain FP64 one at a time")
+    plain, s64 = one_at_a_time(binding.FP64)
+    log(f"[bench] uneven batch: plain {plain}; FP32 one at a time")
+    solo32, s32 = one_at_a_time(binding.FP32)
+    log(f"[bench] uneven batch: FP32 solo {solo32}; FP32 batch")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = binding.Batch(ctx, use_graph=True)
+    t_create = time.perf_counter() - t0   # the batch's clock starts here
+    ids = {B.add(p, opts(binding.FP32, 1)): j for j, p in enumerate(probs)}
+    t_add = time.perf_counter() - t0
+    res = B.run()
+    span = time.perf_counter() - t0
+    info = B.info()
+    B.close()
+    lat, sb, fail = [], {}, 0
+    for r in res:
+        if r["status"] == 0:
+            lat.append(r["end_time"] + t_create)
+            sb[ids[r["id"]]] = r["solution"]
+        else:
+            fail += 1
+    batched = summary(sorted(lat), span, fail)
+    batched.update({"add_s": t_add, "info": info})
+
+    def worst(sols):
+        e = [float(np.linalg.norm(sols[j] - s64[j]) / np.linalg.norm(s64[j])) for j in sols if j in s64]
+        return max(e) if e else None
+
+    ctx.close()
+    return {"problems": n_problems,
+            "workload": "uneven batch: meshes {8,16,32,64}^2, N in [8,128], q in {0,1}, Re 10^U[0,3], seeds 2000+j",
+            "caps": {"newton_maxit": newton_maxit, "gmres_maxit": gmres_maxit, "newton_ew": 1},
+            "plain_fp64_one_at_a_time": plain, "fp32_one_at_a_time": solo32, "fp32_batched": batched,
+            "speedup_solves_per_s_vs_plain": batched["solves_per_s"] / plain["solves_per_s"],
+            "speedup_solves_per_s_vs_fp32_solo": batched["solves_per_s"] / solo32["solves_per_s"],
+            "max_rel_diff_fp32_solo_vs_plain": worst(s32), "max_rel_diff_batched_vs_plain": worst(sb),
+            "converged_sets_equal": sorted(s64) == sorted(sb)}
 
 
 def time_chunk_context(steps: int = 10) -> list:

@@ -576,11 +576,12 @@ void vcycle_batch(stwr_batch* B, const std::vector<Item*>& K) {
 void drop_graph(stwr_batch* B) {
   if (B->vc_exec) (void)hipGraphExecDestroy(B->vc_exec);
   B->vc_exec = nullptr;
-  B->vc_key.clear();
 }
 
-// The V-cycles of K: plans (and, with graphs, the captured launch sequence)
-// are rebuilt whenever K or a member's Newton step changes.
+// The V-cycles of K.  The plans are rebuilt whenever K or a member's Newton
+// step changes; with graphs, the launch sequence is captured once the same
+// K has come back on the next step (a set that changes every step runs its
+// launches directly rather than paying a capture it would use once).
 void vcycles(stwr_batch* B, const std::vector<Item*>& K) {
   std::vector<int64_t> key;
   for (Item* it : K) {
@@ -601,33 +602,32 @@ void vcycles(stwr_batch* B, const std::vector<Item*>& K) {
       build_sweep_plan(B, *B->vc_plans.back(), who);
     }
     B->vc_key = key;
-    if (B->use_graph && !B->ctx->timing) {
-      if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
-      HIPCHK(hipStreamSynchronize(bs(B)));
-      hipStream_t saved = B->ctx->stream;
-      HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-      B->ctx->stream = B->cap;
-      hipGraph_t g = nullptr;
-      try {
-        vcycle_batch(B, K);
-      } catch (...) {
-        B->ctx->stream = saved;
-        if (hipStreamEndCapture(B->cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
-        B->vc_key.clear();
-        throw;
-      }
+  } else if (!B->vc_exec && B->use_graph && !B->ctx->timing) {
+    if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamSynchronize(bs(B)));
+    hipStream_t saved = B->ctx->stream;
+    HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    B->ctx->stream = B->cap;
+    hipGraph_t g = nullptr;
+    try {
+      vcycle_batch(B, K);
+    } catch (...) {
       B->ctx->stream = saved;
-      --B->n_vcycles;   // captured, not run
-      HIPCHK(hipStreamEndCapture(B->cap, &g));
-      const hipError_t e = hipGraphInstantiate(&B->vc_exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        B->vc_exec = nullptr;
-        B->vc_key.clear();
-        HIPCHK(e);
-      }
-      ++B->n_captures;
+      if (hipStreamEndCapture(B->cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      B->vc_key.clear();
+      throw;
     }
+    B->ctx->stream = saved;
+    --B->n_vcycles;   // captured, not run
+    HIPCHK(hipStreamEndCapture(B->cap, &g));
+    const hipError_t e = hipGraphInstantiate(&B->vc_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      B->vc_exec = nullptr;
+      B->vc_key.clear();
+      HIPCHK(e);
+    }
+    ++B->n_captures;
   }
   if (B->vc_exec) {
     HIPCHK(hipGraphLaunch(B->vc_exec, bs(B)));
@@ -896,6 +896,7 @@ void collect(stwr_batch* B) {
     B->done.push_back(r);
     itp = B->items.erase(itp);
     drop_graph(B);
+    B->vc_key.clear();
   }
 }
 
@@ -1029,6 +1030,7 @@ int32_t stwr_batch_destroy(stwr_batch* b) {
   if (!b) return STWR_OK;
   (void)hipStreamSynchronize(b->ctx->stream);
   drop_graph(b);
+  b->vc_key.clear();
   for (auto& it : b->items) {
     {
       std::lock_guard<std::mutex> g(b->ctx->mu);
