@@ -237,6 +237,27 @@ int32_t stwr_problem_n_st(const stwr_problem_desc* desc, int64_t* n_st);
  * 0..39 (40 entries).  out must hold 52 int64. */
 int32_t stwr_mesh_info(int32_t mesh_n, int64_t* out);
 
+/* Host-built Vanka+star patches of one Navier-Stokes level with M = mesh_n
+ * squares a side and pressure degree `degree` (1: Taylor-Hood P2-P1, 2:
+ * P3-P2; Sec. 3 patches, Sec. 3.1 counts), in the free numbering above (for
+ * P3-P2 on its own lattices: velocity node (gi, gj) of the (3M+1)^2 lattice,
+ * interior, is k = (gi-1) + (3M-1)(gj-1) with DoFs 2k and 2k+1; pressure node
+ * g of the (2M+1)^2 lattice is DoF 2 (3M-1)^2 + g).  counts[0..6] = free
+ * DoFs, patches (one per vertex), sum of patch sizes, CSR nonzeros, largest
+ * patch, structural nonzeros of the patch of the vertex nearest the centre
+ * (velocity-velocity and velocity-pressure pairs that share a cell), cells.  patch_ptr (patches + 1) and patch_dofs (sum of sizes; each patch's
+ * DoFs ascending) are filled when not NULL.  Host only. */
+int32_t stwr_level_patches(int32_t mesh_n, int32_t degree, int64_t* counts, int32_t* patch_ptr,
+                           int32_t* patch_dofs);
+/* Host-built prolongation from the mesh_n/2 level to the mesh_n level of the
+ * same pressure degree (nested interpolation of each velocity component and
+ * of the pressure, Sec. 3), by fine free DoF rows: counts[0..2] = fine free
+ * DoFs, coarse free DoFs, nonzeros; p_ptr (fine + 1), p_col, p_val (nonzeros)
+ * and inject (coarse free DoF -> fine free DoF at the same node, coarse) are
+ * filled when not NULL.  mesh_n even.  Host only. */
+int32_t stwr_level_transfer(int32_t mesh_n, int32_t degree, int64_t* counts, int32_t* p_ptr, int32_t* p_col,
+                            double* p_val, int32_t* inject);
+
 /* ---- problem ------------------------------------------------------------ */
 int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc,
                             const stwr_solver_opts* opts, stwr_problem** out);

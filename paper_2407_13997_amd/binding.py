@@ -38,7 +38,7 @@ EXPORTED = [
     "stwr_ctx_set_alloc_mode", "stwr_server_create", "stwr_server_submit", "stwr_server_poll",
     "stwr_server_wait", "stwr_server_now", "stwr_server_destroy",
     "stwr_batch_create", "stwr_batch_add", "stwr_batch_step", "stwr_batch_poll", "stwr_batch_info",
-    "stwr_batch_destroy",
+    "stwr_batch_destroy", "stwr_level_patches", "stwr_level_transfer",
 ]
 
 
@@ -168,6 +168,8 @@ def load(path: str | None = None):
         "stwr_batch_poll": [P, ctypes.POINTER(Result), i32, ctypes.POINTER(i32)],
         "stwr_batch_info": [P, ctypes.POINTER(i64)],
         "stwr_batch_destroy": [P],
+        "stwr_level_patches": [i32, i32, ctypes.POINTER(i64), V, V],
+        "stwr_level_transfer": [i32, i32, ctypes.POINTER(i64), V, V, V, V],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -231,6 +233,46 @@ def mesh_info(mesh_n: int) -> np.ndarray:
     if rc != STWR_OK:
         raise StwrError(rc, lib.stwr_last_error(None).decode())
     return out
+
+
+def level_patches(mesh_n: int, degree: int = 1):
+    """(counts, patch_ptr, patch_dofs) of the host-built Vanka+star patches
+    (stwr_level_patches)."""
+    lib = load()
+    counts = np.zeros(7, dtype=np.int64)
+    cp = counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = lib.stwr_level_patches(mesh_n, degree, cp, None, None)
+    if rc != STWR_OK:
+        raise StwrError(rc, lib.stwr_last_error(None).decode())
+    ptr = np.zeros(counts[1] + 1, dtype=np.int32)
+    dofs = np.zeros(counts[2], dtype=np.int32)
+    rc = lib.stwr_level_patches(mesh_n, degree, cp, ptr.ctypes.data_as(ctypes.c_void_p),
+                                dofs.ctypes.data_as(ctypes.c_void_p))
+    if rc != STWR_OK:
+        raise StwrError(rc, lib.stwr_last_error(None).decode())
+    return counts, ptr, dofs
+
+
+def level_transfer(mesh_n: int, degree: int = 1):
+    """(P as scipy CSR of fine x coarse free DoFs, inject) from stwr_level_transfer."""
+    import scipy.sparse as sp
+    lib = load()
+    counts = np.zeros(3, dtype=np.int64)
+    cp = counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = lib.stwr_level_transfer(mesh_n, degree, cp, None, None, None, None)
+    if rc != STWR_OK:
+        raise StwrError(rc, lib.stwr_last_error(None).decode())
+    nf, nc, nnz = (int(v) for v in counts)
+    ptr = np.zeros(nf + 1, dtype=np.int32)
+    col = np.zeros(nnz, dtype=np.int32)
+    val = np.zeros(nnz)
+    inj = np.zeros(nc, dtype=np.int32)
+    rc = lib.stwr_level_transfer(mesh_n, degree, cp, ptr.ctypes.data_as(ctypes.c_void_p),
+                                 col.ctypes.data_as(ctypes.c_void_p), val.ctypes.data_as(ctypes.c_void_p),
+                                 inj.ctypes.data_as(ctypes.c_void_p))
+    if rc != STWR_OK:
+        raise StwrError(rc, lib.stwr_last_error(None).decode())
+    return sp.csr_matrix((val, col, ptr), shape=(nf, nc)), inj
 
 
 def _ptr(t):

@@ -73,8 +73,16 @@ bool is_heat(const stwr_problem_desc* d) { return d->equation == STWR_EQ_HEAT; }
 // the boundary velocity eliminated, 2 (2M-1)^2 + (M+1)^2; the heat equation's
 // P_k lattice, (kM+1)^2 (every node free).  The level builders give the same
 // counts.
+// Taylor-Hood pressure degree k of a Navier-Stokes problem (degree 0 or 1:
+// P2-P1; 2: P3-P2).
+int th_degree(const stwr_problem_desc* d) { return (!is_heat(d) && d->degree == kThK) ? kThK : 1; }
+
 int64_t free_dofs(const stwr_problem_desc* d, int M) {
   if (is_heat(d)) return (int64_t)(d->degree * M + 1) * (d->degree * M + 1);
+  if (th_degree(d) == kThK) {
+    const int64_t nv = (kThK + 1) * M - 1, np = kThK * M + 1;
+    return 2 * nv * nv + np * np;
+  }
   return 2LL * (2 * M - 1) * (2 * M - 1) + (int64_t)(M + 1) * (M + 1);
 }
 
@@ -84,6 +92,8 @@ void check_desc(const stwr_problem_desc* d) {
     throw StwrError(STWR_ERR_ARG, "bad equation");
   if (is_heat(d) && (d->degree < 1 || d->degree > kMaxPk))
     throw StwrError(STWR_ERR_ARG, "heat equation degree must be 1, 2 or 3");
+  if (!is_heat(d) && (d->degree < 0 || d->degree > kThK))
+    throw StwrError(STWR_ERR_ARG, "Navier-Stokes pressure degree must be 1 (P2-P1) or 2 (P3-P2)");
   if (d->q < 0 || d->q > (is_heat(d) ? kMaxNQ - 1 : 1))
     throw StwrError(STWR_ERR_ARG, is_heat(d) ? "q must be 0..3 for the heat equation" : "q must be 0 or 1");
   if (d->n_levels < 1 || d->n_levels > STWR_MAX_LEVELS) throw StwrError(STWR_ERR_ARG, "bad n_levels");
@@ -202,6 +212,7 @@ void build_levels(const stwr_problem_desc* d, std::vector<Level>& lv) {
   };
   run_all(d->n_levels, [&](int l) {
     if (is_heat(d)) build_level_heat(d->mesh_n >> l, d->degree, lv[l].H);
+    else if (th_degree(d) == kThK) build_level_th(d->mesh_n >> l, kThK, lv[l].H);
     else build_level(d->mesh_n >> l, lv[l].H);
     lv[l].N = d->n_slabs;
     lv[l].NQ = d->q + 1;
@@ -210,6 +221,7 @@ void build_levels(const stwr_problem_desc* d, std::vector<Level>& lv) {
   });
   run_all(d->n_levels - 1, [&](int l) {
     if (is_heat(d)) build_transfer_heat(lv[l].H, lv[l + 1].H, lv[l].Tr);
+    else if (th_degree(d) == kThK) build_transfer_th(lv[l].H, lv[l + 1].H, lv[l].Tr);
     else build_transfer(lv[l].H, lv[l + 1].H, lv[l].Tr);
   });
 }
@@ -1030,6 +1042,63 @@ int32_t stwr_problem_n_st(const stwr_problem_desc* desc, int64_t* n_st) {
   });
 }
 
+int32_t stwr_level_patches(int32_t mesh_n, int32_t degree, int64_t* counts, int32_t* patch_ptr,
+                           int32_t* patch_dofs) {
+  return guarded(nullptr, [&]() -> int32_t {
+    if (!counts || mesh_n < 1 || degree < 1 || degree > kThK) throw StwrError(STWR_ERR_ARG, "bad arguments");
+    HostLevel H;
+    if (degree == kThK) build_level_th(mesh_n, kThK, H);
+    else build_level(mesh_n, H);
+    int mx = 0;
+    for (int v = 0; v < H.nv; ++v) mx = std::max(mx, H.patch_ptr[v + 1] - H.patch_ptr[v]);
+    // structural nonzeros of the patch of the vertex nearest the centre (the
+    // pressure-pressure pairs, which the operator never fills, left out)
+    const int c = H.n1 / 2, v = c + H.n1 * c;
+    const int nb = H.patch_ptr[v + 1] - H.patch_ptr[v], nbu = H.patch_nbu[v];
+    int64_t pnz = 0;
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j)
+        pnz += (i < nbu || j < nbu) && H.patch_nz[H.patch_nz_off[v] + (int64_t)i * nb + j] >= 0;
+    counts[0] = H.nf;
+    counts[1] = H.nv;
+    counts[2] = (int64_t)H.patch_dofs.size();
+    counts[3] = H.row_ptr[H.nf];
+    counts[4] = mx;
+    counts[5] = pnz;
+    counts[6] = H.nc;
+    if (patch_ptr) std::copy(H.patch_ptr.begin(), H.patch_ptr.end(), patch_ptr);
+    if (patch_dofs) std::copy(H.patch_dofs.begin(), H.patch_dofs.end(), patch_dofs);
+    return STWR_OK;
+  });
+}
+
+int32_t stwr_level_transfer(int32_t mesh_n, int32_t degree, int64_t* counts, int32_t* p_ptr, int32_t* p_col,
+                            double* p_val, int32_t* inject) {
+  return guarded(nullptr, [&]() -> int32_t {
+    if (!counts || mesh_n < 2 || mesh_n % 2 || degree < 1 || degree > kThK)
+      throw StwrError(STWR_ERR_ARG, "bad arguments");
+    HostLevel F, C;
+    HostTransfer T;
+    if (degree == kThK) {
+      build_level_th(mesh_n, kThK, F);
+      build_level_th(mesh_n / 2, kThK, C);
+      build_transfer_th(F, C, T);
+    } else {
+      build_level(mesh_n, F);
+      build_level(mesh_n / 2, C);
+      build_transfer(F, C, T);
+    }
+    counts[0] = F.nf;
+    counts[1] = C.nf;
+    counts[2] = (int64_t)T.p_col.size();
+    if (p_ptr) std::copy(T.p_ptr.begin(), T.p_ptr.end(), p_ptr);
+    if (p_col) std::copy(T.p_col.begin(), T.p_col.end(), p_col);
+    if (p_val) std::copy(T.p_val.begin(), T.p_val.end(), p_val);
+    if (inject) std::copy(T.inject.begin(), T.inject.end(), inject);
+    return STWR_OK;
+  });
+}
+
 int32_t stwr_mesh_info(int32_t mesh_n, int64_t* out) {
   return guarded(nullptr, [&]() -> int32_t {
     if (!out || mesh_n < 1) throw StwrError(STWR_ERR_ARG, "bad arguments");
@@ -1097,6 +1166,7 @@ int32_t stwr_problem_create(stwr_ctx* ctx, const stwr_problem_desc* desc, const 
     try {
       build_ref_tables(desc->q, desc->temporal_nodes, P->tab);
       if (is_heat(desc)) build_pk_tables(desc->degree, P->tab);
+      if (th_degree(desc) == kThK) build_th_tables(kThK, P->tab);
       P->d_tab = P->alloc<RefTables>(1);
       HIPCHK(hipMemcpyAsync(P->d_tab, &P->tab, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -572,4 +572,159 @@ void build_transfer_heat(const HostLevel& F, const HostLevel& C, HostTransfer& T
   T.inject.clear();
 }
 
+// ---------------------------------------------------------------------------
+// Taylor-Hood P_{k+1}-P_k on the same mesh (k = 2, the paper's P3-P2).
+
+void build_th_tables(int k, RefTables& t) {
+  if (k < 1 || k + 1 > kMaxPk) throw std::invalid_argument("Taylor-Hood pressure degree must be 1 or 2");
+  build_pk_tables(k + 1, t);
+  for (int x = 0; x < kQx; ++x) pk_eval(k, t.xq[x][0], t.xq[x][1], t.Nq[x], nullptr);
+}
+
+// Lattice nodes of degree K of cell c on a lattice of width nl: node (a, b)
+// of the reference triangle (b outer, a inner) is (K i + a, K j + b) for a
+// lower cell with corner vertex (i, j) and (K i - a, K j - b) for an upper
+// cell with corner vertex (i, j) = (i0 + 1, j0 + 1).
+static void cell_lattice(const HostLevel& L, int c, int K, int nl, int* out) {
+  const int v0 = L.cells[3 * c], vi = v0 % L.n1, vj = v0 / L.n1;
+  const bool lower = c % 2 == 0;
+  int i = 0;
+  for (int b = 0; b <= K; ++b)
+    for (int a = 0; a + b <= K; ++a, ++i) {
+      const int gi = lower ? K * vi + a : K * vi - a;
+      const int gj = lower ? K * vj + b : K * vj - b;
+      out[i] = gi + nl * gj;
+    }
+}
+
+void build_level_th(int M, int k, HostLevel& L) {
+  if (M < 1) throw std::invalid_argument("mesh size must be positive");
+  if (k < 2 || k + 1 > kMaxPk) throw std::invalid_argument("the general Taylor-Hood level takes k = 2");
+  const int K = k + 1;
+  L.kdeg = 0;
+  L.thk = k;
+  L.nlv = (K + 1) * (K + 2) / 2;
+  L.nlp = (k + 1) * (k + 2) / 2;
+  L.nloc = 2 * L.nlv + L.nlp;
+  L.M = M;
+  L.n1 = M + 1;
+  L.n2 = K * M + 1;
+  L.n3 = k * M + 1;
+  L.nv = L.n1 * L.n1;
+  L.nc = 2 * M * M;
+  L.nn = L.n2 * L.n2;
+  L.nfn = (L.n2 - 2) * (L.n2 - 2);
+  L.po = 2 * L.nfn;
+  L.nf = L.po + L.n3 * L.n3;
+  const int n2 = L.n2, nlv = L.nlv, nlp = L.nlp, nloc = L.nloc;
+  mesh_cells(L);
+  L.cell_p2.clear();
+  L.cell_vn.resize((size_t)nlv * L.nc);
+  L.cell_pn.resize((size_t)nlp * L.nc);
+  for (int c = 0; c < L.nc; ++c) {
+    cell_lattice(L, c, K, n2, &L.cell_vn[(size_t)nlv * c]);
+    cell_lattice(L, c, k, L.n3, &L.cell_pn[(size_t)nlp * c]);
+  }
+  L.node_free.assign(L.nn, -1);
+  for (int gj = 1; gj < n2 - 1; ++gj)
+    for (int gi = 1; gi < n2 - 1; ++gi) L.node_free[gi + n2 * gj] = (gi - 1) + (n2 - 2) * (gj - 1);
+  L.cell_dofs.resize((size_t)nloc * L.nc);
+  for (int c = 0; c < L.nc; ++c) {
+    int* d = &L.cell_dofs[(size_t)nloc * c];
+    for (int i = 0; i < nlv; ++i) {
+      const int f = L.node_free[L.cell_vn[(size_t)nlv * c + i]];
+      d[i] = f >= 0 ? 2 * f : -1;
+      d[nlv + i] = f >= 0 ? 2 * f + 1 : -1;
+    }
+    for (int i = 0; i < nlp; ++i) d[2 * nlv + i] = L.po + L.cell_pn[(size_t)nlp * c + i];
+  }
+  csr_from_cells(L);
+  // barycentric lattice coordinates (c, a, b) of the pressure nodes of a cell
+  std::vector<int> lam_a(nlp), lam_b(nlp);
+  {
+    int i = 0;
+    for (int b = 0; b <= k; ++b)
+      for (int a = 0; a + b <= k; ++a, ++i) { lam_a[i] = a; lam_b[i] = b; }
+  }
+  std::vector<std::vector<int>> inc(L.nv);
+  for (int c = 0; c < L.nc; ++c)
+    for (int t = 0; t < 3; ++t) inc[L.cells[3 * c + t]].push_back(c);
+  std::vector<std::vector<int>> pd(L.nv);
+  parallel_for(L.nv, [&](int v) {
+    auto& d = pd[v];
+    for (int c : inc[v]) {
+      for (int i = 0; i < nlv; ++i) {
+        const int f = L.node_free[L.cell_vn[(size_t)nlv * c + i]];
+        if (f >= 0) { d.push_back(2 * f); d.push_back(2 * f + 1); }
+      }
+      int corner = 0;
+      for (int t = 0; t < 3; ++t)
+        if (L.cells[3 * c + t] == v) corner = t;
+      for (int i = 0; i < nlp; ++i) {
+        const int lam[3] = {k - lam_a[i] - lam_b[i], lam_a[i], lam_b[i]};
+        if (lam[corner] > 0) d.push_back(L.po + L.cell_pn[(size_t)nlp * c + i]);
+      }
+    }
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+  });
+  L.patch_ptr.assign(L.nv + 1, 0);
+  L.patch_nbu.assign(L.nv, 0);
+  L.patch_dofs.clear();
+  for (int v = 0; v < L.nv; ++v) {
+    const auto& d = pd[v];
+    if ((int)d.size() > kThMaxNb) throw std::logic_error("Vanka+star patch larger than its bound");
+    L.patch_nbu[v] = (int)(std::lower_bound(d.begin(), d.end(), L.po) - d.begin());
+    L.patch_dofs.insert(L.patch_dofs.end(), d.begin(), d.end());
+    L.patch_ptr[v + 1] = (int)L.patch_dofs.size();
+  }
+  patch_maps(L);
+}
+
+void build_transfer_th(const HostLevel& F, const HostLevel& C, HostTransfer& T) {
+  if (F.M != 2 * C.M || F.thk != C.thk || F.thk < 2)
+    throw std::invalid_argument("Taylor-Hood transfer needs a factor-2 refinement of the same degree");
+  const int k = F.thk, K = k + 1;
+  std::vector<std::vector<std::pair<int, double>>> rows(F.nf);
+  const double hv = 1.0 / (F.M * K), hp = 1.0 / (F.M * k);
+  parallel_for(F.nn, [&](int g) {
+    const int kf = F.node_free[g];
+    if (kf < 0) return;
+    const double x = (g % F.n2) * hv, y = (g / F.n2) * hv;
+    int cell; double xi, eta;
+    locate(C, x, y, cell, xi, eta);
+    double v[kMaxLoc];
+    pk_eval(K, xi, eta, v, nullptr);
+    for (int i = 0; i < C.nlv; ++i) {
+      if (std::fabs(v[i]) < 1e-14) continue;
+      const int kc = C.node_free[C.cell_vn[(size_t)C.nlv * cell + i]];
+      if (kc < 0) continue;
+      rows[2 * kf].push_back({2 * kc, v[i]});
+      rows[2 * kf + 1].push_back({2 * kc + 1, v[i]});
+    }
+  });
+  const int np = F.n3 * F.n3;
+  parallel_for(np, [&](int g) {
+    const double x = (g % F.n3) * hp, y = (g / F.n3) * hp;
+    int cell; double xi, eta;
+    locate(C, x, y, cell, xi, eta);
+    double v[kMaxLoc];
+    pk_eval(k, xi, eta, v, nullptr);
+    for (int i = 0; i < C.nlp; ++i)
+      if (std::fabs(v[i]) >= 1e-14) rows[F.po + g].push_back({C.po + C.cell_pn[(size_t)C.nlp * cell + i], v[i]});
+  });
+  transfer_csr(F, C, rows, T);
+  // injection: coarse lattice node (a, b) is fine lattice node (2a, 2b)
+  T.inject.assign(C.nf, -1);
+  for (int g = 0; g < C.nn; ++g) {
+    const int kc = C.node_free[g];
+    if (kc < 0) continue;
+    const int kf = F.node_free[2 * (g % C.n2) + F.n2 * 2 * (g / C.n2)];
+    T.inject[2 * kc] = 2 * kf;
+    T.inject[2 * kc + 1] = 2 * kf + 1;
+  }
+  for (int g = 0; g < C.n3 * C.n3; ++g)
+    T.inject[C.po + g] = F.po + 2 * (g % C.n3) + F.n3 * 2 * (g / C.n3);
+}
+
 }  // namespace stwr

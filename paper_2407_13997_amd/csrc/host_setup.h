@@ -19,6 +19,13 @@ constexpr int kMaxNbu = 38;   // velocity DoFs in a patch
 constexpr int kMaxPk = 3;     // highest spatial degree of the heat equation's P_k
 constexpr int kMaxLoc = 10;   // nodes of a P_k cell, (k + 1)(k + 2) / 2
 constexpr int kHeatMaxNb = 19;  // DoFs of a P_k vertex-star patch, 3k^2 - 3k + 1 at k = 3
+// Taylor-Hood P_{k+1}-P_k with k = 2 (P3-P2): an interior Vanka+star patch
+// holds 74 velocity DoFs (37 nodes) and 7 pressure DoFs (Sec. 3.1)
+constexpr int kThK = 2;
+constexpr int kThMaxNb = 81;
+constexpr int kThMaxNbu = 74;
+constexpr int kThNlv = 10;    // P3 nodes of a cell
+constexpr int kThNlp = 6;     // P2 nodes of a cell
 
 // Reference tables consumed by the assembly kernels (plain doubles so the
 // struct can be copied to device memory as is).
@@ -36,10 +43,13 @@ struct RefTables {
   double e0[kMaxNQ], e1[kMaxNQ], tnode[kMaxNQ];
   double T[kMaxNQ][kMaxNQ];  // int phi_b' phi_a + phi_b(0) phi_a(0)
   double W[kMaxNQ][kMaxNQ];  // int phi_a phi_b
-  // heat equation: P_k basis (k = kdeg) at the spatial quadrature points
+  // heat equation: P_k basis (k = kdeg) at the spatial quadrature points;
+  // Taylor-Hood P3-P2: the P3 velocity basis (kdeg = 3)
   int kdeg, nloc;
   double Nk[kQx][kMaxLoc];
   double dNk[kQx][kMaxLoc][2];
+  // Taylor-Hood P3-P2: the P2 pressure basis in lattice order
+  double Nq[kQx][kMaxLoc];
 };
 
 // nodes: 0 right Gauss-Radau, 1 Gauss-Legendre (the slab's Lagrange nodes)
@@ -50,6 +60,8 @@ void build_pk_tables(int k, RefTables& t);
 // P_k basis on the reference triangle, equispaced nodes (a, b) / k with
 // a + b <= k ordered b outer, a inner: values v[nloc], gradients g[nloc][2]
 void pk_eval(int k, double xi, double eta, double* v, double (*g)[2]);
+// Taylor-Hood P_{k+1}-P_k bases in lattice order: P_{k+1} into Nk/dNk, P_k into Nq
+void build_th_tables(int k, RefTables& t);
 
 // One level of either discretisation.  Navier-Stokes (kdeg = 0): Taylor-Hood
 // P2-P1, cell_dofs 15 per cell, Vanka+star patches.  Heat (kdeg = k): scalar
@@ -77,9 +89,21 @@ struct HostLevel {
   std::vector<int> dof_slot;     // positions in patch_dofs that hold the DoF
   std::vector<int> slot_patch;   // sum nb: patch owning each slot
   std::vector<int> node_cell_ptr, node_cell;   // heat only
+  // Taylor-Hood P_{k+1}-P_k built by build_level_th (thk = k >= 2; 0 for the
+  // P2-P1 level of build_level): velocity lattice of width n2 = (k+1)M + 1,
+  // pressure lattice of width n3 = kM + 1, nlv / nlp lattice nodes per cell in
+  // cell_vn / cell_pn, cell_dofs = [x DoFs of the nlv nodes, y DoFs, pressure]
+  int thk = 0, n3 = 0, nlv = 0, nlp = 0;
+  std::vector<int> cell_vn, cell_pn;
 };
 
 void build_level(int M, HostLevel& L);
+// Taylor-Hood P_{k+1}-P_k level (k = 2): free numbering as for P2-P1 on the
+// velocity lattice (interior node (gi, gj) -> (gi-1) + (n2-2)(gj-1), DoFs 2k,
+// 2k+1), pressure lattice node g -> 2 (n2-2)^2 + g; Vanka+star patches of
+// every vertex: the free velocity DoFs of every node of the star's cells and
+// the pressure nodes of the star's cells not on the edges opposite the vertex.
+void build_level_th(int M, int k, HostLevel& L);
 void build_level_heat(int M, int k, HostLevel& L);
 
 // Prolongation from coarse (M/2) to fine (M) in free-DoF numbering, stored by
@@ -96,5 +120,9 @@ struct HostTransfer {
 void build_transfer(const HostLevel& fine, const HostLevel& coarse, HostTransfer& T);
 // P_k interpolation of the coarse heat space at the fine lattice nodes (no injection map)
 void build_transfer_heat(const HostLevel& fine, const HostLevel& coarse, HostTransfer& T);
+// Taylor-Hood P_{k+1}-P_k nested interpolation: each velocity component by
+// P_{k+1} interpolation at the fine free nodes, the pressure by P_k, with the
+// injection map (every coarse lattice node is a fine one)
+void build_transfer_th(const HostLevel& fine, const HostLevel& coarse, HostTransfer& T);
 
 }  // namespace stwr

@@ -114,3 +114,64 @@ def test_solution_length_both_equations(kind):
     ns = w.small_problem(8, 2, 1, 5, 1.0, 3)
     h1, h3 = w.heat_problem(8, 2, 1, 1, 5), w.heat_problem(8, 2, 3, 1, 5)
     assert b.problem_n_st(h1) < b.problem_n_st(ns) < b.problem_n_st(h3)
+
+
+@pytest.mark.parametrize("M,k", [(4, 1), (8, 1), (2, 2), (4, 2), (8, 2)])
+def test_level_patches_equal_oracle(M, k):
+    """The library's patch DoF lists (stwr_level_patches) against the oracle's
+    own construction, bit for bit: oracle/mesh.py for P2-P1, the Taylor-Hood
+    oracle for P3-P2 (Sec. 3 Vanka+star patches)."""
+    b = lib()
+    counts, ptr, dofs = b.level_patches(M, k)
+    if k == 1:
+        from oracle.mesh import Mesh
+        pat = Mesh(M).patches()
+        n_free = 2 * (2 * M - 1) ** 2 + (M + 1) ** 2
+    else:
+        import stwr_workloads as w
+        from oracle.mms import make_flow
+        from oracle.taylor_hood import TaylorHoodLevel
+        L = TaylorHoodLevel(M, 2, 0, 1, 1.0, make_flow(w.small_problem(4, 2, 0, 2, 1.0, 1)))
+        pat = L.patches()
+        n_free = L.n_free
+    assert counts[0] == n_free and counts[1] == (M + 1) ** 2 == len(pat)
+    assert counts[2] == sum(len(x) for x in pat)
+    for v in range(len(pat)):
+        assert np.array_equal(dofs[ptr[v]:ptr[v + 1]], pat[v]), v
+
+
+@pytest.mark.parametrize("k,nb,nnz", [(1, 39, 728), (2, 81, 2552)])
+def test_level_patches_interior_counts(k, nb, nnz):
+    """Sec. 3.1 / App. A.1: an interior Vanka+star patch holds 39 (P2-P1) or
+    81 (P3-P2) DoFs and 728 or 2,552 structural nonzeros."""
+    b = lib()
+    counts, ptr, dofs = b.level_patches(8, k)
+    assert counts[4] == nb and counts[5] == nnz
+    assert counts[6] == 2 * 8 * 8
+
+
+@pytest.mark.parametrize("M,k", [(4, 1), (8, 1), (4, 2), (8, 2)])
+def test_level_transfer_equals_oracle(M, k):
+    """Prolongation (stwr_level_transfer) against the oracle's nested-space
+    interpolation in the free numbering (Sec. 3: P = blockdiag(P_u, P_u,
+    P_phi)); the injection maps every coarse free DoF to the fine DoF at the
+    same node and component, where the prolongation is the identity."""
+    b = lib()
+    P, inj = b.level_transfer(M, k)
+    if k == 1:
+        from oracle.mesh import Mesh
+        from oracle.transfer import spacetime_prolongation
+        Po = spacetime_prolongation(Mesh(M), Mesh(M // 2), 1)
+    else:
+        import stwr_workloads as w
+        from oracle.mms import make_flow
+        from oracle.taylor_hood import TaylorHoodLevel, free_prolongation
+        mms = make_flow(w.small_problem(4, 2, 0, 2, 1.0, 1))
+        Po = free_prolongation(TaylorHoodLevel(M, 2, 0, 1, 1.0, mms), TaylorHoodLevel(M // 2, 2, 0, 1, 1.0, mms))
+    assert P.shape == Po.shape
+    assert abs(P - Po).max() <= 1e-13
+    Pd = P.toarray()
+    assert np.all(inj >= 0)
+    for c, f in enumerate(inj):
+        assert Pd[f, c] == pytest.approx(1.0, abs=1e-14)
+        assert np.count_nonzero(np.abs(Pd[f]) > 1e-14) == 1
