@@ -137,6 +137,11 @@ int round_up(int m, int w) { return (m + w - 1) / w * w; }
 // with the patch kernels), rounded up to 256 bytes so that every block, and so
 // every 1 KiB wavefront load inside it, starts on a cache-line boundary.
 int64_t block_elems(int m, int VW) { return round_up(BlockLayout(m, VW).size(), 16 * VW); }
+// The same for a level's own block layout (the large-block layout on
+// Taylor-Hood P3-P2 levels).
+int64_t level_block_elems(const HostLevel& H, int m, int VW) {
+  return H.thk > 0 ? round_up(big_block_size(m, VW), 16 * VW) : block_elems(m, VW);
+}
 
 // Slabs with their own patch blocks: the heat operator is the same on every
 // slab (uniform slabs, time-independent coefficients), so its blocks are
@@ -149,7 +154,7 @@ int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
   int64_t tot = 0;
   for (int v = 0; v < H.nv; ++v) {
     const int m = (H.patch_ptr[v + 1] - H.patch_ptr[v]) * NQ;
-    tot += (int64_t)N * block_elems(m, vw_of(prec));
+    tot += (int64_t)N * level_block_elems(H, m, vw_of(prec));
   }
   return tot;
 }
@@ -170,7 +175,8 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
   b += (uint64_t)nnz * N * NQ * NQ * 8 + nnz * 8;                       // Jv, Mv
   if (H.kdeg > 0) b += (uint64_t)nnz * 8;                               // Kv
   b += (uint64_t)(H.nf + 1 + nnz) * 4;                                  // CSR
-  b += (uint64_t)(H.cells.size() + H.cell_p2.size() + H.cell_dofs.size() + H.cell_nz.size() +
+  b += (uint64_t)(H.cells.size() + H.cell_p2.size() + H.cell_vn.size() + H.cell_pn.size() +
+                 H.cell_dofs.size() + H.cell_nz.size() +
                  H.node_free.size() + H.node_cell_ptr.size() + H.node_cell.size()) * 4;   // cell maps
   b += (uint64_t)(H.nv + 1) * 4 * 2 + (uint64_t)H.patch_dofs.size() * 4 * 2 + H.patch_nz.size() * 4;
   b += (uint64_t)(H.nv + 1) * 8 * 4 + (uint64_t)(H.nf + 1 + H.patch_dofs.size()) * 4;
@@ -247,6 +253,10 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   L.col = P->upload(H.col);
   L.cells = P->upload(H.cells);
   L.cell_p2 = P->upload(H.cell_p2);
+  if (H.thk > 0) {
+    L.cell_vn = P->upload(H.cell_vn);
+    L.cell_pn = P->upload(H.cell_pn);
+  }
   L.cell_dofs = P->upload(H.cell_dofs);
   L.cell_nz = P->upload(H.cell_nz);
   L.node_free = P->upload(H.node_free);
@@ -269,6 +279,8 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   v.cell_dofs = L.cell_dofs; v.cell_nz = L.cell_nz; v.node_free = L.node_free;
   v.n2 = H.n2; v.n1 = H.n1;
   v.kdeg = H.kdeg; v.nloc = H.nloc;
+  v.thk = H.thk; v.n3 = H.n3; v.nlv = H.nlv; v.nlp = H.nlp;
+  v.cell_vn = L.cell_vn; v.cell_pn = L.cell_pn;
   v.node_cell_ptr = L.node_cell_ptr; v.node_cell = L.node_cell;
   v.nbord = H.po < H.nf ? L.NQ : 0;
   v.coarse_slabs = fac_slabs_of(H, L.N);
@@ -368,7 +380,7 @@ void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
   L.fac_off.assign(L.H.nv + 1, 0);
   for (int v = 0; v < L.H.nv; ++v) {
     const int m = (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ;
-    L.fac_off[v + 1] = L.fac_off[v] + block_elems(m, vw_of(prec));
+    L.fac_off[v + 1] = L.fac_off[v] + level_block_elems(L.H, m, vw_of(prec));
   }
   L.pview.slab_stride = L.pview.fac_slabs == 1 ? 0 : L.fac_off[L.H.nv];
   HIPCHK(hipMemcpyAsync(L.d_fac_off, L.fac_off.data(), L.fac_off.size() * 8, hipMemcpyHostToDevice, P->s()));
@@ -429,12 +441,54 @@ void require_factor(stwr_problem* P, int l) {
   if (P->lv[l].fac_prec < 0) throw StwrError(STWR_ERR_STATE, "patch factors missing (call stwr_patch_factor)");
 }
 
+// Large blocks (Taylor-Hood P3-P2, up to 162 rows): the blocks are copied
+// out dense in chunks, inverted in FP64 by the blocked Gauss-Jordan of the
+// coarsest level (partial pivoting), and written into the factor storage at
+// the requested precision.  The chunk workspace is temporary.
+void patch_factor_big(stwr_problem* P, Level& L, int prec) {
+  int mmax = 0;
+  for (int v = 0; v < L.H.nv; ++v) mmax = std::max(mmax, (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ);
+  const int64_t nblocks = (int64_t)L.H.nv * L.pview.fac_slabs;
+  const size_t per = (size_t)mmax * mmax * 8 + (size_t)mmax * 12 + (size_t)32 * mmax * 8;
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>({nblocks, (int64_t)((size_t(1) << 30) / per), 32768}));
+  double *B = nullptr, *colbuf = nullptr, *rbuf = nullptr;
+  int* perm = nullptr;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(P->s());
+    for (void* q : {(void*)B, (void*)colbuf, (void*)rbuf, (void*)perm})
+      if (q) (void)hipFree(q);
+  };
+  try {
+    HIPCHK(hipMalloc(&B, (size_t)chunk * mmax * mmax * 8));
+    HIPCHK(hipMalloc(&colbuf, (size_t)chunk * mmax * 8));
+    HIPCHK(hipMalloc(&rbuf, (size_t)chunk * 32 * mmax * 8));
+    HIPCHK(hipMalloc(&perm, (size_t)chunk * mmax * 4));
+    for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
+      const int cnt = (int)std::min<int64_t>(chunk, nblocks - b0);
+      HIPCHK(launch_patch_extract_dense(L.view, L.pview, L.Jv, (int)b0, cnt, mmax, B, P->s()));
+      HIPCHK(launch_dense_inverse(cnt, mmax, B, P->dstatus, perm, colbuf, rbuf, P->s()));
+      HIPCHK(launch_patch_store_big(L.view, L.pview, prec, B, (int)b0, cnt, mmax, L.fac, P->s()));
+    }
+  } catch (...) {
+    release();
+    throw;
+  }
+  release();
+}
+
 void patch_factor(stwr_problem* P, int l, int prec) {
   if (!P->assembled) throw StwrError(STWR_ERR_STATE, "operator not assembled");
   if (l >= (int)P->lv.size() - 1) throw StwrError(STWR_ERR_ARG, "the coarsest level has no smoother");
   if (prec != STWR_FP32 && prec != STWR_FP64) throw StwrError(STWR_ERR_ARG, "bad precision");
   Level& L = P->lv[l];
   ensure_factor_storage(P, L, prec);
+  if (L.H.thk > 0) {
+    patch_factor_big(P, L, prec);
+    HIPCHK(launch_patch_mass(L.view, L.pview, L.Mv, L.Mp, P->s()));
+    L.fac_prec = prec;
+    check_status_flag(P, "patch factorization");
+    return;
+  }
   L.pview.factor_mfma = P->opts.factor_mfma;
   HIPCHK(launch_patch_factor(L.view, L.pview, L.Jv, prec, L.fac, P->dstatus, P->s()));
   HIPCHK(launch_patch_mass(L.view, L.pview, L.Mv, L.Mp, P->s()));
@@ -449,6 +503,7 @@ void patch_factor(stwr_problem* P, int l, int prec) {
 // transfer matrices of the current factors are rebuilt.
 void set_time_chunks(stwr_problem* P, Level& L, int nc) {
   nc = std::max(1, std::min(nc, L.N));
+  if (L.H.thk > 0) nc = 1;   // the large-block sweep runs the plain forward substitution
   const int len = (L.N + nc - 1) / nc;
   nc = (L.N + len - 1) / len;
   if (nc > 1 && nc > L.chunk_cap) {
@@ -487,7 +542,7 @@ void tune_time_chunks(stwr_problem* P, int l) {
   const int want = P->opts.time_chunks;
   if (want >= 1) { set_time_chunks(P, L, want); return; }
   if (L.chunk_choice > 0) { set_time_chunks(P, L, L.chunk_choice); return; }
-  if (L.H.nv > kTuneMaxPatches || L.N < 4) {
+  if (L.H.nv > kTuneMaxPatches || L.N < 4 || L.H.thk > 0) {
     L.chunk_choice = 1;
     set_time_chunks(P, L, 1);
     return;
@@ -1320,6 +1375,7 @@ int32_t stwr_expand(stwr_problem* p, const double* U, double* full) {
   return guarded(p->ctx, [&]() -> int32_t {
     if (!U || !full) throw StwrError(STWR_ERR_ARG, "null vector");
     if (p->heat()) throw StwrError(STWR_ERR_STATE, "the heat equation has no eliminated DoFs");
+    if (p->lv[0].H.thk > 0) throw StwrError(STWR_ERR_STATE, "no full nodal vector for P3-P2 problems");
     HIPCHK(launch_expand(p->lv[0].view, p->d_tab, p->mms, U, full, p->s()));
     return STWR_OK;
   });

@@ -644,6 +644,311 @@ __global__ __launch_bounds__(256) void k_heat_rhs(LevelView L, const RefTables* 
   for (int a = 0; a < NQ; ++a) b0[t * NQ + a] = n == 0 ? T->e0[a] * s : 0.0;
 }
 
+// ---- Taylor-Hood P3-P2 ------------------------------------------------------------
+// The same space-time forms for the general Taylor-Hood level (thk = k = 2):
+// velocity of degree k+1 with NLV lattice nodes per cell (basis T->Nk /
+// T->dNk), pressure of degree k with NLP nodes (basis T->Nq), both in
+// lattice order; cell_dofs holds [x DoFs of the velocity nodes, y DoFs,
+// pressure DoFs].  One 64-lane workgroup per (cell, slab), slab fastest, FP64
+// atomics into the operator as for P2-P1.
+template <int NQ, int NLV>
+struct ThStage {
+  double ul[2][NLV][NQ];
+  double gN[kQx][NLV][2];
+  double wdet[kQx];
+  double xp[kQx][2];
+  double uq[kMaxG][kQx][2];
+  double gq[kMaxG][kQx][2][2];
+};
+
+// coordinates of velocity lattice node g (spacing h / (k + 1))
+__device__ inline void th_vnode_xy(const LevelView& L, int g, double& x, double& y) {
+  const double hv = L.h / (L.thk + 1);
+  x = (g % L.n2) * hv;
+  y = (g / L.n2) * hv;
+}
+
+template <int NQ, int NLV>
+__device__ void th_stage(const LevelView& L, const RefTables* __restrict__ T, const MmsDev& mms,
+                         const double* __restrict__ U, int c, int n, ThStage<NQ, NLV>& S) {
+  const int tid = threadIdx.x;
+  __shared__ double inv_s[4], adet_s, v0_s[2], J_s[4];
+  if (tid == 0) {
+    double inv[4], adet, v0[2], Jc[4];
+    cell_geometry(L, c, inv, adet, v0, Jc);
+    for (int k = 0; k < 4; ++k) { inv_s[k] = inv[k]; J_s[k] = Jc[k]; }
+    adet_s = adet;
+    v0_s[0] = v0[0]; v0_s[1] = v0[1];
+  }
+  for (int e = tid; e < 2 * NLV * NQ; e += 64) {
+    const int comp = e / (NLV * NQ), i = (e / NQ) % NLV, a = e % NQ;
+    const int node = L.cell_vn[NLV * c + i];
+    const int k = L.node_free[node];
+    double v;
+    if (k >= 0) {
+      v = U[((int64_t)(2 * k + comp) * L.N + n) * NQ + a];
+    } else {
+      double x, y, ux, uy;
+      th_vnode_xy(L, node, x, y);
+      exact_velocity(mms, (n + T->tnode[a]) * L.dt, x, y, ux, uy);
+      v = comp == 0 ? ux : uy;
+    }
+    S.ul[comp][i][a] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kQx * NLV; e += 64) {
+    const int x = e / NLV, i = e % NLV;
+    for (int k = 0; k < 2; ++k)
+      S.gN[x][i][k] = T->dNk[x][i][0] * inv_s[0 * 2 + k] + T->dNk[x][i][1] * inv_s[1 * 2 + k];
+  }
+  if (tid < kQx) {
+    S.wdet[tid] = T->wq[tid] * adet_s;
+    S.xp[tid][0] = v0_s[0] + J_s[0] * T->xq[tid][0] + J_s[1] * T->xq[tid][1];
+    S.xp[tid][1] = v0_s[1] + J_s[2] * T->xq[tid][0] + J_s[3] * T->xq[tid][1];
+  }
+  __syncthreads();
+  const int G = T->G;
+  for (int e = tid; e < G * kQx; e += 64) {
+    const int g = e / kQx, x = e % kQx;
+    for (int comp = 0; comp < 2; ++comp) {
+      double u = 0.0, gx = 0.0, gy = 0.0;
+      for (int i = 0; i < NLV; ++i) {
+        double ui = 0.0;
+        for (int b = 0; b < NQ; ++b) ui += T->Phi[g][b] * S.ul[comp][i][b];
+        u += ui * T->Nk[x][i];
+        gx += ui * S.gN[x][i][0];
+        gy += ui * S.gN[x][i][1];
+      }
+      S.uq[g][x][comp] = u;
+      S.gq[g][x][comp][0] = gx;
+      S.gq[g][x][comp][1] = gy;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NQ, int NLV, int NLP>
+__global__ __launch_bounds__(64) void k_th_jacobian(LevelView L, const RefTables* __restrict__ T,
+                                                    MmsDev mms, const double* __restrict__ U,
+                                                    double* __restrict__ Jv, double* __restrict__ Mv) {
+  constexpr int NL = 2 * NLV + NLP;
+  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
+  __shared__ ThStage<NQ, NLV> S;
+  th_stage<NQ, NLV>(L, T, mms, U, c, n, S);
+  constexpr int G = NQ + 2;
+  const double dt = L.dt, R = mms.reynolds;
+  const int* nzc = L.cell_nz + (int64_t)NL * NL * c;
+  for (int e = tid; e < NLV * NLV + NLP * NLV; e += 64) {
+    if (e < NLV * NLV) {
+      const int i = e / NLV, j = e % NLV;
+      double Mij = 0.0, Kij = 0.0;
+      double c1[G], c2[G][2][2];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        c1[g] = 0.0;
+        c2[g][0][0] = c2[g][0][1] = c2[g][1][0] = c2[g][1][1] = 0.0;
+      }
+#pragma unroll 1
+      for (int x = 0; x < kQx; ++x) {
+        const double w = S.wdet[x], Ni = T->Nk[x][i], Nj = T->Nk[x][j];
+        Mij += w * Ni * Nj;
+        Kij += w * (S.gN[x][i][0] * S.gN[x][j][0] + S.gN[x][i][1] * S.gN[x][j][1]);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          c1[g] += w * Ni * (S.uq[g][x][0] * S.gN[x][j][0] + S.uq[g][x][1] * S.gN[x][j][1]);
+          const double wnn = w * Ni * Nj;
+          for (int ci = 0; ci < 2; ++ci)
+            for (int cj = 0; cj < 2; ++cj) c2[g][ci][cj] += wnn * S.gq[g][x][ci][cj];
+        }
+      }
+      for (int a = 0; a < NQ; ++a)
+        for (int b = 0; b < NQ; ++b) {
+          double C1 = 0.0, C2[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const double cw = T->wg[g] * T->Phi[g][a] * T->Phi[g][b];
+            C1 += cw * c1[g];
+            for (int ci = 0; ci < 2; ++ci)
+              for (int cj = 0; cj < 2; ++cj) C2[ci][cj] += cw * c2[g][ci][cj];
+          }
+          const double diag = T->T[a][b] * Mij + dt * T->W[a][b] * Kij + dt * R * C1;
+          for (int ci = 0; ci < 2; ++ci)
+            for (int cj = 0; cj < 2; ++cj) {
+              const int nz = nzc[NL * (NLV * ci + i) + NLV * cj + j];
+              if (nz < 0) continue;
+              const double v = dt * R * C2[ci][cj] + (ci == cj ? diag : 0.0);
+              atomicAdd(&Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
+            }
+        }
+      if (n == 0) {
+        for (int ci = 0; ci < 2; ++ci) {
+          const int nz = nzc[NL * (NLV * ci + i) + NLV * ci + j];
+          if (nz >= 0) atomicAdd(&Mv[nz], Mij);
+        }
+      }
+    } else {
+      const int t = e - NLV * NLV, j = t / NLV, i = t % NLV;   // pressure node j, velocity node i
+      double B[2] = {0.0, 0.0};
+      for (int x = 0; x < kQx; ++x) {
+        const double w = S.wdet[x] * T->Nq[x][j];
+        B[0] += w * S.gN[x][i][0];
+        B[1] += w * S.gN[x][i][1];
+      }
+      for (int a = 0; a < NQ; ++a)
+        for (int b = 0; b < NQ; ++b)
+          for (int ci = 0; ci < 2; ++ci) {
+            const double v = -dt * T->W[a][b] * B[ci];
+            const int nz1 = nzc[NL * (NLV * ci + i) + 2 * NLV + j];
+            if (nz1 >= 0) atomicAdd(&Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
+            const int nz2 = nzc[NL * (2 * NLV + j) + NLV * ci + i];
+            if (nz2 >= 0) atomicAdd(&Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
+          }
+    }
+  }
+}
+
+template <int NQ, int NLV, int NLP>
+__global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables* __restrict__ T,
+                                                    MmsDev mms, const double* __restrict__ U,
+                                                    double* __restrict__ F) {
+  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
+  __shared__ ThStage<NQ, NLV> S;
+  __shared__ double pl[NLP][NQ];
+  __shared__ double prev[2][NLV];
+  __shared__ double dq[kMaxG][kQx][2], pq[kMaxG][kQx], fq[kMaxG][kQx][2];
+  __shared__ double jq[kQx][2];   // U(s=0) - U_{n-1}(1) at the quadrature points
+  th_stage<NQ, NLV>(L, T, mms, U, c, n, S);
+  const int G = T->G;
+  for (int e = tid; e < NLP * NQ; e += 64) {
+    const int j = e / NQ, a = e % NQ;
+    pl[j][a] = U[((int64_t)(L.po + L.cell_pn[NLP * c + j]) * L.N + n) * NQ + a];
+  }
+  for (int e = tid; e < 2 * NLV; e += 64) {
+    const int comp = e / NLV, i = e % NLV;
+    const int node = L.cell_vn[NLV * c + i];
+    const int k = L.node_free[node];
+    double x, y;
+    th_vnode_xy(L, node, x, y);
+    double v = 0.0;
+    if (n == 0) {
+      double ux, uy;
+      initial_velocity(mms, x, y, ux, uy);
+      v = comp == 0 ? ux : uy;
+    } else {
+      for (int b = 0; b < NQ; ++b) {
+        double vb;
+        if (k >= 0) {
+          vb = U[((int64_t)(2 * k + comp) * L.N + n - 1) * NQ + b];
+        } else {
+          double ux, uy;
+          exact_velocity(mms, (n - 1 + T->tnode[b]) * L.dt, x, y, ux, uy);
+          vb = comp == 0 ? ux : uy;
+        }
+        v += T->e1[b] * vb;
+      }
+    }
+    prev[comp][i] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < G * kQx; e += 64) {
+    const int g = e / kQx, x = e % kQx;
+    for (int comp = 0; comp < 2; ++comp) {
+      double d = 0.0;
+      for (int i = 0; i < NLV; ++i) {
+        double ui = 0.0;
+        for (int b = 0; b < NQ; ++b) ui += T->dPhi[g][b] * S.ul[comp][i][b];
+        d += ui * T->Nk[x][i];
+      }
+      dq[g][x][comp] = d;
+    }
+    double p = 0.0;
+    for (int j = 0; j < NLP; ++j) {
+      double pj = 0.0;
+      for (int b = 0; b < NQ; ++b) pj += T->Phi[g][b] * pl[j][b];
+      p += pj * T->Nq[x][j];
+    }
+    pq[g][x] = p;
+    double fx, fy;
+    forcing(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], fx, fy);
+    fq[g][x][0] = fx;
+    fq[g][x][1] = fy;
+  }
+  if (tid < kQx) {
+    for (int comp = 0; comp < 2; ++comp) {
+      double u0 = 0.0, up = 0.0;
+      for (int i = 0; i < NLV; ++i) {
+        double ui = 0.0;
+        for (int b = 0; b < NQ; ++b) ui += T->e0[b] * S.ul[comp][i][b];
+        u0 += ui * T->Nk[tid][i];
+        up += prev[comp][i] * T->Nk[tid][i];
+      }
+      jq[tid][comp] = u0 - up;
+    }
+  }
+  __syncthreads();
+  const double dt = L.dt, R = mms.reynolds;
+  constexpr int NL = 2 * NLV + NLP;
+  for (int e = tid; e < (2 * NLV + NLP) * NQ; e += 64) {
+    if (e < 2 * NLV * NQ) {
+      const int comp = e / (NLV * NQ), i = (e / NQ) % NLV, a = e % NQ;
+      double acc = 0.0;
+      for (int g = 0; g < G; ++g) {
+        double sg = 0.0;
+        for (int x = 0; x < kQx; ++x) {
+          const double conv = S.uq[g][x][0] * S.gq[g][x][comp][0] + S.uq[g][x][1] * S.gq[g][x][comp][1];
+          const double val = dq[g][x][comp] + dt * (R * conv - fq[g][x][comp]);
+          const double grd = S.gq[g][x][comp][0] * S.gN[x][i][0] + S.gq[g][x][comp][1] * S.gN[x][i][1]
+                           - pq[g][x] * S.gN[x][i][comp];
+          sg += S.wdet[x] * (val * T->Nk[x][i] + dt * grd);
+        }
+        acc += T->wg[g] * T->Phi[g][a] * sg;
+      }
+      double jmp = 0.0;
+      for (int x = 0; x < kQx; ++x) jmp += S.wdet[x] * jq[x][comp] * T->Nk[x][i];
+      acc += T->e0[a] * jmp;
+      const int dof = L.cell_dofs[NL * c + NLV * comp + i];
+      if (dof >= 0) atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], acc);
+    } else {
+      const int t = e - 2 * NLV * NQ, j = t / NQ, a = t % NQ;
+      double acc = 0.0;
+      for (int g = 0; g < G; ++g) {
+        double sg = 0.0;
+        for (int x = 0; x < kQx; ++x)
+          sg += S.wdet[x] * (S.gq[g][x][0][0] + S.gq[g][x][1][1]) * T->Nq[x][j];
+        acc += T->wg[g] * T->Phi[g][a] * sg;
+      }
+      const int dof = L.po + L.cell_pn[NLP * c + j];
+      atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
+    }
+  }
+}
+
+// Space-time velocity L2 error of the P3 velocity (as k_velocity_error).
+template <int NQ, int NLV>
+__global__ __launch_bounds__(64) void k_th_velocity_error(LevelView L, const RefTables* __restrict__ T,
+                                                          MmsDev mms, const double* __restrict__ U,
+                                                          double* __restrict__ part) {
+  const int c = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  __shared__ ThStage<NQ, NLV> S;
+  __shared__ double red[64];
+  th_stage<NQ, NLV>(L, T, mms, U, c, n, S);
+  double acc = 0.0;
+  for (int e = tid; e < T->G * kQx; e += 64) {
+    const int g = e / kQx, x = e % kQx;
+    double ux, uy;
+    exact_velocity(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], ux, uy);
+    const double dx = ux - S.uq[g][x][0], dy = uy - S.uq[g][x][1];
+    acc += T->wg[g] * S.wdet[x] * (dx * dx + dy * dy);
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) part[(int64_t)n * L.nc + c] = L.dt * red[0];
+}
+
 }  // namespace
 
 hipError_t launch_heat_operator(const LevelView& L, const RefTables* tab, double* Jv, double* Mv,
@@ -688,8 +993,14 @@ hipError_t launch_heat_rhs(const LevelView& L, const RefTables* tab, const doubl
 hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDev mms,
                                  const double* U, double* part, double* out, hipStream_t s) {
   dim3 grid(L.nc, L.N);
-  if (L.NQ == 1) hipLaunchKernelGGL(k_velocity_error<1>, grid, dim3(64), 0, s, L, tab, mms, U, part);
-  else hipLaunchKernelGGL(k_velocity_error<2>, grid, dim3(64), 0, s, L, tab, mms, U, part);
+  if (L.thk == kThK) {
+    if (L.NQ == 1) hipLaunchKernelGGL((k_th_velocity_error<1, kThNlv>), grid, dim3(64), 0, s, L, tab, mms, U, part);
+    else hipLaunchKernelGGL((k_th_velocity_error<2, kThNlv>), grid, dim3(64), 0, s, L, tab, mms, U, part);
+  } else if (L.NQ == 1) {
+    hipLaunchKernelGGL(k_velocity_error<1>, grid, dim3(64), 0, s, L, tab, mms, U, part);
+  } else {
+    hipLaunchKernelGGL(k_velocity_error<2>, grid, dim3(64), 0, s, L, tab, mms, U, part);
+  }
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (int64_t)L.nc * L.N, part, out);
   return hipGetLastError();
 }
@@ -704,6 +1015,11 @@ hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, c
 hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
                                     const double* U, double* Jv, double* Mv, hipStream_t s) {
   dim3 grid((unsigned)((int64_t)L.nc * L.N));
+  if (L.thk == kThK) {
+    if (L.NQ == 1) hipLaunchKernelGGL((k_th_jacobian<1, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
+    else hipLaunchKernelGGL((k_th_jacobian<2, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
+    return hipGetLastError();
+  }
   if (L.NQ == 1) hipLaunchKernelGGL(k_jacobian<1>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
   else hipLaunchKernelGGL(k_jacobian<2>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
   return hipGetLastError();
@@ -712,6 +1028,11 @@ hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, Mm
 hipError_t launch_assemble_residual(const LevelView& L, const RefTables* tab, MmsDev mms,
                                     const double* U, double* F, hipStream_t s) {
   dim3 grid((unsigned)((int64_t)L.nc * L.N));
+  if (L.thk == kThK) {
+    if (L.NQ == 1) hipLaunchKernelGGL((k_th_residual<1, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, F);
+    else hipLaunchKernelGGL((k_th_residual<2, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, F);
+    return hipGetLastError();
+  }
   if (L.NQ == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(64), 0, s, L, tab, mms, U, F);
   else hipLaunchKernelGGL(k_residual<2>, grid, dim3(64), 0, s, L, tab, mms, U, F);
   return hipGetLastError();

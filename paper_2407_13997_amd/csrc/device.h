@@ -55,6 +55,12 @@ struct LevelView {
   const int* node_cell;
   int nbord;             // constraint rows bordering a coarsest slab block: q+1 with pressure, else 0
   int coarse_slabs;      // coarsest slab blocks stored: N, or 1 when every slab's block is the same
+  // Taylor-Hood P_{k+1}-P_k of the general path (thk = k = 2; 0 for P2-P1):
+  // velocity lattice width n2, pressure lattice width n3, the nlv velocity and
+  // nlp pressure lattice nodes of each cell (lattice order)
+  int thk, n3, nlv, nlp;
+  const int* cell_vn;
+  const int* cell_pn;
 };
 
 // Time chunks of one sweep (see k_patch_sweep): chunk c covers slabs
@@ -137,6 +143,13 @@ struct BlockLayout {
     return offset(w) + panels(w) * r1 * VW + (k * 4 * r2 + lane) * VW + c % VW;
   }
 };
+
+// Storage of one inverted m x m block of the large-block sweep (Taylor-Hood
+// P3-P2 patches, m up to 162): column panels of VW = 16 / sizeof(T) columns,
+// every row of a panel in turn, element (r, c) at ((c / VW) m + r) VW + c % VW;
+// the columns of the last panel past m are zero.  A wavefront's 16-byte loads
+// of one panel (consecutive rows, one per lane) read one contiguous segment.
+__host__ __device__ constexpr int big_block_size(int m, int VW) { return (m + VW - 1) / VW * m * VW; }
 
 // ---- cross-lane helpers (64-lane wavefronts) ------------------------------------
 // A lane's value read by every lane (the lane index is uniform).
@@ -238,13 +251,23 @@ hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const doubl
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, void* Y, hipStream_t s);
+// Large blocks (L.thk > 0): dense FP64 copies of blocks b0 .. b0 + count - 1
+// of the level (block b: patch at position b / fac_slabs of the patch order,
+// slab b % fac_slabs) into B (count x mmax x mmax, row-major), each padded with
+// the identity past its own order; and, once B holds their inverses, the
+// inverses written into the factor storage in the large-block layout at
+// precision prec.
+hipError_t launch_patch_extract_dense(const LevelView& L, const PatchView& P, const double* Jv, int b0,
+                                      int count, int mmax, double* B, hipStream_t s);
+hipError_t launch_patch_store_big(const LevelView& L, const PatchView& P, int prec, const double* B, int b0,
+                                  int count, int mmax, void* fac, hipStream_t s);
 // Chunk transfer matrices of the current factors (time_chunks > 1 only).
 hipError_t launch_patch_chunk_transfer(const LevelView& L, const PatchView& P, int prec, const void* fac,
                                        const double* Mp, const double* e0, const double* e1,
                                        hipStream_t s);
 // Whether the sweep leaves FP32 outputs (the gather reads them as such).
 inline bool sweep_outputs_f32(const LevelView& L, const PatchView& P, int prec) {
-  return prec == 1 && L.kdeg == 0 && P.time_chunks <= 1;
+  return prec == 1 && L.kdeg == 0 && L.thk == 0 && P.time_chunks <= 1;
 }
 // mode 0: z = sum; mode 1: d = c1 d + c2 sum, x += d.
 hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,

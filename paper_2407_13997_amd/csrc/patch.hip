@@ -985,6 +985,129 @@ __global__ __launch_bounds__(64) void k_patch_chunk_interface(PatchView P, Chunk
   }
 }
 
+// ---- large patch blocks (Taylor-Hood P3-P2) ------------------------------------------
+// Dense identity-padded FP64 copies of the slab blocks A_{v,n} = R_v J_n R_v^T
+// (eq. waveform_patch_solve), one workgroup per block.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_patch_extract_dense(LevelView L, PatchView P,
+                                                             const double* __restrict__ Jv, int b0, int mmax,
+                                                             double* __restrict__ B) {
+  const int b = b0 + blockIdx.x;
+  const int p = P.order[b / P.fac_slabs], n = b % P.fac_slabs;
+  const int s0 = P.patch_ptr[p], nb = P.patch_ptr[p + 1] - s0, m = nb * NQ;
+  const int* nzp = P.patch_nz + P.patch_nz_off[p];
+  double* out = B + (int64_t)blockIdx.x * mmax * mmax;
+  for (int e = threadIdx.x; e < mmax * mmax; e += 256) {
+    const int i = e / mmax, j = e % mmax;
+    double v = i == j ? 1.0 : 0.0;
+    if (i < m && j < m) {
+      const int k = nzp[(i / NQ) * nb + j / NQ];
+      v = k >= 0 ? Jv[(((int64_t)k * L.N + n) * NQ + i % NQ) * NQ + j % NQ] : 0.0;
+    }
+    out[e] = v;
+  }
+}
+
+// The inverses of k_patch_extract_dense's blocks (their leading m x m parts)
+// into the large-block layout at precision T.
+template <int NQ, typename T>
+__global__ __launch_bounds__(256) void k_patch_store_big(PatchView P, const double* __restrict__ B, int b0,
+                                                         int mmax, T* __restrict__ fac) {
+  constexpr int VW = Vec<T>::W;
+  const int b = b0 + blockIdx.x;
+  const int p = P.order[b / P.fac_slabs], n = b % P.fac_slabs;
+  const int m = (P.patch_ptr[p + 1] - P.patch_ptr[p]) * NQ;
+  const double* in = B + (int64_t)blockIdx.x * mmax * mmax;
+  T* out = fac + P.fac_off[p] + (int64_t)n * P.slab_stride;
+  const int size = big_block_size(m, VW);
+  for (int e = threadIdx.x; e < size; e += 256) {
+    const int q = e / (m * VW), rem = e % (m * VW), r = rem / VW, c = q * VW + rem % VW;
+    out[e] = c < m ? (T)in[(int64_t)r * mmax + c] : (T)0;
+  }
+}
+
+// Sweep of the large blocks (m = (q+1) nb up to 162): one workgroup of WAVES
+// wavefronts per patch, thread r owning row r; per slab the right-hand side
+// (residual of the patch DoFs plus the jump coupling e0 (x) M_v y_{n-1}(end))
+// goes to LDS, each row's product streams its 16-byte panel vectors (a
+// wavefront's loads of a panel are one contiguous segment), the result is
+// written to the patch's FP64 outputs, and the slab-end values and the next
+// coupling are formed in LDS.  Arithmetic in T (the factor precision).
+template <int NQ, typename T, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_patch_sweep_big(LevelView L, PatchView P,
+                                                                const T* __restrict__ fac,
+                                                                const double* __restrict__ Mp, TimeEnds te,
+                                                                const double* __restrict__ r,
+                                                                double* __restrict__ Y) {
+  constexpr int MAXM = kThMaxNb * NQ;
+  constexpr int VW = Vec<T>::W;
+  constexpr int MAXP = (MAXM + VW - 1) / VW;
+  constexpr int NN = kThMaxNbu / 2;
+  static_assert(64 * WAVES >= MAXP * VW, "one thread per padded row");
+  using V16 = typename Vec<T>::type;
+  __shared__ int dofs[kThMaxNb];
+  __shared__ T MsT[NN * NN];
+  __shared__ T g[MAXP * VW];
+  __shared__ T yv[MAXM];
+  __shared__ T ylast[kThMaxNbu], mj[kThMaxNbu];
+  const int p = P.order[blockIdx.x];
+  const int row = threadIdx.x;
+  const int s0 = P.patch_ptr[p], nb = P.patch_ptr[p + 1] - s0, nbu = P.patch_nbu[p], nn = nbu / 2;
+  const int m = nb * NQ, PH = (m + VW - 1) / VW, N = L.N;
+  for (int i = row; i < nb; i += 64 * WAVES) dofs[i] = P.patch_dofs[s0 + i];
+  const double* mp = Mp + P.mp_off[p];
+  for (int e = row; e < nn * nn; e += 64 * WAVES) {
+    const int i = e / nn, j = e % nn;
+    MsT[j * nn + i] = (T)mp[2 * i * nbu + 2 * j];
+  }
+  for (int i = row; i < kThMaxNbu; i += 64 * WAVES) mj[i] = (T)0;
+  __syncthreads();
+  const T* A = fac + P.fac_off[p];
+  double* yo = Y + P.y_off[p];
+  const bool has = row < m;
+  const int idof = row / NQ, a = row % NQ;
+  const int64_t nq = (int64_t)N * NQ;
+  for (int n = 0; n < N; ++n) {
+    if (row < PH * VW) {
+      T gv = (T)0;
+      if (has) {
+        gv = (T)r[(int64_t)dofs[idof] * nq + (int64_t)n * NQ + a];
+        if (n > 0 && idof < nbu) gv += (T)te.e0[a] * mj[idof];
+      }
+      g[row] = gv;
+    }
+    __syncthreads();
+    T acc = (T)0;
+    if (has) {
+      const T* blk = A + (int64_t)n * P.slab_stride + row * VW;
+#pragma unroll 8
+      for (int q = 0; q < PH; ++q) {
+        const V16 v = *reinterpret_cast<const V16*>(blk + (int64_t)q * m * VW);
+        const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+        for (int c = 0; c < VW; ++c) acc += e[c] * g[q * VW + c];
+      }
+      yo[(int64_t)n * m + row] = (double)acc;
+      yv[row] = acc;
+    }
+    __syncthreads();
+    if (row < nbu) {
+      T v = (T)0;
+#pragma unroll
+      for (int b = 0; b < NQ; ++b) v += (T)te.e1[b] * yv[row * NQ + b];
+      ylast[row] = v;
+    }
+    __syncthreads();
+    if (row < nbu) {
+      const int a2 = row >> 1, c = row & 1;
+      T v = (T)0;
+      for (int k = 0; k < nn; ++k) v += MsT[k * nn + a2] * ylast[2 * k + c];
+      mj[row] = v;
+    }
+    __syncthreads();
+  }
+}
+
 // Y: FP64 patch outputs at y_off, or FP32 ones at twice y_off (same bytes)
 template <int NQ, typename TY>
 __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P,
@@ -1191,6 +1314,31 @@ int patch_factor_batch_occupancy(int cls) {
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
+hipError_t launch_patch_extract_dense(const LevelView& L, const PatchView& P, const double* Jv, int b0,
+                                      int count, int mmax, double* B, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (L.NQ == 1) hipLaunchKernelGGL(k_patch_extract_dense<1>, dim3(count), dim3(256), 0, s, L, P, Jv, b0, mmax, B);
+  else if (L.NQ == 2) hipLaunchKernelGGL(k_patch_extract_dense<2>, dim3(count), dim3(256), 0, s, L, P, Jv, b0, mmax, B);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_store_big(const LevelView& L, const PatchView& P, int prec, const double* B, int b0,
+                                  int count, int mmax, void* fac, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const dim3 grid(count), block(256);
+  if (prec == 1) {
+    float* f = (float*)fac;
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_store_big<1, float>), grid, block, 0, s, P, B, b0, mmax, f);
+    else hipLaunchKernelGGL((k_patch_store_big<2, float>), grid, block, 0, s, P, B, b0, mmax, f);
+  } else {
+    double* f = (double*)fac;
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_store_big<1, double>), grid, block, 0, s, P, B, b0, mmax, f);
+    else hipLaunchKernelGGL((k_patch_store_big<2, double>), grid, block, 0, s, P, B, b0, mmax, f);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const double* Mv, double* Mp,
                              hipStream_t s) {
   (void)L;
@@ -1228,6 +1376,20 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
                               const double* r, void* Y, hipStream_t s) {
   const TimeEnds te = time_ends(L.NQ, e0, e1);
   double* Yd = (double*)Y;
+  if (L.thk > 0) {
+    // Taylor-Hood P3-P2 patches: the large-block sweep, FP64 outputs
+    const dim3 grid(P.n_patch);
+    if (prec == 1) {
+      const float* f = (const float*)fac;
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep_big<1, float, 2>), grid, dim3(128), 0, s, L, P, f, Mp, te, r, Yd);
+      else hipLaunchKernelGGL((k_patch_sweep_big<2, float, 3>), grid, dim3(192), 0, s, L, P, f, Mp, te, r, Yd);
+    } else {
+      const double* f = (const double*)fac;
+      if (L.NQ == 1) hipLaunchKernelGGL((k_patch_sweep_big<1, double, 2>), grid, dim3(128), 0, s, L, P, f, Mp, te, r, Yd);
+      else hipLaunchKernelGGL((k_patch_sweep_big<2, double, 3>), grid, dim3(192), 0, s, L, P, f, Mp, te, r, Yd);
+    }
+    return hipGetLastError();
+  }
   if (L.kdeg > 0) {
     // scalar heat patches (at most kHeatMaxNb DoFs, (q+1) kHeatMaxNb rows):
     // a wavefront's threads form up to 64 rows and hold up to 20 FP32 or 10

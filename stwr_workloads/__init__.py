@@ -54,7 +54,8 @@ class Problem:
         m = self.mesh_n
         if self.equation == 1:
             return (self.degree * m + 1) ** 2
-        return 2 * (2 * m - 1) ** 2 + (m + 1) ** 2
+        k = 2 if self.degree == 2 else 1      # Taylor-Hood P_{k+1}-P_k
+        return 2 * ((k + 1) * m - 1) ** 2 + (k * m + 1) ** 2
 
     @property
     def n_st(self) -> int:
@@ -149,10 +150,12 @@ def heat_problem(mesh_n: int, n_levels: int, degree: int, q: int, n_slabs: int =
 
 def small_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int,
                   reynolds: float, seed: int, t_final: float = 1.0,
-                  n_psi: int = 4, n_p: int = 3) -> Problem:
-    """A seeded problem of arbitrary (small) size for tests."""
+                  n_psi: int = 4, n_p: int = 3, degree: int = 1) -> Problem:
+    """A seeded problem of arbitrary (small) size for tests; degree is the
+    Taylor-Hood pressure degree k (1: P2-P1, 2: P3-P2)."""
     modes = draw_modes(seed, n_psi, n_p, 4)
-    return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, *modes, seed=seed)
+    return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, *modes, seed=seed,
+                   degree=2 if degree == 2 else 0)
 
 
 def batch_problems(n: int = 64, seed0: int = 2000, meshes=(8, 16, 32, 64),
