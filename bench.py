@@ -366,6 +366,14 @@ PAPER_CHORIN = {
 }
 
 
+# The paper's P3-P2 Chorin runs (the spatial-degree-2 columns of the same
+# tables; q = 1 at N = 20, 40 ran out of memory there).
+PAPER_CHORIN_P3P2 = {
+    (0, 10): (6.51e-3, 629.8, "5 (29)"), (0, 20): (3.32e-3, 2326.1, "4 (19)"),
+    (0, 40): (1.70e-3, 16979.7, "4 (19)"), (1, 10): (1.77e-4, 2868.7, "5 (26)"),
+}
+
+
 # The paper's lid-driven cavity runs (Sec. 4.3, P2-P1 columns): (mesh, q, R)
 # -> (time to solution in s, "Newton (linear)" with Eisenstat-Walker
 # tolerances); 40 x 40 and 80 x 80 are its two and three refinements of the
@@ -415,6 +423,15 @@ def paper_context() -> dict:
         chorin.append({"q": q, "N": N, "st_dofs": prob.n_st, "error": err, "paper_error": p_err,
                        "time_s": dt, "paper_time_s": p_time,
                        "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
+    chorin_p3p2 = []
+    for (q, N), (p_err, p_time, p_its) in sorted(PAPER_CHORIN_P3P2.items()):
+        # five levels at q = 1: the 10 x 10 coarsest bordered blocks of P3-P2
+        # x DG(1) would exceed the dense coarse solve's order
+        prob = w.chorin_problem(80, 5 if q == 1 else 4, q, N, nodes=1, degree=2)
+        st, dt, err = _timed_newton(ctx, prob)
+        chorin_p3p2.append({"q": q, "N": N, "levels": prob.n_levels, "st_dofs": prob.n_st, "error": err,
+                            "paper_error": p_err, "time_s": dt, "paper_time_s": p_time,
+                            "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
     for (M, q, R), (p_time, p_its) in sorted(PAPER_CAVITY.items()):
         prob = w.cavity_problem(M, 3 if M == 40 else 4, q, 20, R)
         st, dt, _ = _timed_newton(ctx, prob)
@@ -422,7 +439,7 @@ def paper_context() -> dict:
                        "paper_time_s": p_time,
                        "iterations": f"{st['newton']} ({sum(st['linear'])})", "paper_iterations": p_its})
     ctx.close()
-    return {"chorin": chorin, "cavity": cavity}
+    return {"chorin": chorin, "chorin_p3p2": chorin_p3p2, "cavity": cavity}
 
 
 # The paper's FGMRES-WRMG heat runs (Sec. 4.1, times to solution at Mref = 3

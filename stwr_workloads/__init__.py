@@ -115,14 +115,15 @@ def named_problem(name: str, index: int = 0) -> Problem:
 
 
 def chorin_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int, reynolds: float = 10.0,
-                   t_final: float = 0.1, nodes: int = 1) -> Problem:
+                   t_final: float = 0.1, nodes: int = 1, degree: int = 1) -> Problem:
     """The Chorin test problem on [0, t_final] (the paper's runs: 80 x 80 mesh
     from a 10 x 10 base, 4 levels, R = 10, t in [0, 0.1], N = 10, 20, 40),
-    with Gauss-Legendre temporal nodes by default (nodes=0: right Radau)."""
+    with Gauss-Legendre temporal nodes by default (nodes=0: right Radau);
+    degree is the Taylor-Hood pressure degree (1: P2-P1, 2: P3-P2)."""
     none_i = np.zeros((0, 2), dtype=np.int64)
     none_f = np.zeros((0, 3))
     return Problem(mesh_n, n_levels, q, n_slabs, t_final, reynolds, none_i, none_f, none_i, none_f,
-                   seed=0, flow=1, nodes=nodes)
+                   seed=0, flow=1, nodes=nodes, degree=2 if degree == 2 else 0)
 
 
 def cavity_problem(mesh_n: int, n_levels: int, q: int, n_slabs: int, reynolds: float,
