@@ -483,7 +483,13 @@ void patch_factor(stwr_problem* P, int l, int prec) {
   Level& L = P->lv[l];
   ensure_factor_storage(P, L, prec);
   if (L.H.thk > 0) {
-    patch_factor_big(P, L, prec);
+    // in registers where a row fits (FP32, and FP64 at one temporal node),
+    // else through dense FP64 copies
+    if (!P->opts.factor_mfma ||
+        launch_patch_factor_big_reg(L.view, L.pview, L.Jv, prec, L.fac, P->dstatus, P->s()) != hipSuccess) {
+      (void)hipGetLastError();
+      patch_factor_big(P, L, prec);
+    }
     HIPCHK(launch_patch_mass(L.view, L.pview, L.Mv, L.Mp, P->s()));
     L.fac_prec = prec;
     check_status_flag(P, "patch factorization");

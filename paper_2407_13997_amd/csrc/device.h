@@ -257,6 +257,8 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
 // the identity past its own order; and, once B holds their inverses, the
 // inverses written into the factor storage in the large-block layout at
 // precision prec.
+hipError_t launch_patch_factor_big_reg(const LevelView& L, const PatchView& P, const double* Jv, int prec,
+                                       void* fac, int* status, hipStream_t s);
 hipError_t launch_patch_extract_dense(const LevelView& L, const PatchView& P, const double* Jv, int b0,
                                       int count, int mmax, double* B, hipStream_t s);
 hipError_t launch_patch_store_big(const LevelView& L, const PatchView& P, int prec, const double* B, int b0,

@@ -88,8 +88,10 @@ struct FactorLds {
   int ofs1[MAXM], ofs2[MAXM];
 };
 
-// The block of patch p (its id, not its position) at slab n.
-template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb>
+// The block of patch p (its id, not its position) at slab n.  BIG writes
+// the inverse in the large-block layout (big_block_size) instead of the
+// wavefront panel layout.
+template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb, bool BIG = false>
 __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView& P, const int p, const int n,
                                              const double* __restrict__ Jv, T* __restrict__ fac,
                                              int* __restrict__ status, FactorLds<NQ, T, TPB, NBMAX>& S) {
@@ -261,8 +263,13 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
       if (pos == k) pos = pk;
       else if (pos == pk) pos = k;
     }
-    ofs1[c] = lay.at(0, pos);
-    ofs2[c] = m > 64 ? lay.at(64, pos) : 0;
+    if constexpr (BIG) {
+      ofs1[c] = (pos / VW) * m * VW + pos % VW;
+      ofs2[c] = 0;
+    } else {
+      ofs1[c] = lay.at(0, pos);
+      ofs2[c] = m > 64 ? lay.at(64, pos) : 0;
+    }
   }
   // the padding of the layout is zeroed once when the storage is allocated;
   // every entry is written here
@@ -272,23 +279,31 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
   for (int r = 0; r < RPL; ++r) {
     const int i = tid + TPB * r;
     if (i < m) {
-      const int rofs = i < 64 ? i * VW : (i - 64) * 4 * VW;
+      if constexpr (BIG) {
 #pragma unroll
-      for (int q = 0; q < MAXM; ++q) {
-        const int c = (q + m) % MAXM;
-        if (c < m) out[(i < 64 ? ofs1[c] : ofs2[c]) + rofs] = a[r][q];
+        for (int q = 0; q < MAXM; ++q) {
+          const int c = (q + m) % MAXM;
+          if (c < m) out[ofs1[c] + i * VW] = a[r][q];
+        }
+      } else {
+        const int rofs = i < 64 ? i * VW : (i - 64) * 4 * VW;
+#pragma unroll
+        for (int q = 0; q < MAXM; ++q) {
+          const int c = (q + m) % MAXM;
+          if (c < m) out[(i < 64 ? ofs1[c] : ofs2[c]) + rofs] = a[r][q];
+        }
       }
     }
   }
 }
 
-template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb>
+template <int NQ, typename T, int TPB, int RPL, int NBMAX = kMaxNb, bool BIG = false>
 __global__ __launch_bounds__(TPB) void k_patch_factor(LevelView L, PatchView P, int first,
                                                       const double* __restrict__ Jv,
                                                       T* __restrict__ fac, int* __restrict__ status) {
   __shared__ FactorLds<NQ, T, TPB, NBMAX> S;
   const int p = P.order[first + blockIdx.x / P.fac_slabs], n = blockIdx.x % P.fac_slabs;
-  factor_block<NQ, T, TPB, RPL, NBMAX>(L, P, p, n, Jv, fac, status, S);
+  factor_block<NQ, T, TPB, RPL, NBMAX, BIG>(L, P, p, n, Jv, fac, status, S);
 }
 
 __global__ __launch_bounds__(256) void k_patch_mass(PatchView P, const double* __restrict__ Mv,
@@ -1312,6 +1327,28 @@ int patch_factor_batch_occupancy(int cls) {
   if (cls == kFacSmall2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_patch_factor_f32_batch<2>, 64, 0);
   if (cls == kFacBig2) return patch_factor_mfma_batch_occupancy();
   return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+// Large blocks inverted in registers (one row per thread, as k_patch_factor)
+// where a row fits: FP32 blocks, and FP64 blocks of one temporal node.
+// Returns hipErrorNotSupported for the others (FP64 at two nodes), which take
+// the dense path.
+hipError_t launch_patch_factor_big_reg(const LevelView& L, const PatchView& P, const double* Jv, int prec,
+                                       void* fac, int* status, hipStream_t s) {
+  const dim3 grid((unsigned)P.n_patch * P.fac_slabs);
+  constexpr int NB = kThMaxNb;
+  if (prec == 1) {
+    float* f = (float*)fac;
+    if (L.NQ == 1) hipLaunchKernelGGL((k_patch_factor<1, float, 128, 1, NB, true>), grid, dim3(128), 0, s, L, P, 0, Jv, f, status);
+    else if (L.NQ == 2) hipLaunchKernelGGL((k_patch_factor<2, float, 192, 1, NB, true>), grid, dim3(192), 0, s, L, P, 0, Jv, f, status);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  if (L.NQ == 1) {
+    hipLaunchKernelGGL((k_patch_factor<1, double, 128, 1, NB, true>), grid, dim3(128), 0, s, L, P, 0, Jv, (double*)fac, status);
+    return hipGetLastError();
+  }
+  return hipErrorNotSupported;
 }
 
 hipError_t launch_patch_extract_dense(const LevelView& L, const PatchView& P, const double* Jv, int b0,
