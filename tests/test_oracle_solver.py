@@ -155,3 +155,57 @@ def test_newton_with_eisenstat_walker_reaches_the_exact_solution():
     eta = s2["eta"]
     assert eta[0] == 0.3 and all(0.0 < e <= 0.9 for e in eta)
     assert eta[-1] < eta[0]
+
+
+def _interpolant(level, prob_mms):
+    """Free space-time vector of the nodal interpolant of the manufactured
+    velocity and of the pressure p(t, x, y) = cos(x + 2 y + t) on a level."""
+    t = level.node_times()[None, :, :]
+    m = level.mesh
+    ux, uy = prob_mms.velocity(t, m.nxy[:, 0][:, None, None], m.nxy[:, 1][:, None, None])
+    p = np.cos(m.vxy[:, 0][:, None, None] + 2 * m.vxy[:, 1][:, None, None] + t)
+    x = np.zeros((level.n_free, level.N, level.nq))
+    fr = m.node_free >= 0
+    k = m.node_free[fr]
+    x[2 * k], x[2 * k + 1] = ux[fr], uy[fr]
+    x[m.p_offset:] = p
+    return x
+
+
+def test_state_injection_of_an_interpolant_is_the_coarse_interpolant():
+    """The Newton iterate reaches the coarse levels by injection (every coarse
+    node is a fine node).  Injecting the fine interpolant of a smooth field
+    gives the coarse interpolant of the same field, value for value, on every
+    level of a three-level hierarchy, for both node families of the mesh (P2
+    velocity nodes, P1 vertices)."""
+    import stwr_workloads as w
+    from oracle.multigrid import Hierarchy, Options
+    prob = w.small_problem(16, 3, 1, 3, 10.0, 17)
+    H = Hierarchy(prob, Options())
+    xs = H.level_states(_interpolant(H.levels[0], H.mms))
+    for l, lev in enumerate(H.levels):
+        assert np.array_equal(xs[l], _interpolant(lev, H.mms)), l
+
+
+def test_taylor_hood_state_injection_of_an_interpolant():
+    """The same on the P3-P2 lattices (velocity (3M+1)^2, pressure (2M+1)^2)."""
+    import stwr_workloads as w
+    from oracle.mms import make_flow
+    from oracle.taylor_hood import TaylorHoodHierarchy
+    prob = w.small_problem(8, 3, 1, 2, 10.0, 18)
+    T = TaylorHoodHierarchy(8, 3, 2, 1, 2, 1.0, make_flow(prob))
+
+    def interp(L):
+        t = ((np.arange(L.N)[:, None] + L.tb.nodes[None, :]) * L.dt)[None, :, :]
+        ux, uy = L.mms.velocity(t, L.V.xy[:, 0][:, None, None], L.V.xy[:, 1][:, None, None])
+        p = np.cos(L.P.xy[:, 0][:, None, None] + 2 * L.P.xy[:, 1][:, None, None] + t)
+        x = np.zeros((L.n_free, L.N, L.nq))
+        fr = L.node_free >= 0
+        k = L.node_free[fr]
+        x[2 * k], x[2 * k + 1] = ux[fr], uy[fr]
+        x[L.p_offset:] = p
+        return x
+
+    xs = T.level_states(interp(T.levels[0]))
+    for l, lev in enumerate(T.levels):
+        assert np.array_equal(xs[l], interp(lev)), l
