@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--vcycles", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-uneven-batch", action="store_true")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="also run the Poisson-rate sweep of the batched server (about ten minutes)")
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--largest-solve", type=int, default=0,
                     help="also run the 128x128 Newton solve with this many levels (0: skip)")
@@ -315,6 +317,9 @@ def main():
     if not args.no_uneven_batch:
         out["uneven_batch"] = uneven_batch(args.batch_problems)
         log(f"[bench] uneven batch: {out['uneven_batch']}")
+    if args.serving_sweep:
+        out["serving_sweep"] = serving_sweep()
+        log(f"[bench] serving sweep: {out['serving_sweep']}")
     if args.largest_solve > 0:
         out["largest_solve"] = largest_solve(args.largest_solve)
         log(f"[bench] largest solve: {out['largest_solve']}")
@@ -720,6 +725,137 @@ def uneven_batch(n_problems: int = 64, newton_maxit: int = 8, gmres_maxit: int =
             "speedup_solves_per_s_vs_fp32_solo": batched["solves_per_s"] / solo32["solves_per_s"],
             "max_rel_diff_fp32_solo_vs_plain": worst(s32), "max_rel_diff_batched_vs_plain": worst(sb),
             "converged_sets_equal": sorted(s64) == sorted(sb)}
+
+
+def fifo_latencies(arrivals, service):
+    """Completion latencies of one server taking requests in arrival order:
+    start_j = max(a_j, finish_{j-1}), finish_j = start_j + s_j."""
+    out, finish = [], 0.0
+    for a, s in zip(arrivals, service):
+        finish = max(a, finish) + s
+        out.append(finish - a)
+    return out
+
+
+def serving_sweep(rates=(1.0, 2.0, 5.0, 200.0), n_req: int = 100, budget_gb: float = 200.0,
+                  newton_maxit: int = 8, gmres_maxit: int = 30) -> dict:
+    """Serving with kernel-level continuous batching: a seeded Poisson stream
+    of n_req solves drawn from the uneven-batch distribution (seeds 3000+j) at
+    each rate, admitted into one stwr_batch as they arrive while their device
+    bytes fit the budget (else they wait, first in first out), so the sweeps
+    and factorizations of every live solve share launches.  Beside it, the
+    plain FP64-smoother path and the FP32 path serving one solve at a time in
+    arrival order: their per-request service times are measured once and the
+    single-server queue replayed for each rate's arrivals.  Same caps and
+    Eisenstat-Walker tolerances as the uneven batch; latency = completion -
+    arrival over the converged requests."""
+    import numpy as np
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    probs = w.batch_problems(n_req, seed0=3000)
+
+    def opts(prec, chunks):
+        o = binding.default_opts()
+        o.smoother_prec = prec
+        o.newton_ew = 1
+        o.newton_maxit = newton_maxit
+        o.gmres_maxit = gmres_maxit
+        o.time_chunks = chunks
+        return o
+
+    ctx = binding.Context(0)
+    service, ok_solo, sols = {}, {}, {}
+    for name, prec in (("fp64", binding.FP64), ("fp32", binding.FP32)):
+        s, okl = [], []
+        for j, p in enumerate(probs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = binding.Problem(ctx, p, opts(prec, 0))
+            U = P.vec()
+            try:
+                st = P.newton_solve(U, allow_unconverged=True)
+                ok = st["fnorm"][-1] <= 1e-10 * st["fnorm"][0]
+            except binding.StwrError:
+                ok = False
+            torch.cuda.synchronize()
+            s.append(time.perf_counter() - t0)
+            okl.append(ok)
+            if ok and name == "fp64":
+                sols[j] = U.cpu().numpy()
+            P.close()
+            if (j + 1) % 20 == 0:
+                log(f"[bench] serving sweep: {name} service times {j + 1}/{n_req} ({sum(s):.1f}s)")
+        service[name], ok_solo[name] = s, okl
+    ctx.close()
+
+    rows = []
+    for rate in rates:
+        arr = w.arrival_times(rate, n_req, seed=3000)
+        rec = {"rate_per_s": rate}
+        for name in ("fp64", "fp32"):
+            lat = fifo_latencies(arr, service[name])
+            okl = [l for l, ok in zip(lat, ok_solo[name]) if ok]
+            span = max(a + l for a, l in zip(arr, lat))
+            rec[f"{name}_one_at_a_time"] = {"solves": len(okl), "makespan_s": span, "solves_per_s": len(okl) / span,
+                                            "p50_latency_s": float(np.percentile(okl, 50)),
+                                            "p99_latency_s": float(np.percentile(okl, 99))}
+        bctx = binding.Context(0, hbm_budget=int(budget_gb * 1e9))
+        B = binding.Batch(bctx, use_graph=True)
+        t0 = time.perf_counter()
+        nxt, waiting, ids, done, lat, errs = 0, [], {}, 0, [], []
+        max_live, n_fail = 0, 0
+        while done < n_req:
+            now = time.perf_counter() - t0
+            while nxt < n_req and arr[nxt] <= now:
+                waiting.append(nxt)
+                nxt += 1
+            while waiting:
+                j = waiting[0]
+                try:
+                    ids[B.add(probs[j], opts(binding.FP32, 1))] = j
+                    waiting.pop(0)
+                except binding.StwrError as e:
+                    if e.code != -3:
+                        raise
+                    if B.info()["live"] == 0:   # larger than the whole budget: rejected
+                        waiting.pop(0)
+                        done += 1
+                        n_fail += 1
+                        continue
+                    break
+            live = B.info()["live"]
+            max_live = max(max_live, live)
+            if live:
+                B.step()
+            elif nxt < n_req:
+                time.sleep(max(0.0, min(0.05, arr[nxt] - (time.perf_counter() - t0))))
+            for r in B.poll():
+                done += 1
+                j = ids[r["id"]]
+                if r["status"] == 0:
+                    lat.append(time.perf_counter() - t0 - arr[j])
+                    if j in sols:
+                        errs.append(float(np.linalg.norm(r["solution"] - sols[j]) / np.linalg.norm(sols[j])))
+                else:
+                    n_fail += 1
+        span = time.perf_counter() - t0
+        info = B.info()
+        B.close()
+        bctx.close()
+        rec["fp32_batched"] = {"solves": len(lat), "failed": n_fail, "makespan_s": span,
+                               "solves_per_s": len(lat) / span,
+                               "p50_latency_s": float(np.percentile(lat, 50)) if lat else None,
+                               "p99_latency_s": float(np.percentile(lat, 99)) if lat else None,
+                               "max_live": max_live, "steps": info["steps"], "graph_captures": info["graph_captures"],
+                               "max_rel_diff_vs_plain": max(errs) if errs else None}
+        log(f"[bench] serving sweep rate {rate}: {rec}")
+        rows.append(rec)
+    return {"requests_per_rate": n_req, "budget_gb": budget_gb,
+            "workload": "Poisson arrivals (seed 3000) of uneven solves: meshes {8,16,32,64}^2, N in [8,128], "
+                        "q in {0,1}, Re 10^U[0,3], seeds 3000+j",
+            "caps": {"newton_maxit": newton_maxit, "gmres_maxit": gmres_maxit, "newton_ew": 1},
+            "one_at_a_time_converged": {k: int(sum(v)) for k, v in ok_solo.items()}, "rates": rows}
 
 
 def time_chunk_context(steps: int = 10) -> list:
