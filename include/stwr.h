@@ -2,7 +2,8 @@
  * stwr.h - C ABI of the space-time waveform-relaxation multigrid library for
  * incompressible Navier-Stokes on one AMD Instinct MI355X (gfx950).
  *
- * Method: Taylor-Hood P2-P1 in space times upwind DG(q) in time (q in {0,1}),
+ * Method: Taylor-Hood P2-P1 (or P3-P2, degree = 2) in space times upwind DG(q)
+ * in time (q in {0,1}),
  * solved all at once in space-time by Newton's method, FGMRES preconditioned
  * by geometric multigrid V-cycles whose smoother is the waveform-relaxation
  * Vanka+star patch relaxation with Chebyshev weights.  Paper sections:
@@ -81,7 +82,8 @@ typedef struct {
   int32_t flow;   /* STWR_FLOW_MODES: the modes above; STWR_FLOW_CHORIN, STWR_FLOW_CAVITY: below */
   int32_t temporal_nodes;  /* STWR_NODES_RADAU (default) or STWR_NODES_GAUSS, see below */
   int32_t equation;        /* STWR_EQ_NAVIER_STOKES (default) or STWR_EQ_HEAT, see below */
-  int32_t degree;          /* spatial degree k of the heat equation's P_k, 1..3 (else ignored) */
+  int32_t degree;          /* heat: spatial degree k of P_k, 1..3; Navier-Stokes: pressure degree k
+                              of Taylor-Hood P_{k+1}-P_k, 2 for P3-P2 (Sec. 3.1), 0 or 1 for P2-P1 */
 } stwr_problem_desc;
 
 /* equation = STWR_EQ_HEAT selects the heat equation u_t - Laplace u = 0 of
@@ -440,7 +442,7 @@ int32_t stwr_server_destroy(stwr_server* s);
  * stwr_batch_add creates the problem at once on the batch's context
  * (STWR_ERR_BUDGET if it does not fit the context's HBM budget; nothing is
  * then kept) and starts it at the next step.  It must be a Navier-Stokes
- * problem with at least two levels and smoother_prec = STWR_FP32; every
+ * P2-P1 problem with at least two levels and smoother_prec = STWR_FP32; every
  * problem of a batch has the same nu_pre and nu_post (the first fixes them).
  * host_out: n_st doubles of host memory for the solution (or NULL), written
  * when the problem finishes and valid once its result is polled.

@@ -932,6 +932,7 @@ int32_t stwr_batch_add(stwr_batch* b, const stwr_problem_desc* desc, const stwr_
   return guarded(b->ctx, [&]() -> int32_t {
     if (!desc || !opts || !id_out) throw StwrError(STWR_ERR_ARG, "null argument");
     if (desc->equation != STWR_EQ_NAVIER_STOKES) throw StwrError(STWR_ERR_ARG, "the batch solves Navier-Stokes problems");
+    if (desc->degree > 1) throw StwrError(STWR_ERR_ARG, "the batch solves P2-P1 problems (patches of at most 39 DoFs)");
     if (opts->smoother_prec != STWR_FP32) throw StwrError(STWR_ERR_ARG, "the batch runs FP32 patch factors and sweeps");
     if (b->nu_pre >= 0 && (opts->nu_pre != b->nu_pre || opts->nu_post != b->nu_post))
       throw StwrError(STWR_ERR_ARG, "every problem of a batch has the same nu_pre and nu_post");

@@ -244,10 +244,11 @@ hipError_t launch_patch_factor_mfma(const LevelView& L, const PatchView& P, cons
                                     int* status, int first, int count, hipStream_t s);
 hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const double* Mv,
                              double* Mp, hipStream_t s);
-// Y: patch outputs, FP64 at element offset y_off[p] (prec 0, and FP32
-// factors of the heat equation's scalar patches), or FP32 at element offset
-// 2 y_off[p] (FP32 factors of Navier-Stokes patches); the buffer holds
-// y_off[n_patch] doubles.
+// Y: patch outputs, FP64 at element offset y_off[p] ([slab][patch DoF][node];
+// prec 0, FP32 factors of the heat equation's scalar patches, of P3-P2
+// patches and of time-chunked sweeps), or FP32 at element offset 2 y_off[p]
+// ([patch DoF][slab][node]; the plain FP32 sweep of P2-P1 patches,
+// sweep_outputs_f32); the buffer holds y_off[n_patch] doubles.
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, void* Y, hipStream_t s);

@@ -14,9 +14,9 @@ constexpr int kBlock = 256;
 
 // y = A x or y = b - A x for the space-time operator of one level:
 // block diagonal part from Jv, plus the jump coupling of slab n to slab n-1,
-// -e0 (x) (M * (e1 . x_{n-1})), on velocity rows.
+// -e0 (x) (M * (e1 . x_{n-1})), on velocity rows.  One lane per (row, slab).
 template <int NQ>
-__global__ __launch_bounds__(kBlock) void k_spmv(int nf, int N, const int* __restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const int* __restrict__ rp,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ Jv,
                                                  const double* __restrict__ Mv, TimeEnds te,
@@ -31,10 +31,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int N, const int* __res
   double acc[NQ];
   for (int a = 0; a < NQ; ++a) acc[a] = 0.0;
   double jump = 0.0;
+  const bool prow = i >= po;
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
     const int j = col[k];
     const double* xv = x + ((int64_t)j * N + n) * NQ;
-    const double* v = Jv + ((int64_t)k * N + n) * NQ * NQ;
+    // an entry of a pressure row or column is the pressure coupling
+    // -dt W (x) B, the same in every slab (linear in the state, uniform
+    // slabs): read slab 0's copy, one line for the whole row, so the
+    // operator streams only the slab-dependent velocity-velocity blocks
+    const bool pc = prow || j >= po;
+    const double* v = Jv + ((int64_t)k * N + (pc ? 0 : n)) * NQ * NQ;
     double xb[NQ];
     for (int bb = 0; bb < NQ; ++bb) xb[bb] = xv[bb];
     for (int a = 0; a < NQ; ++a)
@@ -727,7 +733,7 @@ hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, c
                        hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   const TimeEnds te = time_ends(L.NQ, e0, e1);
-  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_spmv<Q>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.N,
+  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_spmv<Q>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
                                           L.row_ptr, L.col, Jv, Mv, te, x, b, y));
   return hipGetLastError();
 }

@@ -344,7 +344,8 @@ __device__ inline T dotv(const V& w, const T* g) {
 // every patch DoF at a time, with one batch of coalesced loads issued ahead
 // of a block.  The outputs are FP32 (they are computed in FP32, so nothing
 // is lost; the gather widens them), collected in LDS for 32 / (q+1) slabs
-// and written as whole 128-byte lines: writes interleaved with the block
+// and written DoF by DoF ([patch DoF][slab][node], one 128-byte line per DoF
+// and chunk), so each line is whole: writes interleaved with the block
 // stream cost HBM time far beyond their share of the bytes, so they are
 // kept few and full.  The blocks are read once per sweep and are loaded
 // nontemporal, so they do not push the residual and output lines out of L2.  The jump coupling works in FP32 from the scalar patch mass
@@ -369,7 +370,7 @@ struct SweepF32Lds {
   float ylast[kMaxNbu];
   float mj[kMaxNbu];
   float rch[CH][RW];                           // residual of the current CH slabs
-  float ych[2 * CH * MAXM];                    // outputs of the current 2 CH slabs
+  alignas(16) float ych[2 * CH * MAXM];        // outputs of the current 2 CH slabs, [patch DoF][slab][node]
 };
 
 template <int NQ, bool FULL>
@@ -397,7 +398,8 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   float (*rch)[RW] = S.rch;
   constexpr int YCH = 2 * CH;                  // slabs per 128-byte line of FP32 outputs
   float* ych = S.ych;
-  constexpr int YL = (YCH * MAXM + 255) / 256; // 16-byte output stores per lane and line
+  static_assert(YCH * NQ == 32, "an output chunk is one 128-byte line per DoF");
+  constexpr int YL = (kMaxNb * 8 + 63) / 64;   // 16-byte output stores per lane and chunk
   const float e0[2] = {(float)e00, (float)e01}, e1[2] = {(float)e10, (float)e11};
   const int lane = threadIdx.x;
   const GLOBAL_AS int* patch_ptr = gptr(P.patch_ptr);
@@ -422,7 +424,8 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   __syncthreads();
   const GLOBAL_AS float* Ab = gptr(fac) + gptr(P.fac_off)[p];
   const int64_t SS = P.slab_stride;
-  GLOBAL_AS float* yout = gptr(Y) + 2 * gptr(P.y_off)[p];   // FP32 outputs at the byte offset of the FP64 layout
+  GLOBAL_AS float* yout = gptr(Y) + 2 * gptr(P.y_off)[p];   // FP32 outputs at the byte offset of the FP64 layout,
+                                                            // [patch DoF][slab][node]
   const unsigned row1 = lane < r1 ? lane : 0;
   const unsigned base1 = row1 * VW, step1 = r1 * VW;
   const unsigned lane2 = lane < 4 * r2 ? lane : 0;
@@ -471,19 +474,29 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
       if (id < nel) rch[j / NQ][(id >> 4) * NQ + j % NQ] = (float)rv[i];
     }
   };
-  // outputs of slabs n0 .. n0 + ns - 1 (n0 a multiple of YCH), four a lane;
-  // the chunk starts on a line boundary (the output region is line-aligned
-  // and a chunk of YCH slabs is nb whole lines)
+  // outputs of slabs n0 .. n0 + ns - 1 (n0 a multiple of YCH), stored DoF
+  // by DoF: patch row i holds its N slabs' NQ values contiguously (nq
+  // floats from i nq), so a DoF's values of a whole chunk are one 128-byte
+  // line, and the gather reads each DoF's slabs as one coalesced run.  Four
+  // values a lane and store (eight stores per DoF and chunk); 16-byte
+  // stores where the rows are 16-byte aligned (nq a multiple of 4), single
+  // values at a ragged chunk end
   auto flush = [&](int n0, int ns) {
-    const int elems = ns * m;
-    GLOBAL_AS float* yo = yout + (int64_t)n0 * m;
-#pragma unroll
+    const int run = ns * NQ;
+    const bool vec = (nq & 3) == 0;
+    // one store at a time: the next slab's block loads are in flight, so
+    // every register the flush holds adds to the kernel's peak
+#pragma unroll 1
     for (int i = 0; i < YL; ++i) {
-      const int e = 4 * (i * 64 + lane);
-      if (e + 3 < elems) {
-        *reinterpret_cast<GLOBAL_AS f32x4*>(yo + e) = f32x4{ych[e], ych[e + 1], ych[e + 2], ych[e + 3]};
-      } else {
-        for (int j = e; j < elems; ++j) yo[j] = ych[j];
+      const int id = i * 64 + lane, dd = id >> 3, t0 = 4 * (id & 7);
+      if (dd < nb && t0 < run) {
+        GLOBAL_AS float* yo = yout + (int64_t)dd * nq + n0 * NQ + t0;
+        const float* ys = ych + dd * 32 + t0;
+        if (vec && t0 + 3 < run) {
+          *reinterpret_cast<GLOBAL_AS f32x4*>(yo) = *reinterpret_cast<const f32x4*>(ys);
+        } else {
+          for (int t = 0; t < 4 && t0 + t < run; ++t) yo[t] = ys[t];
+        }
       }
     }
   };
@@ -542,7 +555,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
     float v1 = e1[lane % NQ] * acc1;
     if constexpr (NQ == 2) v1 += __shfl_xor(v1, 1);
     if (lane < r1) {
-      ych[sy * m + lane] = acc1;
+      ych[(lane / NQ) * 32 + sy * NQ + lane % NQ] = acc1;
       if (lane % NQ == NQ - 1) ylast[lane / NQ] = v1;
     }
     if constexpr (kTwo) {
@@ -550,7 +563,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
       float v2 = e1[row % NQ] * acc2;
       if constexpr (NQ == 2) v2 += __shfl_xor(v2, 4);
       if (lane < 4 * r2 && quarter == 0) {
-        ych[sy * m + row] = acc2;
+        ych[(row / NQ) * 32 + sy * NQ + row % NQ] = acc2;
         if (row % NQ == NQ - 1) ylast[row / NQ] = v2;
       }
     }
@@ -1123,7 +1136,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep_big(LevelView L, Pat
   }
 }
 
-// Y: FP64 patch outputs at y_off, or FP32 ones at twice y_off (same bytes)
+// Y: FP64 patch outputs at y_off, [slab][patch DoF][node], or FP32 ones at
+// twice y_off (same bytes), [patch DoF][slab][node] (the FP32 sweep's layout)
 template <int NQ, typename TY>
 __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P,
                                                       const TY* __restrict__ Y, int mode,
@@ -1139,7 +1153,8 @@ __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P
     const int p = P.slot_patch[s];
     const int s0 = P.patch_ptr[p];
     const int m = (P.patch_ptr[p + 1] - s0) * NQ;
-    const TY* yp = Y + (sizeof(TY) == 4 ? 2 : 1) * P.y_off[p] + (int64_t)n * m + (s - s0) * NQ;
+    const TY* yp = sizeof(TY) == 4 ? Y + 2 * P.y_off[p] + ((int64_t)(s - s0) * N + n) * NQ
+                                   : Y + P.y_off[p] + (int64_t)n * m + (s - s0) * NQ;
     for (int a = 0; a < NQ; ++a) acc[a] += (double)yp[a];
   }
   const int64_t o = t * NQ;
@@ -1167,18 +1182,21 @@ __global__ __launch_bounds__(256) void k_patch_gather_rows(int nf, int N, PatchV
                                                            double* __restrict__ d, double* __restrict__ x) {
   __shared__ int64_t s_base[kGatherStage];
   __shared__ int s_m[kGatherStage];
-  constexpr int YS = sizeof(TY) == 4 ? 2 : 1;
+  // FP32 outputs are [patch DoF][slab][node] (a DoF's slabs adjacent), FP64
+  // ones [slab][patch DoF][node]: the slab stride is NQ or the patch's rows
+  constexpr bool kDofMajor = sizeof(TY) == 4;
+  constexpr int YS = kDofMajor ? 2 : 1;
   const int R = 256 / N, tid = threadIdx.x;
   const int i0 = blockIdx.x * R, i1 = i0 + R < nf ? i0 + R : nf;
   const int k0 = P.dof_ptr[i0], nk = P.dof_ptr[i1] - k0;
   const bool staged = nk <= kGatherStage;   // uniform over the workgroup
-  // output offset of slot k (row of the DoF in slab 0) and the patch's rows
+  // output offset of slot k (its value of slab 0) and its slab stride
   auto slot = [&](int k, int64_t& base, int& m) {
     const int sl = P.dof_slot[k];
     const int p = P.slot_patch[sl];
     const int s0 = P.patch_ptr[p];
-    m = (P.patch_ptr[p + 1] - s0) * NQ;
-    base = YS * P.y_off[p] + (int64_t)(sl - s0) * NQ;
+    m = kDofMajor ? NQ : (P.patch_ptr[p + 1] - s0) * NQ;
+    base = YS * P.y_off[p] + (int64_t)(sl - s0) * (kDofMajor ? N * NQ : NQ);
   };
   if (staged) {
     for (int e = tid; e < nk; e += 256) slot(k0 + e, s_base[e], s_m[e]);

@@ -126,3 +126,20 @@ def test_batch_budget_rejection():
     assert B.info()["live"] == 0
     B.close()
     small.close()
+
+
+def test_batch_rejects_p3p2():
+    """The batch's sweep and factorization kernels take P2-P1 patches (at
+    most 39 DoFs): a P3-P2 problem (81-DoF patches) is refused as an
+    argument error before anything is created."""
+    torch_cuda()
+    from paper_2407_13997_amd import binding
+    p = w.small_problem(8, 2, 0, 3, 1.0, 506, degree=2)
+    c = binding.Context(0)
+    B = binding.Batch(c)
+    with pytest.raises(binding.StwrError) as e:
+        B.add(p, opts())
+    assert e.value.code == -1
+    assert c.bytes_in_use() == 0 and B.info()["live"] == 0
+    B.close()
+    c.close()
