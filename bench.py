@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--vcycles", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-uneven-batch", action="store_true")
+    ap.add_argument("--p3p2-steps", type=int, default=10,
+                    help="timed sweeps of the P3-P2 leg (80x80 Chorin, q=1, 10 slabs); 0 skips it")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="also run the Poisson-rate sweep of the batched server (about ten minutes)")
     ap.add_argument("--batch-problems", type=int, default=64)
@@ -314,6 +316,9 @@ def main():
         log(f"[bench] single solve: {out['single_solve']}")
         out["serving"] = serving_benchmark()
         log(f"[bench] serving: {out['serving']}")
+    if args.p3p2_steps > 0:
+        out["p3p2_sweep"] = p3p2_sweep(args.p3p2_steps)
+        log(f"[bench] P3-P2 sweep: {out['p3p2_sweep']}")
     if not args.no_uneven_batch:
         out["uneven_batch"] = uneven_batch(args.batch_problems)
         log(f"[bench] uneven batch: {out['uneven_batch']}")
@@ -963,6 +968,63 @@ def serving_benchmark(n_req: int = 16, slots: int = 4) -> dict:
                     "p50_latency_s": float(np.percentile(lat, 50)) if lat else None,
                     "p99_latency_s": float(np.percentile(lat, 99)) if lat else None},
     }
+
+
+def p3p2_sweep(steps: int = 10) -> dict:
+    """The Taylor-Hood P3-P2 x DG(1) relaxation sweep on the paper's largest
+    P3-P2 run (Sec. 4.2: Chorin problem on 80 x 80, 10 slabs; five levels),
+    FP32 factors of the 81-DoF Vanka+star patches (slab blocks of order 162),
+    timed as the main workload: operator, large-block sweep and gather.  Its
+    roofline counts every (patch, slab) inverse block once (m^2 4 bytes) and
+    the FP64 residual and correction (24 n_st)."""
+    import numpy as np
+    import torch
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    prob = w.chorin_problem(80, 5, 1, 10, nodes=1, degree=2)
+    ctx = binding.Context(0)
+    o = binding.default_opts()
+    o.smoother_prec = binding.FP32
+    P = binding.Problem(ctx, prob, o)
+    n_st, nf, n_patch = P.sizes(0)
+    U = P.vec()
+    P.assemble(U)
+    t = time.perf_counter()
+    P.patch_factor(0, binding.FP32)
+    torch.cuda.synchronize()
+    t_fac = time.perf_counter() - t
+    lam = P.eig_estimate(0)
+    a, bnd = o.cheb_lo * lam, o.cheb_hi * lam
+    g = torch.Generator(device="cpu").manual_seed(4001)
+    b = torch.randn(n_st, generator=g, dtype=torch.float64).to("cuda")
+    x = torch.zeros(n_st, dtype=torch.float64, device="cuda")
+    P.relax(0, b, x, 2, a, bnd)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.kernel_times()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        P.relax(0, b, x, 1, a, bnd)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    P.close()
+    ctx.close()
+    ms = e0.elapsed_time(e1) / steps
+    sw = kt["sweep"][0] / max(kt["sweep"][1], 1)
+    _, ptr, _ = binding.level_patches(prob.mesh_n, 2)
+    m = np.diff(ptr).astype(np.int64) * (prob.q + 1)
+    algo = int((m * m).sum()) * prob.n_slabs * 4 + 24 * int(n_st)
+    return {"workload": "chorin_p3p2_dg1_m80_n10 finest-level WR sweep", "st_dofs": int(n_st),
+            "patches": int(n_patch), "steps": steps, "ms_per_step": ms, "value": n_st / (ms * 1e-3),
+            "unit": "st-DoF/s", "factor_finest_s": t_fac,
+            "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+            "roofline": {"bound": "hbm", "kernel": "k_patch_sweep_big (FP32 blocks)", "avg_ms": sw,
+                         "algorithmic_bytes": algo, "achieved": algo / (sw * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": algo / (sw * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def patch_sweep_bytes_algorithmic(prob, s_f: int, n_st: int) -> int:

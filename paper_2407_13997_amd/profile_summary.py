@@ -1,7 +1,8 @@
 """Summarise rocprofv3 databases (rocpd SQLite) for the committed profiles.
 
   kernel-trace db:  per-kernel calls, total and average duration
-  --pmc db:         per-kernel average FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+  --pmc db:         per-kernel average of each counter per dispatch (FETCH_SIZE and
+                    WRITE_SIZE in KiB, the SQ_ / GRBM_ counters in their own units)
 
 Usage: python -m paper_2407_13997_amd.profile_summary TRACE_DB [PMC_DB ...]
 """
@@ -40,7 +41,7 @@ def main(argv):
         print(f"| {n} | {c} | {tot / 1e6:.3f} | {avg / 1e6:.4f} | {mn / 1e6:.4f} | {mx / 1e6:.4f} |")
     for db in argv[1:]:
         print()
-        print("| kernel | counter | dispatches | avg KiB | min KiB | max KiB |")
+        print("| kernel | counter | dispatches | avg | min | max |")
         print("|---|---|---:|---:|---:|---:|")
         for n, cn, c, avg, mn, mx in pmc_stats(db):
             print(f"| {n} | {cn} | {c} | {avg:.1f} | {mn:.1f} | {mx:.1f} |")
