@@ -61,6 +61,22 @@ __device__ inline float4 load_stream(const GLOBAL_AS float* p) {
   const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL_AS f32x4*>(p));
   return make_float4(t.x, t.y, t.z, t.w);
 }
+// the same for 16 bytes of T (four floats or two doubles), as a vector
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct NtVec;
+template <>
+struct NtVec<float> {
+  using type = f32x4;
+};
+template <>
+struct NtVec<double> {
+  using type = f64x2;
+};
+template <typename T>
+__device__ inline typename NtVec<T>::type load_stream16(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<T>::type*>(p));
+}
 
 // Inverse of one (patch, slab) block by Gauss-Jordan elimination with
 // partial pivoting, held in registers: thread t owns rows t + TPB r (r < RPL),
@@ -1072,7 +1088,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep_big(LevelView L, Pat
   constexpr int MAXP = (MAXM + VW - 1) / VW;
   constexpr int NN = kThMaxNbu / 2;
   static_assert(64 * WAVES >= MAXP * VW, "one thread per padded row");
-  using V16 = typename Vec<T>::type;
   __shared__ int dofs[kThMaxNb];
   __shared__ T MsT[NN * NN];
   __shared__ T g[MAXP * VW];
@@ -1110,10 +1125,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep_big(LevelView L, Pat
       const T* blk = A + (int64_t)n * P.slab_stride + row * VW;
 #pragma unroll 8
       for (int q = 0; q < PH; ++q) {
-        const V16 v = *reinterpret_cast<const V16*>(blk + (int64_t)q * m * VW);
-        const T* e = reinterpret_cast<const T*>(&v);
+        // nontemporal: the blocks stream once per sweep, and keeping them out
+        // of L2 keeps the residual lines every slab of the patch reads there
+        const auto v = load_stream16(blk + (int64_t)q * m * VW);
 #pragma unroll
-        for (int c = 0; c < VW; ++c) acc += e[c] * g[q * VW + c];
+        for (int c = 0; c < VW; ++c) acc += v[c] * g[q * VW + c];
       }
       yo[(int64_t)n * m + row] = (double)acc;
       yv[row] = acc;
