@@ -153,7 +153,18 @@ typedef struct {
   int32_t factor_mfma;         /* 1 (default): FP32 patch blocks of more than 64 rows are inverted
                                   by blocked Gauss-Jordan with MFMA trailing updates; 0: by the
                                   column-at-a-time register Gauss-Jordan (same pivoting rule) */
+  int32_t deterministic;       /* 1: results equal bit for bit from run to run (see below);
+                                  0 (default): FP64 atomic assembly, autotuned time chunks */
 } stwr_solver_opts;
+
+/* deterministic = 1 assembles the Navier-Stokes residual and Jacobian of eq.
+ * nsfem cell colour by cell colour (8 colours, no two cells of a colour
+ * sharing a DoF) with plain additions in a fixed order instead of FP64
+ * atomic additions, whose order, and so whose rounding, varies from run to
+ * run; and time_chunks = 0 means the plain sweep instead of a choice by
+ * timing.  Every other step of the solver (patch factors and sweeps, the
+ * owner-gather of the patch corrections, reductions, the coarsest solve)
+ * already runs in a fixed order.  The assembly costs about 10% more. */
 
 /* Time chunks (the cyclic reduction in time of Sec. 3.1, single-GPU form).
  * A patch's sweep is a forward substitution over the N slabs.  With c chunks

@@ -62,7 +62,8 @@ class SolverOpts(ctypes.Structure):
                 ("gmres_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
                 ("newton_rtol", ctypes.c_double), ("vcycle_graph", ctypes.c_int32),
                 ("newton_ew", ctypes.c_int32), ("gmres_atol", ctypes.c_double),
-                ("time_chunks", ctypes.c_int32), ("factor_mfma", ctypes.c_int32)]
+                ("time_chunks", ctypes.c_int32), ("factor_mfma", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 MAX_NEWTON, MAX_LEVELS = 64, 16

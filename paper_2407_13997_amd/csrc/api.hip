@@ -126,7 +126,8 @@ void check_opts(const stwr_solver_opts* o) {
       (o->smoother_prec != STWR_FP64 && o->smoother_prec != STWR_FP32) || !(o->cheb_hi > o->cheb_lo) ||
       !(o->cheb_lo > 0.0) || (o->vcycle_graph != 0 && o->vcycle_graph != 1) ||
       (o->newton_ew != 0 && o->newton_ew != 1) || !(o->gmres_atol >= 0.0) || o->time_chunks < 0 ||
-      o->time_chunks > kMaxTimeChunks || (o->factor_mfma != 0 && o->factor_mfma != 1))
+      o->time_chunks > kMaxTimeChunks || (o->factor_mfma != 0 && o->factor_mfma != 1) ||
+      (o->deterministic != 0 && o->deterministic != 1))
     throw StwrError(STWR_ERR_ARG, "invalid solver options");
 }
 
@@ -177,7 +178,8 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
   b += (uint64_t)(H.nf + 1 + nnz) * 4;                                  // CSR
   b += (uint64_t)(H.cells.size() + H.cell_p2.size() + H.cell_vn.size() + H.cell_pn.size() +
                  H.cell_dofs.size() + H.cell_nz.size() +
-                 H.node_free.size() + H.node_cell_ptr.size() + H.node_cell.size()) * 4;   // cell maps
+                 H.node_free.size() + H.node_cell_ptr.size() + H.node_cell.size() +
+                 (H.kdeg == 0 ? H.color_cells.size() : 0)) * 4;   // cell maps
   b += (uint64_t)(H.nv + 1) * 4 * 2 + (uint64_t)H.patch_dofs.size() * 4 * 2 + H.patch_nz.size() * 4;
   b += (uint64_t)(H.nv + 1) * 8 * 4 + (uint64_t)(H.nf + 1 + H.patch_dofs.size()) * 4;
   b += (uint64_t)4 * n_st * 8;                                          // r, d, x, b
@@ -259,6 +261,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   }
   L.cell_dofs = P->upload(H.cell_dofs);
   L.cell_nz = P->upload(H.cell_nz);
+  if (H.kdeg == 0) L.color_cells = P->upload(H.color_cells);
   L.node_free = P->upload(H.node_free);
   if (H.kdeg > 0) {
     L.node_cell_ptr = P->upload(H.node_cell_ptr);
@@ -281,6 +284,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   v.kdeg = H.kdeg; v.nloc = H.nloc;
   v.thk = H.thk; v.n3 = H.n3; v.nlv = H.nlv; v.nlp = H.nlp;
   v.cell_vn = L.cell_vn; v.cell_pn = L.cell_pn;
+  v.color_cells = L.color_cells; v.color_first = 0; v.det = 0;
   v.node_cell_ptr = L.node_cell_ptr; v.node_cell = L.node_cell;
   v.nbord = H.po < H.nf ? L.NQ : 0;
   v.coarse_slabs = fac_slabs_of(H, L.N);
@@ -545,7 +549,8 @@ void set_time_chunks(stwr_problem* P, Level& L, int nc) {
 // than kTuneMaxPatches patches keep the plain sweep.
 void tune_time_chunks(stwr_problem* P, int l) {
   Level& L = P->lv[l];
-  const int want = P->opts.time_chunks;
+  // a deterministic problem takes no timing-based choice: plain sweeps
+  const int want = P->opts.time_chunks == 0 && P->opts.deterministic ? 1 : P->opts.time_chunks;
   if (want >= 1) { set_time_chunks(P, L, want); return; }
   if (L.chunk_choice > 0) { set_time_chunks(P, L, L.chunk_choice); return; }
   if (L.H.nv > kTuneMaxPatches || L.N < 4 || L.H.thk > 0) {
@@ -853,7 +858,8 @@ void assemble(stwr_problem* P, const double* U) {
     }
     HIPCHK(launch_fill((int64_t)Lv.view.nnz * Lv.N * Lv.NQ * Lv.NQ, 0.0, Lv.Jv, P->s()));
     HIPCHK(launch_fill(Lv.view.nnz, 0.0, Lv.Mv, P->s()));
-    HIPCHK(launch_assemble_jacobian(Lv.view, P->d_tab, P->mms, Ul, Lv.Jv, Lv.Mv, P->s()));
+    HIPCHK(launch_assemble_jacobian(Lv.view, P->d_tab, P->mms, Ul, Lv.Jv, Lv.Mv,
+                                    P->opts.deterministic ? Lv.H.color_ptr : nullptr, P->s()));
     Lv.fac_prec = -1;
     Lv.has_lambda = false;
   }
@@ -876,7 +882,8 @@ void residual(stwr_problem* P, const double* U, double* F) {
     return;
   }
   HIPCHK(launch_fill(L.n_st, 0.0, F, P->s()));
-  HIPCHK(launch_assemble_residual(L.view, P->d_tab, P->mms, U, F, P->s()));
+  HIPCHK(launch_assemble_residual(L.view, P->d_tab, P->mms, U, F, P->opts.deterministic ? L.H.color_ptr : nullptr,
+                                  P->s()));
 }
 
 void setup_smoothers(stwr_problem* P) {
@@ -1008,6 +1015,7 @@ int32_t stwr_default_opts(stwr_solver_opts* o) {
   o->gmres_atol = 0.0;
   o->time_chunks = 0;
   o->factor_mfma = 1;
+  o->deterministic = 0;
   return STWR_OK;
 }
 
@@ -1326,7 +1334,8 @@ int32_t stwr_set_opts(stwr_problem* p, const stwr_solver_opts* opts) {
     if (opts->gmres_restart != p->restart) throw StwrError(STWR_ERR_ARG, "gmres_restart is fixed at creation");
     if (opts->smoother_prec != p->opts.smoother_prec)
       for (auto& L : p->lv) { L.fac_prec = -1; L.has_lambda = false; }
-    if (opts->time_chunks != p->opts.time_chunks || opts->smoother_prec != p->opts.smoother_prec)
+    if (opts->time_chunks != p->opts.time_chunks || opts->smoother_prec != p->opts.smoother_prec ||
+        opts->deterministic != p->opts.deterministic)
       for (auto& L : p->lv) L.chunk_choice = 0;
     p->opts = *opts;
     return STWR_OK;

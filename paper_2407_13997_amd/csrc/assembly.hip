@@ -199,7 +199,7 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
                                                  double* __restrict__ Jv, double* __restrict__ Mv) {
   // one workgroup per (cell, slab), slab fastest: consecutive workgroups
   // update the same operator lines (each holds several slabs of a nonzero)
-  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
+  const int c = cell_of(L), n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ CellStage<NQ> S;
   stage_cell<NQ>(L, T, mms, U, c, n, S);
   // temporal Gauss points (q + 3 = NQ + 2, as the reference tables are built):
@@ -245,13 +245,13 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
             const int nz = nzc[15 * (6 * ci + i) + 6 * cj + j];
             if (nz < 0) continue;
             const double v = dt * R * C2[ci][cj] + (ci == cj ? diag : 0.0);
-            atomicAdd(&Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
+            scatter_add(L, &Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
           }
       }
     if (n == 0) {
       for (int ci = 0; ci < 2; ++ci) {
         const int nz = nzc[15 * (6 * ci + i) + 6 * ci + j];
-        if (nz >= 0) atomicAdd(&Mv[nz], Mij);
+        if (nz >= 0) scatter_add(L, &Mv[nz], Mij);
       }
     }
   } else if (tid < 54) {
@@ -267,9 +267,9 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
         for (int ci = 0; ci < 2; ++ci) {
           const double v = -dt * T->W[a][b] * B[ci];
           const int nz1 = nzc[15 * (6 * ci + i) + 12 + j];
-          if (nz1 >= 0) atomicAdd(&Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
+          if (nz1 >= 0) scatter_add(L, &Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
           const int nz2 = nzc[15 * (12 + j) + 6 * ci + i];
-          if (nz2 >= 0) atomicAdd(&Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
+          if (nz2 >= 0) scatter_add(L, &Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
         }
   }
 }
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
                                                  MmsDev mms, const double* __restrict__ U,
                                                  double* __restrict__ F) {
   // slab fastest, as in k_jacobian
-  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
+  const int c = cell_of(L), n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ CellStage<NQ> S;
   __shared__ double pl[3][NQ];
   __shared__ double prev[2][6];
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
     for (int x = 0; x < kQx; ++x) jmp += S.wdet[x] * jq[x][comp] * T->N2[x][i];
     acc += T->e0[a] * jmp;
     const int dof = L.cell_dofs[15 * c + 6 * comp + i];
-    if (dof >= 0) atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], acc);
+    if (dof >= 0) scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], acc);
   } else if (tid >= 32 && tid < 32 + 3 * NQ) {
     const int j = (tid - 32) / NQ, a = (tid - 32) % NQ;
     double acc = 0.0;
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
       acc += T->wg[g] * T->Phi[g][a] * sg;
     }
     const int dof = L.po + L.cells[3 * c + j];
-    atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
+    scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
   }
 }
 
@@ -732,7 +732,7 @@ __global__ __launch_bounds__(64) void k_th_jacobian(LevelView L, const RefTables
                                                     MmsDev mms, const double* __restrict__ U,
                                                     double* __restrict__ Jv, double* __restrict__ Mv) {
   constexpr int NL = 2 * NLV + NLP;
-  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
+  const int c = cell_of(L), n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ ThStage<NQ, NLV> S;
   th_stage<NQ, NLV>(L, T, mms, U, c, n, S);
   constexpr int G = NQ + 2;
@@ -777,13 +777,13 @@ __global__ __launch_bounds__(64) void k_th_jacobian(LevelView L, const RefTables
               const int nz = nzc[NL * (NLV * ci + i) + NLV * cj + j];
               if (nz < 0) continue;
               const double v = dt * R * C2[ci][cj] + (ci == cj ? diag : 0.0);
-              atomicAdd(&Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
+              scatter_add(L, &Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
             }
         }
       if (n == 0) {
         for (int ci = 0; ci < 2; ++ci) {
           const int nz = nzc[NL * (NLV * ci + i) + NLV * ci + j];
-          if (nz >= 0) atomicAdd(&Mv[nz], Mij);
+          if (nz >= 0) scatter_add(L, &Mv[nz], Mij);
         }
       }
     } else {
@@ -799,9 +799,9 @@ __global__ __launch_bounds__(64) void k_th_jacobian(LevelView L, const RefTables
           for (int ci = 0; ci < 2; ++ci) {
             const double v = -dt * T->W[a][b] * B[ci];
             const int nz1 = nzc[NL * (NLV * ci + i) + 2 * NLV + j];
-            if (nz1 >= 0) atomicAdd(&Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
+            if (nz1 >= 0) scatter_add(L, &Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
             const int nz2 = nzc[NL * (2 * NLV + j) + NLV * ci + i];
-            if (nz2 >= 0) atomicAdd(&Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
+            if (nz2 >= 0) scatter_add(L, &Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
           }
     }
   }
@@ -811,7 +811,7 @@ template <int NQ, int NLV, int NLP>
 __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables* __restrict__ T,
                                                     MmsDev mms, const double* __restrict__ U,
                                                     double* __restrict__ F) {
-  const int c = blockIdx.x / L.N, n = blockIdx.x % L.N, tid = threadIdx.x;
+  const int c = cell_of(L), n = blockIdx.x % L.N, tid = threadIdx.x;
   __shared__ ThStage<NQ, NLV> S;
   __shared__ double pl[NLP][NQ];
   __shared__ double prev[2][NLV];
@@ -907,7 +907,7 @@ __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables
       for (int x = 0; x < kQx; ++x) jmp += S.wdet[x] * jq[x][comp] * T->Nk[x][i];
       acc += T->e0[a] * jmp;
       const int dof = L.cell_dofs[NL * c + NLV * comp + i];
-      if (dof >= 0) atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], acc);
+      if (dof >= 0) scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], acc);
     } else {
       const int t = e - 2 * NLV * NQ, j = t / NQ, a = t % NQ;
       double acc = 0.0;
@@ -918,7 +918,7 @@ __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables
         acc += T->wg[g] * T->Phi[g][a] * sg;
       }
       const int dof = L.po + L.cell_pn[NLP * c + j];
-      atomicAdd(&F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
+      scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
     }
   }
 }
@@ -1012,30 +1012,54 @@ hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, c
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
-                                    const double* U, double* Jv, double* Mv, hipStream_t s) {
-  dim3 grid((unsigned)((int64_t)L.nc * L.N));
-  if (L.thk == kThK) {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_th_jacobian<1, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
-    else hipLaunchKernelGGL((k_th_jacobian<2, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
+// One launch over every cell (atomic additions), or, with color_ptr (host,
+// 9 offsets into L.color_cells), one launch per colour in colour order.
+template <typename F>
+static hipError_t by_colour(const LevelView& L, const int* color_ptr, F launch) {
+  if (!color_ptr) {
+    launch(L, dim3((unsigned)((int64_t)L.nc * L.N)));
     return hipGetLastError();
   }
-  if (L.NQ == 1) hipLaunchKernelGGL(k_jacobian<1>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
-  else hipLaunchKernelGGL(k_jacobian<2>, grid, dim3(64), 0, s, L, tab, mms, U, Jv, Mv);
-  return hipGetLastError();
+  for (int k = 0; k < 8; ++k) {
+    const int cnt = color_ptr[k + 1] - color_ptr[k];
+    if (cnt == 0) continue;
+    LevelView Lc = L;
+    Lc.det = 1;
+    Lc.color_first = color_ptr[k];
+    launch(Lc, dim3((unsigned)((int64_t)cnt * L.N)));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
+                                    const double* U, double* Jv, double* Mv, const int* color_ptr,
+                                    hipStream_t s) {
+  return by_colour(L, color_ptr, [&](const LevelView& Lc, dim3 grid) {
+    if (L.thk == kThK) {
+      if (L.NQ == 1) hipLaunchKernelGGL((k_th_jacobian<1, kThNlv, kThNlp>), grid, dim3(64), 0, s, Lc, tab, mms, U, Jv, Mv);
+      else hipLaunchKernelGGL((k_th_jacobian<2, kThNlv, kThNlp>), grid, dim3(64), 0, s, Lc, tab, mms, U, Jv, Mv);
+    } else if (L.NQ == 1) {
+      hipLaunchKernelGGL(k_jacobian<1>, grid, dim3(64), 0, s, Lc, tab, mms, U, Jv, Mv);
+    } else {
+      hipLaunchKernelGGL(k_jacobian<2>, grid, dim3(64), 0, s, Lc, tab, mms, U, Jv, Mv);
+    }
+  });
 }
 
 hipError_t launch_assemble_residual(const LevelView& L, const RefTables* tab, MmsDev mms,
-                                    const double* U, double* F, hipStream_t s) {
-  dim3 grid((unsigned)((int64_t)L.nc * L.N));
-  if (L.thk == kThK) {
-    if (L.NQ == 1) hipLaunchKernelGGL((k_th_residual<1, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, F);
-    else hipLaunchKernelGGL((k_th_residual<2, kThNlv, kThNlp>), grid, dim3(64), 0, s, L, tab, mms, U, F);
-    return hipGetLastError();
-  }
-  if (L.NQ == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(64), 0, s, L, tab, mms, U, F);
-  else hipLaunchKernelGGL(k_residual<2>, grid, dim3(64), 0, s, L, tab, mms, U, F);
-  return hipGetLastError();
+                                    const double* U, double* F, const int* color_ptr, hipStream_t s) {
+  return by_colour(L, color_ptr, [&](const LevelView& Lc, dim3 grid) {
+    if (L.thk == kThK) {
+      if (L.NQ == 1) hipLaunchKernelGGL((k_th_residual<1, kThNlv, kThNlp>), grid, dim3(64), 0, s, Lc, tab, mms, U, F);
+      else hipLaunchKernelGGL((k_th_residual<2, kThNlv, kThNlp>), grid, dim3(64), 0, s, Lc, tab, mms, U, F);
+    } else if (L.NQ == 1) {
+      hipLaunchKernelGGL(k_residual<1>, grid, dim3(64), 0, s, Lc, tab, mms, U, F);
+    } else {
+      hipLaunchKernelGGL(k_residual<2>, grid, dim3(64), 0, s, Lc, tab, mms, U, F);
+    }
+  });
 }
 
 }  // namespace stwr

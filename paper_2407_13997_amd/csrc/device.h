@@ -61,7 +61,29 @@ struct LevelView {
   int thk, n3, nlv, nlp;
   const int* cell_vn;
   const int* cell_pn;
+  // deterministic assembly: the cells dealt into 8 colours, no two cells of a
+  // colour sharing a vertex (so no DoF), colour by colour (color_cells, nc
+  // entries); an assembly launch covers one colour from color_first and adds
+  // with plain read-modify-writes (det = 1) instead of FP64 atomics (det = 0,
+  // every cell in one launch)
+  const int* color_cells;
+  int color_first, det;
 };
+
+// cell of the calling workgroup of an assembly launch (one workgroup per
+// (cell, slab), slab fastest)
+__device__ __forceinline__ int cell_of(const LevelView& L) {
+  const int k = blockIdx.x / L.N;
+  return L.det ? L.color_cells[L.color_first + k] : k;
+}
+// a cell's contribution to an assembled entry: atomic when every cell is in
+// one launch, a plain addition when the launch holds one colour (no other
+// workgroup of the launch writes the entry, and the colours run in a fixed
+// order, so the sums come out the same bit for bit every run)
+__device__ __forceinline__ void scatter_add(const LevelView& L, double* p, double v) {
+  if (L.det) *p += v;
+  else atomicAdd(p, v);
+}
 
 // Time chunks of one sweep (see k_patch_sweep): chunk c covers slabs
 // [c len, min(N, (c+1) len)); outputs are written for chunks <= y_max;
@@ -184,10 +206,14 @@ __device__ inline T wave_max(T v) {
 }
 
 // ---- assembly ---------------------------------------------------------------
+// color_ptr: null for one launch over every cell with FP64 atomic additions,
+// or the host copy of the 9 colour offsets into L.color_cells for the
+// deterministic colour-by-colour assembly.
 hipError_t launch_assemble_jacobian(const LevelView& L, const RefTables* tab, MmsDev mms,
-                                    const double* U, double* Jv, double* Mv, hipStream_t s);
+                                    const double* U, double* Jv, double* Mv, const int* color_ptr,
+                                    hipStream_t s);
 hipError_t launch_assemble_residual(const LevelView& L, const RefTables* tab, MmsDev mms,
-                                    const double* U, double* F, hipStream_t s);
+                                    const double* U, double* F, const int* color_ptr, hipStream_t s);
 // out[0] = squared space-time velocity L2 error; part: nc * N doubles of workspace
 hipError_t launch_velocity_error(const LevelView& L, const RefTables* tab, MmsDev mms,
                                  const double* U, double* part, double* out, hipStream_t s);

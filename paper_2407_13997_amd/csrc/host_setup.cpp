@@ -261,6 +261,14 @@ static void mesh_cells(HostLevel& L) {
       for (int s = 0; s < 2; ++s)
         for (int k = 0; k < 3; ++k) L.cells[3 * (c0 + s) + k] = tri[s][k];
     }
+  auto colour = [&](int c) { const int sq = c / 2, i = sq % M, j = sq / M; return (i & 1) + 2 * (j & 1) + 4 * (c & 1); };
+  for (int k = 0; k < 9; ++k) L.color_ptr[k] = 0;
+  for (int c = 0; c < L.nc; ++c) ++L.color_ptr[colour(c) + 1];
+  for (int k = 0; k < 8; ++k) L.color_ptr[k + 1] += L.color_ptr[k];
+  L.color_cells.assign(L.nc, 0);
+  int fill[8];
+  for (int k = 0; k < 8; ++k) fill[k] = L.color_ptr[k];
+  for (int c = 0; c < L.nc; ++c) L.color_cells[fill[colour(c)]++] = c;
 }
 
 // ---------------------------------------------------------------------------

@@ -95,6 +95,13 @@ struct HostLevel {
   // cell_vn / cell_pn, cell_dofs = [x DoFs of the nlv nodes, y DoFs, pressure]
   int thk = 0, n3 = 0, nlv = 0, nlp = 0;
   std::vector<int> cell_vn, cell_pn;
+  // the cells in 8 colours, colour (i mod 2) + 2 (j mod 2) + 4 t for triangle
+  // t of square (i, j): two cells of one colour are triangles of the same
+  // orientation in squares at least two apart in i or in j, so they share no
+  // vertex and no DoF.  color_cells lists the cells colour by colour
+  // (ascending within a colour); colour k starts at color_ptr[k].
+  std::vector<int> color_cells;
+  int color_ptr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 void build_level(int M, HostLevel& L);

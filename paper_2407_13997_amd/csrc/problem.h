@@ -123,6 +123,7 @@ struct Level {
   std::vector<int> order;   // host copy of the patch order (pview.order)
   // device arrays
   int *cell_vn = nullptr, *cell_pn = nullptr;   // Taylor-Hood P3-P2 lattice nodes of the cells
+  int* color_cells = nullptr;                    // the cells colour by colour (deterministic assembly)
   int *row_ptr = nullptr, *col = nullptr, *cells = nullptr, *cell_p2 = nullptr,
       *cell_dofs = nullptr, *cell_nz = nullptr, *node_free = nullptr, *node_cell_ptr = nullptr,
       *node_cell = nullptr;

@@ -55,6 +55,29 @@ static void check_level(const HostLevel& L) {
   }
 }
 
+// deterministic assembly colours: every cell in exactly one colour, and no
+// DoF written by two cells of one colour (cell_dofs, nd per cell)
+static void check_colours(const HostLevel& L, int nd) {
+  CHECK(L.color_ptr[0] == 0 && L.color_ptr[8] == L.nc);
+  std::vector<int> seen(L.nc, 0);
+  for (int k = 0; k < 8; ++k) {
+    CHECK(L.color_ptr[k] <= L.color_ptr[k + 1]);
+    std::vector<int> owner(L.nf, -1);
+    for (int e = L.color_ptr[k]; e < L.color_ptr[k + 1]; ++e) {
+      const int c = L.color_cells[e];
+      CHECK(c >= 0 && c < L.nc);
+      seen[c]++;
+      for (int i = 0; i < nd; ++i) {
+        const int d = L.cell_dofs[(size_t)nd * c + i];
+        if (d < 0) continue;
+        CHECK(owner[d] == -1 || owner[d] == c);
+        owner[d] = c;
+      }
+    }
+  }
+  for (int c = 0; c < L.nc; ++c) CHECK(seen[c] == 1);
+}
+
 static void check_transfer(const HostLevel& F, const HostLevel& C, const HostTransfer& T, bool unit_rows) {
   for (int r = 0; r < F.nf; ++r) {
     double s = 0.0;
@@ -76,6 +99,13 @@ int main() {
     build_transfer(F, C, T);
     check_level(F);
     check_level(C);
+    check_colours(F, 15);
+    check_colours(C, 15);
+    {
+      HostLevel Ft;
+      build_level_th(M, 2, Ft);
+      check_colours(Ft, (int)(Ft.cell_dofs.size() / Ft.nc));
+    }
     // velocity rows away from the boundary and pressure rows interpolate constants
     check_transfer(F, C, T, false);
     for (int k = 1; k <= 3; ++k) {
