@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--largest-solve", type=int, default=0,
                     help="also run the 128x128 Newton solve with this many levels (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
+    ap.add_argument("--paper-run", default=None,
+                    help="only solve this one of the paper's runs and print its record (for profiling): "
+                         "chorin_q<q>_n<N>, chorin_p3p2_q<q>_n<N> or cavity_m<M>_q<q>_r<R>")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -159,6 +162,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.paper_run:
+        print(json.dumps({"paper_run": paper_run(args.paper_run)}), flush=True)
+        return
     prob = w.named_problem(w.LARGE)
     if (args.mesh, args.slabs, args.levels) != (128, 64, 6):
         prob = w.Problem(args.mesh, args.levels, 1, args.slabs, 1.0, 1000.0,
@@ -426,6 +432,31 @@ def _timed_newton(ctx, prob):
     err = P.velocity_l2_error(U) if prob.flow != 2 else None
     P.close()
     return st, dt, err
+
+
+def paper_run(name: str) -> dict:
+    """One of the paper's runs by name, as paper_context runs it: the Chorin
+    problem on 80 x 80 (P2-P1 from four levels, P3-P2 from four, five at
+    q = 1) or the lid-driven cavity (M = 40 from three levels, 80 from four;
+    20 slabs)."""
+    import re
+    import stwr_workloads as w
+    from paper_2407_13997_amd import binding
+    m = re.fullmatch(r"chorin(_p3p2)?_q([01])_n(\d+)", name)
+    if m:
+        p3, q, N = m.group(1) is not None, int(m.group(2)), int(m.group(3))
+        prob = w.chorin_problem(80, 5 if (p3 and q == 1) else 4, q, N, nodes=1, degree=2 if p3 else 1)
+    else:
+        m = re.fullmatch(r"cavity_m(40|80)_q([01])_r(\d+)", name)
+        if not m:
+            raise SystemExit(f"unknown paper run {name!r}")
+        M, q, R = int(m.group(1)), int(m.group(2)), float(m.group(3))
+        prob = w.cavity_problem(M, 3 if M == 40 else 4, q, 20, R)
+    ctx = binding.Context(0)
+    st, dt, err = _timed_newton(ctx, prob)
+    ctx.close()
+    return {"run": name, "st_dofs": prob.n_st, "time_s": dt, "error": err, "newton": st["newton"],
+            "linear": list(st["linear"])}
 
 
 def paper_context() -> dict:

@@ -133,24 +133,32 @@ struct PatchView {
 // lanes 4 rr + s, lane s taking local panels s, s + 4, ..., stored as (k, lane)
 // at PH_w r1 VW + (k * 4 r2 + lane) * VW, k < ceil(PH_w / 4).  Padding is zero.
 // FP32 blocks (at most 20 panels) go to one wavefront; FP64 blocks are dealt
-// ten panels per wavefront.
+// ten panels per wavefront.  The FP32 block of an interior q = 1 patch (m =
+// 2 nb = 78) stores the rows r < r1 of its last panel two columns wide
+// (8-byte loads at (P - 1) r1 4 + 2 r), so that only the rows past 64 carry
+// padding: 6,112 floats instead of 6,240.
 __host__ __device__ constexpr int panels_per_wave(int vw) { return vw == 4 ? 20 : 10; }
 
 struct BlockLayout {
-  int m, VW, P, r1, r2, waves, ppw;
+  int m, VW, P, r1, r2, waves, ppw, wl;   // wl: width of the rows r < r1 of the last panel
   __host__ __device__ BlockLayout(int m_, int vw_) : m(m_), VW(vw_) {
     ppw = panels_per_wave(VW);
     P = (m + VW - 1) / VW;
     r1 = m < 64 ? m : 64;
     r2 = m - r1;
     waves = (P + ppw - 1) / ppw;
+    wl = (VW == 4 && m == 2 * kMaxNb) ? 2 : VW;
   }
+  __host__ __device__ bool half() const { return wl != VW; }
   __host__ __device__ int panels(int w) const {
     const int p = P - w * ppw;
     return p < 0 ? 0 : (p > ppw ? ppw : p);
   }
   __host__ __device__ int k2(int w) const { return r2 > 0 ? (panels(w) + 3) / 4 : 0; }
-  __host__ __device__ int share(int w) const { return (panels(w) * r1 + k2(w) * 4 * r2) * VW; }
+  // elements of the rows r < r1 of wavefront w's panels (the last wavefront
+  // holds the last panel)
+  __host__ __device__ int part1(int w) const { return panels(w) * r1 * VW - (w == waves - 1 ? r1 * (VW - wl) : 0); }
+  __host__ __device__ int share(int w) const { return part1(w) + k2(w) * 4 * r2 * VW; }
   __host__ __device__ int offset(int w) const {
     int o = 0;
     for (int v = 0; v < w; ++v) o += share(v);
@@ -160,9 +168,9 @@ struct BlockLayout {
   // element offset of (r, c), r, c < m
   __host__ __device__ int at(int r, int c) const {
     const int q = c / VW, w = q / ppw, ql = q % ppw;
-    if (r < r1) return offset(w) + (ql * r1 + r) * VW + c % VW;
+    if (r < r1) return offset(w) + ql * r1 * VW + r * (q == P - 1 ? wl : VW) + c % VW;
     const int lane = (r - 64) * 4 + ql % 4, k = ql / 4;
-    return offset(w) + panels(w) * r1 * VW + (k * 4 * r2 + lane) * VW + c % VW;
+    return offset(w) + part1(w) + (k * 4 * r2 + lane) * VW + c % VW;
   }
 };
 

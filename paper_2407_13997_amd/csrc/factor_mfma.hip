@@ -193,7 +193,8 @@ __device__ __forceinline__ void factor_block_mfma(const LevelView& L, const Patc
   // undo the column permutation of the pivoting (the swaps (k, perm[k]) for
   // k = m-1 .. 0): output column pos(c) receives A's column c, and ofs[pos]
   // records c.  Then every (row, four-column panel) of the layout is one
-  // 16-byte store, consecutive lanes on consecutive rows.
+  // 16-byte store (8-byte in a narrow last panel), consecutive lanes on
+  // consecutive rows.
   for (int c = lane; c < m; c += 64) {
     int pos = c;
     for (int k = m - 1; k >= 0; --k) {
@@ -214,7 +215,12 @@ __device__ __forceinline__ void factor_block_mfma(const LevelView& L, const Patc
     v.y = 4 * q + 1 < m ? A[r * kFS + ofs[4 * q + 1]] : 0.0f;
     v.z = 4 * q + 2 < m ? A[r * kFS + ofs[4 * q + 2]] : 0.0f;
     v.w = 4 * q + 3 < m ? A[r * kFS + ofs[4 * q + 3]] : 0.0f;
-    *reinterpret_cast<float4*>(out + lay.at(r, 4 * q)) = v;
+    if (r < 64 && q == lay.P - 1 && lay.half()) {
+      // the narrow last panel of the rows below 64: its two columns only
+      *reinterpret_cast<float2*>(out + lay.at(r, 4 * q)) = make_float2(v.x, v.y);
+    } else {
+      *reinterpret_cast<float4*>(out + lay.at(r, 4 * q)) = v;
+    }
   }
 }
 

@@ -61,6 +61,13 @@ __device__ inline float4 load_stream(const GLOBAL_AS float* p) {
   const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL_AS f32x4*>(p));
   return make_float4(t.x, t.y, t.z, t.w);
 }
+// 8 bytes (two floats) of a narrow last panel, as a 16-byte panel value
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ inline float4 load_stream2(const GLOBAL_AS float* p) {
+  const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL_AS f32x2*>(p));
+  return make_float4(t.x, t.y, 0.0f, 0.0f);
+}
+
 // the same for 16 bytes of T (four floats or two doubles), as a vector
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T>
@@ -302,11 +309,16 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
           if (c < m) out[ofs1[c] + i * VW] = a[r][q];
         }
       } else {
-        const int rofs = i < 64 ? i * VW : (i - 64) * 4 * VW;
+        // rows < 64 step VW per row, or the last panel's width wl when it is
+        // narrow (its columns start at (P - 1) r1 VW); rows >= 64 step 4 VW
+        const int last0 = (lay.P - 1) * lay.r1 * VW;
 #pragma unroll
         for (int q = 0; q < MAXM; ++q) {
           const int c = (q + m) % MAXM;
-          if (c < m) out[(i < 64 ? ofs1[c] : ofs2[c]) + rofs] = a[r][q];
+          if (c < m) {
+            const int o = i < 64 ? ofs1[c] + i * (ofs1[c] >= last0 ? lay.wl : VW) : ofs2[c] + (i - 64) * 4 * VW;
+            out[o] = a[r][q];
+          }
         }
       }
     }
@@ -442,11 +454,16 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   const int64_t SS = P.slab_stride;
   GLOBAL_AS float* yout = gptr(Y) + 2 * gptr(P.y_off)[p];   // FP32 outputs at the byte offset of the FP64 layout,
                                                             // [patch DoF][slab][node]
+  // a narrow last panel (m = 2 mod 4): its rows below 64 are two columns
+  // wide, 8-byte loads at baseh, and the rows past 64 start right after them
+  constexpr bool kHalfF = MAXM % 4 == 2;
+  const bool half = FULL && kHalfF;
   const unsigned row1 = lane < r1 ? lane : 0;
   const unsigned base1 = row1 * VW, step1 = r1 * VW;
-  const unsigned lane2 = lane < 4 * r2 ? lane : 0;
-  const unsigned base2 = PH * r1 * VW + lane2 * VW, step2 = 4 * r2 * VW;
   const int lastq = PH - 1, lastk = nk2 > 0 ? nk2 - 1 : 0;
+  const unsigned baseh = lastq * step1 + row1 * 2;
+  const unsigned lane2 = lane < 4 * r2 ? lane : 0;
+  const unsigned base2 = (half ? lastq * r1 * VW + r1 * 2 : PH * r1 * VW) + lane2 * VW, step2 = 4 * r2 * VW;
   const int rowA = lane, rowB = lane + 64;
   const bool hasA = rowA < m, hasB = kTwo && rowB < m;
   const int iA = rowA / NQ, iB = rowB / NQ;
@@ -460,8 +477,13 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
     const GLOBAL_AS float* blk = Ab + (int64_t)n * SS;
 #pragma unroll
     for (int q = 0; q < MAXP; ++q) {
-      const unsigned qq = FULL ? q : (q < lastq ? q : lastq);
-      a1[q] = load_stream(blk + base1 + qq * step1);
+      if constexpr (FULL) {
+        if (kHalfF && q == MAXP - 1) a1[q] = load_stream2(blk + baseh);
+        else a1[q] = load_stream(blk + base1 + q * step1);
+      } else {
+        // the smaller blocks have full-width panels
+        a1[q] = load_stream(blk + base1 + (q < lastq ? q : lastq) * step1);
+      }
     }
     if constexpr (kTwo) {
 #pragma unroll
@@ -771,13 +793,25 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   // this lane's load offsets inside a block (clamped to valid elements)
   const int wbase = lay.offset(w);
   const int row1 = lane < r1 ? lane : 0;
-  const int off2 = wbase + PH * r1 * VW;
+  const int off2 = wbase + lay.part1(w);
+  // FP32 blocks with a narrow last panel: 8-byte loads of its rows below 64
+  const bool halfw = lay.half() && w == lay.waves - 1;
+  const int baseh = wbase + (PH - 1) * r1 * VW + row1 * 2;
   const int lane2 = lane < 4 * r2 ? lane : 0;
   // element offsets: region 1 = base1 + q * step1 (q < PH), region 2 = base2 + k * step2
   const int base1 = wbase + row1 * VW, step1 = r1 * VW;
   const int base2 = off2 + lane2 * VW, step2 = 4 * r2 * VW, nk2 = lay.k2(w);
 #define O1(q) ((q) < PH ? base1 + (q) * step1 : 0)
 #define O2(k) ((kTwo && (k) < nk2) ? base2 + (k) * step2 : 0)
+  auto ld1 = [&](const T* blk, int q) -> V {
+    if constexpr (sizeof(T) == 4) {
+      if (halfw && q == PH - 1) {
+        const float2 t = *reinterpret_cast<const float2*>(blk + baseh);
+        return make_float4(t.x, t.y, 0.0f, 0.0f);
+      }
+    }
+    return *reinterpret_cast<const V*>(blk + O1(q));
+  };
   // the row whose right-hand side this thread forms (threads past the block
   // read row 0's residual and discard it)
   const bool hasRow = tid < m;
@@ -789,7 +823,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
   {
     const T* blk0 = Ab + (int64_t)n0 * S;
 #pragma unroll
-    for (int q = 0; q < PWU; ++q) cur1[q] = *reinterpret_cast<const V*>(blk0 + O1(q));
+    for (int q = 0; q < PWU; ++q) cur1[q] = ld1(blk0, q);
     if constexpr (kTwo) {
 #pragma unroll
       for (int k = 0; k < K2; ++k) cur2[k] = *reinterpret_cast<const V*>(blk0 + O2(k));
@@ -834,7 +868,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
     if constexpr (!INV) {
       const T* nblk = Ab + (int64_t)(n + 1 < n1 ? n + 1 : n) * S;
 #pragma unroll
-      for (int q = 0; q < PWU; ++q) nxt1[q] = *reinterpret_cast<const V*>(nblk + O1(q));
+      for (int q = 0; q < PWU; ++q) nxt1[q] = ld1(nblk, q);
       if constexpr (kTwo) {
 #pragma unroll
         for (int k = 0; k < K2; ++k) nxt2[k] = *reinterpret_cast<const V*>(nblk + O2(k));

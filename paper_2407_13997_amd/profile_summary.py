@@ -23,18 +23,18 @@ def short(name: str) -> str:
 
 def kernel_stats(db: str, by_grid: bool):
     con = sqlite3.connect(db)
-    grid = "grid_x * grid_y * grid_z" if by_grid else "0"
+    grid, group = ("grid_x * grid_y * grid_z", "name, 2") if by_grid else ("0", "name")
     rows = con.execute(f"select name, {grid}, count(*), sum(end - start), avg(end - start), min(end - start), "
-                       f"max(end - start) from kernels group by name, {grid} "
+                       f"max(end - start) from kernels group by {group} "
                        "order by sum(end - start) desc").fetchall()
     return [(short(r[0]),) + tuple(r[1:]) for r in rows]
 
 
 def pmc_stats(db: str, by_grid: bool):
     con = sqlite3.connect(db)
-    grid = "grid_size" if by_grid else "0"
+    grid, group = ("grid_size", "kernel_name, 2, counter_name") if by_grid else ("0", "kernel_name, counter_name")
     rows = con.execute(f"select kernel_name, {grid}, counter_name, count(*), avg(value), min(value), max(value) "
-                       f"from counters_collection group by kernel_name, {grid}, counter_name "
+                       f"from counters_collection group by {group} "
                        "order by kernel_name").fetchall()
     return [(short(r[0]),) + tuple(r[1:]) for r in rows]
 
