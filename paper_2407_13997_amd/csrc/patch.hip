@@ -162,14 +162,32 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
     const int i = tid + TPB * r;
     const int ii = i < m ? i : 0;
     const int* nzr = nzp + (ii / NQ) * nb;
+    // the row's CSR positions CK patch DoFs at a time, then their entries:
+    // every load unconditional (clamped), the zeros selected afterwards, so
+    // a chunk's loads are in flight together instead of one index-then-entry
+    // round trip per entry
+    constexpr int CK = MAXM > 100 ? 4 : 8;   // fewer loads in flight where the row fills the registers
+    const double* jrow = Jv + (int64_t)n * NQ * NQ + (ii % NQ) * NQ;
 #pragma unroll
-    for (int c = 0; c < MAXM; ++c) {
-      T v = (T)0;
-      if (i < m && c < m) {
-        const int k = nzr[c / NQ];
-        if (k >= 0) v = (T)Jv[(((int64_t)k * L.N + n) * NQ + ii % NQ) * NQ + c % NQ];
+    for (int b0 = 0; b0 < NBMAX; b0 += CK) {
+      int kk[CK];
+#pragma unroll
+      for (int b = 0; b < CK; ++b) kk[b] = b0 + b < NBMAX ? nzr[b0 + b < nb ? b0 + b : 0] : -1;
+#pragma unroll
+      for (int b = 0; b < CK; ++b) {
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) {
+          const int c = (b0 + b) * NQ + e;
+          if (c < MAXM) {
+            const bool ok = i < m && c < m && kk[b] >= 0;
+            const double v = jrow[(int64_t)(ok ? kk[b] : 0) * L.N * NQ * NQ + e];
+            a[r][c] = ok ? (T)v : (T)0;
+          }
+        }
       }
-      a[r][c] = v;
+      // one chunk's loads at a time: hoisting every chunk's loads ahead
+      // would need as many registers again as the row itself
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   for (int k = 0; k < m; ++k) {
@@ -249,19 +267,28 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
       for (int r = 0; r < RPL; ++r)
         if (live[r]) a[r][0] = -f[r] * p0;
     }
-    // one column at a time, so that each pivot-row value is read just
-    // before its use
+    // the pivot row in batches of EB 16-byte reads: a batch's reads are in
+    // flight together, so a step waits for the LDS once per batch instead of
+    // once per 16 bytes (with one or two wavefronts per SIMD nothing else
+    // hides that latency), while the batch's registers stay few
+    constexpr int EB = MAXM > 100 ? 2 : 8;
 #pragma unroll
-    for (int j0 = 0; j0 < MP; j0 += RV) {
-      const V16 v = *reinterpret_cast<const V16*>(prow + j0);
-      const T* pj = reinterpret_cast<const T*>(&v);
+    for (int j0 = 0; j0 < MP; j0 += RV * EB) {
+      V16 v[EB];
 #pragma unroll
-      for (int t = 0; t < RV; ++t) {
-        const int j = j0 + t;
-        if (j >= 1 && j < MAXM) {
+      for (int b = 0; b < EB; ++b)
+        if (j0 + b * RV < MP) v[b] = *reinterpret_cast<const V16*>(prow + j0 + b * RV);
 #pragma unroll
-          for (int r = 0; r < RPL; ++r)
-            if (live[r]) a[r][j] -= f[r] * pj[t];
+      for (int b = 0; b < EB; ++b) {
+        const T* pj = reinterpret_cast<const T*>(&v[b]);
+#pragma unroll
+        for (int t = 0; t < RV; ++t) {
+          const int j = j0 + b * RV + t;
+          if (j >= 1 && j < MAXM) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+              if (live[r]) a[r][j] -= f[r] * pj[t];
+          }
         }
       }
     }
