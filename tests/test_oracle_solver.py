@@ -157,6 +157,34 @@ def test_newton_with_eisenstat_walker_reaches_the_exact_solution():
     assert eta[-1] < eta[0]
 
 
+def test_eisenstat_walker_forcing_gives_newton_order_golden_ratio():
+    """The forcing terms pinned by what they do, not by their formula:
+    Eisenstat and Walker's choice 2 with exponent (1 + sqrt 5) / 2 makes an
+    inexact Newton iteration whose linear solves leave exactly the relative
+    residual eta_k converge with q-order (1 + sqrt 5) / 2 (SIAM J. Sci.
+    Comput. 17, 1996).  On x^3 = 2 in 200-digit arithmetic the observed order
+    log(e_k+1 / e_k) / log(e_k / e_k-1) settles at the golden ratio to 1e-9;
+    a fixed tolerance would give order 1, exact solves order 2, another
+    exponent that exponent.  A growing residual is capped at eta_max = 0.9."""
+    import decimal
+    from oracle.multigrid import ew_forcing
+    ctx = decimal.Context(prec=200)
+    D = ctx.create_decimal
+    root = ctx.power(D(2), ctx.divide(D(1), D(3)))
+    x, fprev, eta, errs = D("2.0"), None, 0.0, []
+    for k in range(12):
+        fx = ctx.subtract(ctx.power(x, 3), D(2))
+        eta = ew_forcing(k, float(abs(fx)), float(fprev) if fprev is not None else 1.0, eta)
+        x = ctx.subtract(x, ctx.multiply(ctx.subtract(D(1), D(eta)), ctx.divide(fx, ctx.multiply(D(3), ctx.power(x, 2)))))
+        fprev = abs(fx)
+        errs.append(abs(ctx.subtract(x, root)))
+    e = [float(v) for v in errs]
+    orders = [np.log(e[k] / e[k - 1]) / np.log(e[k - 1] / e[k - 2]) for k in range(9, 12)]
+    phi = (1 + 5 ** 0.5) / 2
+    assert all(abs(o - phi) < 1e-9 for o in orders), orders
+    assert ew_forcing(3, 2.0, 1.0, 0.5) == 0.9
+
+
 def _interpolant(level, prob_mms):
     """Free space-time vector of the nodal interpolant of the manufactured
     velocity and of the pressure p(t, x, y) = cos(x + 2 y + t) on a level."""
