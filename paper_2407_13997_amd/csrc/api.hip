@@ -193,7 +193,7 @@ uint64_t level_bytes(const HostLevel& H, const HostTransfer* T, int N, int NQ, i
   } else {
     const int64_t mm = (int64_t)H.nf * NQ + (H.po < H.nf ? NQ : 0);
     const int64_t cs = fac_slabs_of(H, N);
-    b += (uint64_t)cs * mm * mm * 8 + (uint64_t)cs * mm * 12 + mm * 8 + (mm > kCoarseSmall ? (uint64_t)cs * 32 * mm * 8 : 0);
+    b += (uint64_t)cs * mm * mm * 8 + (uint64_t)cs * mm * 12 + mm * 8 + (mm > kCoarseSmall ? (uint64_t)cs * kRbufRows * mm * 8 : 0);
   }
   if (T) b += (T->p_col.size() + T->r_col.size()) * 12 + (T->p_ptr.size() + T->r_ptr.size()) * 4;
   return b;
@@ -344,7 +344,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
     L.gbuf = P->alloc<double>((size_t)L.coarse_mm);
     L.perm = P->alloc<int>(cs * L.coarse_mm);
     L.colbuf = P->alloc<double>(cs * L.coarse_mm);
-    if (L.coarse_mm > kCoarseSmall) L.rbuf = P->alloc<double>(cs * 32 * L.coarse_mm);
+    if (L.coarse_mm > kCoarseSmall) L.rbuf = P->alloc<double>(cs * kRbufRows * L.coarse_mm);
   }
 }
 
@@ -453,7 +453,7 @@ void patch_factor_big(stwr_problem* P, Level& L, int prec) {
   int mmax = 0;
   for (int v = 0; v < L.H.nv; ++v) mmax = std::max(mmax, (L.H.patch_ptr[v + 1] - L.H.patch_ptr[v]) * L.NQ);
   const int64_t nblocks = (int64_t)L.H.nv * L.pview.fac_slabs;
-  const size_t per = (size_t)mmax * mmax * 8 + (size_t)mmax * 12 + (size_t)32 * mmax * 8;
+  const size_t per = (size_t)mmax * mmax * 8 + (size_t)mmax * 12 + (size_t)kRbufRows * mmax * 8;
   const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>({nblocks, (int64_t)((size_t(1) << 30) / per), 32768}));
   double *B = nullptr, *colbuf = nullptr, *rbuf = nullptr;
   int* perm = nullptr;
@@ -465,7 +465,7 @@ void patch_factor_big(stwr_problem* P, Level& L, int prec) {
   try {
     HIPCHK(hipMalloc(&B, (size_t)chunk * mmax * mmax * 8));
     HIPCHK(hipMalloc(&colbuf, (size_t)chunk * mmax * 8));
-    HIPCHK(hipMalloc(&rbuf, (size_t)chunk * 32 * mmax * 8));
+    HIPCHK(hipMalloc(&rbuf, (size_t)chunk * kRbufRows * mmax * 8));
     HIPCHK(hipMalloc(&perm, (size_t)chunk * mmax * 4));
     for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
       const int cnt = (int)std::min<int64_t>(chunk, nblocks - b0);

@@ -372,8 +372,10 @@ int patch_factor_mfma_batch_occupancy();
 // workgroup; larger ones by the blocked, chip-wide kernels.
 constexpr int kCoarseSmall = 64;
 hipError_t launch_coarse_build(const LevelView& L, const double* Jv, double* B, hipStream_t s);
-// perm: nmat * m ints, colbuf: nmat * m doubles, rbuf: nmat * 32 * m doubles of
-// workspace (used when m > kCoarseSmall; rbuf = NULL selects the unblocked form)
+// perm: nmat * m ints, colbuf: nmat * m doubles, rbuf: nmat * kRbufRows * m
+// doubles of workspace (the panel rows of two panels; used when m >
+// kCoarseSmall; rbuf = NULL selects the unblocked form)
+constexpr int kRbufRows = 64;
 hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* perm,
                                 double* colbuf, double* rbuf, hipStream_t s);
 // gbuf: nf (q+1) + nbord doubles of workspace (used for large coarsest levels)

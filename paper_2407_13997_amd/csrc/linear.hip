@@ -385,13 +385,14 @@ constexpr int kGjPanel8 = 10;   // 3072 < m <= kMaxCoarse
 static_assert(kGjPanel8 <= kGjPanel6 && kGjPanel4 <= kGjPanel, "the update's staging bounds the narrow panels");
 
 // Row swaps of the panel applied to every non-panel column, then the panel
-// rows of those columns copied to R (kGjPanel x m per matrix).
+// rows of those columns copied to R (rows roff.. of the rstride elements of
+// each matrix's R).
 __global__ __launch_bounds__(kBlock) void k_bgj_swap(int m, int k0, int k1, double* __restrict__ Ball,
                                                      const int* __restrict__ perm,
-                                                     double* __restrict__ Rall) {
+                                                     double* __restrict__ Rall, int64_t rstride, int roff) {
   double* B = Ball + (int64_t)blockIdx.y * m * m;
   const int* pm = perm + (int64_t)blockIdx.y * m;
-  double* R = Rall + (int64_t)blockIdx.y * kGjPanel * m;
+  double* R = Rall + (int64_t)blockIdx.y * rstride + (int64_t)roff * m;
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= m || (j >= k0 && j < k1)) return;
   for (int k = k0; k < k1; ++k) {
@@ -406,57 +407,119 @@ __global__ __launch_bounds__(kBlock) void k_bgj_swap(int m, int k0, int k1, doub
 }
 
 // A[i][j] += sum_t W[i][t] R[t][j] over non-panel columns j, in 64 x 64 tiles
-// (panels of at most PBM columns: the staging takes no more LDS than that).
+// (panels of at most PBM columns: the staging takes no more LDS than that),
+// on the FP64 matrix cores: each of the four wavefronts takes a 16-row strip
+// of the tile, four 16 x 16 output tiles held in accumulators initialised
+// with the matrix's own values, and every four panel columns issue one
+// v_mfma_f64_16x16x4f64 per output tile (lane l holds W[l % 16][l / 16] and
+// R[l / 16][l % 16] of the 16 x 4 and 4 x 16 operands, and rows l / 16 + 4 r,
+// r < 4, of column l % 16 of the output).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 template <int PBM>
 __global__ __launch_bounds__(kBlock) void k_bgj_update(int m, int k0, int k1, double* __restrict__ Ball,
-                                                       const double* __restrict__ Rall) {
+                                                       const double* __restrict__ Rall, int64_t rstride) {
   double* B = Ball + (int64_t)blockIdx.z * m * m;
-  const double* R = Rall + (int64_t)blockIdx.z * kGjPanel * m;
+  const double* R = Rall + (int64_t)blockIdx.z * rstride;
   __shared__ double Ws[64][PBM + 1];
   __shared__ double Rs[PBM][64 + 1];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64, tid = threadIdx.x, b = k1 - k0;
   if (j0 + 64 > k0 && j0 < k1 && j0 >= k0 && j0 + 64 <= k1) return;   // tile inside the panel
-  const int tr = tid / 16, tc = tid % 16;   // 4 x 4 outputs per thread
-  // this thread's outputs, loaded first (clamped addresses, so every load is
+  const int w = tid / 64, lane = tid % 64, lr = lane % 16, lk = lane / 16;
+  // this lane's outputs, loaded first (clamped addresses, so every load is
   // issued at once and their latency overlaps the staging below)
-  double bo[4][4];
+  mfma_d4 acc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = min(i0 + tr + 16 * a, m - 1);
+  for (int ct = 0; ct < 4; ++ct) {
+    const int j = min(j0 + 16 * ct + lr, m - 1);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) bo[a][c] = B[(int64_t)i * m + min(j0 + tc + 16 * c, m - 1)];
+    for (int q = 0; q < 4; ++q) acc[ct][q] = B[(int64_t)min(i0 + 16 * w + lk + 4 * q, m - 1) * m + j];
   }
-  for (int e = tid; e < 64 * PBM; e += kBlock) {
+  // W and R staged in LDS: every thread's loads issued at once (clamped
+  // addresses, zeros selected afterwards), then stored, so the staging costs
+  // one memory latency instead of one per element a thread stages
+  static_assert((64 * PBM) % kBlock == 0, "whole staging rounds");
+  constexpr int NS = 64 * PBM / kBlock;
+  double wv[NS], rv[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int e = tid + u * kBlock;
     const int r = e / PBM, t = e % PBM, i = i0 + r;
-    double w = 0.0;
-    if (i < m && t < b) w = B[(int64_t)i * m + k0 + t] - (i == k0 + t ? 1.0 : 0.0);
-    Ws[r][t] = w;
+    wv[u] = B[(int64_t)min(i, m - 1) * m + k0 + min(t, b - 1)];
+    const int t2 = e / 64, c = e % 64;
+    rv[u] = R[(int64_t)min(t2, b - 1) * m + min(j0 + c, m - 1)];
   }
-  for (int e = tid; e < PBM * 64; e += kBlock) {
-    const int t = e / 64, c = e % 64, j = j0 + c;
-    Rs[t][c] = (t < b && j < m) ? R[(int64_t)t * m + j] : 0.0;
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int e = tid + u * kBlock;
+    const int r = e / PBM, t = e % PBM, i = i0 + r;
+    Ws[r][t] = (i < m && t < b) ? wv[u] - (i == k0 + t ? 1.0 : 0.0) : 0.0;
+    const int t2 = e / 64, c = e % 64;
+    Rs[t2][c] = (t2 < b && j0 + c < m) ? rv[u] : 0.0;
   }
   __syncthreads();
-  double acc[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-#pragma unroll 4
-  for (int t = 0; t < b; ++t) {
-    double wv[4], rv4[4];
-    for (int a = 0; a < 4; ++a) wv[a] = Ws[tr + 16 * a][t];
-    for (int c = 0; c < 4; ++c) rv4[c] = Rs[t][tc + 16 * c];
-    for (int a = 0; a < 4; ++a)
-      for (int c = 0; c < 4; ++c) acc[a][c] += wv[a] * rv4[c];
+  // the staging is zero past b, so whole groups of four are exact
+  for (int t0 = 0; t0 < b; t0 += 4) {
+    const double a = Ws[16 * w + lr][t0 + lk];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Rs[t0 + lk][16 * ct + lr], acc[ct], 0, 0, 0);
   }
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + tr + 16 * a;
-    if (i >= m) continue;
-    for (int c = 0; c < 4; ++c) {
-      const int j = j0 + tc + 16 * c;
-      if (j >= m || (j >= k0 && j < k1)) continue;
-      B[(int64_t)i * m + j] = bo[a][c] + acc[a][c];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int j = j0 + 16 * ct + lr;
+    if (j >= m || (j >= k0 && j < k1)) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + 16 * w + lk + 4 * q;
+      if (i < m) B[(int64_t)i * m + j] = acc[ct][q];
     }
   }
+}
+
+// Two panels per pass over the matrix (look-ahead): after panel p (columns
+// [k0, k1)) is factored and swapped, the next panel's columns receive p's
+// update alone (k_bgj_cols), panel p+1 is factored and swapped, its rows R2
+// of the columns not yet updated are brought up to date with p's transform
+// (k_bgj_rfix: R2 += W_p[rows of p+1] R_p), and one rank-(b_p + b_p+1) pass
+// updates every other column with both transforms, W = A[:, k0:k2] - the
+// selector of rows k0..k2, R = [R_p; R2].  Finally panel p's own columns
+// receive p+1's update (k_bgj_cols).  The composition is the product of the
+// two panels' Gauss-Jordan transforms, as two passes would apply it, at half
+// the memory traffic of the dominant update.
+//
+// A[i][c] += sum_s (A[i][w0 + s] - [i == w0 + s]) R[roff + s][c] for the
+// columns c in [c0, c1), every row i.
+__global__ __launch_bounds__(kBlock) void k_bgj_cols(int m, int w0, int bw, int c0, int c1,
+                                                     double* __restrict__ Ball,
+                                                     const double* __restrict__ Rall, int64_t rstride,
+                                                     int roff) {
+  double* B = Ball + (int64_t)blockIdx.y * m * m;
+  const double* R = Rall + (int64_t)blockIdx.y * rstride + (int64_t)roff * m;
+  const int nc = c1 - c0;
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)m * nc) return;
+  const int i = (int)(e / nc), c = c0 + (int)(e % nc);
+  const double* wrow = B + (int64_t)i * m + w0;
+  double acc = 0.0;
+  for (int s2 = 0; s2 < bw; ++s2) acc += (wrow[s2] - (i == w0 + s2 ? 1.0 : 0.0)) * R[(int64_t)s2 * m + c];
+  B[(int64_t)i * m + c] += acc;
+}
+
+// R[roff2 + t][j] += sum_s A[k1 + t][k0 + s] R[s][j], t < k2 - k1, s < k1 - k0,
+// for the columns j outside [k0, k2): the second panel's rows brought up to
+// date with the first panel's transform (their rows k1.. are not the first
+// panel's rows, so its selector contributes nothing).
+__global__ __launch_bounds__(kBlock) void k_bgj_rfix(int m, int k0, int k1, int k2,
+                                                     const double* __restrict__ Ball,
+                                                     double* __restrict__ Rall, int64_t rstride, int roff2) {
+  const double* B = Ball + (int64_t)blockIdx.z * m * m;
+  double* R = Rall + (int64_t)blockIdx.z * rstride;
+  const int t = blockIdx.y, j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= m || (j >= k0 && j < k2)) return;
+  const double* wrow = B + (int64_t)(k1 + t) * m + k0;
+  double acc = 0.0;
+  for (int s2 = 0; s2 < k1 - k0; ++s2) acc += wrow[s2] * R[(int64_t)s2 * m + j];
+  R[(int64_t)(roff2 + t) * m + j] += acc;
 }
 
 // Register-resident panel of the blocked Gauss-Jordan inverse, for m <= 512 RP:
@@ -828,8 +891,7 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
   const int pw = m <= kPanelThreads * 3 ? kGjPanel
                : m <= kPanelThreads * 4 ? kGjPanel4
                : m <= kPanelThreads * 6 ? kGjPanel6 : kGjPanel8;
-  for (int k0 = 0; k0 < m; k0 += pw) {
-    const int k1 = k0 + pw < m ? k0 + pw : m;
+  auto panel = [&](int k0, int k1) {
     if (m <= kPanelThreads)
       hipLaunchKernelGGL((k_bgj_panel_reg<1, kGjPanel>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else if (m <= kPanelThreads * 2)
@@ -842,9 +904,34 @@ hipError_t launch_dense_inverse(int nmat, int m, double* B, int* status, int* pe
       hipLaunchKernelGGL((k_bgj_panel_reg<6, kGjPanel6>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
     else
       hipLaunchKernelGGL((k_bgj_panel_reg<8, kGjPanel8>), dim3(nmat), dim3(kPanelThreads), 0, s, m, k0, k1, B, perm, status);
-    hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf);
-    if (pw > kGjPanel6) hipLaunchKernelGGL(k_bgj_update<kGjPanel>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
-    else hipLaunchKernelGGL(k_bgj_update<kGjPanel6>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf);
+  };
+  // the update pass with W = A[:, k0:k1] and R's first k1 - k0 rows
+  auto update = [&](int k0, int k1) {
+    const int b = k1 - k0;
+    if (b <= 32) hipLaunchKernelGGL(k_bgj_update<32>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf, kRbufRows * (int64_t)m);
+    else if (b <= 48) hipLaunchKernelGGL(k_bgj_update<48>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf, kRbufRows * (int64_t)m);
+    else hipLaunchKernelGGL(k_bgj_update<64>, gt, dim3(kBlock), 0, s, m, k0, k1, B, rbuf, kRbufRows * (int64_t)m);
+  };
+  const int64_t rs = kRbufRows * (int64_t)m;
+  for (int k0 = 0; k0 < m;) {
+    const int k1 = k0 + pw < m ? k0 + pw : m;
+    panel(k0, k1);
+    hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k0, k1, B, perm, rbuf, rs, 0);
+    if (k1 == m) {
+      update(k0, k1);
+      break;
+    }
+    // a second panel, then one pass for both
+    const int k2 = k1 + pw < m ? k1 + pw : m, b1 = k1 - k0, b2 = k2 - k1;
+    hipLaunchKernelGGL(k_bgj_cols, dim3(nblk((int64_t)m * b2), nmat), dim3(kBlock), 0, s, m, k0, b1, k1, k2, B, rbuf,
+                       rs, 0);
+    panel(k1, k2);
+    hipLaunchKernelGGL(k_bgj_swap, gs, dim3(kBlock), 0, s, m, k1, k2, B, perm, rbuf, rs, b1);
+    hipLaunchKernelGGL(k_bgj_rfix, dim3(nblk(m), b2, nmat), dim3(kBlock), 0, s, m, k0, k1, k2, B, rbuf, rs, b1);
+    update(k0, k2);
+    hipLaunchKernelGGL(k_bgj_cols, dim3(nblk((int64_t)m * b1), nmat), dim3(kBlock), 0, s, m, k1, b2, k0, k1, B, rbuf,
+                       rs, b1);
+    k0 = k2;
   }
   hipLaunchKernelGGL(k_gj_unpermute, gp, dim3(kBlock), 0, s, m, B, perm);
   return hipGetLastError();
