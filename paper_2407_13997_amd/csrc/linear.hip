@@ -501,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_bgj_cols(int m, int w0, int bw, int 
   const int i = (int)(e / nc), c = c0 + (int)(e % nc);
   const double* wrow = B + (int64_t)i * m + w0;
   double acc = 0.0;
+#pragma unroll 8
   for (int s2 = 0; s2 < bw; ++s2) acc += (wrow[s2] - (i == w0 + s2 ? 1.0 : 0.0)) * R[(int64_t)s2 * m + c];
   B[(int64_t)i * m + c] += acc;
 }
@@ -518,6 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_bgj_rfix(int m, int k0, int k1, int 
   if (j >= m || (j >= k0 && j < k2)) return;
   const double* wrow = B + (int64_t)(k1 + t) * m + k0;
   double acc = 0.0;
+#pragma unroll 8
   for (int s2 = 0; s2 < k1 - k0; ++s2) acc += wrow[s2] * R[(int64_t)s2 * m + j];
   R[(int64_t)(roff2 + t) * m + j] += acc;
 }
