@@ -181,19 +181,9 @@ def main():
     U = P.vec()
     torch.cuda.synchronize()
     t = time.perf_counter(); P.assemble(U); torch.cuda.synchronize(); t_asm0 = time.perf_counter() - t
-    # timed again once the kernels are loaded, beside the colour-by-colour form
+    # timed again once the kernels are loaded
     t = time.perf_counter(); P.assemble(U); torch.cuda.synchronize(); t_asm = time.perf_counter() - t
     log(f"[bench] assembled all levels in {t_asm0:.2f}s (first), {t_asm:.2f}s")
-    # the deterministic (colour-by-colour) assembly of the same state, for its cost
-    import copy
-    od = copy.copy(opts)
-    od.deterministic = 1
-    P.set_opts(od)
-    t = time.perf_counter(); P.assemble(U); torch.cuda.synchronize(); t_asm_det = time.perf_counter() - t
-    P.set_opts(opts)
-    P.assemble(U)
-    torch.cuda.synchronize()
-    log(f"[bench] deterministic assembly of all levels in {t_asm_det:.2f}s")
     t = time.perf_counter(); P.patch_factor(0, prec); torch.cuda.synchronize(); t_fac = time.perf_counter() - t
     log(f"[bench] factored finest level in {t_fac:.2f}s")
     t = time.perf_counter(); lam = P.eig_estimate(0); t_eig = time.perf_counter() - t
@@ -323,8 +313,7 @@ def main():
                                               "(each patch's residual gather and its own outputs)"}},
         "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
-        "setup_s": {"assemble_all_levels": t_asm, "assemble_all_levels_deterministic": t_asm_det,
-                    "factor_finest": t_fac, "eig_estimate": t_eig},
+        "setup_s": {"assemble_all_levels": t_asm, "factor_finest": t_fac, "eig_estimate": t_eig},
         "vcycle_ms": vc_ms,
         "fp64_sweep": fp64_leg,
         "lambda_finest": lam,

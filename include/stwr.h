@@ -154,17 +154,17 @@ typedef struct {
                                   by blocked Gauss-Jordan with MFMA trailing updates; 0: by the
                                   column-at-a-time register Gauss-Jordan (same pivoting rule) */
   int32_t deterministic;       /* 1: results equal bit for bit from run to run (see below);
-                                  0 (default): FP64 atomic assembly, autotuned time chunks */
+                                  0 (default): time_chunks = 0 chooses by timing */
 } stwr_solver_opts;
 
-/* deterministic = 1 assembles the Navier-Stokes residual and Jacobian of eq.
- * nsfem cell colour by cell colour (8 colours, no two cells of a colour
- * sharing a DoF) with plain additions in a fixed order instead of FP64
- * atomic additions, whose order, and so whose rounding, varies from run to
- * run; and time_chunks = 0 means the plain sweep instead of a choice by
- * timing.  Every other step of the solver (patch factors and sweeps, the
- * owner-gather of the patch corrections, reductions, the coarsest solve)
- * already runs in a fixed order.  The assembly costs about 10% more. */
+/* Every step of a solve runs in a fixed order: the Navier-Stokes residual
+ * and Jacobian of eq. nsfem are assembled cell colour by cell colour (8
+ * colours, no two cells of a colour sharing a DoF) with plain additions, the
+ * patch factors and sweeps, the owner-gather of the patch corrections, the
+ * reductions and the coarsest solve likewise.  The one choice made by timing
+ * is time_chunks = 0 (the chunk count of each small level); deterministic = 1
+ * makes it the plain sweep, and two solves then agree bit for bit.
+ */
 
 /* Time chunks (the cyclic reduction in time of Sec. 3.1, single-GPU form).
  * A patch's sweep is a forward substitution over the N slabs.  With c chunks

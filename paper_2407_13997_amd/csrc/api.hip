@@ -284,7 +284,7 @@ void upload_level(stwr_problem* P, Level& L, bool coarsest) {
   v.kdeg = H.kdeg; v.nloc = H.nloc;
   v.thk = H.thk; v.n3 = H.n3; v.nlv = H.nlv; v.nlp = H.nlp;
   v.cell_vn = L.cell_vn; v.cell_pn = L.cell_pn;
-  v.color_cells = L.color_cells; v.color_first = 0; v.det = 0;
+  v.color_cells = L.color_cells; v.color_first = 0;
   v.node_cell_ptr = L.node_cell_ptr; v.node_cell = L.node_cell;
   v.nbord = H.po < H.nf ? L.NQ : 0;
   v.coarse_slabs = fac_slabs_of(H, L.N);
@@ -858,8 +858,7 @@ void assemble(stwr_problem* P, const double* U) {
     }
     HIPCHK(launch_fill((int64_t)Lv.view.nnz * Lv.N * Lv.NQ * Lv.NQ, 0.0, Lv.Jv, P->s()));
     HIPCHK(launch_fill(Lv.view.nnz, 0.0, Lv.Mv, P->s()));
-    HIPCHK(launch_assemble_jacobian(Lv.view, P->d_tab, P->mms, Ul, Lv.Jv, Lv.Mv,
-                                    P->opts.deterministic ? Lv.H.color_ptr : nullptr, P->s()));
+    HIPCHK(launch_assemble_jacobian(Lv.view, P->d_tab, P->mms, Ul, Lv.Jv, Lv.Mv, Lv.H.color_ptr, P->s()));
     Lv.fac_prec = -1;
     Lv.has_lambda = false;
   }
@@ -882,8 +881,7 @@ void residual(stwr_problem* P, const double* U, double* F) {
     return;
   }
   HIPCHK(launch_fill(L.n_st, 0.0, F, P->s()));
-  HIPCHK(launch_assemble_residual(L.view, P->d_tab, P->mms, U, F, P->opts.deterministic ? L.H.color_ptr : nullptr,
-                                  P->s()));
+  HIPCHK(launch_assemble_residual(L.view, P->d_tab, P->mms, U, F, L.H.color_ptr, P->s()));
 }
 
 void setup_smoothers(stwr_problem* P) {

@@ -1012,19 +1012,14 @@ hipError_t launch_expand(const LevelView& L, const RefTables* tab, MmsDev mms, c
   return hipGetLastError();
 }
 
-// One launch over every cell (atomic additions), or, with color_ptr (host,
-// 9 offsets into L.color_cells), one launch per colour in colour order.
+// One launch per colour (color_ptr: 9 offsets into L.color_cells), in
+// colour order.
 template <typename F>
 static hipError_t by_colour(const LevelView& L, const int* color_ptr, F launch) {
-  if (!color_ptr) {
-    launch(L, dim3((unsigned)((int64_t)L.nc * L.N)));
-    return hipGetLastError();
-  }
   for (int k = 0; k < 8; ++k) {
     const int cnt = color_ptr[k + 1] - color_ptr[k];
     if (cnt == 0) continue;
     LevelView Lc = L;
-    Lc.det = 1;
     Lc.color_first = color_ptr[k];
     launch(Lc, dim3((unsigned)((int64_t)cnt * L.N)));
     const hipError_t e = hipGetLastError();

@@ -1,13 +1,14 @@
-"""The deterministic option (solver option deterministic = 1).
+"""Reproducibility.
 
-With it the Navier-Stokes residual and Jacobian are assembled cell colour by
-cell colour with plain additions in a fixed order, and the time-chunk choice
-is the plain sweep, so a solve gives the same bits every run.  Checked: the
-assembled Jacobian (every level) and the residual against the oracle, P2-P1
-and P3-P2; a colour-by-colour assembly equal bit for bit to a second one;
-two independent Newton solves, with fresh problems, equal bit for bit
-(solution, residual history and iteration counts); the solution equal to the
-atomic assembly's to the Newton tolerance."""
+Every step of a solve runs in a fixed order: the residual and Jacobian are
+assembled cell colour by cell colour with plain additions (no FP64 atomics),
+and with the solver option deterministic = 1 the time-chunk choice is the
+plain sweep instead of a choice by timing, so a solve gives the same bits
+every run.  Checked: the assembled Jacobian (every level) and the residual
+against the oracle, P2-P1 and P3-P2; an assembly equal bit for bit to a
+second one; two independent Newton solves, with fresh problems, equal bit
+for bit (solution, residual history and iteration counts); the solution
+with the timed chunk choice equal to them to the Newton tolerance."""
 import numpy as np
 import pytest
 
