@@ -283,8 +283,14 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
   __shared__ CellStage<NQ> S;
   __shared__ double pl[3][NQ];
   __shared__ double prev[2][6];
-  __shared__ double dq[kMaxG][kQx][2], pq[kMaxG][kQx], fq[kMaxG][kQx][2];
+  // per (temporal, spatial) quadrature point, weighted: the value term
+  // (u_t + R (u . grad) u - f), the gradient term dt (grad u - p I) and the
+  // divergence; then their sums over the spatial points against each basis
+  // function (all lanes take part in both), then the sums over the temporal
+  // points
+  __shared__ double Av[kMaxG][kQx][2], Bv[kMaxG][kQx][2][2], Dv[kMaxG][kQx];
   __shared__ double jq[kQx][2];   // U(s=0) - U_{n-1}(1) at the quadrature points
+  __shared__ double Pv[kMaxG][2][6], Jm[2][6], Qv[kMaxG][3];
   stage_cell<NQ>(L, T, mms, U, c, n, S);
   const int G = T->G;
   if (tid < 3 * NQ) {
@@ -316,8 +322,18 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
     prev[comp][i] = v;
   }
   __syncthreads();
+  const double dt = L.dt, R = mms.reynolds;
   for (int e = tid; e < G * kQx; e += 64) {
     const int g = e / kQx, x = e % kQx;
+    double p = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      double pj = 0.0;
+      for (int b = 0; b < NQ; ++b) pj += T->Phi[g][b] * pl[j][b];
+      p += pj * T->N1[x][j];
+    }
+    double f[2];
+    forcing(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], f[0], f[1]);
+    const double w = S.wdet[x];
     for (int comp = 0; comp < 2; ++comp) {
       double d = 0.0;
       for (int i = 0; i < 6; ++i) {
@@ -325,19 +341,12 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
         for (int b = 0; b < NQ; ++b) ui += T->dPhi[g][b] * S.ul[comp][i][b];
         d += ui * T->N2[x][i];
       }
-      dq[g][x][comp] = d;
+      const double conv = S.uq[g][x][0] * S.gq[g][x][comp][0] + S.uq[g][x][1] * S.gq[g][x][comp][1];
+      Av[g][x][comp] = w * (d + dt * (R * conv - f[comp]));
+      Bv[g][x][comp][0] = w * dt * (S.gq[g][x][comp][0] - (comp == 0 ? p : 0.0));
+      Bv[g][x][comp][1] = w * dt * (S.gq[g][x][comp][1] - (comp == 1 ? p : 0.0));
     }
-    double p = 0.0;
-    for (int j = 0; j < 3; ++j) {
-      double pj = 0.0;
-      for (int b = 0; b < NQ; ++b) pj += T->Phi[g][b] * pl[j][b];
-      p += pj * T->N1[x][j];
-    }
-    pq[g][x] = p;
-    double fx, fy;
-    forcing(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], fx, fy);
-    fq[g][x][0] = fx;
-    fq[g][x][1] = fy;
+    Dv[g][x] = w * (S.gq[g][x][0][0] + S.gq[g][x][1][1]);
   }
   if (tid < kQx) {
     for (int comp = 0; comp < 2; ++comp) {
@@ -352,35 +361,38 @@ __global__ __launch_bounds__(64) void k_residual(LevelView L, const RefTables* _
     }
   }
   __syncthreads();
-  const double dt = L.dt, R = mms.reynolds;
+  // sums over the spatial points: Pv[g][comp][i] (value and gradient terms
+  // against velocity basis i), Jm[comp][i] (the jump), Qv[g][j] (divergence
+  // against pressure basis j)
+  for (int e = tid; e < G * 12 + 12 + G * 3; e += 64) {
+    double acc = 0.0;
+    if (e < G * 12) {
+      const int g = e / 12, comp = (e / 6) % 2, i = e % 6;
+      for (int x = 0; x < kQx; ++x)
+        acc += Av[g][x][comp] * T->N2[x][i] + Bv[g][x][comp][0] * S.gN[x][i][0] + Bv[g][x][comp][1] * S.gN[x][i][1];
+      Pv[g][comp][i] = acc;
+    } else if (e < G * 12 + 12) {
+      const int comp = (e - G * 12) / 6, i = (e - G * 12) % 6;
+      for (int x = 0; x < kQx; ++x) acc += S.wdet[x] * jq[x][comp] * T->N2[x][i];
+      Jm[comp][i] = acc;
+    } else {
+      const int g = (e - G * 12 - 12) / 3, j = (e - G * 12 - 12) % 3;
+      for (int x = 0; x < kQx; ++x) acc += Dv[g][x] * T->N1[x][j];
+      Qv[g][j] = acc;
+    }
+  }
+  __syncthreads();
   if (tid < 12 * NQ) {
     const int comp = tid / (6 * NQ), i = (tid / NQ) % 6, a = tid % NQ;
     double acc = 0.0;
-    for (int g = 0; g < G; ++g) {
-      double sg = 0.0;
-      for (int x = 0; x < kQx; ++x) {
-        const double conv = S.uq[g][x][0] * S.gq[g][x][comp][0] + S.uq[g][x][1] * S.gq[g][x][comp][1];
-        const double val = dq[g][x][comp] + dt * (R * conv - fq[g][x][comp]);
-        const double grd = S.gq[g][x][comp][0] * S.gN[x][i][0] + S.gq[g][x][comp][1] * S.gN[x][i][1]
-                         - pq[g][x] * S.gN[x][i][comp];
-        sg += S.wdet[x] * (val * T->N2[x][i] + dt * grd);
-      }
-      acc += T->wg[g] * T->Phi[g][a] * sg;
-    }
-    double jmp = 0.0;
-    for (int x = 0; x < kQx; ++x) jmp += S.wdet[x] * jq[x][comp] * T->N2[x][i];
-    acc += T->e0[a] * jmp;
+    for (int g = 0; g < G; ++g) acc += T->wg[g] * T->Phi[g][a] * Pv[g][comp][i];
+    acc += T->e0[a] * Jm[comp][i];
     const int dof = L.cell_dofs[15 * c + 6 * comp + i];
     if (dof >= 0) scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], acc);
   } else if (tid >= 32 && tid < 32 + 3 * NQ) {
     const int j = (tid - 32) / NQ, a = (tid - 32) % NQ;
     double acc = 0.0;
-    for (int g = 0; g < G; ++g) {
-      double sg = 0.0;
-      for (int x = 0; x < kQx; ++x)
-        sg += S.wdet[x] * (S.gq[g][x][0][0] + S.gq[g][x][1][1]) * T->N1[x][j];
-      acc += T->wg[g] * T->Phi[g][a] * sg;
-    }
+    for (int g = 0; g < G; ++g) acc += T->wg[g] * T->Phi[g][a] * Qv[g][j];
     const int dof = L.po + L.cells[3 * c + j];
     scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
   }
