@@ -827,8 +827,11 @@ __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables
   __shared__ ThStage<NQ, NLV> S;
   __shared__ double pl[NLP][NQ];
   __shared__ double prev[2][NLV];
-  __shared__ double dq[kMaxG][kQx][2], pq[kMaxG][kQx], fq[kMaxG][kQx][2];
+  // the weighted point values, their spatial sums against each basis
+  // function and then the temporal sums, as in k_residual
+  __shared__ double Av[kMaxG][kQx][2], Bv[kMaxG][kQx][2][2], Dv[kMaxG][kQx];
   __shared__ double jq[kQx][2];   // U(s=0) - U_{n-1}(1) at the quadrature points
+  __shared__ double Pv[kMaxG][2][NLV], Jm[2][NLV], Qv[kMaxG][NLP];
   th_stage<NQ, NLV>(L, T, mms, U, c, n, S);
   const int G = T->G;
   for (int e = tid; e < NLP * NQ; e += 64) {
@@ -862,8 +865,18 @@ __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables
     prev[comp][i] = v;
   }
   __syncthreads();
+  const double dt = L.dt, R = mms.reynolds;
   for (int e = tid; e < G * kQx; e += 64) {
     const int g = e / kQx, x = e % kQx;
+    double p = 0.0;
+    for (int j = 0; j < NLP; ++j) {
+      double pj = 0.0;
+      for (int b = 0; b < NQ; ++b) pj += T->Phi[g][b] * pl[j][b];
+      p += pj * T->Nq[x][j];
+    }
+    double f[2];
+    forcing(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], f[0], f[1]);
+    const double w = S.wdet[x];
     for (int comp = 0; comp < 2; ++comp) {
       double d = 0.0;
       for (int i = 0; i < NLV; ++i) {
@@ -871,19 +884,12 @@ __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables
         for (int b = 0; b < NQ; ++b) ui += T->dPhi[g][b] * S.ul[comp][i][b];
         d += ui * T->Nk[x][i];
       }
-      dq[g][x][comp] = d;
+      const double conv = S.uq[g][x][0] * S.gq[g][x][comp][0] + S.uq[g][x][1] * S.gq[g][x][comp][1];
+      Av[g][x][comp] = w * (d + dt * (R * conv - f[comp]));
+      Bv[g][x][comp][0] = w * dt * (S.gq[g][x][comp][0] - (comp == 0 ? p : 0.0));
+      Bv[g][x][comp][1] = w * dt * (S.gq[g][x][comp][1] - (comp == 1 ? p : 0.0));
     }
-    double p = 0.0;
-    for (int j = 0; j < NLP; ++j) {
-      double pj = 0.0;
-      for (int b = 0; b < NQ; ++b) pj += T->Phi[g][b] * pl[j][b];
-      p += pj * T->Nq[x][j];
-    }
-    pq[g][x] = p;
-    double fx, fy;
-    forcing(mms, (n + T->sg[g]) * L.dt, S.xp[x][0], S.xp[x][1], fx, fy);
-    fq[g][x][0] = fx;
-    fq[g][x][1] = fy;
+    Dv[g][x] = w * (S.gq[g][x][0][0] + S.gq[g][x][1][1]);
   }
   if (tid < kQx) {
     for (int comp = 0; comp < 2; ++comp) {
@@ -898,37 +904,37 @@ __global__ __launch_bounds__(64) void k_th_residual(LevelView L, const RefTables
     }
   }
   __syncthreads();
-  const double dt = L.dt, R = mms.reynolds;
+  const int NP = G * 2 * NLV, NJ = 2 * NLV, NQS = G * NLP;
+  for (int e = tid; e < NP + NJ + NQS; e += 64) {
+    double acc = 0.0;
+    if (e < NP) {
+      const int g = e / (2 * NLV), comp = (e / NLV) % 2, i = e % NLV;
+      for (int x = 0; x < kQx; ++x)
+        acc += Av[g][x][comp] * T->Nk[x][i] + Bv[g][x][comp][0] * S.gN[x][i][0] + Bv[g][x][comp][1] * S.gN[x][i][1];
+      Pv[g][comp][i] = acc;
+    } else if (e < NP + NJ) {
+      const int comp = (e - NP) / NLV, i = (e - NP) % NLV;
+      for (int x = 0; x < kQx; ++x) acc += S.wdet[x] * jq[x][comp] * T->Nk[x][i];
+      Jm[comp][i] = acc;
+    } else {
+      const int g = (e - NP - NJ) / NLP, j = (e - NP - NJ) % NLP;
+      for (int x = 0; x < kQx; ++x) acc += Dv[g][x] * T->Nq[x][j];
+      Qv[g][j] = acc;
+    }
+  }
+  __syncthreads();
   constexpr int NL = 2 * NLV + NLP;
-  for (int e = tid; e < (2 * NLV + NLP) * NQ; e += 64) {
+  for (int e = tid; e < NL * NQ; e += 64) {
+    double acc = 0.0;
     if (e < 2 * NLV * NQ) {
       const int comp = e / (NLV * NQ), i = (e / NQ) % NLV, a = e % NQ;
-      double acc = 0.0;
-      for (int g = 0; g < G; ++g) {
-        double sg = 0.0;
-        for (int x = 0; x < kQx; ++x) {
-          const double conv = S.uq[g][x][0] * S.gq[g][x][comp][0] + S.uq[g][x][1] * S.gq[g][x][comp][1];
-          const double val = dq[g][x][comp] + dt * (R * conv - fq[g][x][comp]);
-          const double grd = S.gq[g][x][comp][0] * S.gN[x][i][0] + S.gq[g][x][comp][1] * S.gN[x][i][1]
-                           - pq[g][x] * S.gN[x][i][comp];
-          sg += S.wdet[x] * (val * T->Nk[x][i] + dt * grd);
-        }
-        acc += T->wg[g] * T->Phi[g][a] * sg;
-      }
-      double jmp = 0.0;
-      for (int x = 0; x < kQx; ++x) jmp += S.wdet[x] * jq[x][comp] * T->Nk[x][i];
-      acc += T->e0[a] * jmp;
+      for (int g = 0; g < G; ++g) acc += T->wg[g] * T->Phi[g][a] * Pv[g][comp][i];
+      acc += T->e0[a] * Jm[comp][i];
       const int dof = L.cell_dofs[NL * c + NLV * comp + i];
       if (dof >= 0) scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], acc);
     } else {
       const int t = e - 2 * NLV * NQ, j = t / NQ, a = t % NQ;
-      double acc = 0.0;
-      for (int g = 0; g < G; ++g) {
-        double sg = 0.0;
-        for (int x = 0; x < kQx; ++x)
-          sg += S.wdet[x] * (S.gq[g][x][0][0] + S.gq[g][x][1][1]) * T->Nq[x][j];
-        acc += T->wg[g] * T->Phi[g][a] * sg;
-      }
+      for (int g = 0; g < G; ++g) acc += T->wg[g] * T->Phi[g][a] * Qv[g][j];
       const int dof = L.po + L.cell_pn[NLP * c + j];
       scatter_add(L, &F[((int64_t)dof * L.N + n) * NQ + a], -dt * acc);
     }
