@@ -91,12 +91,17 @@ __device__ inline typename NtVec<T>::type load_stream16(const T* p) {
 // one column, so the active column is always register 0 and every register
 // index is static; after m steps position j holds column (j + m) mod MAXM
 // (columns past m are zero padding and stay zero).  A step is a pivot search
-// (DPP wavefront maximum and ballots, plus LDS across wavefronts when
-// TPB > 64), a row swap, the pivot row scaled by the pivot's reciprocal and
-// broadcast through LDS, and the elimination in registers.  The column permutation of the pivoting is applied while
-// writing the inverse out in the sweep's panel layout.  Per element the
-// arithmetic and the pivot choice (largest magnitude, ties to the smaller
-// row) are those of the textbook in-place Gauss-Jordan inverse.
+// among the rows not yet used as pivots (DPP wavefront maximum and ballots,
+// plus LDS across wavefronts when TPB > 64), the pivot row scaled by the
+// pivot's reciprocal and broadcast through LDS, and the elimination in
+// registers.  The rows are never swapped: step k's pivot row p_k stays in
+// its thread, so the registers hold (Pi A)^-1 with its row k in physical
+// row p_k, where Pi puts row p_k of A at position k; the inverse is A^-1 =
+// (Pi A)^-1 Pi, written out row k from physical row p_k and stored column k
+// to column p_k of the sweep's layout.  Per element the arithmetic is that
+// of the textbook in-place Gauss-Jordan inverse with partial pivoting
+// (largest magnitude, ties to the smaller physical row); not moving rows
+// saves the swap's register selects and LDS round trip every step.
 template <int NQ, typename T, int TPB, int NBMAX = kMaxNb>
 struct FactorLds {
   static constexpr int MAXM = NBMAX * NQ;
@@ -104,10 +109,10 @@ struct FactorLds {
   // row buffers padded to whole 16-byte vectors
   static constexpr int RV = 16 / sizeof(T), MP = (MAXM + RV - 1) / RV * RV;
   __align__(16) T prow[MP];
-  __align__(16) T swp[2][MP];
   T rv[NW];
   int ri[NW];
-  int perm[MAXM];
+  int perm[MAXM];   // perm[k]: pivot row of step k
+  int invp[MAXM];   // invp[row]: the step it was the pivot of
   int ofs1[MAXM], ofs2[MAXM];
 };
 
@@ -124,7 +129,6 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
   constexpr int RV = 16 / sizeof(T), MP = (MAXM + RV - 1) / RV * RV;
   using V16 = typename Vec<T>::type;
   T* prow = S.prow;
-  T (*swp)[MP] = S.swp;
   T* rv = S.rv;
   int* ri = S.ri;
   int* perm = S.perm;
@@ -136,7 +140,7 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
   const int m = nb * NQ;
   const int* nzp = P.patch_nz + P.patch_nz_off[p];
   T a[RPL][MAXM];
-  // row r of the registers to / from an LDS row buffer, 16 bytes at a time
+  // row r of the registers to an LDS row buffer, 16 bytes at a time
   auto put = [&](T* dst, int r) {
 #pragma unroll
     for (int j = 0; j < MP; j += RV) {
@@ -145,16 +149,6 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
 #pragma unroll
       for (int t = 0; t < RV; ++t) e[t] = j + t < MAXM ? a[r][j + t] : (T)0;
       *reinterpret_cast<V16*>(dst + j) = v;
-    }
-  };
-  auto get = [&](const T* src, int r) {
-#pragma unroll
-    for (int j = 0; j < MP; j += RV) {
-      const V16 v = *reinterpret_cast<const V16*>(src + j);
-      const T* e = reinterpret_cast<const T*>(&v);
-#pragma unroll
-      for (int t = 0; t < RV; ++t)
-        if (j + t < MAXM) a[r][j + t] = e[t];
     }
   };
 #pragma unroll
@@ -190,17 +184,20 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  bool used[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) used[r] = false;
   for (int k = 0; k < m; ++k) {
-    // pivot: largest |entry| of column k among rows >= k, ties to the smaller
-    // row: each wavefront's maximum (DPP), the first of its rows holding it
-    // (ballots; register r = 0 holds the wavefront's smaller rows), then the
-    // best over the wavefronts through LDS
+    // pivot: largest |entry| of column k among the rows not yet used, ties
+    // to the smaller row: each wavefront's maximum (DPP), the first of its
+    // rows holding it (ballots; register r = 0 holds the wavefront's smaller
+    // rows), then the best over the wavefronts through LDS
     T vr[RPL];
     T vmax = (T)-1;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = tid + TPB * r;
-      vr[r] = (i >= k && i < m) ? fabs(a[r][0]) : (T)-1;
+      vr[r] = (!used[r] && i < m) ? fabs(a[r][0]) : (T)-1;
       vmax = fmax(vmax, vr[r]);
     }
     T best = wave_max(vmax);
@@ -221,46 +218,35 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
     int pi = bi;
     if (!(best > (T)0) || !isfinite(best) || pi >= m) {
       if (tid == 0) status[0] = 1;
-      pi = k;
+      pi = pi < m ? pi : 0;   // a failed block: keep going on some row, the status reports it
     }
     if (tid == 0) perm[k] = pi;
-    if (pi != k) {   // uniform: swap rows k and pi
+    // the owner of row pi scales it by the pivot's reciprocal (the pivot
+    // entry becomes 1 / pivot) and publishes it; every row multiplies by its
+    // factor (1 off the pivot row), which is cheaper than selecting the
+    // owner's values element by element
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = tid + TPB * r;
-        if (i == pi) put(swp[0], r);
-        if (i == k) put(swp[1], r);
-      }
-      __syncthreads();
+    for (int r = 0; r < RPL; ++r) {
+      const bool own = tid + TPB * r == pi;
+      used[r] = used[r] || own;
+      const T rp = (T)1 / a[r][0];
+      const T sc = own ? rp : (T)1;
+      a[r][0] = own ? rp : a[r][0];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = tid + TPB * r;
-        if (i == k) get(swp[0], r);
-        if (i == pi) get(swp[1], r);
-      }
+      for (int j = 1; j < MAXM; ++j) a[r][j] *= sc;
+      if (own) put(prow, r);
     }
-    // the pivot row scaled by the pivot's reciprocal (its pivot entry becomes
-    // 1 / pivot); the other rows eliminate column k; then every row rotates
+    __syncthreads();
+    // every other row eliminates column k (a zero factor leaves the pivot
+    // row and the padding rows as they are)
     T f[RPL];
-    bool live[RPL], own[RPL];
+    bool live[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = tid + TPB * r;
-      live[r] = i < m && i != k;
-      own[r] = i == k;
-      f[r] = a[r][0];
+      live[r] = i < m && i != pi;
+      f[r] = live[r] ? a[r][0] : (T)0;
     }
-    // the owner scales its row and publishes it in LDS
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      if (own[r]) {
-        const T rp = (T)1 / a[r][0];
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j) a[r][j] = (j == 0 ? (T)1 : a[r][j]) * rp;
-        put(prow, r);
-      }
-    }
-    __syncthreads();
     {
       const T p0 = prow[0];
 #pragma unroll
@@ -286,8 +272,7 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
           const int j = j0 + b * RV + t;
           if (j >= 1 && j < MAXM) {
 #pragma unroll
-            for (int r = 0; r < RPL; ++r)
-              if (live[r]) a[r][j] -= f[r] * pj[t];
+            for (int r = 0; r < RPL; ++r) a[r][j] -= f[r] * pj[t];
           }
         }
       }
@@ -300,19 +285,18 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
       a[r][MAXM - 1] = t0;
     }
   }
-  // undo the column permutation of the pivoting (the swaps (k, perm[k])
-  // applied to the columns for k = m-1 .. 0): each thread follows its
-  // columns through the swaps, then records the panel-layout offsets of
-  // their destination (rows < 64 and rows >= 64)
+  // A^-1 = (Pi A)^-1 Pi: stored column k goes to column perm[k], and row k
+  // (physical row perm[k]) to row k; record the layout offsets of each
+  // stored column's destination (rows < 64 and rows >= 64) and each
+  // physical row's output row (rows of a failed block fall back to their own)
   const BlockLayout lay(m, VW);
   __syncthreads();
+  int* invp = S.invp;
+  for (int i = tid; i < m; i += TPB) invp[i] = i;
+  __syncthreads();
+  for (int k = tid; k < m; k += TPB) invp[perm[k]] = k;
   for (int c = tid; c < m; c += TPB) {
-    int pos = c;
-    for (int k = m - 1; k >= 0; --k) {
-      const int pk = perm[k];
-      if (pos == k) pos = pk;
-      else if (pos == pk) pos = k;
-    }
+    const int pos = perm[c];
     if constexpr (BIG) {
       ofs1[c] = (pos / VW) * m * VW + pos % VW;
       ofs2[c] = 0;
@@ -327,8 +311,9 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    const int i = tid + TPB * r;
-    if (i < m) {
+    const int ip = tid + TPB * r;
+    if (ip < m) {
+      const int i = invp[ip];   // the output row this physical row holds
       if constexpr (BIG) {
 #pragma unroll
         for (int q = 0; q < MAXM; ++q) {
