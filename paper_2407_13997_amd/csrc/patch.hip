@@ -383,11 +383,13 @@ __device__ inline T dotv(const V& w, const T* g) {
 // outstanding.  The residual is staged a 128-byte line (16 / (q+1) slabs) of
 // every patch DoF at a time, with one batch of coalesced loads issued ahead
 // of a block.  The outputs are FP32 (they are computed in FP32, so nothing
-// is lost; the gather widens them), collected in LDS for 32 / (q+1) slabs
-// and written DoF by DoF ([patch DoF][slab][node], one 128-byte line per DoF
-// and chunk), so each line is whole: writes interleaved with the block
-// stream cost HBM time far beyond their share of the bytes, so they are
-// kept few and full.  The blocks are read once per sweep and are loaded
+// is lost; the gather widens them), collected in LDS for 64 / (q+1) slabs
+// and written DoF by DoF ([patch DoF][slab][node], two whole 128-byte lines
+// per DoF and chunk) with nontemporal stores: writes interleaved with the
+// block stream cost HBM time far beyond their share of the bytes (1.2% of
+// the bytes, 15% of the time when measured against the same kernel storing
+// to a few lines that stay in L2), so they are kept few, whole and
+// streaming.  The blocks are read once per sweep and are loaded
 // nontemporal, so they do not push the residual and output lines out of L2.  The jump coupling works in FP32 from the scalar patch mass
 // block: the velocity mass couples equal components only, with the same
 // scalar block for both, and the patch velocity DoFs come in (x, y) pairs of
@@ -410,7 +412,7 @@ struct SweepF32Lds {
   float ylast[kMaxNbu];
   float mj[kMaxNbu];
   float rch[CH][RW];                           // residual of the current CH slabs
-  alignas(16) float ych[2 * CH * MAXM];        // outputs of the current 2 CH slabs, [patch DoF][slab][node]
+  alignas(16) float ych[4 * CH * MAXM];        // outputs of the current 4 CH slabs, [patch DoF][slab][node]
 };
 
 template <int NQ, bool FULL>
@@ -436,10 +438,10 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   float* ylast = S.ylast;
   float* mj = S.mj;
   float (*rch)[RW] = S.rch;
-  constexpr int YCH = 2 * CH;                  // slabs per 128-byte line of FP32 outputs
+  constexpr int YCH = 4 * CH;                  // slabs per output chunk (two 128-byte lines of FP32 outputs)
   float* ych = S.ych;
-  static_assert(YCH * NQ == 32, "an output chunk is one 128-byte line per DoF");
-  constexpr int YL = (kMaxNb * 8 + 63) / 64;   // 16-byte output stores per lane and chunk
+  static_assert(YCH * NQ == 64, "an output chunk is two 128-byte lines per DoF");
+  constexpr int YL = (kMaxNb * 16 + 63) / 64;  // 16-byte output stores per lane and chunk
   const float e0[2] = {(float)e00, (float)e01}, e1[2] = {(float)e10, (float)e11};
   const int lane = threadIdx.x;
   const GLOBAL_AS int* patch_ptr = gptr(P.patch_ptr);
@@ -526,9 +528,9 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   };
   // outputs of slabs n0 .. n0 + ns - 1 (n0 a multiple of YCH), stored DoF
   // by DoF: patch row i holds its N slabs' NQ values contiguously (nq
-  // floats from i nq), so a DoF's values of a whole chunk are one 128-byte
-  // line, and the gather reads each DoF's slabs as one coalesced run.  Four
-  // values a lane and store (eight stores per DoF and chunk); 16-byte
+  // floats from i nq), so a DoF's values of a whole chunk are two 128-byte
+  // lines, and the gather reads each DoF's slabs as one coalesced run.  Four
+  // values a lane and store (sixteen stores per DoF and chunk); 16-byte
   // stores where the rows are 16-byte aligned (nq a multiple of 4), single
   // values at a ragged chunk end
   auto flush = [&](int n0, int ns) {
@@ -538,12 +540,12 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
     // every register the flush holds adds to the kernel's peak
 #pragma unroll 1
     for (int i = 0; i < YL; ++i) {
-      const int id = i * 64 + lane, dd = id >> 3, t0 = 4 * (id & 7);
+      const int id = i * 64 + lane, dd = id >> 4, t0 = 4 * (id & 15);
       if (dd < nb && t0 < run) {
         GLOBAL_AS float* yo = yout + (int64_t)dd * nq + n0 * NQ + t0;
-        const float* ys = ych + dd * 32 + t0;
+        const float* ys = ych + dd * 64 + t0;
         if (vec && t0 + 3 < run) {
-          *reinterpret_cast<GLOBAL_AS f32x4*>(yo) = *reinterpret_cast<const f32x4*>(ys);
+          __builtin_nontemporal_store(*reinterpret_cast<const f32x4*>(ys), reinterpret_cast<GLOBAL_AS f32x4*>(yo));
         } else {
           for (int t = 0; t < 4 && t0 + t < run; ++t) yo[t] = ys[t];
         }
@@ -605,7 +607,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
     float v1 = e1[lane % NQ] * acc1;
     if constexpr (NQ == 2) v1 += __shfl_xor(v1, 1);
     if (lane < r1) {
-      ych[(lane / NQ) * 32 + sy * NQ + lane % NQ] = acc1;
+      ych[(lane / NQ) * 64 + sy * NQ + lane % NQ] = acc1;
       if (lane % NQ == NQ - 1) ylast[lane / NQ] = v1;
     }
     if constexpr (kTwo) {
@@ -613,7 +615,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
       float v2 = e1[row % NQ] * acc2;
       if constexpr (NQ == 2) v2 += __shfl_xor(v2, 4);
       if (lane < 4 * r2 && quarter == 0) {
-        ych[(row / NQ) * 32 + sy * NQ + row % NQ] = acc2;
+        ych[(row / NQ) * 64 + sy * NQ + row % NQ] = acc2;
         if (row % NQ == NQ - 1) ylast[row / NQ] = v2;
       }
     }
