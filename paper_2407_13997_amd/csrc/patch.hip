@@ -926,7 +926,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
       }
     }
     if constexpr (kFast) {
-      if (hasRow && write_y) yout[(int64_t)n * m + tid] = y;
+      if (hasRow && write_y) __builtin_nontemporal_store(y, yout + (int64_t)n * m + tid);   // streaming output
       // slab-end value of the lane's DoF: its NQ rows sit in adjacent lanes
       double ve = e1a * y;
       if constexpr (NQ == 2) ve += dpp_move<0xB1>(ve);   // quad_perm [1,0,3,2]
@@ -955,7 +955,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
     }
     if (hasRow) {
       ys[tid] = y;
-      if (write_y) yout[(int64_t)n * m + tid] = y;
+      if (write_y) __builtin_nontemporal_store(y, yout + (int64_t)n * m + tid);
     }
     __syncthreads();
     if (tid < nbu) {
@@ -1179,7 +1179,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep_big(LevelView L, Pat
 #pragma unroll
         for (int c = 0; c < VW; ++c) acc += v[c] * g[q * VW + c];
       }
-      yo[(int64_t)n * m + row] = (double)acc;
+      __builtin_nontemporal_store((double)acc, yo + (int64_t)n * m + row);   // streaming output
       yv[row] = acc;
     }
     __syncthreads();
