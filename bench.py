@@ -223,8 +223,9 @@ def main():
     # outputs once
     s_f = 4 if prec == binding.FP32 else 8
     sweep_ms, sweep_n = kt["sweep"]
-    io_bytes = patch_sweep_bytes(prob, s_f)
-    algo_bytes = patch_sweep_bytes_algorithmic(prob, s_f, n_st)
+    s_r = 4 if prec == binding.FP32 else 8   # the FP32 sweep reads an FP32-rounded residual
+    io_bytes = patch_sweep_bytes(prob, s_f, s_r)
+    algo_bytes = patch_sweep_bytes_algorithmic(prob, s_f, n_st, s_r)
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
     achieved = algo_bytes / (sweep_avg_ms * 1e-3) / 1e9
     achieved_io = io_bytes / (sweep_avg_ms * 1e-3) / 1e9
@@ -249,7 +250,7 @@ def main():
         ctx.set_timing(False)
         ms64 = e0.elapsed_time(e1) / args.fp64_steps
         sw64 = kt64["sweep"][0] / max(kt64["sweep"][1], 1)
-        algo64 = patch_sweep_bytes_algorithmic(prob, 8, n_st)
+        algo64 = patch_sweep_bytes_algorithmic(prob, 8, n_st, 8)
         fp64_leg = {"smoother_prec": "fp64", "ms_per_step": ms64, "value": n_st / (ms64 * 1e-3),
                     "unit": "st-DoF/s", "steps": args.fp64_steps,
                     "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt64.items()},
@@ -292,7 +293,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 patch factors/solves, f64 residual/update",
+        "dtype": ("f32 patch factors/solves (residual input rounded to f32), f64 residual/update"
+                  if prec == binding.FP32 else "f64"),
         "data": "synthetic manufactured solution (seeded Fourier modes)",
         "config": {"workload": f"{w.LARGE} finest-level WR sweep" if args.mesh == 128
                    else f"ns_p2p1_dg1_m{args.mesh}_n{args.slabs} finest-level WR sweep",
@@ -306,10 +308,11 @@ def main():
                      "kernel": ("k_patch_sweep_f32 (interior + boundary launches)" if prec == binding.FP32
                                 else "k_patch_sweep"), "avg_ms": sweep_avg_ms,
                      "algorithmic_bytes": algo_bytes,
-                     "algorithmic_bytes_def": "sum over (patch, slab) of m^2 s_f + 24 n_st (r read, z read-modify-write)",
+                     "algorithmic_bytes_def": f"sum over (patch, slab) of m^2 s_f + {s_r + 16} n_st "
+                                              f"(r read, {s_r} bytes; z read-modify-write)",
                      "with_patch_io": {"bytes": io_bytes, "achieved": achieved_io,
                                        "frac": achieved_io / HBM_PEAK_GBS,
-                                       "def": "sum over (patch, slab) of m^2 s_f + 8 m + s_f m "
+                                       "def": f"sum over (patch, slab) of m^2 s_f + {s_r} m + s_f m "
                                               "(each patch's residual gather and its own outputs)"}},
         "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "kernels_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
@@ -1060,22 +1063,23 @@ def p3p2_sweep(steps: int = 10) -> dict:
                          "frac": algo / (sw * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
-def patch_sweep_bytes_algorithmic(prob, s_f: int, n_st: int) -> int:
+def patch_sweep_bytes_algorithmic(prob, s_f: int, n_st: int, s_r: int) -> int:
     """Algorithmic bytes of one WR sweep's patch kernel: every (patch, slab)
-    inverse block once, m^2 s_f bytes (m = (q+1) nb), plus the FP64 residual
-    read once (8 n_st) and the correction read and written once (16 n_st)."""
+    inverse block once, m^2 s_f bytes (m = (q+1) nb), plus the residual read
+    once (s_r n_st: 4 for the FP32 sweep, which reads it rounded to FP32, 8
+    otherwise) and the FP64 correction read and written once (16 n_st)."""
     from paper_2407_13997_amd import binding
     hist = binding.mesh_info(prob.mesh_n)[12:52]
     nq = prob.q + 1
     blocks = sum(int(cnt) * prob.n_slabs * (nb * nq) ** 2 * s_f for nb, cnt in enumerate(hist))
-    return blocks + 24 * int(n_st)
+    return blocks + (s_r + 16) * int(n_st)
 
 
-def patch_sweep_bytes(prob, s_f: int) -> int:
+def patch_sweep_bytes(prob, s_f: int, s_r: int) -> int:
     """Algorithmic bytes of one patch-sweep launch on the finest level:
-    sum over patches of N (m^2 s_f + 8 m + s_f m), m = (q+1) nb the slab block
-    size: the inverse block, the FP64 residual gather and the patch output
-    (in the smoother's precision) per slab."""
+    sum over patches of N (m^2 s_f + s_r m + s_f m), m = (q+1) nb the slab
+    block size: the inverse block, the residual gather (s_r bytes a value)
+    and the patch output (in the smoother's precision) per slab."""
     from paper_2407_13997_amd import binding
     info = binding.mesh_info(prob.mesh_n)
     hist = info[12:52]
@@ -1083,7 +1087,7 @@ def patch_sweep_bytes(prob, s_f: int) -> int:
     tot = 0
     for nb, cnt in enumerate(hist):
         m = nb * nq
-        tot += int(cnt) * prob.n_slabs * (m * m * s_f + 8 * m + s_f * m)
+        tot += int(cnt) * prob.n_slabs * (m * m * s_f + s_r * m + s_f * m)
     return tot
 
 

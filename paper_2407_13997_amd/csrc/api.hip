@@ -149,14 +149,19 @@ int64_t level_block_elems(const HostLevel& H, int m, int VW) {
 // factored once and read for every slab.
 int fac_slabs_of(const HostLevel& H, int N) { return H.kdeg > 0 ? 1 : N; }
 
+// Levels whose FP32 sweep reads an FP32 residual (P2-P1 Navier-Stokes); it
+// sits after the blocks in the factor storage.
+bool has_f32_residual(const HostLevel& H, int prec) { return prec == STWR_FP32 && H.kdeg == 0 && H.thk == 0; }
+
 // Element count of the factor storage of one level at a precision.
 int64_t fac_elems(const HostLevel& H, int N, int NQ, int prec) {
-  N = fac_slabs_of(H, N);
+  const int NS = fac_slabs_of(H, N);
   int64_t tot = 0;
   for (int v = 0; v < H.nv; ++v) {
     const int m = (H.patch_ptr[v + 1] - H.patch_ptr[v]) * NQ;
-    tot += (int64_t)N * level_block_elems(H, m, vw_of(prec));
+    tot += (int64_t)NS * level_block_elems(H, m, vw_of(prec));
   }
+  if (has_f32_residual(H, prec)) tot += (int64_t)H.nf * N * NQ;
   return tot;
 }
 
@@ -387,6 +392,7 @@ void ensure_factor_storage(stwr_problem* P, Level& L, int prec) {
     L.fac_off[v + 1] = L.fac_off[v] + level_block_elems(L.H, m, vw_of(prec));
   }
   L.pview.slab_stride = L.pview.fac_slabs == 1 ? 0 : L.fac_off[L.H.nv];
+  L.rf = has_f32_residual(L.H, prec) ? (float*)L.fac + (int64_t)L.pview.fac_slabs * L.fac_off[L.H.nv] : nullptr;
   HIPCHK(hipMemcpyAsync(L.d_fac_off, L.fac_off.data(), L.fac_off.size() * 8, hipMemcpyHostToDevice, P->s()));
 }
 
@@ -598,13 +604,25 @@ void relax(stwr_problem* P, int l, const double* b, double* x, int n_steps, doub
   Level& L = P->lv[l];
   const double theta = 0.5 * (a + bnd), delta = 0.5 * (bnd - a);
   double rho_old = 0.0;
+  // the FP32 interior sweep rounds its residual to FP32 on reading, so the
+  // operator kernel may as well store it rounded: half the residual's bytes
+  const bool f32r = L.rf && sweep_takes_f32_residual(L.view, L.pview, L.fac_prec);
   for (int k = 0; k < n_steps; ++k) {
-    const double* r = L.r;
-    if (k == 0 && x_is_zero) r = b;   // b - A 0 = b exactly
-    else spmv(P, l, x, b, L.r);
-    {
+    if (k == 0 && x_is_zero) {   // b - A 0 = b exactly
       KernelMark mark(P->ctx, 0);
-      HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, r, L.Y, P->s()));
+      HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, b, L.Y, P->s()));
+    } else if (f32r) {
+      {
+        KernelMark mark(P->ctx, 1);
+        HIPCHK(launch_spmv_f32out(L.view, L.Jv, L.Mv, P->tab.e0, P->tab.e1, x, b, L.rf, P->s()));
+      }
+      KernelMark mark(P->ctx, 0);
+      HIPCHK(launch_patch_sweep_f32r(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, L.rf, L.Y,
+                                     P->s()));
+    } else {
+      spmv(P, l, x, b, L.r);
+      KernelMark mark(P->ctx, 0);
+      HIPCHK(launch_patch_sweep(L.view, L.pview, L.fac_prec, L.fac, L.Mp, P->tab.e0, P->tab.e1, L.r, L.Y, P->s()));
     }
     double c1, c2, rho;
     if (k == 0) {

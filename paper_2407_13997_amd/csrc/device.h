@@ -244,6 +244,9 @@ hipError_t launch_heat_rhs(const LevelView& L, const RefTables* tab, const doubl
 hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, const double* e0,
                        const double* e1, const double* x, const double* b, double* y,
                        hipStream_t s);
+// the same with y = b - A x rounded to FP32 (b required)
+hipError_t launch_spmv_f32out(const LevelView& L, const double* Jv, const double* Mv, const double* e0,
+                              const double* e1, const double* x, const double* b, float* y, hipStream_t s);
 hipError_t launch_transfer(int n_rows, int nt, const int* ptr, const int* col, const double* val,
                            const double* x, double* y, int accumulate, hipStream_t s);
 hipError_t launch_gather(int n, int nt, const int* map, const double* x, double* y, hipStream_t s);
@@ -282,6 +285,12 @@ hipError_t launch_patch_mass(const LevelView& L, const PatchView& P, const doubl
 hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, const void* fac,
                               const double* Mp, const double* e0, const double* e1,
                               const double* r, void* Y, hipStream_t s);
+// The FP32 interior sweep (P2-P1, FP32 blocks, one time chunk) on an FP32
+// residual; sweep_takes_f32_residual tells whether a level takes it.
+bool sweep_takes_f32_residual(const LevelView& L, const PatchView& P, int prec);
+hipError_t launch_patch_sweep_f32r(const LevelView& L, const PatchView& P, int prec, const void* fac,
+                                   const double* Mp, const double* e0, const double* e1, const float* r,
+                                   void* Y, hipStream_t s);
 // Large blocks (L.thk > 0): dense FP64 copies of blocks b0 .. b0 + count - 1
 // of the level (block b: patch at position b / fac_slabs of the patch order,
 // slab b % fac_slabs) into B (count x mmax x mmax, row-major), each padded with

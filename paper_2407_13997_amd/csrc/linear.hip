@@ -15,14 +15,16 @@ constexpr int kBlock = 256;
 // y = A x or y = b - A x for the space-time operator of one level:
 // block diagonal part from Jv, plus the jump coupling of slab n to slab n-1,
 // -e0 (x) (M * (e1 . x_{n-1})), on velocity rows.  One lane per (row, slab).
-template <int NQ>
+// TO: the output's type (FP32 for the residual of the FP32 sweep: the value
+// is formed in FP64 and rounded once on the store).
+template <int NQ, typename TO = double>
 __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const int* __restrict__ rp,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ Jv,
                                                  const double* __restrict__ Mv, TimeEnds te,
                                                  const double* __restrict__ x,
                                                  const double* __restrict__ b,
-                                                 double* __restrict__ y) {
+                                                 TO* __restrict__ y) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= (int64_t)nf * N) return;
   const int i = (int)(t / N), n = (int)(t % N);
@@ -54,10 +56,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const in
       }
     }
   }
-  double* yo = y + t * NQ;
+  TO* yo = y + t * NQ;
   for (int a = 0; a < NQ; ++a) {
     const double out = acc[a] - e0[a] * jump;
-    yo[a] = b ? b[t * NQ + a] - out : out;
+    yo[a] = (TO)(b ? b[t * NQ + a] - out : out);
   }
 }
 
@@ -798,7 +800,17 @@ hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, c
                        hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   const TimeEnds te = time_ends(L.NQ, e0, e1);
-  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL(k_spmv<Q>, dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
+  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL((k_spmv<Q, double>), dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
+                                          L.row_ptr, L.col, Jv, Mv, te, x, b, y));
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_f32out(const LevelView& L, const double* Jv, const double* Mv, const double* e0,
+                              const double* e1, const double* x, const double* b, float* y, hipStream_t s) {
+  if (!b) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)L.nf * L.N;
+  const TimeEnds te = time_ends(L.NQ, e0, e1);
+  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL((k_spmv<Q, float>), dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
                                           L.row_ptr, L.col, Jv, Mv, te, x, b, y));
   return hipGetLastError();
 }

@@ -380,9 +380,10 @@ __device__ inline T dotv(const V& w, const T* g) {
 // slab n's product has consumed its registers, so they are in flight while
 // slab n's output is stored and the jump coupling is formed; every load is
 // unconditional (clamped addresses), so the wait counts leave them
-// outstanding.  The residual is staged a 128-byte line (16 / (q+1) slabs) of
-// every patch DoF at a time, with one batch of coalesced loads issued ahead
-// of a block.  The outputs are FP32 (they are computed in FP32, so nothing
+// outstanding.  The residual is staged 16 / (q+1) slabs of every patch DoF
+// at a time (a 128-byte line of FP64 values, or half a line of FP32 values
+// when the operator kernel stores it rounded), with one batch of coalesced
+// loads issued ahead of a block.  The outputs are FP32 (they are computed in FP32, so nothing
 // is lost; the gather widens them), collected in LDS for 64 / (q+1) slabs
 // and written DoF by DoF ([patch DoF][slab][node], two whole 128-byte lines
 // per DoF and chunk) with nontemporal stores: writes interleaved with the
@@ -415,12 +416,12 @@ struct SweepF32Lds {
   alignas(16) float ych[4 * CH * MAXM];        // outputs of the current 4 CH slabs, [patch DoF][slab][node]
 };
 
-template <int NQ, bool FULL>
+template <int NQ, bool FULL, typename TR = double>
 __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchView& P, const int p,
                                                 const float* __restrict__ fac,
                                                 const double* __restrict__ Mp, const double e00,
                                                 const double e01, const double e10,
-                                                const double e11, const double* __restrict__ r,
+                                                const double e11, const TR* __restrict__ r,
                                                 float* __restrict__ Y, SweepF32Lds<NQ>& S) {
   constexpr int MAXM = kMaxNb * NQ;
   constexpr int VW = 4;
@@ -428,7 +429,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   constexpr int K2 = (MAXP + 3) / 4;
   constexpr bool kTwo = MAXM > 64;
   constexpr int R1F = MAXM < 64 ? MAXM : 64, R2F = MAXM - R1F;
-  constexpr int kLine = 16;                    // doubles in one 128-byte line
+  constexpr int kLine = 16;                    // residual values of a DoF staged at a time (a 128-byte line of doubles)
   constexpr int CH = kLine / NQ;               // slabs per residual line
   constexpr int RL = (kMaxNb * kLine + 63) / 64;   // residual loads per lane and line
   constexpr int RW = kTwo ? 128 : 64;
@@ -445,7 +446,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   const float e0[2] = {(float)e00, (float)e01}, e1[2] = {(float)e10, (float)e11};
   const int lane = threadIdx.x;
   const GLOBAL_AS int* patch_ptr = gptr(P.patch_ptr);
-  const GLOBAL_AS double* gr = gptr(r);
+  const GLOBAL_AS TR* gr = gptr(r);
   const int s0 = patch_ptr[p];
   const int nb = FULL ? kMaxNb : patch_ptr[p + 1] - s0;
   const int nbu = FULL ? kMaxNbu : gptr(P.patch_nbu)[p];
@@ -486,7 +487,7 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   const int nel = nb * kLine;
   float4 a1[MAXP];
   float4 a2[kTwo ? K2 : 1];
-  double rv[RL];
+  TR rv[RL];
   auto issue = [&](int n) {
     const GLOBAL_AS float* blk = Ab + (int64_t)n * SS;
 #pragma unroll
@@ -634,17 +635,20 @@ __device__ __forceinline__ void sweep_f32_patch(const LevelView& L, const PatchV
   }
 }
 
-template <int NQ>
+// TR: the residual's type.  FP32 residuals (rounded by the operator kernel
+// that writes them) give the same outputs as FP64 ones rounded here, and
+// halve the residual's bytes on both sides.
+template <int NQ, typename TR>
 __global__ __launch_bounds__(64) void k_patch_sweep_f32(LevelView L, PatchView P,
                                                        const float* __restrict__ fac,
                                                        const double* __restrict__ Mp, double e00,
                                                        double e01, double e10, double e11,
-                                                       const double* __restrict__ r,
+                                                       const TR* __restrict__ r,
                                                        float* __restrict__ Y) {
   __shared__ SweepF32Lds<NQ> S;
   const int p = P.order[blockIdx.x];
-  if ((int)blockIdx.x < P.n_full) sweep_f32_patch<NQ, true>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
-  else sweep_f32_patch<NQ, false>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
+  if ((int)blockIdx.x < P.n_full) sweep_f32_patch<NQ, true, TR>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
+  else sweep_f32_patch<NQ, false, TR>(L, P, p, fac, Mp, e00, e01, e10, e11, r, Y, S);
 }
 
 // Persistent FP32 sweep over the patches of many (problem, level) jobs with
@@ -1540,14 +1544,32 @@ hipError_t launch_patch_sweep(const LevelView& L, const PatchView& P, int prec, 
     const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
     dim3 grid(P.n_patch);
     if (L.NQ == 1) {
-      hipLaunchKernelGGL(k_patch_sweep_f32<1>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
+      hipLaunchKernelGGL((k_patch_sweep_f32<1, double>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     } else {
-      hipLaunchKernelGGL(k_patch_sweep_f32<2>, grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
+      hipLaunchKernelGGL((k_patch_sweep_f32<2, double>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
     }
     return hipGetLastError();
   }
   if (L.NQ == 1) return sweep_generic<1, double, 2, false, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
   return sweep_generic<2, double, 4, false, kMaxNb, kMaxNbu>(L, P, fac, Mp, te, r, Yd, s);
+}
+
+bool sweep_takes_f32_residual(const LevelView& L, const PatchView& P, int prec) {
+  return L.thk == 0 && L.kdeg == 0 && prec == 1 && P.time_chunks <= 1 && (L.NQ == 1 || L.NQ == 2);
+}
+
+hipError_t launch_patch_sweep_f32r(const LevelView& L, const PatchView& P, int prec, const void* fac,
+                                   const double* Mp, const double* e0, const double* e1, const float* r,
+                                   void* Y, hipStream_t s) {
+  if (!sweep_takes_f32_residual(L, P, prec)) return hipErrorInvalidValue;
+  const double e01 = L.NQ > 1 ? e0[1] : 0.0, e11 = L.NQ > 1 ? e1[1] : 0.0;
+  dim3 grid(P.n_patch);
+  if (L.NQ == 1) {
+    hipLaunchKernelGGL((k_patch_sweep_f32<1, float>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
+  } else {
+    hipLaunchKernelGGL((k_patch_sweep_f32<2, float>), grid, dim3(64), 0, s, L, P, (const float*)fac, Mp, e0[0], e01, e1[0], e11, r, (float*)Y);
+  }
+  return hipGetLastError();
 }
 
 template <int NQ, typename T, int NBUMAX>

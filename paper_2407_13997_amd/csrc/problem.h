@@ -137,6 +137,7 @@ struct Level {
   int *P_ptr = nullptr, *P_col = nullptr, *R_ptr = nullptr, *R_col = nullptr, *inject = nullptr;
   double *P_val = nullptr, *R_val = nullptr;
   double *r = nullptr, *d = nullptr, *x = nullptr, *b = nullptr;
+  float* rf = nullptr;   // FP32 residual of the FP32 interior sweep (inside the factor storage)
   double* Binv = nullptr;   // coarsest only
   double* gbuf = nullptr;   // coarsest only: right-hand side of one slab
   int* perm = nullptr;      // coarsest only: pivot rows of the slab inverses
