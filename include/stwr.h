@@ -362,7 +362,9 @@ int32_t stwr_patch_apply_noalloc(stwr_problem* p, int32_t level, const double* r
 int32_t stwr_eig_estimate(stwr_problem* p, int32_t level, double* lambda);
 
 /* n_steps Chebyshev-accelerated relaxation sweeps on A_l x = b over [a, bnd];
- * x is updated in place. */
+ * x is updated in place.  Each sweep forms r = b - A_l x in FP64; with FP32
+ * patch factors on a P2-P1 level (one time chunk) r is stored rounded to
+ * FP32, the precision the FP32 patch solves take it in. */
 int32_t stwr_relax(stwr_problem* p, int32_t level, const double* b, double* x,
                    int32_t n_steps, double a, double bnd);
 
