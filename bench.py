@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--largest-solve", type=int, default=0,
                     help="also run the 128x128 Newton solve with this many levels (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0)
+    ap.add_argument("--read-rate-gib", type=float, default=8.0,
+                    help="buffer for the measured HBM read rate (0 = skip)")
     ap.add_argument("--paper-run", default=None,
                     help="only solve this one of the paper's runs and print its record (for profiling): "
                          "chorin_q<q>_n<N>, chorin_p3p2_q<q>_n<N> or cavity_m<M>_q<q>_r<R>")
@@ -272,6 +274,14 @@ def main():
             P.vcycle(b, vx)
         torch.cuda.synchronize()
         vc_ms = (time.perf_counter() - tv) / args.vcycles * 1e3
+    # the device's attainable HBM read rate (a plain streaming read of 8 GiB,
+    # outside the timed region), reported beside the published peak
+    read_gbs = None
+    if args.read_rate_gib > 0:
+        rb = torch.ones(int(args.read_rate_gib * (1 << 30)) // 4, dtype=torch.float32, device="cuda")
+        read_gbs = ctx.read_rate(rb, 10)
+        del rb
+        log(f"[bench] measured HBM read rate {read_gbs:.1f} GB/s")
     if args.copy_calibration_gib > 0:
         # a plain device copy of known size, for scaling hardware byte counters
         nb = int(args.copy_calibration_gib * (1 << 30)) // 8
@@ -308,6 +318,8 @@ def main():
                      "kernel": ("k_patch_sweep_f32 (interior + boundary launches)" if prec == binding.FP32
                                 else "k_patch_sweep"), "avg_ms": sweep_avg_ms,
                      "algorithmic_bytes": algo_bytes,
+                     "measured_read_gbs": read_gbs,
+                     "frac_of_measured_read": achieved / read_gbs if read_gbs else None,
                      "algorithmic_bytes_def": f"sum over (patch, slab) of m^2 s_f + {s_r + 16} n_st "
                                               f"(r read, {s_r} bytes; z read-modify-write)",
                      "with_patch_io": {"bytes": io_bytes, "achieved": achieved_io,

@@ -224,6 +224,18 @@ int32_t stwr_ctx_bytes_in_use(const stwr_ctx* ctx, uint64_t* bytes);
 int32_t stwr_ctx_set_timing(stwr_ctx* ctx, int32_t enable);
 int32_t stwr_ctx_kernel_times(stwr_ctx* ctx, double* ms, int64_t* launches);
 
+/* Measurement aid for the roofline of the memory-bound kernels (the patch
+ * sweep of Sec. 3 and the operator of eq. nsfem): the device's attainable HBM
+ * read rate, reported beside the published peak.  Reads `bytes` of the
+ * caller's device buffer `buf` (a multiple of 16, at least 64 MiB so that
+ * caches do not serve it; not modified) with a grid-stride kernel of 16-byte
+ * nontemporal loads, eight 256-thread workgroups per CU, on the context's
+ * stream; one untimed launch, then `reps` launches timed with HIP events.
+ * *gbs = bytes / fastest launch, in GB/s.  Allocates and frees a small
+ * partial-sum buffer and synchronises the stream.  STWR_ERR_ARG on a bad
+ * size, pointer or reps < 1. */
+int32_t stwr_ctx_read_rate(stwr_ctx* ctx, const void* buf, uint64_t bytes, int32_t reps, double* gbs);
+
 /* Allocate problem memory stream-ordered (hipMallocAsync/hipFreeAsync on the
  * context's stream) instead of hipMalloc/hipFree, so that freeing a finished
  * problem does not synchronise the device while other streams work. */

@@ -34,7 +34,7 @@ EXPORTED = [
     "stwr_eig_estimate",
     "stwr_relax", "stwr_restrict", "stwr_prolong_add", "stwr_coarse_solve",
     "stwr_setup_smoothers", "stwr_vcycle", "stwr_fgmres", "stwr_newton_solve",
-    "stwr_project_pressure", "stwr_ctx_set_timing", "stwr_ctx_kernel_times",
+    "stwr_project_pressure", "stwr_ctx_set_timing", "stwr_ctx_kernel_times", "stwr_ctx_read_rate",
     "stwr_ctx_set_alloc_mode", "stwr_server_create", "stwr_server_submit", "stwr_server_poll",
     "stwr_server_wait", "stwr_server_now", "stwr_server_destroy",
     "stwr_batch_create", "stwr_batch_add", "stwr_batch_step", "stwr_batch_poll", "stwr_batch_info",
@@ -155,6 +155,7 @@ def load(path: str | None = None):
         "stwr_project_pressure": [P, i32, V],
         "stwr_ctx_set_timing": [P, i32],
         "stwr_ctx_kernel_times": [P, ctypes.POINTER(f64), ctypes.POINTER(i64)],
+        "stwr_ctx_read_rate": [P, V, u64, i32, ctypes.POINTER(f64)],
         "stwr_ctx_set_alloc_mode": [P, i32],
         "stwr_server_create": [i32, i32, u64, ctypes.POINTER(P)],
         "stwr_server_submit": [P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolverOpts), V,
@@ -317,6 +318,16 @@ class Context:
         n = (ctypes.c_int64 * 3)()
         self.check(self.lib.stwr_ctx_kernel_times(self.h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(("sweep", "operator", "gather"))}
+
+    def read_rate(self, buf, reps: int = 5) -> float:
+        """Attainable HBM read rate in GB/s, measured on the contiguous device
+        tensor `buf` (at least 64 MiB, a multiple of 16 bytes; not modified)."""
+        assert buf.is_cuda and buf.is_contiguous(), "need a contiguous device tensor"
+        out = ctypes.c_double()
+        nbytes = buf.numel() * buf.element_size()
+        self.check(self.lib.stwr_ctx_read_rate(self.h, ctypes.c_void_p(buf.data_ptr()), nbytes, reps,
+                                               ctypes.byref(out)))
+        return float(out.value)
 
     def error(self) -> str:
         return self.lib.stwr_last_error(self.h).decode()

@@ -1079,6 +1079,38 @@ int32_t stwr_ctx_set_alloc_mode(stwr_ctx* ctx, int32_t stream_ordered) {
   return STWR_OK;
 }
 
+int32_t stwr_ctx_read_rate(stwr_ctx* ctx, const void* buf, uint64_t bytes, int32_t reps, double* gbs) {
+  if (!ctx || !buf || !gbs || bytes < ((uint64_t)64 << 20) || bytes % 16 != 0 || reps < 1) return STWR_ERR_ARG;
+  return guarded(ctx, [&]() -> int32_t {
+    HIPCHK(hipSetDevice(ctx->device));
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int grid = 8 * (cus > 0 ? cus : 1);   // eight 256-thread workgroups per CU
+    float* out = nullptr;
+    HIPCHK(hipMalloc(&out, (size_t)grid * 256 * sizeof(float)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best = 0.0f;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = launch_stream_read(buf, (int64_t)bytes, grid, out, ctx->stream);   // warm-up
+    for (int k = 0; k < reps && err == hipSuccess; ++k) {
+      err = hipEventRecord(e0, ctx->stream);
+      if (err == hipSuccess) err = launch_stream_read(buf, (int64_t)bytes, grid, out, ctx->stream);
+      if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess && (k == 0 || ms < best)) best = ms;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    HIPCHK(err);
+    *gbs = best > 0.0f ? (double)bytes / ((double)best * 1e6) : 0.0;
+    return STWR_OK;
+  });
+}
+
 int32_t stwr_ctx_set_timing(stwr_ctx* ctx, int32_t enable) {
   if (!ctx) return STWR_ERR_ARG;
   ctx->timing = enable != 0;

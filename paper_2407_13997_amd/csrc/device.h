@@ -262,6 +262,9 @@ hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* 
 hipError_t launch_scale_dev(int64_t n, const double* num, int invert, const double* x, double* y,
                             hipStream_t s);  // y = x * (*num) or x / (*num)
 hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s);
+// read `bytes` (a multiple of 16) of device memory with `grid` workgroups of
+// 256 threads; out receives grid * 256 partial sums
+hipError_t launch_stream_read(const void* buf, int64_t bytes, int grid, float* out, hipStream_t s);
 hipError_t launch_start_vector(int64_t n, double* y, hipStream_t s);
 hipError_t launch_pressure_project(int nf, int po, int nt, double* x, double* work,
                                    hipStream_t s);

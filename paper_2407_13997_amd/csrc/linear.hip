@@ -139,6 +139,21 @@ __global__ __launch_bounds__(kBlock) void k_scale_dev(int64_t n, const double* _
   if (e < n) y[e] = invert ? x[e] / num[0] : x[e] * num[0];
 }
 
+// Attainable HBM read rate: a grid-stride read of n4 16-byte vectors with
+// nontemporal loads (each lane one vector in flight at a time), one partial
+// sum per thread written out so the loads are not dropped.
+typedef float stream_f4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_stream_read(const stream_f4* __restrict__ x, int64_t n4,
+                                                        float* __restrict__ out) {
+  float acc = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) {
+    const stream_f4 v = __builtin_nontemporal_load(x + i);
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = acc;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double v, double* __restrict__ y) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < n) y[e] = v;
@@ -849,6 +864,12 @@ hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* 
 hipError_t launch_scale_dev(int64_t n, const double* num, int invert, const double* x, double* y,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_scale_dev, dim3(nblk(n)), dim3(kBlock), 0, s, n, num, invert, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const void* buf, int64_t bytes, int grid, float* out, hipStream_t s) {
+  if (bytes < 16 || bytes % 16 != 0 || grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(kBlock), 0, s, (const stream_f4*)buf, bytes / 16, out);
   return hipGetLastError();
 }
 
