@@ -256,8 +256,10 @@ __device__ __forceinline__ void factor_block(const LevelView& L, const PatchView
     // the pivot row in batches of EB 16-byte reads: a batch's reads are in
     // flight together, so a step waits for the LDS once per batch instead of
     // once per 16 bytes (with one or two wavefronts per SIMD nothing else
-    // hides that latency), while the batch's registers stay few
-    constexpr int EB = MAXM > 100 ? 2 : 8;
+    // hides that latency), while the batch's registers stay within the two
+    // wavefronts per SIMD the row registers allow (162-row blocks: 10 reads,
+    // 222 VGPRs; 2 reads took 5% longer)
+    constexpr int EB = MAXM > 100 ? 10 : 8;
 #pragma unroll
     for (int j0 = 0; j0 < MP; j0 += RV * EB) {
       V16 v[EB];
