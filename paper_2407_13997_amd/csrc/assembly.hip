@@ -193,6 +193,14 @@ __device__ void stage_cell(const LevelView& L, const RefTables* __restrict__ T, 
   __syncthreads();
 }
 
+// Symmetric temporal pair s of NQ nodes (a <= b), s = 0 .. NQ (NQ + 1) / 2 - 1.
+template <int NQ>
+__device__ __forceinline__ void temporal_pair(int s, int& a, int& b) {
+  a = 0;
+  while (s >= NQ - a) { s -= NQ - a; ++a; }
+  b = a + s;
+}
+
 template <int NQ>
 __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* __restrict__ T,
                                                  MmsDev mms, const double* __restrict__ U,
@@ -200,77 +208,93 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
   // one workgroup per (cell, slab), slab fastest: consecutive workgroups
   // update the same operator lines (each holds several slabs of a nonzero)
   const int c = cell_of(L), n = blockIdx.x % L.N, tid = threadIdx.x;
+  constexpr int NS = NQ * (NQ + 1) / 2;   // temporal pairs a <= b
   __shared__ CellStage<NQ> S;
+  // the convection terms with the temporal quadrature folded in first: for a
+  // temporal pair (a, b) and a spatial point x, w_x sum_g wg Phi_a Phi_b of
+  // the state's gradient (the Newton term) and of its value (the transport
+  // term).  Both are symmetric in (a, b), so NS pairs cover all NQ^2.
+  __shared__ double WD[NS][kQx][4], WU[NS][kQx][2];
   stage_cell<NQ>(L, T, mms, U, c, n, S);
-  // temporal Gauss points (q + 3 = NQ + 2, as the reference tables are built):
-  // a compile-time count keeps the per-thread accumulators in registers
-  constexpr int G = NQ + 2;
+  constexpr int G = NQ + 2;   // temporal Gauss points (q + 3), as the tables are built
   const double dt = L.dt, R = mms.reynolds;
   const int* nzc = L.cell_nz + (int64_t)225 * c;
-  if (tid < 36) {
-    const int i = tid / 6, j = tid % 6;
-    double Mij = 0.0, Kij = 0.0;
-    double c1[G], c2[G][2][2];
+  for (int e = tid; e < NS * kQx; e += 64) {
+    const int sp = e / kQx, x = e % kQx;
+    int a, b;
+    temporal_pair<NQ>(sp, a, b);
+    double d[4] = {0.0, 0.0, 0.0, 0.0}, u[2] = {0.0, 0.0};
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      c1[g] = 0.0;
-      c2[g][0][0] = c2[g][0][1] = c2[g][1][0] = c2[g][1][1] = 0.0;
+      const double cw = T->wg[g] * T->Phi[g][a] * T->Phi[g][b];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) d[k] += cw * S.gq[g][x][k / 2][k % 2];
+      u[0] += cw * S.uq[g][x][0];
+      u[1] += cw * S.uq[g][x][1];
     }
+    const double w = S.wdet[x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) WD[sp][x][k] = w * d[k];
+    WU[sp][x][0] = w * u[0];
+    WU[sp][x][1] = w * u[1];
+  }
+  __syncthreads();
+  // tasks spread over all lanes: (temporal pair, velocity pair i, j), each
+  // the spatial sums of its entries, then the 18 pressure-velocity pairs
+  constexpr int NV = 36 * NS, NT = NV + 18;
 #pragma unroll 1
-    for (int x = 0; x < kQx; ++x) {
-      const double w = S.wdet[x], Ni = T->N2[x][i], Nj = T->N2[x][j];
-      Mij += w * Ni * Nj;
-      Kij += w * (S.gN[x][i][0] * S.gN[x][j][0] + S.gN[x][i][1] * S.gN[x][j][1]);
+  for (int task = tid; task < NT; task += 64) {
+    if (task < NV) {
+      const int sp = task / 36, i = (task % 36) / 6, j = task % 6;
+      int a, b;
+      temporal_pair<NQ>(sp, a, b);
+      double Mij = 0.0, Kij = 0.0, C1 = 0.0, C2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int x = 0; x < kQx; ++x) {
+        const double w = S.wdet[x], Ni = T->N2[x][i], Nj = T->N2[x][j];
+        Mij += w * Ni * Nj;
+        Kij += w * (S.gN[x][i][0] * S.gN[x][j][0] + S.gN[x][i][1] * S.gN[x][j][1]);
+        C1 += Ni * (WU[sp][x][0] * S.gN[x][j][0] + WU[sp][x][1] * S.gN[x][j][1]);
+        const double nn = Ni * Nj;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        c1[g] += w * Ni * (S.uq[g][x][0] * S.gN[x][j][0] + S.uq[g][x][1] * S.gN[x][j][1]);
-        const double wnn = w * Ni * Nj;
-        for (int ci = 0; ci < 2; ++ci)
-          for (int cj = 0; cj < 2; ++cj) c2[g][ci][cj] += wnn * S.gq[g][x][ci][cj];
+        for (int k = 0; k < 4; ++k) C2[k] += nn * WD[sp][x][k];
       }
-    }
-    for (int a = 0; a < NQ; ++a)
-      for (int b = 0; b < NQ; ++b) {
-        double C1 = 0.0, C2[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const double cw = T->wg[g] * T->Phi[g][a] * T->Phi[g][b];
-          C1 += cw * c1[g];
-          for (int ci = 0; ci < 2; ++ci)
-            for (int cj = 0; cj < 2; ++cj) C2[ci][cj] += cw * c2[g][ci][cj];
-        }
-        const double diag = T->T[a][b] * Mij + dt * T->W[a][b] * Kij + dt * R * C1;
+      // the entries (a, b) and, off the diagonal, (b, a)
+      for (int pass = 0; pass < (a == b ? 1 : 2); ++pass) {
+        const int aa = pass ? b : a, bb = pass ? a : b;
+        const double diag = T->T[aa][bb] * Mij + dt * T->W[aa][bb] * Kij + dt * R * C1;
         for (int ci = 0; ci < 2; ++ci)
           for (int cj = 0; cj < 2; ++cj) {
             const int nz = nzc[15 * (6 * ci + i) + 6 * cj + j];
             if (nz < 0) continue;
-            const double v = dt * R * C2[ci][cj] + (ci == cj ? diag : 0.0);
-            scatter_add(L, &Jv[(((int64_t)nz * L.N + n) * NQ + a) * NQ + b], v);
+            const double v = dt * R * C2[2 * ci + cj] + (ci == cj ? diag : 0.0);
+            scatter_add(L, &Jv[(((int64_t)nz * L.N + n) * NQ + aa) * NQ + bb], v);
           }
       }
-    if (n == 0) {
-      for (int ci = 0; ci < 2; ++ci) {
-        const int nz = nzc[15 * (6 * ci + i) + 6 * ci + j];
-        if (nz >= 0) scatter_add(L, &Mv[nz], Mij);
-      }
-    }
-  } else if (tid < 54) {
-    const int t = tid - 36, j = t / 6, i = t % 6;   // pressure j, velocity node i
-    double B[2] = {0.0, 0.0};
-    for (int x = 0; x < kQx; ++x) {
-      const double w = S.wdet[x] * T->N1[x][j];
-      B[0] += w * S.gN[x][i][0];
-      B[1] += w * S.gN[x][i][1];
-    }
-    for (int a = 0; a < NQ; ++a)
-      for (int b = 0; b < NQ; ++b)
+      if (n == 0 && sp == 0) {
         for (int ci = 0; ci < 2; ++ci) {
-          const double v = -dt * T->W[a][b] * B[ci];
-          const int nz1 = nzc[15 * (6 * ci + i) + 12 + j];
-          if (nz1 >= 0) scatter_add(L, &Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
-          const int nz2 = nzc[15 * (12 + j) + 6 * ci + i];
-          if (nz2 >= 0) scatter_add(L, &Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
+          const int nz = nzc[15 * (6 * ci + i) + 6 * ci + j];
+          if (nz >= 0) scatter_add(L, &Mv[nz], Mij);
         }
+      }
+    } else {
+      const int t = task - NV, j = t / 6, i = t % 6;   // pressure j, velocity node i
+      double B[2] = {0.0, 0.0};
+      for (int x = 0; x < kQx; ++x) {
+        const double w = S.wdet[x] * T->N1[x][j];
+        B[0] += w * S.gN[x][i][0];
+        B[1] += w * S.gN[x][i][1];
+      }
+      for (int a = 0; a < NQ; ++a)
+        for (int b = 0; b < NQ; ++b)
+          for (int ci = 0; ci < 2; ++ci) {
+            const double v = -dt * T->W[a][b] * B[ci];
+            const int nz1 = nzc[15 * (6 * ci + i) + 12 + j];
+            if (nz1 >= 0) scatter_add(L, &Jv[(((int64_t)nz1 * L.N + n) * NQ + a) * NQ + b], v);
+            const int nz2 = nzc[15 * (12 + j) + 6 * ci + i];
+            if (nz2 >= 0) scatter_add(L, &Jv[(((int64_t)nz2 * L.N + n) * NQ + a) * NQ + b], v);
+          }
+    }
   }
 }
 
