@@ -36,6 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const in
   const bool prow = i >= po;
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
     const int j = col[k];
+    const double m = Mv[k];
     const double* xv = x + ((int64_t)j * N + n) * NQ;
     // an entry of a pressure row or column is the pressure coupling
     // -dt W (x) B, the same in every slab (linear in the state, uniform
@@ -43,17 +44,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const in
     // operator streams only the slab-dependent velocity-velocity blocks
     const bool pc = prow || j >= po;
     const double* v = Jv + ((int64_t)k * N + (pc ? 0 : n)) * NQ * NQ;
-    double xb[NQ];
-    for (int bb = 0; bb < NQ; ++bb) xb[bb] = xv[bb];
+    // the previous slab's values (unused at n = 0), loaded with the entry's
+    // other values and its mass coefficient so that an entry costs two
+    // memory round trips (its column, then everything else) instead of three
+    const double* xq = xv - (n > 0 ? NQ : 0);
+    double xb[NQ], xp[NQ];
+    for (int bb = 0; bb < NQ; ++bb) { xb[bb] = xv[bb]; xp[bb] = xq[bb]; }
     for (int a = 0; a < NQ; ++a)
       for (int bb = 0; bb < NQ; ++bb) acc[a] += v[a * NQ + bb] * xb[bb];
-    if (n > 0) {
-      const double m = Mv[k];
-      if (m != 0.0) {
-        double xl = 0.0;
-        for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xv[bb - NQ];
-        jump += m * xl;
-      }
+    if (n > 0 && m != 0.0) {
+      double xl = 0.0;
+      for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xp[bb];
+      jump += m * xl;
     }
   }
   TO* yo = y + t * NQ;
