@@ -248,6 +248,22 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
       const int sp = task / 36, i = (task % 36) / 6, j = task % 6;
       int a, b;
       temporal_pair<NQ>(sp, a, b);
+      // the entries this task adds to, (ci, cj) blocks of the pairs (a, b)
+      // and (b, a): their current values are loaded now, so the read of the
+      // read-modify-write overlaps the sums below (no other workgroup of
+      // this colour and no other task touches them)
+      double* dst[2][4];
+      double old[2][4];
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ci = e / 2, cj = e % 2;
+          const int nz = nzc[15 * (6 * ci + i) + 6 * cj + j];
+          const int aa = pass ? b : a, bb = pass ? a : b;
+          dst[pass][e] = (nz >= 0 && (pass == 0 || a != b)) ? &Jv[(((int64_t)nz * L.N + n) * NQ + aa) * NQ + bb] : nullptr;
+          old[pass][e] = dst[pass][e] ? *dst[pass][e] : 0.0;
+        }
       double Mij = 0.0, Kij = 0.0, C1 = 0.0, C2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
       for (int x = 0; x < kQx; ++x) {
@@ -260,16 +276,16 @@ __global__ __launch_bounds__(64) void k_jacobian(LevelView L, const RefTables* _
         for (int k = 0; k < 4; ++k) C2[k] += nn * WD[sp][x][k];
       }
       // the entries (a, b) and, off the diagonal, (b, a)
-      for (int pass = 0; pass < (a == b ? 1 : 2); ++pass) {
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
         const int aa = pass ? b : a, bb = pass ? a : b;
         const double diag = T->T[aa][bb] * Mij + dt * T->W[aa][bb] * Kij + dt * R * C1;
-        for (int ci = 0; ci < 2; ++ci)
-          for (int cj = 0; cj < 2; ++cj) {
-            const int nz = nzc[15 * (6 * ci + i) + 6 * cj + j];
-            if (nz < 0) continue;
-            const double v = dt * R * C2[2 * ci + cj] + (ci == cj ? diag : 0.0);
-            scatter_add(L, &Jv[(((int64_t)nz * L.N + n) * NQ + aa) * NQ + bb], v);
-          }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ci = e / 2, cj = e % 2;
+          const double v = dt * R * C2[e] + (ci == cj ? diag : 0.0);
+          if (dst[pass][e]) *dst[pass][e] = old[pass][e] + v;
+        }
       }
       if (n == 0 && sp == 0) {
         for (int ci = 0; ci < 2; ++ci) {
