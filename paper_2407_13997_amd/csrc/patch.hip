@@ -932,7 +932,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_patch_sweep(LevelView L, PatchVi
       }
     }
     if constexpr (kFast) {
-      if (hasRow && write_y) __builtin_nontemporal_store(y, yout + (int64_t)n * m + tid);   // streaming output
+      // a plain store: the one-wavefront patches (the heat equation) write little,
+      // and the gather finds it in cache (a nontemporal store was slower)
+      if (hasRow && write_y) yout[(int64_t)n * m + tid] = y;
       // slab-end value of the lane's DoF: its NQ rows sit in adjacent lanes
       double ve = e1a * y;
       if constexpr (NQ == 2) ve += dpp_move<0xB1>(ve);   // quad_perm [1,0,3,2]
