@@ -1,10 +1,11 @@
 """The WR patch sweep over many slabs (eq. waveform_patch_solve) against the
 oracle's patch smoother, element by element.
 
-The FP32 sweep kernel stages the residual one 128-byte line of a DoF at a time
-(8 slabs at q = 1, 16 at q = 0) and writes its outputs every 16 (q = 1) or
-32 (q = 0) slabs; N = 37 and N = 40 cross several of both boundaries and end
-on a ragged tail (37 divides by neither).  The 8x8 mesh has interior patches
+The FP32 sweep kernel stages the residual 16 values of a DoF at a time (8
+slabs at q = 1, 16 at q = 0) and writes its outputs every 32 (q = 1) or 64
+(q = 0) slabs; N = 37 and N = 40 cross several staging boundaries and, at
+q = 1, an output flush, and end on a ragged tail (37 divides by neither);
+N = 70 at q = 0 crosses a flush there.  The 8x8 mesh has interior patches
 (nb = 39, the compile-time specialisation) and every boundary patch size.
 Each case is checked for one patch application and for one and three
 Chebyshev relaxation sweeps, FP64 and FP32 factors, plain and time-chunked.
@@ -25,7 +26,7 @@ from gpu_common import entrywise, gpu_problem, log, seeded, to_dev, to_host, tor
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(1, 37), (1, 40), (0, 37), (0, 40)]
+CASES = [(1, 37), (1, 40), (0, 37), (0, 40), (0, 70)]
 BARS = {0: (1e-12, 1e-10), 1: (1e-5, 1e-4)}
 
 _cache = {}
@@ -94,3 +95,25 @@ def test_relax_long(q, N, prec):
         log(f"[sweep long] relax q={q} N={N} prec={prec} steps={steps} slab {es:.2e} entry {ee:.2e}")
         assert es <= BARS[prec][0] and ee <= BARS[prec][1]
     G.close()
+
+
+@pytest.mark.parametrize("q,N", [(1, 37), (0, 40)])
+def test_relax_f32_residual_is_the_rounded_fp64_one(q, N):
+    """With FP32 factors a relaxation sweep stores the residual rounded to
+    FP32 and the sweep reads it; a patch application on the FP64 residual
+    rounds it on reading instead.  Both must give the same correction bit for
+    bit: one sweep from x0 equals x0 + (2 / (a + bnd)) M^-1 (b - A x0)."""
+    torch = torch_cuda()
+    prob, lev, U, A, S = oracle_case(q, N)
+    G = gpu_case(prob, U, 1, 1)
+    b, x0 = to_dev(seeded(lev.n_st, 800 + N)), to_dev(seeded(lev.n_st, 900 + N))
+    a, bnd = 1.9, 8.3
+    x = x0.clone()
+    G.relax(0, b, x, 1, a, bnd)
+    r, z = G.vec(0), G.vec(0)
+    G.residual(0, b, x0, r)
+    G.patch_apply(0, r, z)
+    ref = x0 + (1.0 / (0.5 * (a + bnd))) * z
+    log(f"[sweep long] f32 residual q={q} N={N} max diff {float((x - ref).abs().max()):.3e}")
+    G.close()
+    assert torch.equal(x, ref)
