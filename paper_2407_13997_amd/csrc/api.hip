@@ -636,7 +636,9 @@ void relax(stwr_problem* P, int l, const double* b, double* x, int n_steps, doub
     }
     {
       KernelMark mark(P->ctx, 2);
-      HIPCHK(launch_patch_gather(L.view, L.pview, L.fac_prec, L.Y, 1, c1, c2, nullptr, L.d, x, P->s()));
+      // the last step's direction is not needed again: it is not stored
+      HIPCHK(launch_patch_gather(L.view, L.pview, L.fac_prec, L.Y, k + 1 < n_steps ? 1 : 2, c1, c2, nullptr, L.d, x,
+                                 P->s()));
     }
     rho_old = rho;
   }

@@ -314,7 +314,8 @@ hipError_t launch_patch_chunk_transfer(const LevelView& L, const PatchView& P, i
 inline bool sweep_outputs_f32(const LevelView& L, const PatchView& P, int prec) {
   return prec == 1 && L.kdeg == 0 && L.thk == 0 && P.time_chunks <= 1;
 }
-// mode 0: z = sum; mode 1: d = c1 d + c2 sum, x += d.
+// mode 0: z = sum; mode 1: d = c1 d + c2 sum, x += d; mode 2: the same x update
+// without storing d (the last step of a Chebyshev sequence).
 hipError_t launch_patch_gather(const LevelView& L, const PatchView& P, int prec, const void* Y,
                                int mode, double c1, double c2, double* z, double* d, double* x,
                                hipStream_t s);

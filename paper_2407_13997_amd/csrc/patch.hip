@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_patch_gather(int nf, int N, PatchView P
   } else {
     for (int a = 0; a < NQ; ++a) {
       const double dd = (c1 == 0.0 ? 0.0 : c1 * d[o + a]) + c2 * acc[a];
-      d[o + a] = dd;
+      if (mode == 1) d[o + a] = dd;   // mode 2: a sequence's last step, d is not read again
       x[o + a] += dd;
     }
   }
@@ -1304,7 +1304,7 @@ __global__ __launch_bounds__(256) void k_patch_gather_rows(int nf, int N, PatchV
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
       const double dd = (c1 == 0.0 ? 0.0 : c1 * d[o + a]) + c2 * acc[a];
-      d[o + a] = dd;
+      if (mode == 1) d[o + a] = dd;   // mode 2: a sequence's last step, d is not read again
       x[o + a] += dd;
     }
   }
