@@ -1301,11 +1301,49 @@ __global__ __launch_bounds__(256) void k_patch_gather_rows(int nf, int N, PatchV
 #pragma unroll
     for (int a = 0; a < NQ; ++a) z[o + a] = acc[a];
   } else {
+    // a thread's NQ values of x (and d) are loaded together, then stored
+    // together, so that they move as one 16-byte vector where x and d are
+    // 16-byte aligned (o is even); a caller's vector of another alignment
+    // takes the value-by-value path
+    double xv[NQ], dv[NQ], dd[NQ];
+    bool v16 = false;
+    if constexpr (NQ == 2) {
+      v16 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(d)) & 15) == 0;
+      if (v16) {
+        const double2 t = *reinterpret_cast<const double2*>(x + o);
+        xv[0] = t.x;
+        xv[1] = t.y;
+        if (c1 != 0.0) {
+          const double2 u = *reinterpret_cast<const double2*>(d + o);
+          dv[0] = u.x;
+          dv[1] = u.y;
+        } else {
+          dv[0] = dv[1] = 0.0;
+        }
+      }
+    }
+    if (!v16) {
 #pragma unroll
-    for (int a = 0; a < NQ; ++a) {
-      const double dd = (c1 == 0.0 ? 0.0 : c1 * d[o + a]) + c2 * acc[a];
-      if (mode == 1) d[o + a] = dd;   // mode 2: a sequence's last step, d is not read again
-      x[o + a] += dd;
+      for (int a = 0; a < NQ; ++a) {
+        xv[a] = x[o + a];
+        dv[a] = c1 == 0.0 ? 0.0 : d[o + a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) dd[a] = (c1 == 0.0 ? 0.0 : c1 * dv[a]) + c2 * acc[a];
+    if constexpr (NQ == 2) {
+      if (v16) {
+        if (mode == 1) *reinterpret_cast<double2*>(d + o) = make_double2(dd[0], dd[1]);
+        *reinterpret_cast<double2*>(x + o) = make_double2(xv[0] + dd[0], xv[1] + dd[1]);
+      }
+    }
+    if (!v16) {
+      if (mode == 1) {   // mode 2: a sequence's last step, d is not read again
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) d[o + a] = dd[a];
+      }
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) x[o + a] = xv[a] + dd[a];
     }
   }
 }
