@@ -16,8 +16,11 @@ constexpr int kBlock = 256;
 // block diagonal part from Jv, plus the jump coupling of slab n to slab n-1,
 // -e0 (x) (M * (e1 . x_{n-1})), on velocity rows.  One lane per (row, slab).
 // TO: the output's type (FP32 for the residual of the FP32 sweep: the value
-// is formed in FP64 and rounded once on the store).
-template <int NQ, typename TO = double>
+// is formed in FP64 and rounded once on the store).  U > 1: a row's entries
+// U at a time, every load of a group issued before any is used (the long
+// rows of the Taylor-Hood P3-P2 levels; on P2-P1 rows the extra registers
+// cost more than the shorter wait).  The arithmetic is the same either way.
+template <int NQ, typename TO = double, int U = 1>
 __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const int* __restrict__ rp,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ Jv,
@@ -34,28 +37,70 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nf, int po, int N, const in
   for (int a = 0; a < NQ; ++a) acc[a] = 0.0;
   double jump = 0.0;
   const bool prow = i >= po;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const int j = col[k];
-    const double m = Mv[k];
-    const double* xv = x + ((int64_t)j * N + n) * NQ;
-    // an entry of a pressure row or column is the pressure coupling
-    // -dt W (x) B, the same in every slab (linear in the state, uniform
-    // slabs): read slab 0's copy, one line for the whole row, so the
-    // operator streams only the slab-dependent velocity-velocity blocks
-    const bool pc = prow || j >= po;
-    const double* v = Jv + ((int64_t)k * N + (pc ? 0 : n)) * NQ * NQ;
-    // the previous slab's values (unused at n = 0), loaded with the entry's
-    // other values and its mass coefficient so that an entry costs two
-    // memory round trips (its column, then everything else) instead of three
-    const double* xq = xv - (n > 0 ? NQ : 0);
-    double xb[NQ], xp[NQ];
-    for (int bb = 0; bb < NQ; ++bb) { xb[bb] = xv[bb]; xp[bb] = xq[bb]; }
-    for (int a = 0; a < NQ; ++a)
-      for (int bb = 0; bb < NQ; ++bb) acc[a] += v[a * NQ + bb] * xb[bb];
-    if (n > 0 && m != 0.0) {
-      double xl = 0.0;
-      for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xp[bb];
-      jump += m * xl;
+  if constexpr (U == 1) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = col[k];
+      const double m = Mv[k];
+      const double* xv = x + ((int64_t)j * N + n) * NQ;
+      // an entry of a pressure row or column is the pressure coupling
+      // -dt W (x) B, the same in every slab (linear in the state, uniform
+      // slabs): read slab 0's copy, one line for the whole row, so the
+      // operator streams only the slab-dependent velocity-velocity blocks
+      const bool pc = prow || j >= po;
+      const double* v = Jv + ((int64_t)k * N + (pc ? 0 : n)) * NQ * NQ;
+      // the previous slab's values (unused at n = 0), loaded with the entry's
+      // other values and its mass coefficient so that an entry costs two
+      // memory round trips (its column, then everything else) instead of three
+      const double* xq = xv - (n > 0 ? NQ : 0);
+      double xb[NQ], xp[NQ];
+      for (int bb = 0; bb < NQ; ++bb) { xb[bb] = xv[bb]; xp[bb] = xq[bb]; }
+      for (int a = 0; a < NQ; ++a)
+        for (int bb = 0; bb < NQ; ++bb) acc[a] += v[a * NQ + bb] * xb[bb];
+      if (n > 0 && m != 0.0) {
+        double xl = 0.0;
+        for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xp[bb];
+        jump += m * xl;
+      }
+    }
+  } else {
+    const int kb = rp[i], ke = rp[i + 1];
+    for (int k0 = kb; k0 < ke; k0 += U) {
+      int jg[U];
+      double mg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u < ke ? k0 + u : ke - 1;   // clamped: past the row's end the entry is unused
+        jg[u] = col[k];
+        mg[u] = Mv[k];
+      }
+      double xb[U][NQ], xp[U][NQ], v[U][NQ * NQ];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u < ke ? k0 + u : ke - 1;
+        const double* xv = x + ((int64_t)jg[u] * N + n) * NQ;
+        const bool pc = prow || jg[u] >= po;
+        const double* vk = Jv + ((int64_t)k * N + (pc ? 0 : n)) * NQ * NQ;
+        const double* xq = xv - (n > 0 ? NQ : 0);
+#pragma unroll
+        for (int bb = 0; bb < NQ; ++bb) {
+          xb[u][bb] = xv[bb];
+          xp[u][bb] = xq[bb];
+        }
+#pragma unroll
+        for (int e = 0; e < NQ * NQ; ++e) v[u][e] = vk[e];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u < ke) {
+          for (int a = 0; a < NQ; ++a)
+            for (int bb = 0; bb < NQ; ++bb) acc[a] += v[u][a * NQ + bb] * xb[u][bb];
+          if (n > 0 && mg[u] != 0.0) {
+            double xl = 0.0;
+            for (int bb = 0; bb < NQ; ++bb) xl += e1[bb] * xp[u][bb];
+            jump += mg[u] * xl;
+          }
+        }
+      }
     }
   }
   TO* yo = y + t * NQ;
@@ -817,8 +862,13 @@ hipError_t launch_spmv(const LevelView& L, const double* Jv, const double* Mv, c
                        hipStream_t s) {
   const int64_t n = (int64_t)L.nf * L.N;
   const TimeEnds te = time_ends(L.NQ, e0, e1);
-  STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL((k_spmv<Q, double>), dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
-                                          L.row_ptr, L.col, Jv, Mv, te, x, b, y));
+  if (L.thk > 0) {
+    STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL((k_spmv<Q, double, 4>), dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
+                                            L.row_ptr, L.col, Jv, Mv, te, x, b, y));
+  } else {
+    STWR_NQ_SWITCH(L.NQ, hipLaunchKernelGGL((k_spmv<Q, double>), dim3(nblk(n)), dim3(kBlock), 0, s, L.nf, L.po, L.N,
+                                            L.row_ptr, L.col, Jv, Mv, te, x, b, y));
+  }
   return hipGetLastError();
 }
 
